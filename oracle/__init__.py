@@ -1,0 +1,306 @@
+"""FP64 CPU oracle for the DG LES right-hand side and LSRK54 step.
+
+TEST INFRASTRUCTURE ONLY.  Only ``tests/``, ``__graft_entry__.smoke()`` and the
+CPU-baseline leg of ``bench.py`` may import this package.  It shares no code
+with the GPU library (``paper_2110_00853_amd``) and never imports it; both are
+fed the same seeded inputs by ``paper_2110_00853_amd.workloads``.
+
+The C sources (``cmref.c``, ``cmref_mlp.c``) are compiled with gcc, ``-O2
+-ffp-contract=off`` and no fast-math, into ``liboracle.so`` next to them.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_SOURCES = ["cmref.c", "cmref_mlp.c"]
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle shared library (gcc, OpenMP, no FMA contraction)."""
+    if not force and os.path.exists(_LIB_PATH):
+        return _LIB_PATH
+    srcs = [os.path.join(_HERE, s) for s in _SOURCES]
+    tmp = _LIB_PATH + ".tmp%d" % os.getpid()
+    cmd = ["gcc", "-O2", "-std=c99", "-D_GNU_SOURCE", "-fPIC", "-shared", "-fopenmp",
+           "-ffp-contract=off", "-fno-fast-math", "-o", tmp] + srcs + ["-lm"]
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+class GridDesc(C.Structure):
+    _fields_ = [("N", C.c_int), ("ne", C.c_int * 3), ("lo", C.c_double * 3),
+                ("hi", C.c_double * 3), ("periodic", C.c_int * 3), ("topo", C.c_int),
+                ("topo_h", C.c_double), ("topo_a", C.c_double), ("topo_xc", C.c_double)]
+
+
+class ModelDesc(C.Structure):
+    _fields_ = [("nvar", C.c_int), ("closure", C.c_int), ("nu", C.c_double),
+                ("Cs", C.c_double), ("Prt", C.c_double), ("richardson", C.c_int),
+                ("g", C.c_double), ("f_cor", C.c_double), ("u_g", C.c_double),
+                ("v_g", C.c_double), ("sponge", C.c_int), ("sp_zs", C.c_double),
+                ("sp_ztop", C.c_double), ("sp_alpha", C.c_double), ("sp_gamma", C.c_double),
+                ("sp_u", C.c_double * 3), ("sfc_flux", C.c_int), ("theta_flux", C.c_double),
+                ("qt_flux", C.c_double), ("subsidence", C.c_int), ("sub_w0", C.c_double),
+                ("sub_ztop", C.c_double)]
+
+
+_P = np.ctypeslib.ndpointer(dtype=np.float64, flags="C_CONTIGUOUS")
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            build()
+        L = C.CDLL(_LIB_PATH)
+        L.cmref_gll.argtypes = [C.c_int, _P, _P, _P]
+        L.cmref_grid_create.argtypes = [C.POINTER(GridDesc), C.c_int]
+        L.cmref_grid_create.restype = C.c_void_p
+        L.cmref_grid_destroy.argtypes = [C.c_void_p]
+        L.cmref_grid_nnodes.argtypes = [C.c_void_p]
+        L.cmref_grid_nnodes.restype = C.c_long
+        L.cmref_grid_coords.argtypes = [C.c_void_p, _P]
+        L.cmref_grid_metrics.argtypes = [C.c_void_p, _P, _P]
+        L.cmref_grid_wJ.argtypes = [C.c_void_p, _P]
+        L.cmref_grid_metric_identity.argtypes = [C.c_void_p, _P]
+        L.cmref_pvsat.argtypes = [C.c_double]
+        L.cmref_pvsat.restype = C.c_double
+        L.cmref_saturation_adjust.argtypes = [C.c_double, C.c_double, C.c_double,
+                                              C.POINTER(C.c_double), C.POINTER(C.c_double)]
+        L.cmref_thermo_nodes.argtypes = [C.c_int, C.c_long, _P, _P, C.c_double, _P, _P, _P, _P]
+        L.cmref_rusanov_point.argtypes = [C.c_int, _P, _P, C.c_double, C.c_double, C.c_double,
+                                          C.c_double, C.c_double, _P, _P]
+        L.cmref_smagorinsky_point.argtypes = [_P, C.c_double, C.c_double, C.c_double, C.c_double,
+                                              C.c_int, C.POINTER(C.c_double)]
+        L.cmref_model_create.argtypes = [C.c_void_p, C.POINTER(ModelDesc), C.c_void_p]
+        L.cmref_model_create.restype = C.c_void_p
+        L.cmref_model_destroy.argtypes = [C.c_void_p]
+        L.cmref_model_reference.argtypes = [C.c_void_p, _P, _P]
+        L.cmref_model_set_mlp.argtypes = [C.c_void_p, _P, C.c_int, _P, _P, C.c_int]
+        L.cmref_model_mlp_fallbacks.argtypes = [C.c_void_p]
+        L.cmref_model_mlp_fallbacks.restype = C.c_long
+        L.cmref_rhs.argtypes = [C.c_void_p, _P, _P, C.c_double]
+        L.cmref_gradients.argtypes = [C.c_void_p, _P, _P, _P]
+        L.cmref_gradients.restype = C.c_int
+        L.cmref_lsrk54_coeffs.argtypes = [_P, _P, _P]
+        L.cmref_lsrk_steps.argtypes = [C.c_void_p, _P, _P, C.c_double, C.c_double, C.c_int]
+        L.cmref_integrals.argtypes = [C.c_void_p, _P, _P]
+        L.cmref_num_threads.restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def gll(N: int):
+    """GLL nodes, weights and differentiation matrix D[i, j] = l_j'(x_i)."""
+    Q = N + 1
+    xi = np.zeros(Q)
+    w = np.zeros(Q)
+    D = np.zeros(Q * Q)
+    if lib().cmref_gll(N, xi, w, D):
+        raise ValueError("unsupported N")
+    return xi, w, D.reshape(Q, Q)
+
+
+def _grid_desc(g: dict) -> GridDesc:
+    d = GridDesc()
+    d.N = int(g.get("N", 4))
+    for a in range(3):
+        d.ne[a] = int(g["ne"][a])
+        d.lo[a] = float(g["lo"][a])
+        d.hi[a] = float(g["hi"][a])
+        d.periodic[a] = int(bool(g["periodic"][a]))
+    d.topo = int(g.get("topo", 0))
+    d.topo_h = float(g.get("topo_h", 0.0))
+    d.topo_a = float(g.get("topo_a", 1.0))
+    d.topo_xc = float(g.get("topo_xc", 0.0))
+    return d
+
+
+def _model_desc(m: dict) -> ModelDesc:
+    d = ModelDesc()
+    d.nvar = int(m.get("nvar", 5))
+    d.closure = {"none": 0, "const": 1, "smag": 2, "mlp": 3}[m.get("closure", "none")]
+    d.nu = float(m.get("nu", 0.0))
+    d.Cs = float(m.get("Cs", 0.21))
+    d.Prt = float(m.get("Prt", 1.0 / 3.0))
+    d.richardson = int(bool(m.get("richardson", False)))
+    d.g = float(m.get("g", 9.81))
+    d.f_cor = float(m.get("f_cor", 0.0))
+    d.u_g = float(m.get("u_g", 0.0))
+    d.v_g = float(m.get("v_g", 0.0))
+    sp = m.get("sponge")
+    if sp:
+        d.sponge = 1
+        d.sp_zs, d.sp_ztop = float(sp["z_s"]), float(sp["z_top"])
+        d.sp_alpha, d.sp_gamma = float(sp["alpha"]), float(sp["gamma"])
+        for c in range(3):
+            d.sp_u[c] = float(sp["u_relax"][c])
+    sf = m.get("sfc_flux")
+    if sf:
+        d.sfc_flux = 1
+        d.theta_flux = float(sf["theta_flux"])
+        d.qt_flux = float(sf["qt_flux"])
+    sb = m.get("subsidence")
+    if sb:
+        d.subsidence = 1
+        d.sub_w0 = float(sb["w0"])
+        d.sub_ztop = float(sb["z_top"])
+    return d
+
+
+class Grid:
+    def __init__(self, desc: dict, dense: bool = False):
+        self._d = _grid_desc(desc)
+        self.h = lib().cmref_grid_create(C.byref(self._d), int(dense))
+        if not self.h:
+            raise RuntimeError("oracle grid creation failed")
+        self.nnodes = lib().cmref_grid_nnodes(self.h)
+
+    def __del__(self):
+        if getattr(self, "h", None):
+            lib().cmref_grid_destroy(self.h)
+            self.h = None
+
+    def coords(self):
+        out = np.zeros(3 * self.nnodes)
+        lib().cmref_grid_coords(self.h, out)
+        return out.reshape(3, self.nnodes)
+
+    def metrics(self):
+        Ja = np.zeros(9 * self.nnodes)
+        J = np.zeros(self.nnodes)
+        lib().cmref_grid_metrics(self.h, Ja, J)
+        return Ja.reshape(3, 3, self.nnodes), J
+
+    def wJ(self):
+        out = np.zeros(self.nnodes)
+        lib().cmref_grid_wJ(self.h, out)
+        return out
+
+    def metric_identity(self):
+        out = np.zeros(3 * self.nnodes)
+        lib().cmref_grid_metric_identity(self.h, out)
+        return out.reshape(3, self.nnodes)
+
+
+class Model:
+    def __init__(self, grid: Grid, desc: dict, Yref: np.ndarray | None = None):
+        self.grid = grid
+        self._d = _model_desc(desc)
+        self.nvar = self._d.nvar
+        yref = None
+        if Yref is not None:
+            yref = np.ascontiguousarray(Yref, dtype=np.float64)
+            assert yref.shape == (self.nvar, grid.nnodes)
+        self._yref = yref
+        ptr = yref.ctypes.data_as(C.c_void_p) if yref is not None else None
+        self.h = lib().cmref_model_create(grid.h, C.byref(self._d), ptr)
+
+    def __del__(self):
+        if getattr(self, "h", None):
+            lib().cmref_model_destroy(self.h)
+            self.h = None
+
+    def _chk(self, Y):
+        Y = np.ascontiguousarray(Y, dtype=np.float64)
+        assert Y.shape == (self.nvar, self.grid.nnodes)
+        return Y
+
+    def rhs(self, Y, t: float = 0.0):
+        Y = self._chk(Y)
+        R = np.zeros_like(Y)
+        lib().cmref_rhs(self.h, Y, R, float(t))
+        return R
+
+    def gradients(self, Y):
+        Y = self._chk(Y)
+        nn = self.grid.nnodes
+        grad = np.zeros(8 * 3 * nn)
+        F2 = np.zeros(self.nvar * 3 * nn)
+        nG = lib().cmref_gradients(self.h, Y, grad, F2)
+        return grad[: nG * 3 * nn].reshape(nG, 3, nn), F2.reshape(self.nvar, 3, nn)
+
+    def reference(self):
+        nn = self.grid.nnodes
+        pr = np.zeros(nn)
+        rr = np.zeros(nn)
+        lib().cmref_model_reference(self.h, pr, rr)
+        return pr, rr
+
+    def steps(self, Y, dt: float, nsteps: int, t: float = 0.0, dQ=None):
+        """Advance a copy of Y by nsteps LSRK54 steps; returns (Y, dQ)."""
+        Y = self._chk(Y).copy()
+        dQ = np.zeros_like(Y) if dQ is None else np.ascontiguousarray(dQ, dtype=np.float64).copy()
+        lib().cmref_lsrk_steps(self.h, Y, dQ, float(t), float(dt), int(nsteps))
+        return Y, dQ
+
+    def integrals(self, Y):
+        """Domain integrals of each variable (w J weighted) and kinetic energy."""
+        Y = self._chk(Y)
+        out = np.zeros(self.nvar + 1)
+        lib().cmref_integrals(self.h, Y, out)
+        return out
+
+    def set_mlp(self, params: np.ndarray, lo: np.ndarray, hi: np.ndarray, use_fallback=True):
+        p = np.ascontiguousarray(params, dtype=np.float64)
+        lib().cmref_model_set_mlp(self.h, p, p.size, np.ascontiguousarray(lo, dtype=np.float64),
+                                  np.ascontiguousarray(hi, dtype=np.float64), int(use_fallback))
+        self._mlp = p
+
+    def mlp_fallbacks(self) -> int:
+        return lib().cmref_model_mlp_fallbacks(self.h)
+
+
+def pvsat(T: float) -> float:
+    return lib().cmref_pvsat(float(T))
+
+
+def saturation_adjust(rho: float, qt: float, I: float):
+    T = C.c_double()
+    ql = C.c_double()
+    lib().cmref_saturation_adjust(float(rho), float(qt), float(I), C.byref(T), C.byref(ql))
+    return T.value, ql.value
+
+
+def thermo_nodes(Y: np.ndarray, z: np.ndarray, g: float):
+    """T, p, q_l, theta_v at every node of a state [nvar, n]."""
+    Y = np.ascontiguousarray(Y, dtype=np.float64)
+    nvar, n = Y.shape
+    z = np.ascontiguousarray(z, dtype=np.float64)
+    T, p, ql, thv = (np.zeros(n) for _ in range(4))
+    lib().cmref_thermo_nodes(nvar, n, Y, z, float(g), T, p, ql, thv)
+    return T, p, ql, thv
+
+
+def rusanov(Ym, Yp, n, zm=0.0, zp=0.0, g=0.0, prm=0.0, prp=0.0):
+    Ym = np.ascontiguousarray(Ym, dtype=np.float64)
+    Yp = np.ascontiguousarray(Yp, dtype=np.float64)
+    out = np.zeros(Ym.size)
+    lib().cmref_rusanov_point(Ym.size, Ym, Yp, zm, zp, g, prm, prp,
+                              np.ascontiguousarray(n, dtype=np.float64), out)
+    return out
+
+
+def smagorinsky(gu: np.ndarray, N2: float, Cs: float, Delta: float, Prt: float, richardson: bool):
+    nu = C.c_double()
+    lib().cmref_smagorinsky_point(np.ascontiguousarray(gu, dtype=np.float64).ravel(), N2, Cs,
+                                  Delta, Prt, int(richardson), C.byref(nu))
+    return nu.value
+
+
+def lsrk54_coeffs():
+    A, B, Cc = np.zeros(5), np.zeros(5), np.zeros(5)
+    lib().cmref_lsrk54_coeffs(A, B, Cc)
+    return A, B, Cc
+
+
+def num_threads() -> int:
+    return lib().cmref_num_threads()

@@ -1,0 +1,914 @@
+/*
+ * FP64 CPU oracle for the nodal DG right-hand side, the LSRK54 step and the
+ * conservation integrals.
+ *
+ * TEST INFRASTRUCTURE ONLY (see cmref.h).  Written as plain loops in the
+ * order the paper states the method; correctness over speed.  Parity is
+ * pinned by the CPU tests (closed forms, invariants, brute-force dense
+ * operators), not by the GPU code.
+ *
+ * Sections of the paper followed:
+ *   Sect. 2 (governing equations, Table 1 constants, EOS, saturation adj.)
+ *   Sect. 3.1 (nodal GLL expansion, tensor-product derivatives, mapping,
+ *              weak/strong DG form, Rusanov flux, BR1 auxiliary gradient,
+ *              semi-discrete matrix problem)
+ *   Sect. 3.2 (low-storage explicit Runge-Kutta, Carpenter-Kennedy family)
+ *   Sect. 4   (SGS stress, diffusivity, Smagorinsky-Lilly, Richardson corr.)
+ *   Sect. 6   (normalised mass / energy integrals)
+ *   App. A    (wall ghost states, prescribed wall fluxes, Rayleigh sponge)
+ */
+#include "cmref.h"
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+#include <stdio.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+/* ---- constants: Table 1, plus the readings for the values the paper omits
+ *      (g, p0, c_pd = c_vd + R_d, triple-point pressure) ------------------- */
+static const double RD = 287.0, RV = 462.0;
+static const double CVD = 717.5, CVV = 1397.5, CVL = 4181.0;
+static const double TREF0 = 273.16;          /* T_0 */
+static const double LV0 = 2.5008e6;
+static const double P00 = 1.0e5;
+static const double PTRIPLE = 611.657;
+#define CPD (CVD + RD)
+#define CPV (CVV + RV)
+#define CPL (CVL)
+#define IV0 (LV0 - RV * TREF0)               /* I_{v,0} = L_{v,0} - R_v T_0 */
+
+/* ======================================================================== */
+/* GLL nodes, weights and differentiation matrix (Sect. 3.1)                */
+/* ======================================================================== */
+
+/* Legendre P_N(x) and its derivative by the three-term recurrence. */
+static void legendre(int N, double x, double* P, double* dP)
+{
+    double p0 = 1.0, p1 = x, d0 = 0.0, d1 = 1.0;
+    if (N == 0) { *P = 1.0; *dP = 0.0; return; }
+    for (int n = 1; n < N; ++n) {
+        double p2 = ((2.0 * n + 1.0) * x * p1 - n * p0) / (n + 1.0);
+        double d2 = d0 + (2.0 * n + 1.0) * p1;
+        p0 = p1; p1 = p2; d0 = d1; d1 = d2;
+    }
+    *P = p1; *dP = d1;
+}
+
+/* Nodes: +-1 and the roots of P_N' (Newton on P_N' using P_N'' from the
+ * Legendre ODE).  Weights 2/(N(N+1) P_N(x)^2).  D_ij = l_j'(x_i) from the
+ * classical Legendre closed form P_N(x_i)/(P_N(x_j)(x_i-x_j)), i != j, with
+ * the diagonal set to minus the off-diagonal row sum. */
+int cmref_gll(int N, double* xi, double* w, double* D)
+{
+    if (N < 1 || N + 1 > CMREF_MAXQ) return 1;
+    int Q = N + 1;
+    xi[0] = -1.0; xi[N] = 1.0;
+    for (int i = 1; i < N; ++i) {
+        double x = -cos(M_PI * i / N);
+        for (int it = 0; it < 100; ++it) {
+            double P, dP; legendre(N, x, &P, &dP);
+            double d2P = (2.0 * x * dP - N * (N + 1.0) * P) / (1.0 - x * x);
+            double dx = dP / d2P;
+            x -= dx;
+            if (fabs(dx) < 1e-16) break;
+        }
+        xi[i] = x;
+    }
+    if (N % 2 == 0) xi[N / 2] = 0.0;
+    double PN[CMREF_MAXQ];
+    for (int i = 0; i < Q; ++i) {
+        double P, dP; legendre(N, xi[i], &P, &dP);
+        PN[i] = P;
+        w[i] = 2.0 / (N * (N + 1.0) * P * P);
+    }
+    for (int i = 0; i < Q; ++i) {
+        double s = 0.0;
+        for (int j = 0; j < Q; ++j) {
+            if (j == i) continue;
+            D[i * Q + j] = PN[i] / (PN[j] * (xi[i] - xi[j]));
+            s += D[i * Q + j];
+        }
+        D[i * Q + i] = -s;
+    }
+    return 0;
+}
+
+/* ======================================================================== */
+/* Grid: brick of hexahedra, optional terrain-following warp (Sect. 4.3/4.4) */
+/* ======================================================================== */
+typedef struct {
+    int N, Q, Np;
+    int ne[3];
+    long nelem, nnodes;
+    double lo[3], hi[3], h[3];
+    int periodic[3];
+    double xi[CMREF_MAXQ], w[CMREF_MAXQ], D[CMREF_MAXQ * CMREF_MAXQ];
+    double* xyz;    /* [3][nnodes] */
+    double* Ja;     /* [9][nnodes], entry 3*d + c = c-component of J a^d */
+    double* J;      /* [nnodes] */
+    int dense;      /* apply explicit Kronecker operators for derivatives */
+    double* K[3];   /* dense operators Np x Np, built when dense */
+} grid_t;
+
+static double agnesi(const cmref_grid_desc* d, double x)
+{
+    double r = x - d->topo_xc;
+    return d->topo_h * d->topo_a * d->topo_a / (r * r + d->topo_a * d->topo_a);
+}
+
+/* Reference derivative along direction dir of the nodal field f (element
+ * base pointer fe, stride 1 within the element) at local node (i,j,k). */
+static double dref(const grid_t* G, const double* fe, int dir, int i, int j, int k)
+{
+    int Q = G->Q;
+    double s = 0.0;
+    if (G->dense) {
+        int a = i + Q * (j + Q * k);
+        const double* row = G->K[dir] + (long)a * G->Np;
+        for (int b = 0; b < G->Np; ++b) s += row[b] * fe[b];
+        return s;
+    }
+    if (dir == 0) for (int l = 0; l < Q; ++l) s += G->D[i * Q + l] * fe[l + Q * (j + Q * k)];
+    if (dir == 1) for (int l = 0; l < Q; ++l) s += G->D[j * Q + l] * fe[i + Q * (l + Q * k)];
+    if (dir == 2) for (int l = 0; l < Q; ++l) s += G->D[k * Q + l] * fe[i + Q * (j + Q * l)];
+    return s;
+}
+
+void* cmref_grid_create(const cmref_grid_desc* d, int dense)
+{
+    grid_t* G = (grid_t*)calloc(1, sizeof(grid_t));
+    if (!G) return NULL;
+    G->N = d->N; G->Q = d->N + 1; G->Np = G->Q * G->Q * G->Q;
+    if (cmref_gll(d->N, G->xi, G->w, G->D)) { free(G); return NULL; }
+    for (int a = 0; a < 3; ++a) {
+        G->ne[a] = d->ne[a]; G->lo[a] = d->lo[a]; G->hi[a] = d->hi[a];
+        G->h[a] = (d->hi[a] - d->lo[a]) / d->ne[a]; G->periodic[a] = d->periodic[a];
+    }
+    G->nelem = (long)d->ne[0] * d->ne[1] * d->ne[2];
+    G->nnodes = G->nelem * G->Np;
+    long nn = G->nnodes;
+    int Q = G->Q, Np = G->Np;
+    G->xyz = (double*)malloc(sizeof(double) * 3 * nn);
+    G->Ja = (double*)malloc(sizeof(double) * 9 * nn);
+    G->J = (double*)malloc(sizeof(double) * nn);
+    G->dense = dense;
+    if (dense) {
+        for (int dir = 0; dir < 3; ++dir) {
+            G->K[dir] = (double*)calloc((size_t)Np * Np, sizeof(double));
+            for (int k = 0; k < Q; ++k) for (int j = 0; j < Q; ++j) for (int i = 0; i < Q; ++i) {
+                int a = i + Q * (j + Q * k);
+                for (int l = 0; l < Q; ++l) {
+                    int b;
+                    if (dir == 0) b = l + Q * (j + Q * k);
+                    else if (dir == 1) b = i + Q * (l + Q * k);
+                    else b = i + Q * (j + Q * l);
+                    G->K[dir][(long)a * Np + b] = G->D[(dir == 0 ? i : dir == 1 ? j : k) * Q + l];
+                }
+            }
+        }
+    }
+    double ztop = d->hi[2], zlo = d->lo[2];
+    /* node coordinates */
+    #pragma omp parallel for schedule(static)
+    for (long e = 0; e < G->nelem; ++e) {
+        int ex = (int)(e % d->ne[0]);
+        int ey = (int)((e / d->ne[0]) % d->ne[1]);
+        int ez = (int)(e / ((long)d->ne[0] * d->ne[1]));
+        for (int k = 0; k < Q; ++k) for (int j = 0; j < Q; ++j) for (int i = 0; i < Q; ++i) {
+            long n = e * Np + i + Q * (j + Q * k);
+            double x = d->lo[0] + (ex + (1.0 + G->xi[i]) / 2.0) * G->h[0];
+            double y = d->lo[1] + (ey + (1.0 + G->xi[j]) / 2.0) * G->h[1];
+            double zh = d->lo[2] + (ez + (1.0 + G->xi[k]) / 2.0) * G->h[2];
+            double z = zh;
+            if (d->topo == 1) z = zh + agnesi(d, x) * (ztop - zh) / (ztop - zlo);
+            G->xyz[n] = x; G->xyz[nn + n] = y; G->xyz[2 * nn + n] = z;
+        }
+    }
+    /* metric terms: x_{,xi^d} by D along d; J a^1 = x_eta x x_zeta, ... */
+    #pragma omp parallel for schedule(static)
+    for (long e = 0; e < G->nelem; ++e) {
+        for (int k = 0; k < Q; ++k) for (int j = 0; j < Q; ++j) for (int i = 0; i < Q; ++i) {
+            long n = e * Np + i + Q * (j + Q * k);
+            double dx[3][3]; /* dx[d][c] = d x_c / d xi^d */
+            for (int dir = 0; dir < 3; ++dir)
+                for (int c = 0; c < 3; ++c)
+                    dx[dir][c] = dref(G, G->xyz + c * nn + e * Np, dir, i, j, k);
+            double Ja[3][3];
+            for (int dir = 0; dir < 3; ++dir) {
+                const double* a = dx[(dir + 1) % 3];
+                const double* b = dx[(dir + 2) % 3];
+                Ja[dir][0] = a[1] * b[2] - a[2] * b[1];
+                Ja[dir][1] = a[2] * b[0] - a[0] * b[2];
+                Ja[dir][2] = a[0] * b[1] - a[1] * b[0];
+            }
+            double Jd = dx[0][0] * Ja[0][0] + dx[0][1] * Ja[0][1] + dx[0][2] * Ja[0][2];
+            for (int dir = 0; dir < 3; ++dir)
+                for (int c = 0; c < 3; ++c) G->Ja[(3 * dir + c) * nn + n] = Ja[dir][c];
+            G->J[n] = Jd;
+        }
+    }
+    return G;
+}
+
+void cmref_grid_destroy(void* h)
+{
+    grid_t* G = (grid_t*)h;
+    if (!G) return;
+    free(G->xyz); free(G->Ja); free(G->J);
+    for (int d = 0; d < 3; ++d) free(G->K[d]);
+    free(G);
+}
+
+long cmref_grid_nnodes(void* h) { return ((grid_t*)h)->nnodes; }
+
+void cmref_grid_coords(void* h, double* out)
+{
+    grid_t* G = (grid_t*)h;
+    memcpy(out, G->xyz, sizeof(double) * 3 * G->nnodes);
+}
+
+void cmref_grid_metrics(void* h, double* Ja, double* J)
+{
+    grid_t* G = (grid_t*)h;
+    memcpy(Ja, G->Ja, sizeof(double) * 9 * G->nnodes);
+    memcpy(J, G->J, sizeof(double) * G->nnodes);
+}
+
+/* w_i w_j w_k |J| at every node: the collocated (inexact) quadrature weight. */
+void cmref_grid_wJ(void* h, double* out)
+{
+    grid_t* G = (grid_t*)h;
+    int Q = G->Q, Np = G->Np;
+    for (long e = 0; e < G->nelem; ++e)
+        for (int k = 0; k < Q; ++k) for (int j = 0; j < Q; ++j) for (int i = 0; i < Q; ++i) {
+            long n = e * Np + i + Q * (j + Q * k);
+            out[n] = G->w[i] * G->w[j] * G->w[k] * G->J[n];
+        }
+}
+
+/* Divergence-of-metrics residual sum_d D_d (J a^d)_c, component c, per node. */
+void cmref_grid_metric_identity(void* h, double* out /* [3][nnodes] */)
+{
+    grid_t* G = (grid_t*)h;
+    int Q = G->Q, Np = G->Np; long nn = G->nnodes;
+    for (long e = 0; e < G->nelem; ++e)
+        for (int k = 0; k < Q; ++k) for (int j = 0; j < Q; ++j) for (int i = 0; i < Q; ++i) {
+            long n = e * Np + i + Q * (j + Q * k);
+            for (int c = 0; c < 3; ++c) {
+                double s = 0.0;
+                for (int dir = 0; dir < 3; ++dir)
+                    s += dref(G, G->Ja + (3 * dir + c) * nn + e * Np, dir, i, j, k);
+                out[c * nn + n] = s;
+            }
+        }
+}
+
+/* Neighbour of element (ex,ey,ez) across face (dir, side); -1 at a wall. */
+static long neighbour(const grid_t* G, int ex, int ey, int ez, int dir, int side)
+{
+    int c[3] = {ex, ey, ez};
+    c[dir] += side;
+    if (c[dir] < 0 || c[dir] >= G->ne[dir]) {
+        if (!G->periodic[dir]) return -1;
+        c[dir] = (c[dir] + G->ne[dir]) % G->ne[dir];
+    }
+    return c[0] + (long)G->ne[0] * (c[1] + (long)G->ne[1] * c[2]);
+}
+
+/* ======================================================================== */
+/* Thermodynamics (Sect. 2.5-2.7)                                            */
+/* ======================================================================== */
+
+/* Saturation vapour pressure over liquid: Clausius-Clapeyron integrated with
+ * constant heat capacities, L_v(T) = L_v0 + (c_pv - c_pl)(T - T_0). */
+double cmref_pvsat(double T)
+{
+    double dc = CPV - CPL;
+    return PTRIPLE * pow(T / TREF0, dc / RV) * exp((LV0 - dc * TREF0) / RV * (1.0 / TREF0 - 1.0 / T));
+}
+
+static double qvsat(double T, double rho) { return cmref_pvsat(T) / (rho * RV * T); }
+
+/* Equilibrium internal energy I*(T; rho, q_t), liquid-only apportioning. */
+static double Istar(double T, double rho, double qt)
+{
+    double qv = qvsat(T, rho);
+    if (qv > qt) qv = qt;
+    double ql = qt - qv;
+    return (1.0 - qt) * CVD * (T - TREF0) + qv * (CVV * (T - TREF0) + IV0) + ql * CVL * (T - TREF0);
+}
+
+/* Saturation adjustment: the root T of I*(T) - I = 0.  The oracle brackets
+ * it and bisects to adjacent doubles (a different algorithm from the GPU's
+ * Newton iteration, converging to the same root). */
+void cmref_saturation_adjust(double rho, double qt, double I, double* T_out, double* ql_out)
+{
+    double Tu = TREF0 + (I - qt * IV0) / ((1.0 - qt) * CVD + qt * CVV);
+    if (qt <= qvsat(Tu, rho)) { *T_out = Tu; *ql_out = 0.0; return; }
+    double lo = Tu, hi = Tu + LV0 * qt / CVD;
+    while (Istar(hi, rho, qt) - I < 0.0) hi += LV0 * qt / CVD;
+    for (int it = 0; it < 200; ++it) {
+        double mid = 0.5 * (lo + hi);
+        if (mid <= lo || mid >= hi) break;
+        if (Istar(mid, rho, qt) - I < 0.0) lo = mid; else hi = mid;
+    }
+    /* the two adjacent doubles bracket the root; take the one with the
+     * smaller residual */
+    double rl = fabs(Istar(lo, rho, qt) - I), rh = fabs(Istar(hi, rho, qt) - I);
+    double T = (rl <= rh) ? lo : hi;
+    double qv = qvsat(T, rho);
+    if (qv > qt) qv = qt;
+    *T_out = T; *ql_out = qt - qv;
+}
+
+typedef struct {
+    double rho, u[3], e, qt;
+    double T, p, c, h, thv, ql, qv, Rm;
+} prim_t;
+
+/* State -> primitive/thermodynamic quantities at one node (z = height). */
+static void thermo(const double* Yn, int nvar, double z, double g, prim_t* P)
+{
+    double rho = Yn[0];
+    P->rho = rho;
+    for (int c = 0; c < 3; ++c) P->u[c] = Yn[1 + c] / rho;
+    P->e = Yn[4] / rho;
+    P->qt = (nvar > 5) ? Yn[5] / rho : 0.0;
+    double ke = 0.5 * (P->u[0] * P->u[0] + P->u[1] * P->u[1] + P->u[2] * P->u[2]);
+    double I = P->e - ke - g * z;
+    double qt = P->qt, T, ql;
+    if (nvar > 5) cmref_saturation_adjust(rho, qt, I, &T, &ql);
+    else { T = TREF0 + I / CVD; ql = 0.0; }
+    double qv = qt - ql;
+    double Rm = RD * (1.0 - qt) + RV * qv;
+    double p = rho * Rm * T;
+    double cvm = (1.0 - qt) * CVD + qv * CVV + ql * CVL;
+    double gam = (cvm + Rm) / cvm;
+    P->T = T; P->ql = ql; P->qv = qv; P->Rm = Rm; P->p = p;
+    P->c = sqrt(gam * Rm * T);
+    P->h = P->e + p / rho;
+    P->thv = T * pow(P00 / p, RD / CPD) * Rm / RD;
+}
+
+/* Per-node thermodynamic diagnostics for tests: T, p, q_l, theta_v. */
+void cmref_thermo_nodes(int nvar, long n, const double* Y, const double* z, double g,
+                        double* T, double* p, double* ql, double* thv)
+{
+    #pragma omp parallel for schedule(static)
+    for (long i = 0; i < n; ++i) {
+        double Yn[6];
+        for (int v = 0; v < nvar; ++v) Yn[v] = Y[v * n + i];
+        prim_t P; thermo(Yn, nvar, z[i], g, &P);
+        T[i] = P.T; p[i] = P.p; ql[i] = P.ql; thv[i] = P.thv;
+    }
+}
+
+/* ======================================================================== */
+/* Fluxes                                                                   */
+/* ======================================================================== */
+
+/* Inviscid flux F1 (Sect. 3.1 compact form; momentum carries p - p_r). */
+static void flux1(const prim_t* P, int nvar, double pr, double F[][3])
+{
+    for (int d = 0; d < 3; ++d) {
+        double ud = P->u[d];
+        F[0][d] = P->rho * ud;
+        for (int c = 0; c < 3; ++c) F[1 + c][d] = P->rho * P->u[c] * ud + (c == d ? (P->p - pr) : 0.0);
+        F[4][d] = (P->rho * P->e + P->p) * ud;
+        if (nvar > 5) F[5][d] = P->rho * P->qt * ud;
+    }
+}
+
+/* Rusanov numerical flux n.F1*: centred average plus half the maximum wave
+ * speed times the jump (the factor 1/2 is the reading of the printed
+ * formula, see the design notes). */
+static void rusanov(const double* Ym, const prim_t* Pm, double prm,
+                    const double* Yp, const prim_t* Pp, double prp,
+                    const double n[3], int nvar, double* out)
+{
+    double Fm[6][3], Fp[6][3];
+    flux1(Pm, nvar, prm, Fm);
+    flux1(Pp, nvar, prp, Fp);
+    double unm = Pm->u[0] * n[0] + Pm->u[1] * n[1] + Pm->u[2] * n[2];
+    double unp = Pp->u[0] * n[0] + Pp->u[1] * n[1] + Pp->u[2] * n[2];
+    double lm = fabs(unm) + Pm->c, lp = fabs(unp) + Pp->c;
+    double lam = lm > lp ? lm : lp;
+    for (int v = 0; v < nvar; ++v) {
+        double fm = Fm[v][0] * n[0] + Fm[v][1] * n[1] + Fm[v][2] * n[2];
+        double fp = Fp[v][0] * n[0] + Fp[v][1] * n[1] + Fp[v][2] * n[2];
+        out[v] = 0.5 * (fm + fp) + 0.5 * lam * (Ym[v] - Yp[v]);
+    }
+}
+
+/* Point evaluation of the Rusanov flux for the identity tests. */
+void cmref_rusanov_point(int nvar, const double* Ym, const double* Yp, double zm, double zp,
+                         double g, double prm, double prp, const double* n, double* out)
+{
+    prim_t Pm, Pp;
+    thermo(Ym, nvar, zm, g, &Pm);
+    thermo(Yp, nvar, zp, g, &Pp);
+    rusanov(Ym, &Pm, prm, Yp, &Pp, prp, n, nvar, out);
+}
+
+/* ======================================================================== */
+/* Model                                                                    */
+/* ======================================================================== */
+typedef struct {
+    grid_t* G;
+    cmref_model_desc m;
+    double* pr;    /* reference pressure per node */
+    double* rhor;  /* reference density per node */
+    double Delta;  /* filter width (dx dy dz)^(1/3), dx = h/N */
+    /* learned closure parameters (FP64 copy), optional */
+    double* mlp;
+    int mlp_n;
+    double mlp_lo[12], mlp_hi[12];
+    int mlp_use_fallback;
+    long mlp_fallbacks;
+} model_t;
+
+void* cmref_model_create(void* grid, const cmref_model_desc* m, const double* Yref)
+{
+    model_t* M = (model_t*)calloc(1, sizeof(model_t));
+    M->G = (grid_t*)grid;
+    M->m = *m;
+    long nn = M->G->nnodes;
+    M->pr = (double*)calloc(nn, sizeof(double));
+    M->rhor = (double*)calloc(nn, sizeof(double));
+    if (Yref) {
+        /* reference state: the unperturbed background pushed through the
+         * same thermodynamic functions as the prognostic state */
+        const double* z = M->G->xyz + 2 * nn;
+        #pragma omp parallel for schedule(static)
+        for (long i = 0; i < nn; ++i) {
+            double Yn[6];
+            for (int v = 0; v < m->nvar; ++v) Yn[v] = Yref[v * nn + i];
+            prim_t P; thermo(Yn, m->nvar, z[i], m->g, &P);
+            M->pr[i] = P.p; M->rhor[i] = P.rho;
+        }
+    }
+    grid_t* G = M->G;
+    M->Delta = cbrt((G->h[0] / G->N) * (G->h[1] / G->N) * (G->h[2] / G->N));
+    return M;
+}
+
+void cmref_model_destroy(void* h)
+{
+    model_t* M = (model_t*)h;
+    if (!M) return;
+    free(M->pr); free(M->rhor); free(M->mlp);
+    free(M);
+}
+
+void cmref_model_reference(void* h, double* pr, double* rhor)
+{
+    model_t* M = (model_t*)h;
+    memcpy(pr, M->pr, sizeof(double) * M->G->nnodes);
+    memcpy(rhor, M->rhor, sizeof(double) * M->G->nnodes);
+}
+
+/* learned closure hook, implemented in cmref_mlp.c */
+int cmref_mlp_closure(const double* params, const double* lo, const double* hi, int use_fallback,
+                      const double gu[3][3], double N2, double Delta, double nu_sl,
+                      double* nu, double* Prt);
+
+void cmref_model_set_mlp(void* h, const double* params, int nparams,
+                         const double* lo, const double* hi, int use_fallback)
+{
+    model_t* M = (model_t*)h;
+    free(M->mlp);
+    M->mlp = (double*)malloc(sizeof(double) * nparams);
+    memcpy(M->mlp, params, sizeof(double) * nparams);
+    M->mlp_n = nparams;
+    memcpy(M->mlp_lo, lo, sizeof(double) * 12);
+    memcpy(M->mlp_hi, hi, sizeof(double) * 12);
+    M->mlp_use_fallback = use_fallback;
+}
+
+long cmref_model_mlp_fallbacks(void* h) { return ((model_t*)h)->mlp_fallbacks; }
+
+/* Smagorinsky-Lilly eddy viscosity with the Richardson stability factor
+ * (eq. smago and eq. richardson).  |S|^2 = 2 S_ij S_ij in both places. */
+double cmref_smagorinsky(const double gu[3][3], double N2, double Cs, double Delta,
+                         double Prt, int richardson)
+{
+    double SS = 0.0;
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+            double Sij = 0.5 * (gu[i][j] + gu[j][i]);
+            SS += 2.0 * Sij * Sij;
+        }
+    if (SS <= 0.0) return 0.0;
+    double fb = 1.0;
+    if (richardson) {
+        double Ri = N2 / SS;
+        if (Ri > 0.0) {
+            double a = 1.0 - Ri / Prt;
+            fb = pow(a > 0.0 ? a : 0.0, 0.25);
+        }
+    }
+    return (Cs * Delta) * (Cs * Delta) * sqrt(SS) * fb;
+}
+
+void cmref_smagorinsky_point(const double* gu9, double N2, double Cs, double Delta, double Prt,
+                             int richardson, double* nu)
+{
+    double gu[3][3];
+    for (int i = 0; i < 3; ++i) for (int j = 0; j < 3; ++j) gu[i][j] = gu9[3 * i + j];
+    *nu = cmref_smagorinsky(gu, N2, Cs, Delta, Prt, richardson);
+}
+
+/* gradient-variable slots */
+enum { GU = 0, GV = 1, GW = 2, GH = 3 };
+
+typedef struct {
+    int nG;        /* number of gradient variables */
+    int iq, ith;   /* slots of q_t and theta_v (-1 if absent) */
+} gslots_t;
+
+static gslots_t slots(const cmref_model_desc* m)
+{
+    gslots_t s; s.nG = 4; s.iq = -1; s.ith = -1;
+    if (m->nvar > 5) s.iq = s.nG++;
+    if ((m->closure == 2 && m->richardson) || m->closure == 3) s.ith = s.nG++;
+    return s;
+}
+
+/* workspace for one RHS evaluation */
+typedef struct {
+    prim_t* P;      /* per node */
+    double* gvar;   /* [nG][nnodes] */
+    double* grad;   /* [nG][3][nnodes] */
+    double* F2;     /* [nvar][3][nnodes] */
+} work_t;
+
+/* BR1 auxiliary gradient of every gradient variable: chain-rule volume
+ * derivative plus the lift of (g* - g^-) n with the centred g*; walls use
+ * the interior value (g* = g^-). */
+static void br1_gradients(const model_t* M, work_t* W, gslots_t s)
+{
+    const grid_t* G = M->G;
+    int Q = G->Q, Np = G->Np, N = G->N; long nn = G->nnodes;
+    #pragma omp parallel for schedule(static)
+    for (long e = 0; e < G->nelem; ++e) {
+        int ex = (int)(e % G->ne[0]);
+        int ey = (int)((e / G->ne[0]) % G->ne[1]);
+        int ez = (int)(e / ((long)G->ne[0] * G->ne[1]));
+        for (int k = 0; k < Q; ++k) for (int j = 0; j < Q; ++j) for (int i = 0; i < Q; ++i) {
+            int loc = i + Q * (j + Q * k);
+            long n = e * Np + loc;
+            double J = G->J[n];
+            for (int q = 0; q < s.nG; ++q) {
+                const double* ge = W->gvar + q * nn + e * Np;
+                double gr[3] = {0, 0, 0};
+                for (int dir = 0; dir < 3; ++dir) {
+                    double dg = dref(G, ge, dir, i, j, k);
+                    for (int c = 0; c < 3; ++c) gr[c] += G->Ja[(3 * dir + c) * nn + n] / J * dg;
+                }
+                /* face lifts */
+                int idx[3] = {i, j, k};
+                for (int dir = 0; dir < 3; ++dir) {
+                    for (int side = -1; side <= 1; side += 2) {
+                        if ((side < 0 && idx[dir] != 0) || (side > 0 && idx[dir] != N)) continue;
+                        long en = neighbour(G, ex, ey, ez, dir, side);
+                        if (en < 0) continue; /* wall: g* = g^- */
+                        int m3[3] = {i, j, k};
+                        m3[dir] = (side < 0) ? N : 0;
+                        long np = en * Np + m3[0] + Q * (m3[1] + Q * m3[2]);
+                        double gm = W->gvar[q * nn + n], gp = W->gvar[q * nn + np];
+                        double Ja0 = G->Ja[(3 * dir + 0) * nn + n];
+                        double Ja1 = G->Ja[(3 * dir + 1) * nn + n];
+                        double Ja2 = G->Ja[(3 * dir + 2) * nn + n];
+                        double Js = sqrt(Ja0 * Ja0 + Ja1 * Ja1 + Ja2 * Ja2);
+                        double nv[3] = {side * Ja0 / Js, side * Ja1 / Js, side * Ja2 / Js};
+                        double lift = Js / (J * G->w[N]);
+                        double gstar = 0.5 * (gm + gp);
+                        for (int c = 0; c < 3; ++c) gr[c] += lift * (gstar - gm) * nv[c];
+                    }
+                }
+                for (int c = 0; c < 3; ++c) W->grad[(q * 3 + c) * nn + n] = gr[c];
+            }
+        }
+    }
+}
+
+/* Diffusive flux F2 from the closure (Sect. 4): rho tau = -2 rho nu_t S,
+ * rho d_qt = -rho D_t grad q_t, energy u.(rho tau) - rho D_t grad h_tot,
+ * momentum also carries d_qt (x) rho u. */
+static void diffusive_flux(model_t* M, work_t* W, gslots_t s)
+{
+    const grid_t* G = M->G; long nn = G->nnodes;
+    const cmref_model_desc* m = &M->m;
+    long fallbacks = 0;
+    #pragma omp parallel for schedule(static) reduction(+:fallbacks)
+    for (long n = 0; n < nn; ++n) {
+        const prim_t* P = &W->P[n];
+        double gu[3][3];
+        for (int i = 0; i < 3; ++i) for (int j = 0; j < 3; ++j) gu[i][j] = W->grad[(i * 3 + j) * nn + n];
+        double N2 = 0.0;
+        if (s.ith >= 0) N2 = m->g / P->thv * W->grad[(s.ith * 3 + 2) * nn + n];
+        double nu = 0.0, Prt = m->Prt;
+        if (m->closure == 1) nu = m->nu;
+        else if (m->closure == 2) nu = cmref_smagorinsky(gu, N2, m->Cs, M->Delta, m->Prt, m->richardson);
+        else if (m->closure == 3) {
+            double nu_sl = cmref_smagorinsky(gu, N2, m->Cs, M->Delta, m->Prt, m->richardson);
+            if (M->mlp) {
+                double nn_, pp_;
+                int fb = cmref_mlp_closure(M->mlp, M->mlp_lo, M->mlp_hi, M->mlp_use_fallback,
+                                           (const double (*)[3])gu, N2, M->Delta, nu_sl, &nn_, &pp_);
+                if (fb) { nu = nu_sl; Prt = m->Prt; fallbacks++; }
+                else { nu = nn_; Prt = pp_; }
+            } else nu = nu_sl;
+        }
+        double Dt = nu / Prt;
+        double S[3][3], rt[3][3];
+        for (int i = 0; i < 3; ++i) for (int j = 0; j < 3; ++j) S[i][j] = 0.5 * (gu[i][j] + gu[j][i]);
+        for (int i = 0; i < 3; ++i) for (int j = 0; j < 3; ++j) rt[i][j] = -2.0 * P->rho * nu * S[i][j];
+        double rd[3] = {0, 0, 0};
+        if (m->nvar > 5)
+            for (int j = 0; j < 3; ++j) rd[j] = -P->rho * Dt * W->grad[(s.iq * 3 + j) * nn + n];
+        for (int j = 0; j < 3; ++j) {
+            W->F2[(0 * 3 + j) * nn + n] = (m->nvar > 5) ? rd[j] : 0.0;
+            for (int i = 0; i < 3; ++i)
+                W->F2[((1 + i) * 3 + j) * nn + n] = rt[i][j] + ((m->nvar > 5) ? rd[j] * P->u[i] : 0.0);
+            double ue = P->u[0] * rt[0][j] + P->u[1] * rt[1][j] + P->u[2] * rt[2][j];
+            W->F2[(4 * 3 + j) * nn + n] = ue - P->rho * Dt * W->grad[(GH * 3 + j) * nn + n];
+            if (m->nvar > 5) W->F2[(5 * 3 + j) * nn + n] = rd[j];
+        }
+    }
+    M->mlp_fallbacks = fallbacks;
+}
+
+static void work_alloc(const model_t* M, work_t* W, gslots_t s)
+{
+    long nn = M->G->nnodes;
+    W->P = (prim_t*)malloc(sizeof(prim_t) * nn);
+    W->gvar = (double*)malloc(sizeof(double) * s.nG * nn);
+    W->grad = (double*)calloc((size_t)s.nG * 3 * nn, sizeof(double));
+    W->F2 = (double*)calloc((size_t)M->m.nvar * 3 * nn, sizeof(double));
+}
+
+static void work_free(work_t* W) { free(W->P); free(W->gvar); free(W->grad); free(W->F2); }
+
+/* primitives and gradient variables at every node */
+static void prepare(const model_t* M, const double* Y, work_t* W, gslots_t s)
+{
+    const grid_t* G = M->G; long nn = G->nnodes; int nvar = M->m.nvar;
+    const double* z = G->xyz + 2 * nn;
+    #pragma omp parallel for schedule(static)
+    for (long n = 0; n < nn; ++n) {
+        double Yn[6];
+        for (int v = 0; v < nvar; ++v) Yn[v] = Y[v * nn + n];
+        thermo(Yn, nvar, z[n], M->m.g, &W->P[n]);
+        const prim_t* P = &W->P[n];
+        W->gvar[GU * nn + n] = P->u[0];
+        W->gvar[GV * nn + n] = P->u[1];
+        W->gvar[GW * nn + n] = P->u[2];
+        W->gvar[GH * nn + n] = P->h;
+        if (s.iq >= 0) W->gvar[s.iq * nn + n] = P->qt;
+        if (s.ith >= 0) W->gvar[s.ith * nn + n] = P->thv;
+    }
+}
+
+/* The semi-discrete DG operator (eq. matrixProblem, strong form):
+ *   dY/dt = -(1/J) sum_d D_d (J a^d . F) + S
+ *           + sum_faces J^s/(J w_N) (n.F^- - n.F^*)
+ * with F = F1 + F2, F1* Rusanov, F2* centred; walls use the reflecting ghost
+ * state for F1* and a prescribed n.F2*. */
+static void rhs_eval(model_t* M, const double* Y, double* R, work_t* W)
+{
+    const grid_t* G = M->G;
+    const cmref_model_desc* m = &M->m;
+    int Q = G->Q, Np = G->Np, N = G->N, nvar = m->nvar; long nn = G->nnodes;
+    gslots_t s = slots(m);
+    prepare(M, Y, W, s);
+    if (m->closure != 0) {
+        br1_gradients(M, W, s);
+        diffusive_flux(M, W, s);
+    }
+    const double* z = G->xyz + 2 * nn;
+    /* total flux contracted with the metric: G_v^d = J a^d . F_v, per node */
+    double* Gf = (double*)malloc(sizeof(double) * nvar * 3 * nn);
+    #pragma omp parallel for schedule(static)
+    for (long n = 0; n < nn; ++n) {
+        double F[6][3];
+        flux1(&W->P[n], nvar, M->pr[n], F);
+        for (int v = 0; v < nvar; ++v) for (int d = 0; d < 3; ++d) F[v][d] += W->F2[(v * 3 + d) * nn + n];
+        for (int v = 0; v < nvar; ++v)
+            for (int dir = 0; dir < 3; ++dir) {
+                double sum = 0.0;
+                for (int c = 0; c < 3; ++c) sum += G->Ja[(3 * dir + c) * nn + n] * F[v][c];
+                Gf[(v * 3 + dir) * nn + n] = sum;
+            }
+    }
+    #pragma omp parallel for schedule(static)
+    for (long e = 0; e < G->nelem; ++e) {
+        int ex = (int)(e % G->ne[0]);
+        int ey = (int)((e / G->ne[0]) % G->ne[1]);
+        int ez = (int)(e / ((long)G->ne[0] * G->ne[1]));
+        for (int k = 0; k < Q; ++k) for (int j = 0; j < Q; ++j) for (int i = 0; i < Q; ++i) {
+            int loc = i + Q * (j + Q * k);
+            long n = e * Np + loc;
+            double J = G->J[n];
+            const prim_t* Pm = &W->P[n];
+            double Rn[6];
+            /* volume: conservative strong-form divergence */
+            for (int v = 0; v < nvar; ++v) {
+                double div = 0.0;
+                for (int dir = 0; dir < 3; ++dir)
+                    div += dref(G, Gf + (v * 3 + dir) * nn + e * Np, dir, i, j, k);
+                Rn[v] = -div / J;
+            }
+            /* own total flux */
+            double Fm[6][3];
+            flux1(Pm, nvar, M->pr[n], Fm);
+            for (int v = 0; v < nvar; ++v) for (int d = 0; d < 3; ++d) Fm[v][d] += W->F2[(v * 3 + d) * nn + n];
+            double Ym[6];
+            for (int v = 0; v < nvar; ++v) Ym[v] = Y[v * nn + n];
+            /* faces this node lies on */
+            int idx[3] = {i, j, k};
+            for (int dir = 0; dir < 3; ++dir) {
+                for (int side = -1; side <= 1; side += 2) {
+                    if ((side < 0 && idx[dir] != 0) || (side > 0 && idx[dir] != N)) continue;
+                    double Ja0 = G->Ja[(3 * dir + 0) * nn + n];
+                    double Ja1 = G->Ja[(3 * dir + 1) * nn + n];
+                    double Ja2 = G->Ja[(3 * dir + 2) * nn + n];
+                    double Js = sqrt(Ja0 * Ja0 + Ja1 * Ja1 + Ja2 * Ja2);
+                    double nv[3] = {side * Ja0 / Js, side * Ja1 / Js, side * Ja2 / Js};
+                    double lift = Js / (J * G->w[N]);
+                    double fstar[6], f2star[6];
+                    long en = neighbour(G, ex, ey, ez, dir, side);
+                    if (en >= 0) {
+                        int m3[3] = {i, j, k};
+                        m3[dir] = (side < 0) ? N : 0;
+                        long np = en * Np + m3[0] + Q * (m3[1] + Q * m3[2]);
+                        double Yp[6];
+                        for (int v = 0; v < nvar; ++v) Yp[v] = Y[v * nn + np];
+                        rusanov(Ym, Pm, M->pr[n], Yp, &W->P[np], M->pr[np], nv, nvar, fstar);
+                        for (int v = 0; v < nvar; ++v) {
+                            double a = 0.0, b = 0.0;
+                            for (int c = 0; c < 3; ++c) {
+                                a += W->F2[(v * 3 + c) * nn + n] * nv[c];
+                                b += W->F2[(v * 3 + c) * nn + np] * nv[c];
+                            }
+                            f2star[v] = 0.5 * (a + b);
+                        }
+                    } else {
+                        /* reflecting ghost: u+ = u- - 2 (n.u-) n, scalars mirrored */
+                        double Yp[6];
+                        for (int v = 0; v < nvar; ++v) Yp[v] = Ym[v];
+                        double mn = Ym[1] * nv[0] + Ym[2] * nv[1] + Ym[3] * nv[2];
+                        for (int c = 0; c < 3; ++c) Yp[1 + c] = Ym[1 + c] - 2.0 * mn * nv[c];
+                        prim_t Pp; thermo(Yp, nvar, z[n], m->g, &Pp);
+                        rusanov(Ym, Pm, M->pr[n], Yp, &Pp, M->pr[n], nv, nvar, fstar);
+                        for (int v = 0; v < nvar; ++v) f2star[v] = 0.0;
+                        if (m->closure != 0 && m->sfc_flux && dir == 2 && side < 0) {
+                            /* prescribed upward surface fluxes; outward normal is -z */
+                            double qf = (nvar > 5) ? m->qt_flux : 0.0;
+                            double up_e = Pm->rho * (CPD * m->theta_flux + LV0 * qf);
+                            f2star[4] = -up_e;
+                            if (nvar > 5) { f2star[0] = -Pm->rho * qf; f2star[5] = -Pm->rho * qf; }
+                        }
+                    }
+                    for (int v = 0; v < nvar; ++v) {
+                        double fm = Fm[v][0] * nv[0] + Fm[v][1] * nv[1] + Fm[v][2] * nv[2];
+                        Rn[v] += lift * (fm - (fstar[v] + f2star[v]));
+                    }
+                }
+            }
+            /* sources */
+            Rn[3] -= (Pm->rho - M->rhor[n]) * m->g;
+            if (m->f_cor != 0.0) {
+                Rn[1] += m->f_cor * (Ym[2] - Pm->rho * m->v_g);
+                Rn[2] -= m->f_cor * (Ym[1] - Pm->rho * m->u_g);
+            }
+            if (m->sponge && z[n] > m->sp_zs) {
+                double zeta = (z[n] - m->sp_zs) / (m->sp_ztop - m->sp_zs);
+                double tau = m->sp_alpha * pow(sin(0.5 * M_PI * zeta), m->sp_gamma);
+                for (int c = 0; c < 3; ++c) Rn[1 + c] -= tau * (Ym[1 + c] - Pm->rho * m->sp_u[c]);
+            }
+            if (m->subsidence && m->closure != 0) {
+                double zz = z[n] < m->sub_ztop ? z[n] : m->sub_ztop;
+                double ws = -m->sub_w0 * sin(M_PI * zz / m->sub_ztop);
+                Rn[4] -= Pm->rho * ws * W->grad[(GH * 3 + 2) * nn + n];
+                if (nvar > 5) Rn[5] -= Pm->rho * ws * W->grad[(s.iq * 3 + 2) * nn + n];
+            }
+            for (int v = 0; v < nvar; ++v) R[v * nn + n] = Rn[v];
+        }
+    }
+    free(Gf);
+}
+
+void cmref_rhs(void* h, const double* Y, double* R, double t)
+{
+    (void)t;
+    model_t* M = (model_t*)h;
+    work_t W; work_alloc(M, &W, slots(&M->m));
+    rhs_eval(M, Y, R, &W);
+    work_free(&W);
+}
+
+/* BR1 gradients ([nG][3][nnodes]) and F2 ([nvar][3][nnodes]) of a state. */
+int cmref_gradients(void* h, const double* Y, double* grad, double* F2)
+{
+    model_t* M = (model_t*)h;
+    gslots_t s = slots(&M->m);
+    work_t W; work_alloc(M, &W, s);
+    prepare(M, Y, &W, s);
+    br1_gradients(M, &W, s);
+    diffusive_flux(M, &W, s);
+    long nn = M->G->nnodes;
+    if (grad) memcpy(grad, W.grad, sizeof(double) * s.nG * 3 * nn);
+    if (F2) memcpy(F2, W.F2, sizeof(double) * M->m.nvar * 3 * nn);
+    work_free(&W);
+    return s.nG;
+}
+
+/* ======================================================================== */
+/* LSRK54 (Carpenter & Kennedy 1994, five stages, fourth order, 2N storage) */
+/* ======================================================================== */
+static const double LSRK_A[5] = {
+    0.0,
+    -567301805773.0 / 1357537059087.0,
+    -2404267990393.0 / 2016746695238.0,
+    -3550918686646.0 / 2091501179385.0,
+    -1275806237668.0 / 842570457699.0};
+static const double LSRK_B[5] = {
+    1432997174477.0 / 9575080441755.0,
+    5161836677717.0 / 13612068292357.0,
+    1720146321549.0 / 2090206949498.0,
+    3134564353537.0 / 4481467310338.0,
+    2277821191437.0 / 14882151754819.0};
+static const double LSRK_C[5] = {
+    0.0,
+    1432997174477.0 / 9575080441755.0,
+    2526269341429.0 / 6820363266100.0,
+    2006345519317.0 / 3224310063776.0,
+    2802321613138.0 / 2924317926251.0};
+
+void cmref_lsrk54_coeffs(double* A, double* B, double* C)
+{
+    for (int s = 0; s < 5; ++s) { A[s] = LSRK_A[s]; B[s] = LSRK_B[s]; C[s] = LSRK_C[s]; }
+}
+
+/* One step in place: for each stage dQ = A_s dQ + dt R(Y); Y += B_s dQ. */
+void cmref_lsrk_steps(void* h, double* Y, double* dQ, double t, double dt, int nsteps)
+{
+    model_t* M = (model_t*)h;
+    long n = (long)M->m.nvar * M->G->nnodes;
+    double* R = (double*)malloc(sizeof(double) * n);
+    work_t W; work_alloc(M, &W, slots(&M->m));
+    for (int step = 0; step < nsteps; ++step) {
+        for (int s = 0; s < 5; ++s) {
+            rhs_eval(M, Y, R, &W);
+            #pragma omp parallel for schedule(static)
+            for (long i = 0; i < n; ++i) {
+                dQ[i] = LSRK_A[s] * dQ[i] + dt * R[i];
+                Y[i] = Y[i] + LSRK_B[s] * dQ[i];
+            }
+        }
+        t += dt;
+    }
+    work_free(&W);
+    free(R);
+}
+
+/* ======================================================================== */
+/* Integrals (Sect. 6): sum of w_i w_j w_k |J| Y_v, Neumaier-compensated in  */
+/* long double.  out[v] for v < nvar, then kinetic energy.                   */
+/* ======================================================================== */
+void cmref_integrals(void* h, const double* Y, double* out)
+{
+    model_t* M = (model_t*)h;
+    grid_t* G = M->G; long nn = G->nnodes; int nvar = M->m.nvar;
+    double* wJ = (double*)malloc(sizeof(double) * nn);
+    cmref_grid_wJ(G, wJ);
+    for (int v = 0; v <= nvar; ++v) {
+        long double s = 0.0L, c = 0.0L;
+        for (long n = 0; n < nn; ++n) {
+            long double x;
+            if (v < nvar) x = (long double)wJ[n] * Y[v * nn + n];
+            else {
+                double r = Y[n];
+                double ke = 0.5 * (Y[nn + n] * Y[nn + n] + Y[2 * nn + n] * Y[2 * nn + n] + Y[3 * nn + n] * Y[3 * nn + n]) / r;
+                x = (long double)wJ[n] * ke;
+            }
+            long double tt = s + x;
+            if (fabsl(s) >= fabsl(x)) c += (s - tt) + x; else c += (x - tt) + s;
+            s = tt;
+        }
+        out[v] = (double)(s + c);
+    }
+    free(wJ);
+}
+
+int cmref_num_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
