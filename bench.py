@@ -1,0 +1,196 @@
+"""Throughput of the DG right-hand side + LSRK54 step on one MI355X.
+
+A step is one LSRK54 time step: five stages, each one gradient/closure pass
+and one tendency pass with the fused stage update, over the whole mesh.
+Default workload: the dry rising bubble on 32 x 32 x 32 elements, N = 4
+(4,096,000 nodes, 5 variables), Smagorinsky-Lilly with the Richardson
+correction, FP64.  Inputs are synthetic and resident in HBM before timing.
+
+Prints ONE JSON line: DOF-updates/s = nodes x vars x 5 stages x steps / t,
+the roofline of the dominant kernel (tendency pass) from hipEvents around
+every launch in the timed region, the FP32-bulk variant, and the FP64 CPU
+oracle timed on this host on whole steps of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, vendor figure
+
+
+def alg_bytes(nvar: int, nf: int, s: int):
+    """Algorithmic HBM bytes per node: gradient pass reads Y, writes F2;
+    tendency pass reads Y, F2, dQ and writes dQ, Y_new (the first stage does
+    not read dQ).  Neighbour face re-reads are counted as cache hits."""
+    grad = (nvar + nf) * s
+    tend_first = (3 * nvar + nf) * s
+    tend_other = (4 * nvar + nf) * s
+    return grad, tend_first, tend_other
+
+
+def run(args):
+    import numpy as np
+    import torch
+
+    from paper_2110_00853_amd import binding as B
+    from paper_2110_00853_amd import workloads as W
+
+    c = W.case(args.case)
+    if args.ne:
+        ne = [int(a) for a in args.ne.split(",")]
+        scale = [ne[a] / c["grid"]["ne"][a] for a in range(3)]
+        c["grid"]["hi"] = [c["grid"]["hi"][a] * scale[a] for a in range(3)]
+        c["grid"]["ne"] = ne
+    Y0, Yref, dt = W.initial_state(c)
+    grid = B.Grid(c["grid"], device=0)
+    nn, nvar = grid.n_nodes, c["model"]["nvar"]
+
+    def timed(precision: str, steps: int, warmup: int):
+        m = B.Model(grid, c["model"], Yref, precision=precision)
+        Ya, Yb, dQ = m.new_state(Y0), m.new_state(), m.new_state()
+        stream = torch.cuda.current_stream()
+        t = 0.0
+        for _ in range(warmup):
+            m.lsrk_step(Ya, Yb, dQ, t, dt, stream)
+            Ya, Yb = Yb, Ya
+            t += dt
+        torch.cuda.synchronize()
+        m.profile(True)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        w0 = time.perf_counter()
+        e0.record(stream)
+        for _ in range(steps):
+            m.lsrk_step(Ya, Yb, dQ, t, dt, stream)
+            Ya, Yb = Yb, Ya
+            t += dt
+        e1.record(stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - w0
+        ms = e0.elapsed_time(e1)
+        prof = m.profile_read()
+        m.profile(False)
+        diag = m.diagnostics(Ya, dt)
+        return m, Ya, ms, wall, prof, diag
+
+    m64, Y64, ms, wall, prof, diag = timed("fp64", args.steps, args.warmup)
+    ms_step = ms / args.steps
+    value = nn * nvar * 5 * args.steps / (ms * 1e-3)
+    nf = {5: 9, 6: 12}[nvar] + (0 if not c["model"].get("subsidence") else (1 if nvar == 5 else 2))
+    g_b, tf_b, to_b = alg_bytes(nvar, nf, 8)
+    tend_ms, tend_n = prof["tend"]
+    grad_ms, grad_n = prof["grad"]
+    tend_bytes = nn * (tf_b + 4 * to_b) / 5.0          # average launch (1 first + 4 other stages)
+    tend_avg_s = tend_ms * 1e-3 / tend_n
+    grad_avg_s = grad_ms * 1e-3 / max(grad_n, 1)
+    achieved = tend_bytes / tend_avg_s / 1e9
+    step_bytes = nn * (5 * g_b + tf_b + 4 * to_b)
+    out = {
+        "metric": "DOF-updates/s (nodes x vars x RK stages) for DG RHS+LSRK",
+        "value": value,
+        "unit": "DOF-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": "%s: dry rising bubble, %dx%dx%d elements N=4 (%d nodes, %d vars), "
+                        "Smagorinsky-Lilly Cs=0.21 + Richardson, LSRK54" % (
+                            args.case, *c["grid"]["ne"], nn, nvar),
+            "n_nodes": nn, "nvar": nvar, "dt": dt, "wall_s": wall,
+        },
+        "roofline": {
+            "bound": "hbm",
+            "kernel": "k_tend (tendency pass + fused LSRK54 stage update)",
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": None,
+            "avg_launch_us": tend_avg_s * 1e6,
+            "alg_bytes_per_launch": tend_bytes,
+            "grad_kernel": {"avg_launch_us": grad_avg_s * 1e6,
+                            "achieved": nn * g_b / grad_avg_s / 1e9},
+            "whole_step_alg_GBs": step_bytes / (ms_step * 1e-3) / 1e9,
+            "whole_step_frac": step_bytes / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS,
+        },
+        "diagnostics_after": {k: diag[k] for k in ("max_abs_w", "max_cfl", "T_min", "T_max", "n_nonfinite")},
+    }
+    if not args.no_fp32:
+        m32, Y32, ms32, _, prof32, _ = timed("fp32", args.steps, args.warmup)
+        v32 = nn * nvar * 5 * args.steps / (ms32 * 1e-3)
+        a = Y64.cpu().numpy()
+        b = Y32.cpu().numpy().astype(np.float64)
+        err = [float(np.abs(a[v] - b[v]).max() / np.abs(a[v]).max()) for v in range(nvar)]
+        g32, tf32, to32 = alg_bytes(nvar, nf, 4)
+        t32_ms, t32_n = prof32["tend"]
+        out["fp32_bulk"] = {
+            "value": v32, "ms_per_step": ms32 / args.steps, "speedup_vs_fp64": v32 / value,
+            "tend_achieved_GBs": nn * (tf32 + 4 * to32) / 5.0 / (t32_ms * 1e-3 / t32_n) / 1e9,
+            "state_rel_err_vs_fp64_after_steps": err,
+            "note": "warmup+steps LSRK54 steps from the same initial state; max-norm error per variable",
+        }
+        del m32, Y32
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(c, Y0, Yref, nn, nvar, dt)
+    return out
+
+
+def cpu_baseline(c, Y0, Yref, nn, nvar, dt, budget_s=10.0, max_steps=6):
+    """The FP64 oracle on this host, as it stands: whole LSRK54 steps of the
+    same workload, repeated until about budget_s seconds of CPU work."""
+    import oracle
+
+    og = oracle.Grid(c["grid"])
+    om = oracle.Model(og, c["model"], Yref)
+    Y, dQ = Y0, None
+    steps = 0
+    t0 = time.perf_counter()
+    while steps < max_steps:
+        Y, dQ = om.steps(Y, dt, 1, dQ=dQ)
+        steps += 1
+        if time.perf_counter() - t0 >= budget_s:
+            break
+    t = time.perf_counter() - t0
+    return {
+        "value": nn * nvar * 5 * steps / t,
+        "unit": "DOF-updates/s",
+        "cores": oracle.num_threads(),
+        "kind": "oracle",
+        "sample": "%d LSRK54 step(s) of the same workload (%d nodes x %d vars x 5 stages), %.1f s"
+                  % (steps, nn, nvar, t),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--case", default="bubble_32")
+    ap.add_argument("--ne", default=None, help="override element counts, e.g. 16,16,16")
+    ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path (run with --gpus 1)",
+              file=sys.stderr)
+        sys.exit(2)
+    out = run(args)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

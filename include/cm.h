@@ -1,0 +1,216 @@
+/*
+ * cm.h -- C ABI of the MI355X (gfx950) nodal discontinuous-Galerkin LES hot
+ * path: the right-hand side of the compressible Navier-Stokes equations with
+ * total energy (and total water) as prognostic variables, and the explicit
+ * low-storage Runge-Kutta step that calls it every stage.
+ *
+ * Method: Sridhar et al., "Large-eddy simulations with ClimateMachine",
+ * GMD 2022 -- Sect. 2 (governing equations, Table 1, equation of state,
+ * saturation adjustment), Sect. 3.1 (nodal GLL discretisation, mapping,
+ * Rusanov flux eq. nonviscFlux, BR1 auxiliary gradient, semi-discrete
+ * operator eq. matrixProblem), Sect. 3.2 (low-storage RK), Sect. 4 (SGS
+ * closures eq. smago, eq. richardson), Sect. 6 (mass/energy integrals),
+ * App. A (wall ghost states, prescribed wall fluxes, Rayleigh sponge).
+ *
+ * Conventions for every call:
+ *  - State buffers (Y, Y_alt, dQ, dYdt) are caller-owned DEVICE memory on
+ *    the grid's device, contiguous, layout [nvar][n_nodes]; element-major
+ *    node order: node = 125*e + i + 5*(j + 5*k), i along x, and
+ *    e = ex + ne[0]*(ey + ne[1]*ez).  Element type double (CM_FP64) or
+ *    float (CM_FP32_BULK), at least 16-byte aligned.  The library never
+ *    frees or retains them beyond a call.
+ *  - Grid and model objects own their device arrays (metrics, reference
+ *    state, diffusive-flux scratch, reduction scratch) and free them on
+ *    destroy.
+ *  - Compute calls are asynchronous on the hipStream_t passed as void*
+ *    (NULL = the default stream).  Only create/copy calls and
+ *    cm_diagnostics synchronise.
+ *  - Every call returns a cm_status; on failure cm_last_error() returns a
+ *    thread-local message.  No C++ exception crosses this boundary.  Calls
+ *    on one model must not overlap on different streams.
+ */
+#ifndef CM_H
+#define CM_H
+
+#include <stdint.h>
+
+#if defined(__GNUC__) || defined(__clang__)
+#define CM_API __attribute__((visibility("default")))
+#else
+#define CM_API
+#endif
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    CM_OK = 0,
+    CM_ERR_ARG = 1,          /* invalid argument (null pointer, bad size, bad enum) */
+    CM_ERR_HIP = 2,          /* a HIP runtime call failed */
+    CM_ERR_ALLOC = 3,        /* device or host allocation failed */
+    CM_ERR_UNSUPPORTED = 4,  /* valid but not implemented (e.g. N != 4) */
+    CM_ERR_NONFINITE = 5,    /* cm_diagnostics found NaN/Inf in the state */
+    CM_ERR_STATE = 6         /* object used in a wrong state (e.g. MLP closure without weights) */
+} cm_status;
+
+typedef enum { CM_FP64 = 0, CM_FP32_BULK = 1 } cm_precision;
+
+typedef enum {
+    CM_CLOSURE_NONE = 0,   /* inviscid */
+    CM_CLOSURE_CONST = 1,  /* constant kinematic viscosity nu */
+    CM_CLOSURE_SMAG = 2,   /* Smagorinsky-Lilly (eq. smago), optional Richardson factor */
+    CM_CLOSURE_MLP = 3     /* learned eddy viscosity / Prandtl number, Smagorinsky fallback */
+} cm_closure;
+
+/* Mesh (Sect. 3.1): brick of ne[0] x ne[1] x ne[2] hexahedra over
+ * [lo, hi]; periodic[d] != 0 wraps direction d, otherwise its two end faces
+ * are free-slip walls.  topo = 1 warps the mesh terrain-following over the
+ * Agnesi ridge z_sfc(x) = topo_h topo_a^2 / ((x - topo_xc)^2 + topo_a^2)
+ * (eq. agnesi) with linear decay to a flat lid at hi[2] (Sect. 4.3). */
+typedef struct {
+    int N;               /* polynomial order; only 4 is supported */
+    int ne[3];
+    double lo[3], hi[3]; /* metres */
+    int periodic[3];
+    int topo;            /* 0 flat, 1 Agnesi ridge along x */
+    double topo_h, topo_a, topo_xc;
+} cm_grid_desc;
+
+typedef struct {
+    int64_t n_elem;
+    int64_t n_nodes;     /* 125 * n_elem (face nodes counted per element) */
+    int N;
+    int warped;
+    double dmin_node;    /* minimum distance between adjacent GLL nodes [m] */
+} cm_grid_info;
+
+/* Physics of one model (Sects. 2, 4, App. A).  Units SI. */
+typedef struct {
+    int nvar;            /* 5: rho, rho u, rho v, rho w, rho e_tot; 6: + rho q_t */
+    int precision;       /* cm_precision */
+    int closure;         /* cm_closure */
+    double nu;           /* CM_CLOSURE_CONST viscosity [m^2/s] */
+    double Cs;           /* Smagorinsky coefficient */
+    double Prt;          /* turbulent Prandtl number (1/3 in the paper) */
+    int richardson;      /* multiply nu_t by the stability factor f_b(Ri) */
+    double g;            /* gravity [m/s^2]; 0 disables gravity */
+    double f_cor, u_g, v_g;            /* f-plane Coriolis and geostrophic wind */
+    int sponge;                        /* Rayleigh sponge (eq. sponge) */
+    double sp_zs, sp_ztop, sp_alpha, sp_gamma, sp_u[3];
+    int sfc_flux;                      /* prescribed bottom fluxes (kinematic) */
+    double theta_flux, qt_flux;        /* [K m/s], [m/s] */
+    int subsidence;                    /* w_s = -w0 sin(pi z / z_top) acting on h_tot, q_t */
+    double sub_w0, sub_ztop;
+} cm_model_desc;
+
+typedef struct {
+    double mass, energy, water;  /* integrals of rho, rho e_tot, rho q_t (w_i w_j w_k |J|) */
+    double ke;                   /* integral of |rho u|^2 / (2 rho) */
+    double max_abs_w;            /* max |w| [m/s] */
+    double max_cfl;              /* max (|u| + c) dt / dmin_node, 0 if dt <= 0 */
+    double T_min, T_max;         /* temperature range [K] */
+    int64_t n_nonfinite;         /* number of non-finite state entries */
+} cm_diag;
+
+typedef struct cm_grid cm_grid;
+typedef struct cm_model cm_model;
+typedef struct cm_mlp cm_mlp;
+
+/* Build GLL nodes/weights and the differentiation matrix, node coordinates,
+ * and (for warped meshes) per-node metric terms J a^d and 1/J from the
+ * differentiated coordinates (Sect. 3.1 eq. mapping); uploads them to
+ * hip_device.  *out owns its device arrays.
+ * Errors: CM_ERR_ARG (null, ne < 1, hi <= lo), CM_ERR_UNSUPPORTED (N != 4),
+ * CM_ERR_HIP / CM_ERR_ALLOC. */
+CM_API cm_status cm_grid_create(const cm_grid_desc* desc, int hip_device, cm_grid** out);
+CM_API cm_status cm_grid_destroy(cm_grid* grid);
+CM_API cm_status cm_grid_query(const cm_grid* grid, cm_grid_info* out);
+/* Host copies: xyz_host [3][n_nodes]; wJ_host [n_nodes] = w_i w_j w_k |J|;
+ * Ja_host [3 (d)][3 (component)][n_nodes] and J_host [n_nodes]. */
+CM_API cm_status cm_grid_copy_coords(const cm_grid* grid, double* xyz_host);
+CM_API cm_status cm_grid_copy_wJ(const cm_grid* grid, double* wJ_host);
+CM_API cm_status cm_grid_copy_metrics(const cm_grid* grid, double* Ja_host, double* J_host);
+
+/* Create a model on a grid.  Yref_host (host, [nvar][n_nodes], float64) is
+ * the hydrostatic background; the library pushes it through its own
+ * thermodynamics to obtain the reference pressure p_r and density rho_r
+ * factored out of the momentum flux and the buoyancy (Sect. 2.3).  NULL
+ * means p_r = rho_r = 0.  In CM_FP32_BULK the background is first rounded
+ * to float, so a state equal to it is exactly at rest.
+ * Errors: CM_ERR_ARG, CM_ERR_UNSUPPORTED (nvar not 5/6), CM_ERR_HIP/ALLOC. */
+CM_API cm_status cm_model_create(const cm_grid* grid, const cm_model_desc* desc, const double* Yref_host,
+                          cm_model** out);
+CM_API cm_status cm_model_destroy(cm_model* model);
+
+/* Learned closure weights for CM_CLOSURE_MLP (host, float32).  params: the
+ * 9282 parameters of the 12-64-64-64-2 SiLU network, layer by layer, each
+ * weight matrix row-major [out][in] followed by its bias.  norm: 48 floats:
+ * input mean[12], std[12], then the standardised training range lo[12],
+ * hi[12].  A node falls back to Smagorinsky when a standardised input leaves
+ * the range widened by 10 % of its half-width on each side, or when the
+ * network output is not finite. */
+CM_API cm_status cm_model_set_mlp(cm_model* model, const float* params_host, const float* norm_host);
+/* number of nodes that fell back to Smagorinsky in the last RHS (syncs) */
+CM_API cm_status cm_model_mlp_fallbacks(cm_model* model, int64_t* count, void* hip_stream);
+
+/* dYdt = R(Y): the semi-discrete DG operator (eq. matrixProblem, strong
+ * form) with F = F1 + F2, Rusanov F1*, centred F2*, BR1 gradients, closure,
+ * sources.  Y and dYdt must not alias.  t is the model time (unused by the
+ * present sources). */
+CM_API cm_status cm_dg_rhs(cm_model* model, const void* Y, void* dYdt, double t, void* hip_stream);
+
+/* One LSRK54 step (Carpenter-Kennedy 2N storage, 5 stages): for s = 1..5,
+ * dQ = A_s dQ + dt R(Y_s, t + C_s dt); Y_{s+1} = Y_s + B_s dQ.  The stages
+ * ping-pong Y -> Y_alt -> Y -> Y_alt -> Y -> Y_alt because neighbouring
+ * elements still read the old state within a stage: on return the NEW state
+ * is in Y_alt and Y holds an intermediate stage (swap the handles).  dQ need
+ * not be initialised (A_1 = 0).  Y, Y_alt, dQ must be distinct. */
+CM_API cm_status cm_lsrk_step(cm_model* model, void* Y, void* Y_alt, void* dQ, double t, double dt,
+                       void* hip_stream);
+
+/* Conservation and health diagnostics (Sect. 6): compensated (Neumaier) FP64
+ * integrals in a deterministic two-stage reduction, extrema, CFL and a
+ * non-finite count.  Synchronises the stream.  Returns CM_ERR_NONFINITE
+ * (with *out filled) when the state holds NaN/Inf. */
+CM_API cm_status cm_diagnostics(cm_model* model, const void* Y, double dt, cm_diag* out_host, void* hip_stream);
+
+/* ---- learned closure training (12-64-64-64-2 SiLU MLP, BF16 MFMA, FP32
+ * accumulate, FP32 master weights, Adam) ------------------------------- */
+typedef struct {
+    int n_in, n_hidden, n_layers_hidden, n_out;   /* must be 12, 64, 3, 2 */
+    float lr, beta1, beta2, eps;                  /* Adam */
+} cm_mlp_desc;
+
+/* Initialise the network (uniform +-1/sqrt(fan_in) weights, zero biases) from
+ * a 64-bit seed.  device buffers owned by the object. */
+CM_API cm_status cm_mlp_create(const cm_mlp_desc* desc, uint64_t seed, int hip_device, cm_mlp** out);
+CM_API cm_status cm_mlp_destroy(cm_mlp* mlp);
+/* X_dev [batch][12] standardised inputs, T_dev [batch][2] targets (device,
+ * float32).  One forward + backward + Adam update on the mean squared error;
+ * *loss_host (if non-NULL) receives the batch loss (synchronises). */
+CM_API cm_status cm_mlp_train_step(cm_mlp* mlp, const float* X_dev, const float* T_dev, int batch,
+                            float* loss_host, void* hip_stream);
+/* Gradient of the batch loss w.r.t. all 9282 parameters (host, float32). */
+CM_API cm_status cm_mlp_grads(cm_mlp* mlp, const float* X_dev, const float* T_dev, int batch, float* grad_host,
+                       void* hip_stream);
+/* out_dev [batch][2] raw network outputs for standardised inputs. */
+CM_API cm_status cm_mlp_infer(cm_mlp* mlp, const float* X_dev, float* out_dev, int batch, void* hip_stream);
+CM_API cm_status cm_mlp_get_params(const cm_mlp* mlp, float* params_host);
+CM_API cm_status cm_mlp_set_params(cm_mlp* mlp, const float* params_host);
+
+/* Instrumentation: with profiling enabled the library brackets every kernel
+ * launch of this model with a pair of hipEvents on the launch stream.
+ * cm_model_profile(m, 1) starts (and clears) a record; read returns the
+ * summed kernel durations [ms] and launch counts per kind: [0] gradient +
+ * closure pass, [1] tendency pass (incl. the fused stage update).  The read
+ * synchronises on the recorded events. */
+CM_API cm_status cm_model_profile(cm_model* model, int enable);
+CM_API cm_status cm_model_profile_read(cm_model* model, double* ms_host, int64_t* count_host);
+
+CM_API const char* cm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CM_H */

@@ -1,0 +1,496 @@
+// C ABI entry points: grid and model objects, argument checks, dispatch to
+// the HIP kernels, error reporting.
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+
+#include "cm_impl.hpp"
+
+namespace cm {
+
+static thread_local std::string g_err;
+
+void set_error(const std::string& msg) { g_err = msg; }
+
+cm_status hip_fail(hipError_t e, const char* where)
+{
+    set_error(std::string(where) + ": " + hipGetErrorString(e));
+    return e == hipErrorOutOfMemory ? CM_ERR_ALLOC : CM_ERR_HIP;
+}
+
+// GLL nodes and weights for N = 4 in closed form; differentiation matrix from
+// barycentric weights, D_ij = (lambda_j / lambda_i) / (x_i - x_j), with the
+// diagonal set to minus the off-diagonal row sum (so D annihilates constants).
+static void gll4(double* xi, double* w, double* D)
+{
+    const double a = std::sqrt(3.0 / 7.0);
+    const double x[NQ] = {-1.0, -a, 0.0, a, 1.0};
+    const double ww[NQ] = {1.0 / 10.0, 49.0 / 90.0, 32.0 / 45.0, 49.0 / 90.0, 1.0 / 10.0};
+    double lam[NQ];
+    for (int j = 0; j < NQ; ++j) {
+        double p = 1.0;
+        for (int k = 0; k < NQ; ++k)
+            if (k != j) p *= (x[j] - x[k]);
+        lam[j] = 1.0 / p;
+    }
+    for (int i = 0; i < NQ; ++i) {
+        xi[i] = x[i];
+        w[i] = ww[i];
+        double s = 0.0;
+        for (int j = 0; j < NQ; ++j) {
+            if (j == i) continue;
+            double d = (lam[j] / lam[i]) / (x[i] - x[j]);
+            D[i * NQ + j] = d;
+            s += d;
+        }
+        D[i * NQ + i] = -s;
+    }
+}
+
+static inline int64_t node_index(const cm_grid* g, int ex, int ey, int ez, int i, int j, int k)
+{
+    int64_t e = ex + (int64_t)g->desc.ne[0] * (ey + (int64_t)g->desc.ne[1] * ez);
+    return e * NP + i + NQ * (j + NQ * k);
+}
+
+// coordinates and (cross-product form) metric terms on the host, FP64
+static void build_geometry(cm_grid* g)
+{
+    const cm_grid_desc& d = g->desc;
+    const int64_t nn = g->n_nodes;
+    g->xyz.assign(3 * nn, 0.0);
+    const double ztop = d.hi[2], zlo = d.lo[2];
+    for (int ez = 0; ez < d.ne[2]; ++ez)
+        for (int ey = 0; ey < d.ne[1]; ++ey)
+            for (int ex = 0; ex < d.ne[0]; ++ex)
+                for (int k = 0; k < NQ; ++k)
+                    for (int j = 0; j < NQ; ++j)
+                        for (int i = 0; i < NQ; ++i) {
+                            int64_t n = node_index(g, ex, ey, ez, i, j, k);
+                            double x = d.lo[0] + (ex + 0.5 * (1.0 + g->xi[i])) * g->h[0];
+                            double y = d.lo[1] + (ey + 0.5 * (1.0 + g->xi[j])) * g->h[1];
+                            double z = d.lo[2] + (ez + 0.5 * (1.0 + g->xi[k])) * g->h[2];
+                            if (d.topo == 1) {
+                                double r = x - d.topo_xc;
+                                double zs = d.topo_h * d.topo_a * d.topo_a / (r * r + d.topo_a * d.topo_a);
+                                z += zs * (ztop - z) / (ztop - zlo);
+                            }
+                            g->xyz[n] = x;
+                            g->xyz[nn + n] = y;
+                            g->xyz[2 * nn + n] = z;
+                        }
+    g->Ja.assign(9 * nn, 0.0);
+    g->J.assign(nn, 0.0);
+    if (d.topo == 0) {
+        const double hx = g->h[0], hy = g->h[1], hz = g->h[2];
+        for (int64_t n = 0; n < nn; ++n) {
+            g->Ja[0 * nn + n] = 0.25 * hy * hz;
+            g->Ja[4 * nn + n] = 0.25 * hx * hz;
+            g->Ja[8 * nn + n] = 0.25 * hx * hy;
+            g->J[n] = 0.125 * hx * hy * hz;
+        }
+        return;
+    }
+    // warped: dX[d][c] = sum_l D_{.,l} x_c along reference direction d
+    for (int64_t e = 0; e < g->n_elem; ++e)
+        for (int k = 0; k < NQ; ++k)
+            for (int j = 0; j < NQ; ++j)
+                for (int i = 0; i < NQ; ++i) {
+                    int64_t n = e * NP + i + NQ * (j + NQ * k);
+                    double dX[3][3];
+                    for (int c = 0; c < 3; ++c) {
+                        const double* f = g->xyz.data() + c * nn + e * NP;
+                        double s0 = 0, s1 = 0, s2 = 0;
+                        for (int l = 0; l < NQ; ++l) {
+                            s0 += g->D[i * NQ + l] * f[l + NQ * (j + NQ * k)];
+                            s1 += g->D[j * NQ + l] * f[i + NQ * (l + NQ * k)];
+                            s2 += g->D[k * NQ + l] * f[i + NQ * (j + NQ * l)];
+                        }
+                        dX[0][c] = s0;
+                        dX[1][c] = s1;
+                        dX[2][c] = s2;
+                    }
+                    for (int dd = 0; dd < 3; ++dd) {
+                        const double* a = dX[(dd + 1) % 3];
+                        const double* b = dX[(dd + 2) % 3];
+                        g->Ja[(3 * dd + 0) * nn + n] = a[1] * b[2] - a[2] * b[1];
+                        g->Ja[(3 * dd + 1) * nn + n] = a[2] * b[0] - a[0] * b[2];
+                        g->Ja[(3 * dd + 2) * nn + n] = a[0] * b[1] - a[1] * b[0];
+                    }
+                    g->J[n] = dX[0][0] * g->Ja[0 * nn + n] + dX[0][1] * g->Ja[1 * nn + n] +
+                              dX[0][2] * g->Ja[2 * nn + n];
+                }
+}
+
+cm_model::ProfRec* prof_begin(cm_model* m, int kind, hipStream_t s)
+{
+    if (!m->profiling) return nullptr;
+    if (m->prof_used == m->prof.size()) {
+        cm_model::ProfRec r;
+        if (hipEventCreate(&r.a) != hipSuccess) return nullptr;
+        if (hipEventCreate(&r.b) != hipSuccess) { (void)hipEventDestroy(r.a); return nullptr; }
+        m->prof.push_back(r);
+    }
+    cm_model::ProfRec* r = &m->prof[m->prof_used++];
+    r->kind = kind;
+    (void)hipEventRecord(r->a, s);
+    return r;
+}
+
+void prof_end(cm_model::ProfRec* r, hipStream_t s)
+{
+    if (r) (void)hipEventRecord(r->b, s);
+}
+
+}  // namespace cm
+
+using namespace cm;
+
+#define CM_TRY_HIP(expr, where)                      \
+    do {                                             \
+        hipError_t _e = (expr);                      \
+        if (_e != hipSuccess) return hip_fail(_e, where); \
+    } while (0)
+
+extern "C" {
+
+const char* cm_last_error(void) { return g_err.c_str(); }
+
+cm_status cm_grid_create(const cm_grid_desc* desc, int hip_device, cm_grid** out)
+{
+    if (!desc || !out) { set_error("cm_grid_create: null argument"); return CM_ERR_ARG; }
+    *out = nullptr;
+    if (desc->N != 4) { set_error("cm_grid_create: only N = 4 is supported"); return CM_ERR_UNSUPPORTED; }
+    for (int a = 0; a < 3; ++a) {
+        if (desc->ne[a] < 1 || !(desc->hi[a] > desc->lo[a])) {
+            set_error("cm_grid_create: need ne >= 1 and hi > lo in every direction");
+            return CM_ERR_ARG;
+        }
+    }
+    if (desc->topo != 0 && desc->topo != 1) { set_error("cm_grid_create: topo must be 0 or 1"); return CM_ERR_ARG; }
+    if (desc->topo == 1 && !(desc->topo_a > 0.0)) { set_error("cm_grid_create: topo_a must be > 0"); return CM_ERR_ARG; }
+    int64_t ne = (int64_t)desc->ne[0] * desc->ne[1] * desc->ne[2];
+    if (ne * NP * 16 >= ((int64_t)1 << 31)) { set_error("cm_grid_create: grid too large for 32-bit kernel indexing"); return CM_ERR_UNSUPPORTED; }
+    int ndev = 0;
+    CM_TRY_HIP(hipGetDeviceCount(&ndev), "hipGetDeviceCount");
+    if (hip_device < 0 || hip_device >= ndev) { set_error("cm_grid_create: bad device ordinal"); return CM_ERR_ARG; }
+    cm_grid* g = new (std::nothrow) cm_grid();
+    if (!g) { set_error("cm_grid_create: out of host memory"); return CM_ERR_ALLOC; }
+    g->device = hip_device;
+    g->desc = *desc;
+    g->n_elem = ne;
+    g->n_nodes = ne * NP;
+    for (int a = 0; a < 3; ++a) g->h[a] = (desc->hi[a] - desc->lo[a]) / desc->ne[a];
+    gll4(g->xi, g->w, g->D);
+    double hmin = std::fmin(g->h[0], std::fmin(g->h[1], g->h[2]));
+    g->dmin = hmin * 0.5 * (g->xi[1] - g->xi[0]);
+    try {
+        build_geometry(g);
+    } catch (const std::bad_alloc&) {
+        delete g;
+        set_error("cm_grid_create: out of host memory");
+        return CM_ERR_ALLOC;
+    }
+    hipError_t e = hipSetDevice(hip_device);
+    if (e == hipSuccess && desc->topo == 1) {
+        const int64_t nn = g->n_nodes;
+        std::vector<double> m64(10 * nn);
+        std::vector<float> m32(10 * nn);
+        for (int q = 0; q < 9; ++q)
+            for (int64_t n = 0; n < nn; ++n) m64[q * nn + n] = g->Ja[q * nn + n];
+        for (int64_t n = 0; n < nn; ++n) m64[9 * nn + n] = 1.0 / g->J[n];
+        for (int64_t q = 0; q < 10 * nn; ++q) m32[q] = (float)m64[q];
+        e = hipMalloc(&g->d_metrics64, sizeof(double) * 10 * nn);
+        if (e == hipSuccess) e = hipMalloc(&g->d_metrics32, sizeof(float) * 10 * nn);
+        if (e == hipSuccess) e = hipMalloc(&g->d_z, sizeof(double) * nn);
+        if (e == hipSuccess) e = hipMemcpy(g->d_metrics64, m64.data(), sizeof(double) * 10 * nn, hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipMemcpy(g->d_metrics32, m32.data(), sizeof(float) * 10 * nn, hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipMemcpy(g->d_z, g->xyz.data() + 2 * nn, sizeof(double) * nn, hipMemcpyHostToDevice);
+    }
+    if (e == hipSuccess) e = upload_constants(g);
+    if (e != hipSuccess) {
+        cm_status st = hip_fail(e, "cm_grid_create");
+        cm_grid_destroy(g);
+        return st;
+    }
+    *out = g;
+    return CM_OK;
+}
+
+cm_status cm_grid_destroy(cm_grid* g)
+{
+    if (!g) return CM_OK;
+    (void)hipSetDevice(g->device);
+    if (g->d_metrics64) (void)hipFree(g->d_metrics64);
+    if (g->d_metrics32) (void)hipFree(g->d_metrics32);
+    if (g->d_z) (void)hipFree(g->d_z);
+    delete g;
+    return CM_OK;
+}
+
+cm_status cm_grid_query(const cm_grid* g, cm_grid_info* out)
+{
+    if (!g || !out) { set_error("cm_grid_query: null argument"); return CM_ERR_ARG; }
+    out->n_elem = g->n_elem;
+    out->n_nodes = g->n_nodes;
+    out->N = 4;
+    out->warped = g->desc.topo;
+    out->dmin_node = g->dmin;
+    return CM_OK;
+}
+
+cm_status cm_grid_copy_coords(const cm_grid* g, double* xyz)
+{
+    if (!g || !xyz) { set_error("cm_grid_copy_coords: null argument"); return CM_ERR_ARG; }
+    std::memcpy(xyz, g->xyz.data(), sizeof(double) * 3 * g->n_nodes);
+    return CM_OK;
+}
+
+cm_status cm_grid_copy_wJ(const cm_grid* g, double* wJ)
+{
+    if (!g || !wJ) { set_error("cm_grid_copy_wJ: null argument"); return CM_ERR_ARG; }
+    for (int64_t e = 0; e < g->n_elem; ++e)
+        for (int k = 0; k < NQ; ++k)
+            for (int j = 0; j < NQ; ++j)
+                for (int i = 0; i < NQ; ++i) {
+                    int64_t n = e * NP + i + NQ * (j + NQ * k);
+                    wJ[n] = g->w[i] * g->w[j] * g->w[k] * g->J[n];
+                }
+    return CM_OK;
+}
+
+cm_status cm_grid_copy_metrics(const cm_grid* g, double* Ja, double* J)
+{
+    if (!g || !Ja || !J) { set_error("cm_grid_copy_metrics: null argument"); return CM_ERR_ARG; }
+    std::memcpy(Ja, g->Ja.data(), sizeof(double) * 9 * g->n_nodes);
+    std::memcpy(J, g->J.data(), sizeof(double) * g->n_nodes);
+    return CM_OK;
+}
+
+cm_status cm_model_destroy(cm_model* m)
+{
+    if (!m) return CM_OK;
+    (void)hipSetDevice(m->grid->device);
+    if (m->d_F2) (void)hipFree(m->d_F2);
+    if (m->d_pr) (void)hipFree(m->d_pr);
+    if (m->d_rhor) (void)hipFree(m->d_rhor);
+    if (m->d_partials) (void)hipFree(m->d_partials);
+    if (m->d_mlp_w) (void)hipFree(m->d_mlp_w);
+    if (m->d_mlp_norm) (void)hipFree(m->d_mlp_norm);
+    if (m->d_fallbacks) (void)hipFree(m->d_fallbacks);
+    for (auto& r : m->prof) {
+        (void)hipEventDestroy(r.a);
+        (void)hipEventDestroy(r.b);
+    }
+    delete m;
+    return CM_OK;
+}
+
+cm_status cm_model_create(const cm_grid* g, const cm_model_desc* desc, const double* Yref, cm_model** out)
+{
+    if (!g || !desc || !out) { set_error("cm_model_create: null argument"); return CM_ERR_ARG; }
+    *out = nullptr;
+    if (desc->nvar != 5 && desc->nvar != 6) { set_error("cm_model_create: nvar must be 5 or 6"); return CM_ERR_UNSUPPORTED; }
+    if (desc->precision != CM_FP64 && desc->precision != CM_FP32_BULK) { set_error("cm_model_create: bad precision"); return CM_ERR_ARG; }
+    if (desc->closure < 0 || desc->closure > 3) { set_error("cm_model_create: bad closure"); return CM_ERR_ARG; }
+    if (desc->closure != CM_CLOSURE_NONE && !(desc->Prt > 0.0)) { set_error("cm_model_create: Prt must be > 0"); return CM_ERR_ARG; }
+    if (desc->sponge && !(desc->sp_ztop > desc->sp_zs)) { set_error("cm_model_create: sponge needs z_top > z_s"); return CM_ERR_ARG; }
+    if (desc->subsidence && !(desc->sub_ztop > 0.0)) { set_error("cm_model_create: subsidence needs z_top > 0"); return CM_ERR_ARG; }
+    CM_TRY_HIP(hipSetDevice(g->device), "hipSetDevice");
+    cm_model* m = new (std::nothrow) cm_model();
+    if (!m) { set_error("cm_model_create: out of host memory"); return CM_ERR_ALLOC; }
+    m->grid = g;
+    m->desc = *desc;
+    const int64_t nn = g->n_nodes;
+    const int moist = desc->nvar == 6;
+    m->nf = 0;
+    if (desc->closure != CM_CLOSURE_NONE) {
+        m->nf = moist ? 12 : 9;
+        if (desc->subsidence) m->nf += moist ? 2 : 1;
+    }
+    const size_t s = desc->precision == CM_FP64 ? 8 : 4;
+    m->Delta = std::cbrt((g->h[0] / 4.0) * (g->h[1] / 4.0) * (g->h[2] / 4.0));
+    hipError_t e = hipSuccess;
+    if (m->nf > 0) e = hipMalloc(&m->d_F2, s * m->nf * nn);
+    // reference state: per level when the mesh is flat and the background is
+    // horizontally uniform, else per node
+    m->has_ref = Yref != nullptr;
+    std::vector<double> Yr;
+    if (e == hipSuccess && Yref) {
+        int uniform = g->desc.topo == 0;
+        const int nv = desc->nvar;
+        if (uniform) {
+            const int64_t nlev_stride = (int64_t)g->desc.ne[0] * g->desc.ne[1];
+            for (int64_t el = 0; el < g->n_elem && uniform; ++el) {
+                int64_t base = (el / nlev_stride) * nlev_stride;  // first element of the same layer
+                for (int n = 0; n < NP && uniform; ++n)
+                    for (int v = 0; v < nv; ++v) {
+                        // nodes sharing (k) level: compare against (ex, ey) = (0, 0) element, same (i, j, k)?
+                        // horizontally uniform means independent of i, j, ex, ey
+                        int k = n / (NQ * NQ);
+                        double a = Yref[v * nn + el * NP + n];
+                        double b = Yref[v * nn + base * NP + k * NQ * NQ];
+                        if (a != b) { uniform = 0; break; }
+                    }
+            }
+        }
+        m->ref_per_node = !uniform;
+        const int64_t nref = uniform ? (int64_t)g->desc.ne[2] * NQ : nn;
+        Yr.assign((size_t)nv * nref, 0.0);
+        for (int64_t r = 0; r < nref; ++r) {
+            int64_t src = r;
+            if (uniform) {
+                int64_t ez = r / NQ, k = r % NQ;
+                src = ez * (int64_t)g->desc.ne[0] * g->desc.ne[1] * NP + k * NQ * NQ;
+            }
+            for (int v = 0; v < nv; ++v) {
+                double val = Yref[v * nn + src];
+                if (desc->precision == CM_FP32_BULK) val = (double)(float)val;
+                Yr[v * nref + r] = val;
+            }
+        }
+        e = hipMalloc(&m->d_pr, sizeof(double) * nref);
+        if (e == hipSuccess) e = hipMalloc(&m->d_rhor, sizeof(double) * nref);
+    }
+    if (e == hipSuccess) {
+        m->n_partials = 2048;
+        e = hipMalloc(&m->d_partials, sizeof(double) * 16 * m->n_partials);
+    }
+    if (e == hipSuccess) e = hipMalloc(&m->d_fallbacks, sizeof(unsigned long long));
+    if (e == hipSuccess) e = hipMemset(m->d_fallbacks, 0, sizeof(unsigned long long));
+    // kernel parameters
+    KParams& k = m->kp;
+    k.ne0 = g->desc.ne[0]; k.ne1 = g->desc.ne[1]; k.ne2 = g->desc.ne[2];
+    k.per0 = g->desc.periodic[0] != 0; k.per1 = g->desc.periodic[1] != 0; k.per2 = g->desc.periodic[2] != 0;
+    k.n_elem = (int)g->n_elem;
+    k.nn = nn;
+    k.lo0 = g->desc.lo[0]; k.lo1 = g->desc.lo[1]; k.lo2 = g->desc.lo[2];
+    k.h0 = g->h[0]; k.h1 = g->h[1]; k.h2 = g->h[2];
+    for (int q = 0; q < NQ; ++q) k.zgll[q] = 0.5 * (1.0 + g->xi[q]);
+    k.warped = g->desc.topo == 1;
+    k.metrics = desc->precision == CM_FP64 ? (const void*)g->d_metrics64 : (const void*)g->d_metrics32;
+    k.zn = g->d_z;
+    k.pr = m->d_pr; k.rhor = m->d_rhor;
+    k.ref_per_node = m->ref_per_node; k.has_ref = m->has_ref;
+    k.g = desc->g;
+    k.closure = desc->closure;
+    k.nu = desc->nu; k.Cs = desc->Cs; k.Prt = desc->Prt; k.Delta = m->Delta;
+    k.richardson = desc->richardson != 0;
+    k.f_cor = desc->f_cor; k.u_g = desc->u_g; k.v_g = desc->v_g;
+    k.sponge = desc->sponge != 0;
+    k.sp_zs = desc->sp_zs; k.sp_ztop = desc->sp_ztop; k.sp_alpha = desc->sp_alpha; k.sp_gamma = desc->sp_gamma;
+    k.sp_u0 = desc->sp_u[0]; k.sp_u1 = desc->sp_u[1]; k.sp_u2 = desc->sp_u[2];
+    k.sfc_flux = desc->sfc_flux != 0; k.theta_flux = desc->theta_flux; k.qt_flux = desc->qt_flux;
+    k.subsidence = desc->subsidence != 0; k.sub_w0 = desc->sub_w0; k.sub_ztop = desc->sub_ztop;
+    k.nf = m->nf;
+    k.mlp_w = nullptr; k.mlp_norm = nullptr; k.mlp_fallback_on = 1; k.mlp_fallbacks = m->d_fallbacks;
+    if (e == hipSuccess && Yref) {
+        // push the background through the device thermodynamics
+        const int64_t nref = m->ref_per_node ? nn : (int64_t)g->desc.ne[2] * NQ;
+        double* d_Yr = nullptr;
+        e = hipMalloc(&d_Yr, sizeof(double) * Yr.size());
+        if (e == hipSuccess) e = hipMemcpy(d_Yr, Yr.data(), sizeof(double) * Yr.size(), hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = launch_reference(m, d_Yr, nullptr);
+        if (e == hipSuccess) e = hipDeviceSynchronize();
+        if (d_Yr) (void)hipFree(d_Yr);
+        (void)nref;
+    }
+    if (e != hipSuccess) {
+        cm_status st = hip_fail(e, "cm_model_create");
+        cm_model_destroy(m);
+        return st;
+    }
+    *out = m;
+    return CM_OK;
+}
+
+static cm_status check_model(const cm_model* m, const char* where)
+{
+    if (!m) { set_error(std::string(where) + ": null model"); return CM_ERR_ARG; }
+    if (m->desc.closure == CM_CLOSURE_MLP && !m->mlp_ready) {
+        set_error(std::string(where) + ": learned closure selected but no weights set");
+        return CM_ERR_STATE;
+    }
+    return CM_OK;
+}
+
+cm_status cm_dg_rhs(cm_model* m, const void* Y, void* dYdt, double t, void* stream)
+{
+    (void)t;
+    cm_status st = check_model(m, "cm_dg_rhs");
+    if (st != CM_OK) return st;
+    if (!Y || !dYdt) { set_error("cm_dg_rhs: null state pointer"); return CM_ERR_ARG; }
+    if (Y == dYdt) { set_error("cm_dg_rhs: Y and dYdt must not alias"); return CM_ERR_ARG; }
+    CM_TRY_HIP(hipSetDevice(m->grid->device), "hipSetDevice");
+    hipStream_t s = (hipStream_t)stream;
+    CM_TRY_HIP(launch_rhs(m, Y, dYdt, nullptr, 0, 0.0, 0.0, 0.0, s), "cm_dg_rhs launch");
+    return CM_OK;
+}
+
+// Carpenter & Kennedy (1994) five-stage fourth-order 2N-storage coefficients
+static const double LSRK_A[5] = {0.0, -567301805773.0 / 1357537059087.0, -2404267990393.0 / 2016746695238.0,
+                                 -3550918686646.0 / 2091501179385.0, -1275806237668.0 / 842570457699.0};
+static const double LSRK_B[5] = {1432997174477.0 / 9575080441755.0, 5161836677717.0 / 13612068292357.0,
+                                 1720146321549.0 / 2090206949498.0, 3134564353537.0 / 4481467310338.0,
+                                 2277821191437.0 / 14882151754819.0};
+
+cm_status cm_lsrk_step(cm_model* m, void* Y, void* Y_alt, void* dQ, double t, double dt, void* stream)
+{
+    (void)t;
+    cm_status st = check_model(m, "cm_lsrk_step");
+    if (st != CM_OK) return st;
+    if (!Y || !Y_alt || !dQ) { set_error("cm_lsrk_step: null state pointer"); return CM_ERR_ARG; }
+    if (Y == Y_alt || Y == dQ || Y_alt == dQ) { set_error("cm_lsrk_step: Y, Y_alt, dQ must be distinct"); return CM_ERR_ARG; }
+    if (!(dt > 0.0) || !std::isfinite(dt)) { set_error("cm_lsrk_step: dt must be positive and finite"); return CM_ERR_ARG; }
+    CM_TRY_HIP(hipSetDevice(m->grid->device), "hipSetDevice");
+    hipStream_t s = (hipStream_t)stream;
+    void* src = Y;
+    void* dst = Y_alt;
+    for (int stage = 0; stage < 5; ++stage) {
+        CM_TRY_HIP(launch_rhs(m, src, dst, dQ, stage == 0 ? 2 : 1, LSRK_A[stage], LSRK_B[stage], dt, s),
+                   "cm_lsrk_step launch");
+        void* tmp = src;
+        src = dst;
+        dst = tmp;
+    }
+    return CM_OK;
+}
+
+cm_status cm_model_profile(cm_model* m, int enable)
+{
+    if (!m) { set_error("cm_model_profile: null model"); return CM_ERR_ARG; }
+    m->profiling = enable != 0;
+    m->prof_used = 0;
+    return CM_OK;
+}
+
+cm_status cm_model_profile_read(cm_model* m, double* ms, int64_t* count)
+{
+    if (!m || !ms || !count) { set_error("cm_model_profile_read: null argument"); return CM_ERR_ARG; }
+    ms[0] = ms[1] = 0.0;
+    count[0] = count[1] = 0;
+    for (size_t q = 0; q < m->prof_used; ++q) {
+        const cm_model::ProfRec& r = m->prof[q];
+        CM_TRY_HIP(hipEventSynchronize(r.b), "hipEventSynchronize");
+        float t = 0.0f;
+        CM_TRY_HIP(hipEventElapsedTime(&t, r.a, r.b), "hipEventElapsedTime");
+        ms[r.kind] += t;
+        count[r.kind] += 1;
+    }
+    return CM_OK;
+}
+
+cm_status cm_diagnostics(cm_model* m, const void* Y, double dt, cm_diag* out, void* stream)
+{
+    if (!m || !Y || !out) { set_error("cm_diagnostics: null argument"); return CM_ERR_ARG; }
+    CM_TRY_HIP(hipSetDevice(m->grid->device), "hipSetDevice");
+    CM_TRY_HIP(launch_diagnostics(m, Y, dt, out, (hipStream_t)stream), "cm_diagnostics");
+    if (out->n_nonfinite > 0) {
+        set_error("cm_diagnostics: state holds non-finite values");
+        return CM_ERR_NONFINITE;
+    }
+    return CM_OK;
+}
+
+}  // extern "C"

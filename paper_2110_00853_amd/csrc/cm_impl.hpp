@@ -1,0 +1,129 @@
+// Internal declarations of the gfx950 DG LES library (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/cm.h"
+
+namespace cm {
+
+constexpr int NQ = 5;            // GLL points per direction (N = 4)
+constexpr int NP = NQ * NQ * NQ; // nodes per element
+constexpr int BLOCK = 128;       // two wave64 per element
+
+// ---- thermodynamic constants: Table 1, and the readings g, p0,
+//      c_pd = c_vd + R_d, triple-point pressure of water --------------------
+struct Phys {
+    static constexpr double Rd = 287.0, Rv = 462.0;
+    static constexpr double cvd = 717.5, cvv = 1397.5, cvl = 4181.0;
+    static constexpr double T0 = 273.16;
+    static constexpr double Lv0 = 2.5008e6;
+    static constexpr double p0 = 1.0e5;
+    static constexpr double ptr = 611.657;
+    static constexpr double cpd = cvd + Rd;
+    static constexpr double cpv = cvv + Rv;
+    static constexpr double cpl = cvl;
+    static constexpr double Iv0 = Lv0 - Rv * T0;
+    static constexpr double kappa = Rd / cpd;
+};
+
+// Everything the kernels need, passed by value.
+struct KParams {
+    int ne0, ne1, ne2;
+    int per0, per1, per2;
+    int n_elem;
+    int64_t nn;                 // nodes
+    double lo0, lo1, lo2;
+    double h0, h1, h2;          // element extents (Cartesian metrics)
+    double zgll[NQ];            // (1 + xi_k)/2
+    int warped;
+    const void* metrics;        // warped: [10][nn] = J a^d_c (9), 1/J  (storage type)
+    const double* zn;           // warped: node heights [nn]
+    // reference state: either per level (flat, horizontally uniform) or per node
+    const double* pr;           // reference pressure
+    const double* rhor;         // reference density
+    int ref_per_node;
+    int has_ref;
+    // physics
+    double g;
+    int closure;
+    double nu, Cs, Prt, Delta;
+    int richardson;
+    double f_cor, u_g, v_g;
+    int sponge;
+    double sp_zs, sp_ztop, sp_alpha, sp_gamma, sp_u0, sp_u1, sp_u2;
+    int sfc_flux;
+    double theta_flux, qt_flux;
+    int subsidence;
+    double sub_w0, sub_ztop;
+    int nf;                     // words per node of the stored diffusive flux
+    // learned closure
+    const void* mlp_w;          // packed bf16 weights (device)
+    const float* mlp_norm;      // mean[12], std[12], lo[12], hi[12]
+    int mlp_fallback_on;
+    unsigned long long* mlp_fallbacks;
+};
+
+}  // namespace cm
+
+struct cm_grid {
+    int device = 0;
+    cm_grid_desc desc{};
+    int64_t n_elem = 0, n_nodes = 0;
+    double h[3] = {0, 0, 0};
+    double xi[cm::NQ], w[cm::NQ], D[cm::NQ * cm::NQ];
+    std::vector<double> xyz;     // host [3][nn]
+    std::vector<double> Ja, J;   // host [9][nn], [nn]
+    double* d_metrics64 = nullptr;  // warped only: [10][nn]
+    float* d_metrics32 = nullptr;
+    double* d_z = nullptr;          // warped only: node heights
+    double dmin = 0.0;
+};
+
+struct cm_model {
+    const cm_grid* grid = nullptr;
+    cm_model_desc desc{};
+    int nf = 0;
+    void* d_F2 = nullptr;        // [nf][nn] storage type
+    double* d_pr = nullptr;
+    double* d_rhor = nullptr;
+    int ref_per_node = 0;
+    int has_ref = 0;
+    double Delta = 0.0;
+    // diagnostics scratch
+    double* d_partials = nullptr;
+    int n_partials = 0;
+    // learned closure
+    void* d_mlp_w = nullptr;
+    float* d_mlp_norm = nullptr;
+    unsigned long long* d_fallbacks = nullptr;
+    int mlp_ready = 0;
+    cm::KParams kp{};
+    // optional per-launch event timing
+    struct ProfRec {
+        hipEvent_t a, b;
+        int kind;
+    };
+    std::vector<ProfRec> prof;
+    size_t prof_used = 0;
+    int profiling = 0;
+};
+
+namespace cm {
+void set_error(const std::string& msg);
+cm_status hip_fail(hipError_t e, const char* where);
+
+// kernel launchers (dg_kernels.hip)
+hipError_t launch_reference(const cm_model* m, const double* Yref_dev, hipStream_t s);
+hipError_t launch_rhs(cm_model* m, const void* Y, void* out, void* dQ, int mode, double A, double B,
+                      double dt, hipStream_t s);
+hipError_t upload_constants(const cm_grid* g);
+// event brackets around one launch when profiling is on
+cm_model::ProfRec* prof_begin(cm_model* m, int kind, hipStream_t s);
+void prof_end(cm_model::ProfRec* r, hipStream_t s);
+// reductions (reduce.hip)
+hipError_t launch_diagnostics(const cm_model* m, const void* Y, double dt, cm_diag* out, hipStream_t s);
+}  // namespace cm

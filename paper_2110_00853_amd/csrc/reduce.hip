@@ -1,0 +1,219 @@
+// Conservation and health diagnostics (Sect. 6: normalised mass and total
+// energy integrals).  Deterministic two-stage reduction: a fixed node->thread
+// assignment with Neumaier-compensated FP64 sums per thread, a fixed-order
+// tree per block, and one block combining the per-block partials in order.
+#include <cmath>
+
+#include "cm_impl.hpp"
+
+namespace cm {
+
+constexpr int RB = 256;      // threads per reduction block
+constexpr int NPART = 16;    // doubles per partial record
+
+struct Neu {
+    double s, c;
+};
+
+__device__ __forceinline__ void neu_add(Neu& a, double x)
+{
+    const double t = a.s + x;
+    if (fabs(a.s) >= fabs(x)) a.c += (a.s - t) + x;
+    else a.c += (x - t) + a.s;
+    a.s = t;
+}
+
+__device__ __forceinline__ void neu_merge(Neu& a, const Neu& b)
+{
+    neu_add(a, b.s);
+    a.c += b.c;
+}
+
+__device__ __forceinline__ double pvsat_d(double T)
+{
+    constexpr double dc = Phys::cpv - Phys::cpl;
+    return Phys::ptr * exp(dc / Phys::Rv * log(T / Phys::T0) +
+                           (Phys::Lv0 - dc * Phys::T0) / Phys::Rv * (1.0 / Phys::T0 - 1.0 / T));
+}
+
+// temperature and sound speed of one node (same thermodynamics as the RHS)
+template <bool MOIST>
+__device__ void temp_sound(double rho, double mx, double my, double mz, double re, double rq, double z, double g,
+                           double& T, double& c)
+{
+    const double ir = 1.0 / rho;
+    const double I = re * ir - 0.5 * (mx * mx + my * my + mz * mz) * ir * ir - g * z;
+    if (!MOIST) {
+        T = Phys::T0 + I / Phys::cvd;
+        c = sqrt(Phys::cpd / Phys::cvd * Phys::Rd * T);
+        return;
+    }
+    const double qt = rq * ir;
+    const double Tu = Phys::T0 + (I - qt * Phys::Iv0) / ((1.0 - qt) * Phys::cvd + qt * Phys::cvv);
+    double Tn = Tu;
+    if (qt > pvsat_d(Tu) / (rho * Phys::Rv * Tu)) {
+        for (int it = 0; it < 20; ++it) {
+            const double qv = pvsat_d(Tn) / (rho * Phys::Rv * Tn);
+            const double dT = Tn - Phys::T0;
+            const double f = (1.0 - qt) * Phys::cvd * dT + qv * (Phys::cvv * dT + Phys::Iv0) + (qt - qv) * Phys::cvl * dT - I;
+            const double Lv = Phys::Lv0 + (Phys::cpv - Phys::cpl) * dT;
+            const double dqv = qv * (Lv / (Phys::Rv * Tn * Tn) - 1.0 / Tn);
+            const double cvm = (1.0 - qt) * Phys::cvd + qv * Phys::cvv + (qt - qv) * Phys::cvl;
+            const double step = f / (cvm + dqv * (Phys::Iv0 + (Phys::cvv - Phys::cvl) * dT));
+            Tn -= step;
+            if (fabs(step) <= 1e-13 * Tn) break;
+        }
+    }
+    double qv = pvsat_d(Tn) / (rho * Phys::Rv * Tn);
+    qv = qv < qt ? qv : qt;
+    const double ql = qt - qv;
+    const double Rm = Phys::Rd * (1.0 - qt) + Phys::Rv * qv;
+    const double cvm = (1.0 - qt) * Phys::cvd + qv * Phys::cvv + ql * Phys::cvl;
+    T = Tn;
+    c = sqrt((cvm + Rm) / cvm * Rm * Tn);
+}
+
+struct DiagArgs {
+    int64_t nn;
+    int ne0, ne1;
+    double lo2, h2, zg[NQ];
+    double w[NQ];
+    double Jc;               // Cartesian Jacobian
+    const double* invJ;      // warped: per-node 1/J (FP64) or null
+    const double* zn;        // warped: node heights or null
+    double g, dt, dmin;
+};
+
+template <typename R, bool MOIST>
+__global__ __launch_bounds__(RB) void k_diag1(const DiagArgs A, const R* __restrict__ Y, double* __restrict__ part)
+{
+    constexpr int NV = MOIST ? 6 : 5;
+    Neu acc[4] = {{0, 0}, {0, 0}, {0, 0}, {0, 0}};
+    double maxw = 0.0, maxcfl = 0.0, Tmin = INFINITY, Tmax = -INFINITY, nonfin = 0.0;
+    const int64_t stride = (int64_t)gridDim.x * RB;
+    for (int64_t n = (int64_t)blockIdx.x * RB + threadIdx.x; n < A.nn; n += stride) {
+        double y[NV];
+        bool fin = true;
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            y[v] = (double)Y[v * A.nn + n];
+            if (!isfinite(y[v])) { nonfin += 1.0; fin = false; }
+        }
+        if (!fin) continue;
+        const int t = (int)(n % NP);
+        const int i = t % NQ, j = (t / NQ) % NQ, k = t / (NQ * NQ);
+        const int64_t e = n / NP;
+        const double J = A.invJ ? 1.0 / A.invJ[n] : A.Jc;
+        const double wJ = A.w[i] * A.w[j] * A.w[k] * J;
+        const double z = A.zn ? A.zn[n] : A.lo2 + ((double)(e / ((int64_t)A.ne0 * A.ne1)) + A.zg[k]) * A.h2;
+        neu_add(acc[0], wJ * y[0]);
+        neu_add(acc[1], wJ * y[4]);
+        if (MOIST) neu_add(acc[2], wJ * y[5]);
+        neu_add(acc[3], wJ * 0.5 * (y[1] * y[1] + y[2] * y[2] + y[3] * y[3]) / y[0]);
+        const double ir = 1.0 / y[0];
+        const double aw = fabs(y[3] * ir);
+        maxw = aw > maxw ? aw : maxw;
+        double T, c;
+        temp_sound<MOIST>(y[0], y[1], y[2], y[3], y[4], MOIST ? y[5] : 0.0, z, A.g, T, c);
+        Tmin = T < Tmin ? T : Tmin;
+        Tmax = T > Tmax ? T : Tmax;
+        if (A.dt > 0.0) {
+            const double sp = sqrt(y[1] * y[1] + y[2] * y[2] + y[3] * y[3]) * ir + c;
+            const double cfl = sp * A.dt / A.dmin;
+            maxcfl = cfl > maxcfl ? cfl : maxcfl;
+        }
+    }
+    __shared__ double sh[RB][NPART];
+    const int tid = threadIdx.x;
+    for (int q = 0; q < 4; ++q) { sh[tid][2 * q] = acc[q].s; sh[tid][2 * q + 1] = acc[q].c; }
+    sh[tid][8] = maxw; sh[tid][9] = maxcfl; sh[tid][10] = Tmin; sh[tid][11] = Tmax; sh[tid][12] = nonfin;
+    __syncthreads();
+    for (int off = RB / 2; off > 0; off >>= 1) {
+        if (tid < off) {
+            for (int q = 0; q < 4; ++q) {
+                Neu a = {sh[tid][2 * q], sh[tid][2 * q + 1]};
+                const Neu b = {sh[tid + off][2 * q], sh[tid + off][2 * q + 1]};
+                neu_merge(a, b);
+                sh[tid][2 * q] = a.s;
+                sh[tid][2 * q + 1] = a.c;
+            }
+            sh[tid][8] = fmax(sh[tid][8], sh[tid + off][8]);
+            sh[tid][9] = fmax(sh[tid][9], sh[tid + off][9]);
+            sh[tid][10] = fmin(sh[tid][10], sh[tid + off][10]);
+            sh[tid][11] = fmax(sh[tid][11], sh[tid + off][11]);
+            sh[tid][12] = sh[tid][12] + sh[tid + off][12];
+        }
+        __syncthreads();
+    }
+    if (tid < NPART) part[(int64_t)blockIdx.x * NPART + tid] = tid < 13 ? sh[0][tid] : 0.0;
+}
+
+// combine the per-block partials in block order (one thread, deterministic)
+__global__ void k_diag2(const double* __restrict__ part, int nblk, double* __restrict__ out)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    Neu acc[4] = {{0, 0}, {0, 0}, {0, 0}, {0, 0}};
+    double maxw = 0.0, maxcfl = 0.0, Tmin = INFINITY, Tmax = -INFINITY, nonfin = 0.0;
+    for (int b = 0; b < nblk; ++b) {
+        const double* p = part + (int64_t)b * NPART;
+        for (int q = 0; q < 4; ++q) neu_merge(acc[q], Neu{p[2 * q], p[2 * q + 1]});
+        maxw = fmax(maxw, p[8]);
+        maxcfl = fmax(maxcfl, p[9]);
+        Tmin = fmin(Tmin, p[10]);
+        Tmax = fmax(Tmax, p[11]);
+        nonfin += p[12];
+    }
+    for (int q = 0; q < 4; ++q) out[q] = acc[q].s + acc[q].c;
+    out[4] = maxw; out[5] = maxcfl; out[6] = Tmin; out[7] = Tmax; out[8] = nonfin;
+}
+
+hipError_t launch_diagnostics(const cm_model* m, const void* Y, double dt, cm_diag* outp, hipStream_t s)
+{
+    const cm_grid* g = m->grid;
+    DiagArgs A;
+    A.nn = g->n_nodes;
+    A.ne0 = g->desc.ne[0];
+    A.ne1 = g->desc.ne[1];
+    A.lo2 = g->desc.lo[2];
+    A.h2 = g->h[2];
+    for (int q = 0; q < NQ; ++q) { A.zg[q] = 0.5 * (1.0 + g->xi[q]); A.w[q] = g->w[q]; }
+    A.Jc = 0.125 * g->h[0] * g->h[1] * g->h[2];
+    A.invJ = g->d_metrics64 ? g->d_metrics64 + 9 * g->n_nodes : nullptr;
+    A.zn = g->d_z;
+    A.g = m->desc.g;
+    A.dt = dt;
+    A.dmin = g->dmin;
+    int nblk = (int)((A.nn + RB - 1) / RB);
+    if (nblk > m->n_partials - 1) nblk = m->n_partials - 1;
+    double* part = m->d_partials;
+    double* dout = m->d_partials + (int64_t)(m->n_partials - 1) * NPART;
+    const bool moist = m->desc.nvar == 6;
+    if (m->desc.precision == CM_FP64) {
+        if (moist) hipLaunchKernelGGL((k_diag1<double, true>), dim3(nblk), dim3(RB), 0, s, A, (const double*)Y, part);
+        else hipLaunchKernelGGL((k_diag1<double, false>), dim3(nblk), dim3(RB), 0, s, A, (const double*)Y, part);
+    } else {
+        if (moist) hipLaunchKernelGGL((k_diag1<float, true>), dim3(nblk), dim3(RB), 0, s, A, (const float*)Y, part);
+        else hipLaunchKernelGGL((k_diag1<float, false>), dim3(nblk), dim3(RB), 0, s, A, (const float*)Y, part);
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_diag2, dim3(1), dim3(64), 0, s, part, nblk, dout);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    double h[9];
+    e = hipMemcpyAsync(h, dout, sizeof(h), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return e;
+    outp->mass = h[0];
+    outp->energy = h[1];
+    outp->water = h[2];
+    outp->ke = h[3];
+    outp->max_abs_w = h[4];
+    outp->max_cfl = h[5];
+    outp->T_min = h[6];
+    outp->T_max = h[7];
+    outp->n_nonfinite = (int64_t)h[8];
+    return hipSuccess;
+}
+
+}  // namespace cm

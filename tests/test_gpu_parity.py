@@ -1,0 +1,196 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 CPU oracle on
+identical seeded inputs (tolerances: tendency 1e-11 relative per variable in
+the max norm, state after 100 LSRK54 steps 1e-9)."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2110_00853_amd import binding as B
+from paper_2110_00853_amd import workloads as W
+from parity import hmin, rhs_errors, state_errors
+
+pytestmark = pytest.mark.gpu
+
+RHS_TOL = 1e-11
+STEP_TOL = 1e-9
+
+
+def _small(name, ne, hi, **grid_kw):
+    c = W.case(name, ne=ne, hi=hi)
+    c["grid"].update(grid_kw)
+    return c
+
+
+SMALL_CASES = {
+    # the 4^3-element bubble itself (constant nu, walls in z)
+    "bubble_4": W.case("bubble_4"),
+    # Smagorinsky + Richardson on a ragged element count, 200 m elements
+    "smag_ragged": _small("bubble_32", (5, 3, 7), (1000.0, 600.0, 1400.0)),
+    # moist, surface fluxes, subsidence, Coriolis
+    "moist": _small("moist_64", (4, 4, 6), (400.0, 400.0, 3000.0)),
+    # warped terrain-following mesh with sponge
+    "warped": _small("agnesi_96", (6, 2, 5), (1500.0, 500.0, 1600.0), topo_a=300.0, topo_xc=750.0, topo_h=200.0),
+    # one element, periodic in every direction (its own neighbour), no gravity
+    "single_periodic": _small("bubble_32", (1, 1, 1), (200.0, 200.0, 200.0), periodic=[1, 1, 1]),
+    # inviscid (no gradient pass)
+    "inviscid": _small("bubble_4", (3, 2, 2), (1500.0, 1000.0, 1000.0)),
+}
+SMALL_CASES["single_periodic"]["model"]["g"] = 0.0
+SMALL_CASES["inviscid"]["model"]["closure"] = "none"
+
+
+def _state(c, seed=11):
+    if c.get("name") == "bubble_4" and c["grid"]["ne"] == [4, 4, 4]:
+        Y, Yref, _ = W.initial_state(c)
+        return Y, Yref
+    Y, Yref, _ = W.perturbed_state(c, seed=seed, amp_u=6.0, amp_T=2.0, amp_q=1.5e-3)
+    if c["model"].get("g", 9.81) == 0.0:
+        Yref = None
+    return Y, Yref
+
+
+@pytest.fixture(scope="module")
+def dev():
+    import torch
+
+    assert torch.cuda.is_available()
+    B.load()
+    return torch
+
+
+@pytest.mark.parametrize("name", list(SMALL_CASES))
+def test_grid_geometry_matches_oracle(dev, name):
+    c = SMALL_CASES[name]
+    g = B.Grid(c["grid"])
+    og = oracle.Grid(c["grid"])
+    assert np.allclose(g.coords(), og.coords(), rtol=0, atol=1e-9)
+    Ja, J = g.metrics()
+    oJa, oJ = og.metrics()
+    assert np.allclose(J, oJ, rtol=1e-12)
+    assert np.allclose(Ja, oJa, rtol=1e-12, atol=1e-12 * np.abs(oJa).max())
+    assert np.allclose(g.wJ(), og.wJ(), rtol=1e-12)
+
+
+@pytest.mark.parametrize("name", list(SMALL_CASES))
+def test_rhs_fp64_matches_oracle(dev, name):
+    c = SMALL_CASES[name]
+    Y, Yref = _state(c)
+    g = B.Grid(c["grid"])
+    m = B.Model(g, c["model"], Yref)
+    Yd = m.new_state(Y)
+    Rd = m.new_state()
+    m.rhs(Yd, Rd)
+    dev.cuda.synchronize()
+    Rg = Rd.cpu().numpy()
+    Rref = oracle.Model(oracle.Grid(c["grid"]), c["model"], Yref).rhs(Y)
+    err = rhs_errors(Rg, Rref, Y, hmin(c["grid"]))
+    print(name, "rhs errors per variable", err)
+    assert np.all(np.isfinite(Rg))
+    assert np.all(err < RHS_TOL), err
+
+
+@pytest.mark.parametrize("name", ["bubble_4", "moist", "warped"])
+def test_lsrk_step_matches_oracle(dev, name):
+    c = SMALL_CASES[name]
+    Y, Yref = _state(c)
+    _, _, speed = W.perturbed_state(c, seed=11, amp_u=6.0, amp_T=2.0, amp_q=1.5e-3)
+    dt = W.cfl_dt(c["grid"], speed)
+    g = B.Grid(c["grid"])
+    m = B.Model(g, c["model"], Yref)
+    Ya, Yb, dQ = m.new_state(Y), m.new_state(), m.new_state()
+    nsteps = 3
+    for _ in range(nsteps):
+        m.lsrk_step(Ya, Yb, dQ, 0.0, dt)
+        Ya, Yb = Yb, Ya
+    dev.cuda.synchronize()
+    Yg = Ya.cpu().numpy()
+    Yo, _ = oracle.Model(oracle.Grid(c["grid"]), c["model"], Yref).steps(Y, dt, nsteps)
+    err = state_errors(Yg, Yo)
+    print(name, "state errors after", nsteps, "steps", err)
+    assert np.all(err < 1e-10), err
+
+
+def test_bubble_4_hundred_steps(dev):
+    """The 4^3-element dry bubble: state after 100 LSRK54 steps within 1e-9."""
+    c = W.case("bubble_4")
+    Y, Yref, dt = W.initial_state(c)
+    g = B.Grid(c["grid"])
+    m = B.Model(g, c["model"], Yref)
+    Ya, Yb, dQ = m.new_state(Y), m.new_state(), m.new_state()
+    for _ in range(100):
+        m.lsrk_step(Ya, Yb, dQ, 0.0, dt)
+        Ya, Yb = Yb, Ya
+    dev.cuda.synchronize()
+    Yg = Ya.cpu().numpy()
+    Yo, _ = oracle.Model(oracle.Grid(c["grid"]), c["model"], Yref).steps(Y, dt, 100)
+    err = state_errors(Yg, Yo)
+    change = np.array([np.abs(Yo[v] - Y[v]).max() for v in range(5)])
+    print("100-step state errors", err, "relative to the change", err * np.abs(Yo).max(axis=1) / change)
+    assert np.all(err < STEP_TOL), err
+
+
+def test_diagnostics_match_oracle_integrals(dev):
+    c = SMALL_CASES["moist"]
+    Y, Yref = _state(c)
+    g = B.Grid(c["grid"])
+    m = B.Model(g, c["model"], Yref)
+    d = m.diagnostics(m.new_state(Y), dt=0.1)
+    ref = oracle.Model(oracle.Grid(c["grid"]), c["model"], Yref).integrals(Y)
+    assert d["mass"] == pytest.approx(ref[0], rel=1e-14)
+    assert d["energy"] == pytest.approx(ref[4], rel=1e-14)
+    assert d["water"] == pytest.approx(ref[5], rel=1e-14)
+    assert d["ke"] == pytest.approx(ref[6], rel=1e-13)
+    T, p, ql, thv = oracle.thermo_nodes(Y, oracle.Grid(c["grid"]).coords()[2], 9.81)
+    assert d["T_min"] == pytest.approx(T.min(), rel=1e-12)
+    assert d["T_max"] == pytest.approx(T.max(), rel=1e-12)
+    assert d["n_nonfinite"] == 0 and d["status"] == B.CM_OK
+
+
+def test_nonfinite_state_is_reported(dev):
+    c = SMALL_CASES["inviscid"]
+    Y, Yref = _state(c)
+    Y = Y.copy()
+    Y[4, 17] = np.nan
+    Y[2, 3] = np.inf
+    g = B.Grid(c["grid"])
+    m = B.Model(g, c["model"], Yref)
+    d = m.diagnostics(m.new_state(Y))
+    assert d["status"] == B.CM_ERR_NONFINITE and d["n_nonfinite"] == 2
+
+
+def test_conservation_on_gpu_closed_box(dev):
+    """Mass and total energy conserved to round-off over 50 steps on the GPU
+    (moist, walls in z, Smagorinsky + Richardson, no surface fluxes)."""
+    c = _small("moist_64", (3, 3, 4), (300.0, 300.0, 2000.0))
+    for key in ("sfc_flux", "subsidence"):
+        c["model"].pop(key, None)
+    Y, Yref, speed = W.perturbed_state(c, seed=3, amp_u=4.0, amp_T=1.0, amp_q=1e-3)
+    g = B.Grid(c["grid"])
+    m = B.Model(g, c["model"], Yref)
+    Ya, Yb, dQ = m.new_state(Y), m.new_state(), m.new_state()
+    d0 = m.diagnostics(Ya)
+    for _ in range(50):
+        m.lsrk_step(Ya, Yb, dQ, 0.0, W.cfl_dt(c["grid"], speed))
+        Ya, Yb = Yb, Ya
+    d1 = m.diagnostics(Ya)
+    for k in ("mass", "energy", "water"):
+        assert abs(d1[k] - d0[k]) / abs(d0[k]) < 1e-14, (k, d0[k], d1[k])
+    assert np.abs(Ya.cpu().numpy() - Y).max() > 1e-4
+
+
+def test_fp32_bulk_rhs_error_is_stated(dev):
+    """FP32-bulk tendency against the FP64 oracle: error stated, bounded."""
+    for name in ("smag_ragged", "moist", "warped"):
+        c = SMALL_CASES[name]
+        Y, Yref = _state(c)
+        g = B.Grid(c["grid"])
+        m = B.Model(g, c["model"], Yref, precision="fp32")
+        Yd = m.new_state(Y)
+        Rd = m.new_state()
+        m.rhs(Yd, Rd)
+        dev.cuda.synchronize()
+        Rg = Rd.cpu().numpy().astype(np.float64)
+        Rref = oracle.Model(oracle.Grid(c["grid"]), c["model"], Yref).rhs(Y)
+        err = rhs_errors(Rg, Rref, Y, hmin(c["grid"]))
+        print(name, "fp32-bulk rhs errors per variable", err)
+        assert np.all(np.isfinite(Rg)) and np.all(err < 5e-2), err
