@@ -84,7 +84,15 @@ def lib():
         L.cmref_model_create.restype = C.c_void_p
         L.cmref_model_destroy.argtypes = [C.c_void_p]
         L.cmref_model_reference.argtypes = [C.c_void_p, _P, _P]
-        L.cmref_model_set_mlp.argtypes = [C.c_void_p, _P, C.c_int, _P, _P, C.c_int]
+        L.cmref_model_set_mlp.argtypes = [C.c_void_p, _P, C.c_int, _P, _P, C.c_int, C.c_int]
+        L.cmref_mlp_nparams.restype = C.c_int
+        L.cmref_mlp_forward.argtypes = [_P, _P, C.c_int, _P]
+        L.cmref_mlp_forward_bf16.argtypes = [_P, _P, C.c_int, _P]
+        L.cmref_mlp_grad.argtypes = [_P, _P, _P, C.c_int, _P]
+        L.cmref_mlp_grad.restype = C.c_double
+        L.cmref_adam_step.argtypes = [_P, _P, _P, _P, C.c_int, C.c_double, C.c_double, C.c_double, C.c_double]
+        L.cmref_bf16.argtypes = [C.c_double]
+        L.cmref_bf16.restype = C.c_double
         L.cmref_model_mlp_fallbacks.argtypes = [C.c_void_p]
         L.cmref_model_mlp_fallbacks.restype = C.c_long
         L.cmref_rhs.argtypes = [C.c_void_p, _P, _P, C.c_double]
@@ -249,10 +257,14 @@ class Model:
         lib().cmref_integrals(self.h, Y, out)
         return out
 
-    def set_mlp(self, params: np.ndarray, lo: np.ndarray, hi: np.ndarray, use_fallback=True):
-        p = np.ascontiguousarray(params, dtype=np.float64)
+    def set_mlp(self, params: np.ndarray, mean: np.ndarray, std: np.ndarray, lo: np.ndarray,
+                hi: np.ndarray, use_fallback=True, bf16=False):
+        """Learned closure: network parameters, input mean/std and the
+        standardised training range; bf16 emulates the GPU's operand rounding."""
+        p = np.ascontiguousarray(np.concatenate([np.asarray(params, np.float64), np.asarray(mean, np.float64),
+                                                 np.asarray(std, np.float64)]))
         lib().cmref_model_set_mlp(self.h, p, p.size, np.ascontiguousarray(lo, dtype=np.float64),
-                                  np.ascontiguousarray(hi, dtype=np.float64), int(use_fallback))
+                                  np.ascontiguousarray(hi, dtype=np.float64), int(use_fallback), int(bf16))
         self._mlp = p
 
     def mlp_fallbacks(self) -> int:
@@ -300,6 +312,38 @@ def lsrk54_coeffs():
     A, B, Cc = np.zeros(5), np.zeros(5), np.zeros(5)
     lib().cmref_lsrk54_coeffs(A, B, Cc)
     return A, B, Cc
+
+
+NPARAM = 9282
+
+
+def mlp_forward(params, X, bf16=False):
+    """Raw outputs [n, 2] of the 12-64-64-64-2 SiLU network for standardised
+    inputs X [n, 12] (FP64, or with bfloat16 matrix operands)."""
+    p = np.ascontiguousarray(params, dtype=np.float64)
+    X = np.ascontiguousarray(X, dtype=np.float64)
+    out = np.zeros((X.shape[0], 2))
+    (lib().cmref_mlp_forward_bf16 if bf16 else lib().cmref_mlp_forward)(p, X.ravel(), X.shape[0], out.ravel())
+    return out
+
+
+def mlp_grad(params, X, T):
+    """Mean squared error of the raw outputs and its gradient (FP64)."""
+    p = np.ascontiguousarray(params, dtype=np.float64)
+    X = np.ascontiguousarray(X, dtype=np.float64)
+    T = np.ascontiguousarray(T, dtype=np.float64)
+    g = np.zeros(NPARAM)
+    loss = lib().cmref_mlp_grad(p, X.ravel(), T.ravel(), X.shape[0], g)
+    return loss, g
+
+
+def adam_step(params, grad, m, v, step, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
+    """One Adam update in place on float64 arrays."""
+    lib().cmref_adam_step(params, np.ascontiguousarray(grad, dtype=np.float64), m, v, int(step), lr, b1, b2, eps)
+
+
+def bf16(x: float) -> float:
+    return lib().cmref_bf16(float(x))
 
 
 def num_threads() -> int:

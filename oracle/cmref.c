@@ -423,6 +423,7 @@ typedef struct {
     double Delta;  /* filter width (dx dy dz)^(1/3), dx = h/N */
     /* learned closure parameters (FP64 copy), optional */
     double* mlp;
+    double* mlp_bf16;   /* bf16-rounded weights when the BF16 emulation is on */
     int mlp_n;
     double mlp_lo[12], mlp_hi[12];
     int mlp_use_fallback;
@@ -458,7 +459,7 @@ void cmref_model_destroy(void* h)
 {
     model_t* M = (model_t*)h;
     if (!M) return;
-    free(M->pr); free(M->rhor); free(M->mlp);
+    free(M->pr); free(M->rhor); free(M->mlp); free(M->mlp_bf16);
     free(M);
 }
 
@@ -470,17 +471,27 @@ void cmref_model_reference(void* h, double* pr, double* rhor)
 }
 
 /* learned closure hook, implemented in cmref_mlp.c */
-int cmref_mlp_closure(const double* params, const double* lo, const double* hi, int use_fallback,
-                      const double gu[3][3], double N2, double Delta, double nu_sl,
+int cmref_mlp_closure(const double* params, const double* Wb, const double* lo, const double* hi,
+                      int use_fallback, const double gu[3][3], double N2, double Delta, double nu_sl,
                       double* nu, double* Prt);
+void cmref_mlp_round_weights(const double* p, double* out);
+int cmref_mlp_nparams(void);
 
+/* params = [network, mean[12], std[12]]; bf16 != 0 evaluates the network
+ * with bfloat16 matrix operands (the GPU's rounding points) */
 void cmref_model_set_mlp(void* h, const double* params, int nparams,
-                         const double* lo, const double* hi, int use_fallback)
+                         const double* lo, const double* hi, int use_fallback, int bf16)
 {
     model_t* M = (model_t*)h;
     free(M->mlp);
+    free(M->mlp_bf16);
+    M->mlp_bf16 = NULL;
     M->mlp = (double*)malloc(sizeof(double) * nparams);
     memcpy(M->mlp, params, sizeof(double) * nparams);
+    if (bf16) {
+        M->mlp_bf16 = (double*)malloc(sizeof(double) * cmref_mlp_nparams());
+        cmref_mlp_round_weights(params, M->mlp_bf16);
+    }
     M->mlp_n = nparams;
     memcpy(M->mlp_lo, lo, sizeof(double) * 12);
     memcpy(M->mlp_hi, hi, sizeof(double) * 12);
@@ -616,7 +627,7 @@ static void diffusive_flux(model_t* M, work_t* W, gslots_t s)
             double nu_sl = cmref_smagorinsky(gu, N2, m->Cs, M->Delta, m->Prt, m->richardson);
             if (M->mlp) {
                 double nn_, pp_;
-                int fb = cmref_mlp_closure(M->mlp, M->mlp_lo, M->mlp_hi, M->mlp_use_fallback,
+                int fb = cmref_mlp_closure(M->mlp, M->mlp_bf16, M->mlp_lo, M->mlp_hi, M->mlp_use_fallback,
                                            (const double (*)[3])gu, N2, M->Delta, nu_sl, &nn_, &pp_);
                 if (fb) { nu = nu_sl; Prt = m->Prt; fallbacks++; }
                 else { nu = nn_; Prt = pp_; }

@@ -1,0 +1,108 @@
+"""Pins of the learned-closure reference network (oracle): forward pass on
+hand-built weights with a closed form, back-propagated gradient against
+central finite differences, bfloat16 rounding on known values, Adam's first
+step, and the closure's output mapping and fallback rule."""
+import numpy as np
+import pytest
+
+NI, NH, NO = 12, 64, 2
+
+
+def offsets():
+    o = {}
+    k = 0
+    for name, size in (("W1", NH * NI), ("b1", NH), ("W2", NH * NH), ("b2", NH), ("W3", NH * NH), ("b3", NH),
+                       ("W4", NO * NH), ("b4", NO)):
+        o[name] = (k, size)
+        k += size
+    assert k == 9282
+    return o
+
+
+def silu(x):
+    return x / (1 + np.exp(-x))
+
+
+def test_forward_closed_form_chain(oracle_lib):
+    """A single active path input0 -> h1_0 -> h2_0 -> h3_0 -> o_0 with unit
+    weights gives o_0 = silu(silu(silu(x0))) + b4_0 and o_1 = b4_1."""
+    O = offsets()
+    p = np.zeros(9282)
+    p[O["W1"][0] + 0 * NI + 0] = 1.0
+    p[O["W2"][0] + 0] = 1.0
+    p[O["W3"][0] + 0] = 1.0
+    p[O["W4"][0] + 0] = 1.0
+    p[O["b4"][0] + 0] = 0.25
+    p[O["b4"][0] + 1] = -0.5
+    X = np.zeros((3, NI))
+    X[:, 0] = [-2.0, 0.3, 4.0]
+    out = oracle_lib.mlp_forward(p, X)
+    exp0 = silu(silu(silu(X[:, 0]))) + 0.25
+    assert np.allclose(out[:, 0], exp0, rtol=1e-15, atol=1e-15)
+    assert np.allclose(out[:, 1], -0.5)
+
+
+def _random_params(seed):
+    rng = np.random.default_rng(seed)
+    O = offsets()
+    p = np.zeros(9282)
+    for name, fan in (("W1", NI), ("W2", NH), ("W3", NH), ("W4", NH)):
+        a, n = O[name]
+        p[a:a + n] = rng.uniform(-1, 1, n) / np.sqrt(fan)
+    for name in ("b1", "b2", "b3", "b4"):
+        a, n = O[name]
+        p[a:a + n] = rng.uniform(-0.1, 0.1, n)
+    return p
+
+
+def test_gradient_matches_finite_differences(oracle_lib):
+    rng = np.random.default_rng(1)
+    p = _random_params(2)
+    X = rng.normal(size=(7, NI))
+    T = rng.normal(size=(7, NO))
+    loss, g = oracle_lib.mlp_grad(p, X, T)
+    idx = np.concatenate([rng.choice(9282, 60, replace=False), [0, 767, 768, 9279, 9280, 9281]])
+    for q in idx:
+        h = 1e-6
+        pp, pm = p.copy(), p.copy()
+        pp[q] += h
+        pm[q] -= h
+        lp, _ = oracle_lib.mlp_grad(pp, X, T)
+        lm, _ = oracle_lib.mlp_grad(pm, X, T)
+        fd = (lp - lm) / (2 * h)
+        assert g[q] == pytest.approx(fd, rel=1e-6, abs=1e-9), q
+    # the loss is the mean over samples of the summed squared output error
+    o = oracle_lib.mlp_forward(p, X)
+    assert loss == pytest.approx(np.sum((o - T) ** 2) / 7, rel=1e-13)
+
+
+def test_bf16_round_to_nearest_even(oracle_lib):
+    b = oracle_lib.bf16
+    assert b(1.0) == 1.0
+    assert b(1.0 + 2.0 ** -8) == 1.0                     # tie -> even (mantissa ...0)
+    assert b(1.0 + 3 * 2.0 ** -8) == 1.0 + 2.0 ** -6      # tie -> even (rounds up)
+    assert b(1.0 + 2.0 ** -8 + 2.0 ** -12) == 1.0 + 2.0 ** -7
+    assert b(-3.14159) == -3.140625
+    assert b(65504.0) == 65536.0
+    assert b(1e-3) == pytest.approx(1e-3, rel=2 ** -8)
+
+
+def test_bf16_forward_close_to_fp64(oracle_lib):
+    rng = np.random.default_rng(3)
+    p = _random_params(4)
+    X = rng.normal(size=(256, NI))
+    a = oracle_lib.mlp_forward(p, X)
+    b = oracle_lib.mlp_forward(p, X, bf16=True)
+    rel = np.abs(a - b).max() / np.abs(a).max()
+    assert 1e-5 < rel < 5e-2
+
+
+def test_adam_first_step_moves_by_lr(oracle_lib):
+    """With bias correction the first Adam step is lr * g / (|g| + eps)."""
+    p = np.linspace(-1, 1, 9282)
+    g = np.where(np.arange(9282) % 2, 0.3, -2e-3)
+    m = np.zeros(9282)
+    v = np.zeros(9282)
+    p0 = p.copy()
+    oracle_lib.adam_step(p, g, m, v, 1, lr=1e-3)
+    assert np.allclose(p0 - p, 1e-3 * g / (np.abs(g) + 1e-8), rtol=1e-12)
