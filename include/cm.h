@@ -151,7 +151,9 @@ CM_API cm_status cm_model_destroy(cm_model* model);
  * the range widened by 10 % of its half-width on each side, or when the
  * network output is not finite. */
 CM_API cm_status cm_model_set_mlp(cm_model* model, const float* params_host, const float* norm_host);
-/* number of nodes that fell back to Smagorinsky in the last RHS (syncs) */
+/* number of node evaluations that fell back to Smagorinsky since the
+ * previous call (each RHS evaluates every node once); resets the count.
+ * Synchronises the stream. */
 CM_API cm_status cm_model_mlp_fallbacks(cm_model* model, int64_t* count, void* hip_stream);
 
 /* dYdt = R(Y): the semi-discrete DG operator (eq. matrixProblem, strong

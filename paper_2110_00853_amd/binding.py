@@ -293,3 +293,66 @@ class Model:
         c = C.c_int64()
         _check(load().cm_model_mlp_fallbacks(self.h, C.byref(c), _stream_ptr(stream)))
         return c.value
+
+
+class MLP:
+    """Learned-closure network (cm_mlp_*): 12-64-64-64-2 SiLU, BF16 MFMA
+    forward/backward with FP32 accumulation, FP32 master weights, Adam."""
+
+    NPARAM = 9282
+
+    def __init__(self, seed: int = 0, lr: float = 1e-3, beta1: float = 0.9, beta2: float = 0.999,
+                 eps: float = 1e-8, device: int = 0):
+        d = MLPDesc()
+        d.n_in, d.n_hidden, d.n_layers_hidden, d.n_out = 12, 64, 3, 2
+        d.lr, d.beta1, d.beta2, d.eps = lr, beta1, beta2, eps
+        h = _VP()
+        _check(load().cm_mlp_create(C.byref(d), int(seed), device, C.byref(h)))
+        self.h = h
+        self.device = device
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.cm_mlp_destroy(self.h)
+            self.h = None
+
+    @staticmethod
+    def _chk(t, cols):
+        if not t.is_cuda or t.dtype.itemsize != 4 or t.dim() != 2 or t.shape[1] != cols or not t.is_contiguous():
+            raise ValueError("expected a contiguous float32 CUDA tensor [batch, %d]" % cols)
+
+    def params(self) -> np.ndarray:
+        out = np.zeros(self.NPARAM, dtype=np.float32)
+        _check(load().cm_mlp_get_params(self.h, _np_ptr(out)))
+        return out
+
+    def set_params(self, p: np.ndarray):
+        p = np.ascontiguousarray(p, dtype=np.float32)
+        if p.size != self.NPARAM:
+            raise ValueError("need 9282 parameters")
+        _check(load().cm_mlp_set_params(self.h, _np_ptr(p)))
+
+    def infer(self, X, out=None, stream=None):
+        import torch
+
+        self._chk(X, 12)
+        if out is None:
+            out = torch.empty((X.shape[0], 2), dtype=torch.float32, device=X.device)
+        self._chk(out, 2)
+        _check(load().cm_mlp_infer(self.h, X.data_ptr(), out.data_ptr(), X.shape[0], _stream_ptr(stream)))
+        return out
+
+    def grads(self, X, T, stream=None) -> np.ndarray:
+        self._chk(X, 12)
+        self._chk(T, 2)
+        g = np.zeros(self.NPARAM, dtype=np.float32)
+        _check(load().cm_mlp_grads(self.h, X.data_ptr(), T.data_ptr(), X.shape[0], _np_ptr(g), _stream_ptr(stream)))
+        return g
+
+    def train_step(self, X, T, want_loss: bool = True, stream=None):
+        self._chk(X, 12)
+        self._chk(T, 2)
+        loss = C.c_float(0.0)
+        _check(load().cm_mlp_train_step(self.h, X.data_ptr(), T.data_ptr(), X.shape[0],
+                                         C.byref(loss) if want_loss else None, _stream_ptr(stream)))
+        return float(loss.value) if want_loss else None

@@ -353,6 +353,16 @@ cm_status cm_model_create(const cm_grid* g, const cm_model_desc* desc, const dou
         e = hipMalloc(&m->d_pr, sizeof(double) * nref);
         if (e == hipSuccess) e = hipMalloc(&m->d_rhor, sizeof(double) * nref);
     }
+    if (e == hipSuccess && !Yref) {
+        // no background: p_r = rho_r = 0 (per-level zeros, so the kernels
+        // read the reference unconditionally)
+        m->ref_per_node = 0;
+        const size_t nref = (size_t)g->desc.ne[2] * NQ;
+        e = hipMalloc(&m->d_pr, sizeof(double) * nref);
+        if (e == hipSuccess) e = hipMalloc(&m->d_rhor, sizeof(double) * nref);
+        if (e == hipSuccess) e = hipMemset(m->d_pr, 0, sizeof(double) * nref);
+        if (e == hipSuccess) e = hipMemset(m->d_rhor, 0, sizeof(double) * nref);
+    }
     if (e == hipSuccess) {
         m->n_partials = 2048;
         e = hipMalloc(&m->d_partials, sizeof(double) * 16 * m->n_partials);
@@ -367,6 +377,8 @@ cm_status cm_model_create(const cm_grid* g, const cm_model_desc* desc, const dou
     k.nn = nn;
     k.lo0 = g->desc.lo[0]; k.lo1 = g->desc.lo[1]; k.lo2 = g->desc.lo[2];
     k.h0 = g->h[0]; k.h1 = g->h[1]; k.h2 = g->h[2];
+    k.r2h0 = 2.0 / g->h[0]; k.r2h1 = 2.0 / g->h[1]; k.r2h2 = 2.0 / g->h[2];
+    k.lift0 = 2.0 / (g->h[0] * g->w[4]); k.lift1 = 2.0 / (g->h[1] * g->w[4]); k.lift2 = 2.0 / (g->h[2] * g->w[4]);
     for (int q = 0; q < NQ; ++q) k.zgll[q] = 0.5 * (1.0 + g->xi[q]);
     k.warped = g->desc.topo == 1;
     k.metrics = desc->precision == CM_FP64 ? (const void*)g->d_metrics64 : (const void*)g->d_metrics32;
@@ -376,15 +388,19 @@ cm_status cm_model_create(const cm_grid* g, const cm_model_desc* desc, const dou
     k.g = desc->g;
     k.closure = desc->closure;
     k.nu = desc->nu; k.Cs = desc->Cs; k.Prt = desc->Prt; k.Delta = m->Delta;
+    k.invPrt = desc->Prt > 0.0 ? 1.0 / desc->Prt : 0.0;
     k.richardson = desc->richardson != 0;
     k.f_cor = desc->f_cor; k.u_g = desc->u_g; k.v_g = desc->v_g;
     k.sponge = desc->sponge != 0;
     k.sp_zs = desc->sp_zs; k.sp_ztop = desc->sp_ztop; k.sp_alpha = desc->sp_alpha; k.sp_gamma = desc->sp_gamma;
     k.sp_u0 = desc->sp_u[0]; k.sp_u1 = desc->sp_u[1]; k.sp_u2 = desc->sp_u[2];
+    k.sp_inv = desc->sponge ? 1.0 / (desc->sp_ztop - desc->sp_zs) : 0.0;
     k.sfc_flux = desc->sfc_flux != 0; k.theta_flux = desc->theta_flux; k.qt_flux = desc->qt_flux;
     k.subsidence = desc->subsidence != 0; k.sub_w0 = desc->sub_w0; k.sub_ztop = desc->sub_ztop;
+    k.sub_inv = desc->subsidence ? 1.0 / desc->sub_ztop : 0.0;
     k.nf = m->nf;
-    k.mlp_w = nullptr; k.mlp_norm = nullptr; k.mlp_fallback_on = 1; k.mlp_fallbacks = m->d_fallbacks;
+    k.mlp_frag = nullptr; k.mlp_bias = nullptr; k.mlp_norm = nullptr;
+    k.mlp_fallback_on = 1; k.mlp_fallbacks = m->d_fallbacks;
     if (e == hipSuccess && Yref) {
         // push the background through the device thermodynamics
         const int64_t nref = m->ref_per_node ? nn : (int64_t)g->desc.ne[2] * NQ;

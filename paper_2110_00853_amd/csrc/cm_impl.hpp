@@ -38,6 +38,8 @@ struct KParams {
     int64_t nn;                 // nodes
     double lo0, lo1, lo2;
     double h0, h1, h2;          // element extents (Cartesian metrics)
+    double r2h0, r2h1, r2h2;    // 2 / h_d
+    double lift0, lift1, lift2; // 2 / (h_d w_N): J^s / (J w_N) on flat meshes
     double zgll[NQ];            // (1 + xi_k)/2
     int warped;
     const void* metrics;        // warped: [10][nn] = J a^d_c (9), 1/J  (storage type)
@@ -50,19 +52,20 @@ struct KParams {
     // physics
     double g;
     int closure;
-    double nu, Cs, Prt, Delta;
+    double nu, Cs, Prt, invPrt, Delta;
     int richardson;
     double f_cor, u_g, v_g;
     int sponge;
-    double sp_zs, sp_ztop, sp_alpha, sp_gamma, sp_u0, sp_u1, sp_u2;
+    double sp_zs, sp_ztop, sp_alpha, sp_gamma, sp_u0, sp_u1, sp_u2, sp_inv;
     int sfc_flux;
     double theta_flux, qt_flux;
     int subsidence;
-    double sub_w0, sub_ztop;
+    double sub_w0, sub_ztop, sub_inv;
     int nf;                     // words per node of the stored diffusive flux
     // learned closure
-    const void* mlp_w;          // packed bf16 weights (device)
-    const float* mlp_norm;      // mean[12], std[12], lo[12], hi[12]
+    const uint16_t* mlp_frag;   // bf16 B fragments of the four layers
+    const float* mlp_bias;      // biases: 64, 64, 64, 2 (padded to 16)
+    const double* mlp_norm;     // mean[12], std[12], lo[12], hi[12]
     int mlp_fallback_on;
     unsigned long long* mlp_fallbacks;
 };
@@ -98,7 +101,7 @@ struct cm_model {
     int n_partials = 0;
     // learned closure
     void* d_mlp_w = nullptr;
-    float* d_mlp_norm = nullptr;
+    double* d_mlp_norm = nullptr;
     unsigned long long* d_fallbacks = nullptr;
     int mlp_ready = 0;
     cm::KParams kp{};

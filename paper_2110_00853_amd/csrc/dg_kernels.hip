@@ -18,6 +18,7 @@
 #include <cmath>
 
 #include "cm_impl.hpp"
+#include "mlp_common.hpp"
 
 namespace cm {
 
@@ -40,6 +41,35 @@ template <> __device__ __forceinline__ float dmat<float>(int r, int c) { return 
 // GLL end weight w_N = 1/10
 constexpr double WN = 0.1;
 
+// FP64 reciprocal and square root from the hardware estimates refined by
+// Newton-Raphson (reciprocal) and Goldschmidt (square root) steps: within an
+// ulp or two of the correctly rounded results, at a third of the
+// instructions of the IEEE sequences.  Arguments are positive and finite.
+__device__ __forceinline__ double frcp(double x)
+{
+    double r = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-x, r, 1.0);
+    return fma(r, e, r);
+}
+__device__ __forceinline__ float frcp(float x) { return 1.0f / x; }
+
+__device__ __forceinline__ double fsqrt(double x)
+{
+    const double y = __builtin_amdgcn_rsq(x);
+    double g = x * y, h = 0.5 * y;
+    double r = fma(-g, h, 0.5);
+    g = fma(g, r, g);
+    h = fma(h, r, h);
+    r = fma(-g, h, 0.5);
+    g = fma(g, r, g);
+    h = fma(h, r, h);
+    const double d = fma(-g, g, x);
+    return fma(d, h, g);
+}
+__device__ __forceinline__ float fsqrt(float x) { return sqrtf(x); }
+
 // ---------------------------------------------------------------------------
 // block -> element: blocks are dealt round-robin to the eight XCDs; give each
 // XCD one contiguous run of elements so neighbours share its L2.
@@ -51,19 +81,22 @@ __device__ __forceinline__ int elem_of_block(int b, int n)
     return b;
 }
 
-__device__ __forceinline__ int nbr_elem(const KParams& P, int ex, int ey, int ez, int dir, int side)
+// neighbour element across face (dir, side), -1 at a wall; ezn receives the
+// neighbour's layer index (no integer division per lane)
+__device__ __forceinline__ int nbr_elem(const KParams& P, int ex, int ey, int ez, int dir, int side, int& ezn)
 {
     int c0 = ex, c1 = ey, c2 = ez;
     if (dir == 0) {
         c0 += side;
-        if (c0 < 0 || c0 >= P.ne0) { if (!P.per0) return -1; c0 = (c0 + P.ne0) % P.ne0; }
+        if (c0 < 0 || c0 >= P.ne0) { if (!P.per0) return -1; c0 = c0 < 0 ? P.ne0 - 1 : 0; }
     } else if (dir == 1) {
         c1 += side;
-        if (c1 < 0 || c1 >= P.ne1) { if (!P.per1) return -1; c1 = (c1 + P.ne1) % P.ne1; }
+        if (c1 < 0 || c1 >= P.ne1) { if (!P.per1) return -1; c1 = c1 < 0 ? P.ne1 - 1 : 0; }
     } else {
         c2 += side;
-        if (c2 < 0 || c2 >= P.ne2) { if (!P.per2) return -1; c2 = (c2 + P.ne2) % P.ne2; }
+        if (c2 < 0 || c2 >= P.ne2) { if (!P.per2) return -1; c2 = c2 < 0 ? P.ne2 - 1 : 0; }
     }
+    ezn = c2;
     return c0 + P.ne0 * (c1 + P.ne1 * c2);
 }
 
@@ -90,31 +123,33 @@ __device__ __forceinline__ double pvsat(double T)
     // Clausius-Clapeyron integrated with constant heat capacities:
     // p* = p_tr (T/T0)^((c_pv-c_pl)/R_v) exp((L_v0-(c_pv-c_pl)T0)/R_v (1/T0 - 1/T))
     constexpr double dc = Phys::cpv - Phys::cpl;
-    return Phys::ptr * exp(dc / Phys::Rv * log(T / Phys::T0) +
-                           (Phys::Lv0 - dc * Phys::T0) / Phys::Rv * (1.0 / Phys::T0 - 1.0 / T));
+    return Phys::ptr * exp(dc / Phys::Rv * log(T * (1.0 / Phys::T0)) +
+                           (Phys::Lv0 - dc * Phys::T0) / Phys::Rv * (1.0 / Phys::T0 - frcp(T)));
 }
 
 // Saturation adjustment: T from (rho, q_t, I) by Newton iteration with the
 // analytic derivative dI*/dT; unsaturated air returns T_u directly.
 __device__ __forceinline__ void saturation_adjust(double rho, double qt, double I, double& T, double& ql)
 {
-    const double Tu = Phys::T0 + (I - qt * Phys::Iv0) / ((1.0 - qt) * Phys::cvd + qt * Phys::cvv);
-    const double qvs_u = pvsat(Tu) / (rho * Phys::Rv * Tu);
+    const double Tu = Phys::T0 + (I - qt * Phys::Iv0) * frcp((1.0 - qt) * Phys::cvd + qt * Phys::cvv);
+    const double irv = frcp(rho * Phys::Rv);
+    const double qvs_u = pvsat(Tu) * irv * frcp(Tu);
     if (qt <= qvs_u) { T = Tu; ql = 0.0; return; }
     double Tn = Tu;
     for (int it = 0; it < 20; ++it) {
-        const double qv = pvsat(Tn) / (rho * Phys::Rv * Tn);
+        const double iT = frcp(Tn);
+        const double qv = pvsat(Tn) * irv * iT;
         const double dT = Tn - Phys::T0;
         const double f = (1.0 - qt) * Phys::cvd * dT + qv * (Phys::cvv * dT + Phys::Iv0) + (qt - qv) * Phys::cvl * dT - I;
         const double Lv = Phys::Lv0 + (Phys::cpv - Phys::cpl) * dT;
-        const double dqv = qv * (Lv / (Phys::Rv * Tn * Tn) - 1.0 / Tn);
+        const double dqv = qv * (Lv * (1.0 / Phys::Rv) * iT * iT - iT);
         const double cvm = (1.0 - qt) * Phys::cvd + qv * Phys::cvv + (qt - qv) * Phys::cvl;
         const double fp = cvm + dqv * (Phys::Iv0 + (Phys::cvv - Phys::cvl) * dT);
-        const double step = f / fp;
+        const double step = f * frcp(fp);
         Tn -= step;
         if (fabs(step) <= 1e-13 * Tn) break;
     }
-    double qv = pvsat(Tn) / (rho * Phys::Rv * Tn);
+    double qv = pvsat(Tn) * irv * frcp(Tn);
     qv = qv < qt ? qv : qt;
     T = Tn;
     ql = qt - qv;
@@ -124,7 +159,7 @@ template <bool MOIST>
 __device__ __forceinline__ void thermo(double rho, double mx, double my, double mz, double re, double rq, double z,
                                        double g, Th& o)
 {
-    const double ir = 1.0 / rho;
+    const double ir = frcp(rho);
     o.rho = rho;
     o.u = mx * ir; o.v = my * ir; o.w = mz * ir;
     o.e = re * ir;
@@ -136,13 +171,13 @@ __device__ __forceinline__ void thermo(double rho, double mx, double my, double 
         o.Rm = Phys::Rd * (1.0 - o.qt) + Phys::Rv * o.qv;
         const double cvm = (1.0 - o.qt) * Phys::cvd + o.qv * Phys::cvv + o.ql * Phys::cvl;
         o.p = rho * o.Rm * o.T;
-        o.c = sqrt((cvm + o.Rm) / cvm * o.Rm * o.T);
+        o.c = fsqrt((cvm + o.Rm) * frcp(cvm) * o.Rm * o.T);
     } else {
         o.qt = 0.0; o.ql = 0.0; o.qv = 0.0;
         o.T = Phys::T0 + I * (1.0 / Phys::cvd);
         o.Rm = Phys::Rd;
         o.p = rho * Phys::Rd * o.T;
-        o.c = sqrt(Phys::cpd / Phys::cvd * Phys::Rd * o.T);
+        o.c = fsqrt(Phys::cpd / Phys::cvd * Phys::Rd * o.T);
     }
     o.h = o.e + o.p * ir;
 }
@@ -150,7 +185,7 @@ __device__ __forceinline__ void thermo(double rho, double mx, double my, double 
 // virtual potential temperature theta_v = T (p0/p)^(R_d/c_pd) R_m/R_d
 __device__ __forceinline__ double theta_v(const Th& o)
 {
-    return o.T * exp(Phys::kappa * log(Phys::p0 / o.p)) * (o.Rm / Phys::Rd);
+    return o.T * exp(Phys::kappa * log(Phys::p0 * frcp(o.p))) * (o.Rm * (1.0 / Phys::Rd));
 }
 
 // ---------------------------------------------------------------------------
@@ -190,44 +225,6 @@ hipError_t launch_reference(const cm_model* m, const double* Yr, hipStream_t s)
 }
 
 // ---------------------------------------------------------------------------
-// metric helpers
-// ---------------------------------------------------------------------------
-template <typename R>
-struct Metric {
-    R Ja[3][3];
-    R invJ;
-};
-
-template <typename R, bool WARP>
-__device__ __forceinline__ void load_metric(const KParams& P, int64_t node, Metric<R>& M)
-{
-    if (WARP) {
-        const R* m = (const R*)P.metrics;
-#pragma unroll
-        for (int q = 0; q < 9; ++q) M.Ja[q / 3][q % 3] = m[(int64_t)q * P.nn + node];
-        M.invJ = m[9 * P.nn + node];
-    }
-}
-
-// face normal, |J^s| and lift factor J^s/(J w_N) at a node of face (dir, side)
-template <typename R, bool WARP>
-__device__ __forceinline__ void face_geom(const KParams& P, const Metric<R>& M, int dir, int side, R n[3], R& lift)
-{
-    if (WARP) {
-        const R a0 = M.Ja[dir][0], a1 = M.Ja[dir][1], a2 = M.Ja[dir][2];
-        const R Js = sqrt(a0 * a0 + a1 * a1 + a2 * a2);
-        const R inv = (R)side / Js;
-        n[0] = a0 * inv; n[1] = a1 * inv; n[2] = a2 * inv;
-        lift = Js * M.invJ * (R)(1.0 / WN);
-    } else {
-        n[0] = n[1] = n[2] = (R)0;
-        n[dir] = (R)side;
-        const double h = dir == 0 ? P.h0 : (dir == 1 ? P.h1 : P.h2);
-        lift = (R)(2.0 / (h * WN));
-    }
-}
-
-// ---------------------------------------------------------------------------
 // Smagorinsky-Lilly with the Richardson stability factor (eq. smago,
 // eq. richardson), |S|^2 = 2 S_ij S_ij
 // ---------------------------------------------------------------------------
@@ -242,27 +239,211 @@ __device__ __forceinline__ R smagorinsky(const KParams& P, const R S[3][3], R N2
     if (!(SS > (R)0)) return (R)0;
     R fb = (R)1;
     if (P.richardson) {
-        const R Ri = N2 / SS;
+        const R Ri = N2 * frcp(SS);
         if (Ri > (R)0) {
-            R a = (R)1 - Ri / (R)P.Prt;
+            R a = (R)1 - Ri * (R)P.invPrt;
             a = a > (R)0 ? a : (R)0;
-            fb = sqrt(sqrt(a));
+            fb = a > (R)0 ? fsqrt(fsqrt(a)) : (R)0;
         }
     }
     const R cd = (R)(P.Cs * P.Delta);
-    return cd * cd * sqrt(SS) * fb;
+    return cd * cd * fsqrt(SS) * fb;
+}
+
+// ---------------------------------------------------------------------------
+// face-node tasks: the 6 x 25 face nodes of an element are spread over the
+// block's lanes (150 tasks on 128 lanes), so face work runs on dense lanes
+// instead of masked passes over the owners.  Task -> (direction, side, own
+// node, mirrored node in the neighbour).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void face_task(int task, int& dir, int& sd, int& own, int& nbr)
+{
+    dir = task / 50;
+    const int r = task - 50 * dir;
+    sd = r / 25;
+    const int f = r - 25 * sd;
+    const int a = f % NQ, b = f / NQ;
+    const int c = sd ? NQ - 1 : 0, cn = sd ? 0 : NQ - 1;
+    if (dir == 0) { own = c + NQ * (a + NQ * b); nbr = cn + NQ * (a + NQ * b); }
+    else if (dir == 1) { own = a + NQ * (c + NQ * b); nbr = a + NQ * (cn + NQ * b); }
+    else { own = a + NQ * (b + NQ * c); nbr = a + NQ * (b + NQ * cn); }
+}
+
+// unit normal (side * J a^dir / |J a^dir|) and lift factor J^s / (J w_N)
+template <typename R, bool WARP>
+__device__ __forceinline__ void face_normal(const KParams& P, int64_t node, int dir, int side, R n[3], R& lift)
+{
+    if (WARP) {
+        const R* m = (const R*)P.metrics;
+        const R a0 = m[(int64_t)(3 * dir + 0) * P.nn + node];
+        const R a1 = m[(int64_t)(3 * dir + 1) * P.nn + node];
+        const R a2 = m[(int64_t)(3 * dir + 2) * P.nn + node];
+        const R invJ = m[9 * P.nn + node];
+        const R Js = fsqrt(a0 * a0 + a1 * a1 + a2 * a2);
+        const R s = (R)side * frcp(Js);
+        n[0] = a0 * s; n[1] = a1 * s; n[2] = a2 * s;
+        lift = Js * invJ * (R)(1.0 / WN);
+    } else {
+        n[0] = dir == 0 ? (R)side : (R)0;
+        n[1] = dir == 1 ? (R)side : (R)0;
+        n[2] = dir == 2 ? (R)side : (R)0;
+        lift = (R)(dir == 0 ? P.lift0 : (dir == 1 ? P.lift1 : P.lift2));
+    }
+}
+
+// ---------------------------------------------------------------------------
+// learned closure: fused BF16-MFMA forward of the 12-64-64-64-2 SiLU network
+// for the 128 rows (nodes) of one element.  Wave w owns rows 64w..64w+63
+// (four 16-row tiles).  Inputs sX [128][20] and activations sH [128][68]
+// are bf16 in LDS (rows padded against bank conflicts); the B operands are
+// the pre-packed weight fragments; outputs sO [128][2] FP32.
+// ---------------------------------------------------------------------------
+constexpr int MLP_XS = 20, MLP_HS = 68;
+
+__device__ __forceinline__ void mlp_layer_epilogue(const f32x4 (&acc)[4][4], const float* __restrict__ bias,
+                                                   uint16_t (*sH)[MLP_HS], int row0, int lane)
+{
+    const int r = lane & 15, kq = (lane >> 4) * 4;
+#pragma unroll
+    for (int rt = 0; rt < 4; ++rt)
+#pragma unroll
+        for (int ct = 0; ct < 4; ++ct) {
+            const float b = bias[16 * ct + r];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) sH[row0 + 16 * rt + kq + q][16 * ct + r] = f2bf(silu_f(acc[rt][ct][q] + b));
+        }
+}
+
+__device__ void mlp_forward_element(const KParams& P, uint16_t (*sX)[MLP_XS], uint16_t (*sH)[MLP_HS],
+                                    float (*sO)[2])
+{
+    const int lane = threadIdx.x & 63, row0 = (threadIdx.x >> 6) * 64;
+    const int r = lane & 15, kq = (lane >> 4) * 4;
+    const bf16x4* frag = (const bf16x4*)P.mlp_frag;
+    f32x4 acc[4][4];
+    // layer 1: K = 16 (12 inputs, zero padded)
+#pragma unroll
+    for (int ct = 0; ct < 4; ++ct) {
+        const bf16x4 b = frag[(0 * 4 + ct) * 64 + lane];
+#pragma unroll
+        for (int rt = 0; rt < 4; ++rt) {
+            const bf16x4 a = *(const bf16x4*)&sX[row0 + 16 * rt + r][kq];
+            acc[rt][ct] = mfma16(a, b, f32x4{0.0f, 0.0f, 0.0f, 0.0f});
+        }
+    }
+    __syncthreads();
+    mlp_layer_epilogue(acc, P.mlp_bias, sH, row0, lane);
+    __syncthreads();
+    // layers 2 and 3: K = 64
+#pragma unroll 1
+    for (int layer = 0; layer < 2; ++layer) {
+        const int fbase = FRAG_L1 + layer * FRAG_L2;
+#pragma unroll
+        for (int rt = 0; rt < 4; ++rt)
+#pragma unroll
+            for (int ct = 0; ct < 4; ++ct) acc[rt][ct] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks) {
+            bf16x4 a[4];
+#pragma unroll
+            for (int rt = 0; rt < 4; ++rt) a[rt] = *(const bf16x4*)&sH[row0 + 16 * rt + r][16 * ks + kq];
+#pragma unroll
+            for (int ct = 0; ct < 4; ++ct) {
+                const bf16x4 b = frag[(fbase + ks * 4 + ct) * 64 + lane];
+#pragma unroll
+                for (int rt = 0; rt < 4; ++rt) acc[rt][ct] = mfma16(a[rt], b, acc[rt][ct]);
+            }
+        }
+        __syncthreads();
+        mlp_layer_epilogue(acc, P.mlp_bias + 64 * (layer + 1), sH, row0, lane);
+        __syncthreads();
+    }
+    // layer 4: N = 2 (one 16-column tile, zero padded)
+    f32x4 o[4];
+#pragma unroll
+    for (int rt = 0; rt < 4; ++rt) o[rt] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+    const int f4 = FRAG_L1 + FRAG_L2 + FRAG_L3;
+#pragma unroll
+    for (int ks = 0; ks < 4; ++ks) {
+        const bf16x4 b = frag[(f4 + ks) * 64 + lane];
+#pragma unroll
+        for (int rt = 0; rt < 4; ++rt) {
+            const bf16x4 a = *(const bf16x4*)&sH[row0 + 16 * rt + r][16 * ks + kq];
+            o[rt] = mfma16(a, b, o[rt]);
+        }
+    }
+    if (r < 2) {
+        const float b = P.mlp_bias[192 + r];
+#pragma unroll
+        for (int rt = 0; rt < 4; ++rt)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) sO[row0 + 16 * rt + kq + q][r] = o[rt][q] + b;
+    }
+    __syncthreads();
+}
+
+__device__ __forceinline__ double softplus_d(double x) { return x > 30.0 ? x : log1p(exp(x)); }
+
+// neighbour state of one gradient face task
+template <typename R, bool MOIST>
+struct GradLoad {
+    int dir, sd, own, nbl, en, ezn;
+    R Yp[MOIST ? 6 : 5];
+};
+
+template <typename R, bool MOIST>
+__device__ __forceinline__ void grad_load(const KParams& P, const R* __restrict__ Y, int task, int e, int ex, int ey,
+                                          int ez, GradLoad<R, MOIST>& f)
+{
+    face_task(task, f.dir, f.sd, f.own, f.nbl);
+    f.en = nbr_elem(P, ex, ey, ez, f.dir, f.sd ? 1 : -1, f.ezn);
+    const int64_t np = (int64_t)(f.en >= 0 ? f.en : e) * NP + f.nbl;
+#pragma unroll
+    for (int v = 0; v < (MOIST ? 6 : 5); ++v) f.Yp[v] = Y[v * P.nn + np];
+}
+
+// lift * (g* - g^-) of one face task into sJ[dir][q][own]
+template <typename R, bool MOIST, bool WARP>
+__device__ __forceinline__ void grad_face(const KParams& P, const GradLoad<R, MOIST>& f, int e, bool need_thv,
+                                          R (*sg)[BLOCK], R (*sJ)[MOIST ? 6 : 5][BLOCK])
+{
+    constexpr int NG = MOIST ? 6 : 5;
+    constexpr int GQ = 4, GT = MOIST ? 5 : 4;
+    R jump[NG];
+    if (f.en >= 0) {
+        Th tp;
+        thermo<MOIST>((double)f.Yp[0], (double)f.Yp[1], (double)f.Yp[2], (double)f.Yp[3], (double)f.Yp[4],
+                      MOIST ? (double)f.Yp[5] : 0.0, node_z(P, f.en, f.ezn, f.nbl / (NQ * NQ), f.nbl), P.g, tp);
+        R gp[NG];
+        gp[0] = (R)tp.u; gp[1] = (R)tp.v; gp[2] = (R)tp.w; gp[3] = (R)tp.h;
+        if (MOIST) gp[GQ] = (R)tp.qt;
+        gp[GT] = need_thv ? (R)theta_v(tp) : (R)0;
+        R n[3], lift;
+        face_normal<R, WARP>(P, (int64_t)e * NP + f.own, f.dir, f.sd ? 1 : -1, n, lift);
+#pragma unroll
+        for (int q = 0; q < NG; ++q) {
+            const R gm = sg[q][f.own];
+            jump[q] = lift * ((R)0.5 * (gm + gp[q]) - gm);
+        }
+    } else {
+#pragma unroll
+        for (int q = 0; q < NG; ++q) jump[q] = (R)0;
+    }
+#pragma unroll
+    for (int q = 0; q < NG; ++q) sJ[f.dir][q][f.own] = jump[q];
 }
 
 // ---------------------------------------------------------------------------
 // gradient + closure pass
 // ---------------------------------------------------------------------------
-template <typename R, bool MOIST, bool WARP>
+template <typename R, bool MOIST, bool WARP, bool MLP>
 __global__ __launch_bounds__(BLOCK) void k_grad(const KParams P, const R* __restrict__ Y, R* __restrict__ F2)
 {
     constexpr int NV = MOIST ? 6 : 5;
     constexpr int NG = MOIST ? 6 : 5;  // u v w h [qt] thv
     constexpr int GQ = 4, GT = MOIST ? 5 : 4;
-    __shared__ R sg[NG][BLOCK];
+    __shared__ R sg[NG][BLOCK];        // gradient variables of the element
+    __shared__ R sJ[3][NG][BLOCK];     // lift * (g* - g^-) per face direction
 
     const int e = elem_of_block(blockIdx.x, P.n_elem);
     const int t = threadIdx.x;
@@ -271,27 +452,64 @@ __global__ __launch_bounds__(BLOCK) void k_grad(const KParams P, const R* __rest
     const int i = tt % NQ, j = (tt / NQ) % NQ, k = tt / (NQ * NQ);
     const int ex = e % P.ne0, ey = (e / P.ne0) % P.ne1, ez = e / (P.ne0 * P.ne1);
     const int64_t nn = P.nn;
-    const int64_t node = (int64_t)e * NP + tt;
-    const bool need_thv = (P.closure == CM_CLOSURE_SMAG && P.richardson) || P.closure == CM_CLOSURE_MLP;
+    const int64_t ebase = (int64_t)e * NP;
+    const int64_t node = ebase + tt;
+    const bool need_thv = (P.closure == CM_CLOSURE_SMAG && P.richardson) || MLP;
 
-    double Yv[NV];
-#pragma unroll
-    for (int v = 0; v < NV; ++v) Yv[v] = (double)Y[v * nn + node];
-    const double z = node_z(P, e, ez, k, tt);
+    GradLoad<R, MOIST> g0;
+    grad_load<R, MOIST>(P, Y, t, e, ex, ey, ez, g0);
+
+    // phase A: thermodynamics and gradient variables into LDS
     Th th;
-    thermo<MOIST>(Yv[0], Yv[1], Yv[2], Yv[3], Yv[4], MOIST ? Yv[5] : 0.0, z, P.g, th);
-    R gm[NG];
-    gm[0] = (R)th.u; gm[1] = (R)th.v; gm[2] = (R)th.w; gm[3] = (R)th.h;
-    if (MOIST) gm[GQ] = (R)th.qt;
-    gm[GT] = need_thv ? (R)theta_v(th) : (R)0;
+    {
+        double Yv[NV];
 #pragma unroll
-    for (int q = 0; q < NG; ++q) sg[q][t] = gm[q];
+        for (int v = 0; v < NV; ++v) Yv[v] = (double)Y[v * nn + node];
+        thermo<MOIST>(Yv[0], Yv[1], Yv[2], Yv[3], Yv[4], MOIST ? Yv[5] : 0.0, node_z(P, e, ez, k, tt), P.g, th);
+    }
+    sg[0][t] = (R)th.u; sg[1][t] = (R)th.v; sg[2][t] = (R)th.w; sg[3][t] = (R)th.h;
+    if (MOIST) sg[GQ][t] = (R)th.qt;
+    sg[GT][t] = need_thv ? (R)theta_v(th) : (R)0;
     __syncthreads();
 
-    Metric<R> M;
-    load_metric<R, WARP>(P, node, M);
-    R gr[NG][3];
+    // phase B: face tasks -> lift * (g* - g^-), centred g* (walls: 0); the
+    // first task's neighbour state was loaded at kernel entry
+    grad_face<R, MOIST, WARP>(P, g0, e, need_thv, sg, sJ);
+    if (t + BLOCK < 150) {
+        GradLoad<R, MOIST> g1;
+        grad_load<R, MOIST>(P, Y, t + BLOCK, e, ex, ey, ez, g1);
+        grad_face<R, MOIST, WARP>(P, g1, e, need_thv, sg, sJ);
+    }
+    __syncthreads();
+
+    // phase C: per gradient variable, volume derivative by the 1-D GLL matrix
+    // along each direction, chain rule, plus the lifts of the faces this node
+    // lies on; the physical gradient replaces this node's lift entries in
+    // LDS (sJ[c][q][t] = d g_q / d x_c), which only this lane touches now
+    R Ja[3][3], invJ = (R)0;
+    if (WARP) {
+        const R* m = (const R*)P.metrics;
 #pragma unroll
+        for (int q = 0; q < 9; ++q) Ja[q / 3][q % 3] = m[(int64_t)q * nn + node];
+        invJ = m[9 * nn + node];
+    }
+    const int idx[3] = {i, j, k};
+    R nrm[3][3];
+#pragma unroll
+    for (int dir = 0; dir < 3; ++dir) {
+        const R side = idx[dir] == 0 ? (R)-1 : (R)1;
+        if (WARP) {
+            const R Js = fsqrt(Ja[dir][0] * Ja[dir][0] + Ja[dir][1] * Ja[dir][1] + Ja[dir][2] * Ja[dir][2]);
+            const R s = side * frcp(Js);
+            nrm[dir][0] = Ja[dir][0] * s; nrm[dir][1] = Ja[dir][1] * s; nrm[dir][2] = Ja[dir][2] * s;
+        } else {
+            nrm[dir][0] = dir == 0 ? side : (R)0;
+            nrm[dir][1] = dir == 1 ? side : (R)0;
+            nrm[dir][2] = dir == 2 ? side : (R)0;
+        }
+    }
+    const bool onf[3] = {i == 0 || i == NQ - 1, j == 0 || j == NQ - 1, k == 0 || k == NQ - 1};
+#pragma unroll 1
     for (int q = 0; q < NG; ++q) {
         R d0 = 0, d1 = 0, d2 = 0;
 #pragma unroll
@@ -300,51 +518,30 @@ __global__ __launch_bounds__(BLOCK) void k_grad(const KParams P, const R* __rest
             d1 += dmat<R>(j, l) * sg[q][i + NQ * (l + NQ * k)];
             d2 += dmat<R>(k, l) * sg[q][i + NQ * (j + NQ * l)];
         }
+        R gc[3];
         if (WARP) {
 #pragma unroll
-            for (int c = 0; c < 3; ++c) gr[q][c] = M.invJ * (M.Ja[0][c] * d0 + M.Ja[1][c] * d1 + M.Ja[2][c] * d2);
+            for (int c = 0; c < 3; ++c) gc[c] = invJ * (Ja[0][c] * d0 + Ja[1][c] * d1 + Ja[2][c] * d2);
         } else {
-            gr[q][0] = (R)(2.0 / P.h0) * d0;
-            gr[q][1] = (R)(2.0 / P.h1) * d1;
-            gr[q][2] = (R)(2.0 / P.h2) * d2;
+            gc[0] = (R)P.r2h0 * d0;
+            gc[1] = (R)P.r2h1 * d1;
+            gc[2] = (R)P.r2h2 * d2;
         }
-    }
-
-    // centred BR1 lifts on faces with a neighbour (walls: g* = g^-)
-    const int idx[3] = {i, j, k};
 #pragma unroll
-    for (int dir = 0; dir < 3; ++dir) {
+        for (int dir = 0; dir < 3; ++dir) {
+            if (!onf[dir]) continue;
+            const R jv = sJ[dir][q][t];
 #pragma unroll
-        for (int sd = 0; sd < 2; ++sd) {
-            const int side = sd ? 1 : -1;
-            if (idx[dir] != (sd ? NQ - 1 : 0)) continue;
-            const int en = nbr_elem(P, ex, ey, ez, dir, side);
-            if (en < 0) continue;
-            int m3[3] = {i, j, k};
-            m3[dir] = sd ? 0 : NQ - 1;
-            const int tn = m3[0] + NQ * (m3[1] + NQ * m3[2]);
-            const int64_t np = (int64_t)en * NP + tn;
-            double Yp[NV];
-#pragma unroll
-            for (int v = 0; v < NV; ++v) Yp[v] = (double)Y[v * nn + np];
-            const int ezn = en / (P.ne0 * P.ne1);
-            const double zp = node_z(P, en, ezn, m3[2], tn);
-            Th tp;
-            thermo<MOIST>(Yp[0], Yp[1], Yp[2], Yp[3], Yp[4], MOIST ? Yp[5] : 0.0, zp, P.g, tp);
-            R gp[NG];
-            gp[0] = (R)tp.u; gp[1] = (R)tp.v; gp[2] = (R)tp.w; gp[3] = (R)tp.h;
-            if (MOIST) gp[GQ] = (R)tp.qt;
-            gp[GT] = need_thv ? (R)theta_v(tp) : (R)0;
-            R n[3], lift;
-            face_geom<R, WARP>(P, M, dir, side, n, lift);
-#pragma unroll
-            for (int q = 0; q < NG; ++q) {
-                const R jump = (R)0.5 * (gm[q] + gp[q]) - gm[q];
-#pragma unroll
-                for (int c = 0; c < 3; ++c) gr[q][c] += lift * jump * n[c];
-            }
+            for (int c = 0; c < 3; ++c) gc[c] += jv * nrm[dir][c];
         }
+#pragma unroll
+        for (int c = 0; c < 3; ++c) sJ[c][q][t] = gc[c];
     }
+    R gr[4][3];   // velocity gradient and grad h_tot
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) gr[q][c] = sJ[c][q][t];
 
     // closure and diffusive flux
     R S[3][3];
@@ -356,29 +553,73 @@ __global__ __launch_bounds__(BLOCK) void k_grad(const KParams P, const R* __rest
     if (P.closure == CM_CLOSURE_CONST) {
         nu = (R)P.nu;
     } else if (P.closure == CM_CLOSURE_SMAG || P.closure == CM_CLOSURE_MLP) {
-        const R N2 = P.richardson ? (R)P.g / gm[GT] * gr[GT][2] : (R)0;
+        const R N2 = P.richardson || MLP ? (R)P.g * frcp(sg[GT][t]) * sJ[2][GT][t] : (R)0;
         nu = smagorinsky<R>(P, S, N2);
+        if (MLP) {
+            // learned closure: standardised inputs (velocity gradient, N^2,
+            // filter width, TKE estimate (nu_SL / (0.1 Delta))^2), fused
+            // network on the element's nodes, Smagorinsky fallback
+            __shared__ uint16_t sX[BLOCK][MLP_XS];
+            __shared__ uint16_t sH[BLOCK][MLP_HS];
+            __shared__ float sO[BLOCK][2];
+            double raw[12];
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+#pragma unroll
+                for (int b = 0; b < 3; ++b) raw[3 * a + b] = (double)gr[a][b];
+            raw[9] = (double)N2;
+            raw[10] = P.Delta;
+            const double kk = (double)nu / (0.1 * P.Delta);
+            raw[11] = kk * kk;
+            bool out_of_range = false;
+#pragma unroll
+            for (int q = 0; q < 12; ++q) {
+                const double x = (raw[q] - P.mlp_norm[q]) / P.mlp_norm[12 + q];
+                const double c = 0.5 * (P.mlp_norm[24 + q] + P.mlp_norm[36 + q]);
+                const double hw = 0.5 * (P.mlp_norm[36 + q] - P.mlp_norm[24 + q]);
+                if (fabs(x - c) > 1.1 * hw) out_of_range = true;
+                sX[t][q] = f2bf((float)x);
+            }
+#pragma unroll
+            for (int q = 12; q < MLP_XS; ++q) sX[t][q] = 0;
+            __syncthreads();
+            mlp_forward_element(P, sX, sH, sO);
+            double SSd = 0.0;
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+#pragma unroll
+                for (int b = 0; b < 3; ++b) SSd += 2.0 * (double)S[a][b] * (double)S[a][b];
+            const double nu_m = P.Delta * P.Delta * sqrt(SSd) * softplus_d((double)sO[t][0]);
+            const double pr_m = 0.1 + softplus_d((double)sO[t][1]);
+            const bool fb = P.mlp_fallback_on && (out_of_range || !isfinite(nu_m) || !isfinite(pr_m));
+            if (!fb) {
+                nu = (R)nu_m;
+                Prt = (R)pr_m;
+            }
+            const unsigned long long nfb = __popcll(__ballot(fb && act));
+            if ((threadIdx.x & 63) == 0 && nfb) atomicAdd(P.mlp_fallbacks, nfb);
+        }
     }
     const R rho = (R)th.rho;
-    const R Dt = nu / Prt;
+    const R Dt = MLP ? nu * frcp(Prt) : nu * (R)P.invPrt;
     const R c2 = (R)(-2.0) * rho * nu;
     R w[14] = {};
     w[0] = c2 * S[0][0]; w[1] = c2 * S[1][1]; w[2] = c2 * S[2][2];
     w[3] = c2 * S[0][1]; w[4] = c2 * S[0][2]; w[5] = c2 * S[1][2];
-    const R u0 = gm[0], u1 = gm[1], u2 = gm[2];
+    const R u0 = (R)th.u, u1 = (R)th.v, u2 = (R)th.w;
     const R rDt = rho * Dt;
     w[6] = u0 * w[0] + u1 * w[3] + u2 * w[4] - rDt * gr[3][0];
     w[7] = u0 * w[3] + u1 * w[1] + u2 * w[5] - rDt * gr[3][1];
     w[8] = u0 * w[4] + u1 * w[5] + u2 * w[2] - rDt * gr[3][2];
     if (MOIST) {
-        w[9] = -rDt * gr[GQ][0];
-        w[10] = -rDt * gr[GQ][1];
-        w[11] = -rDt * gr[GQ][2];
+        w[9] = -rDt * sJ[0][GQ][t];
+        w[10] = -rDt * sJ[1][GQ][t];
+        w[11] = -rDt * sJ[2][GQ][t];
     }
     // subsidence needs d/dz of h_tot (and q_t) in the tendency pass
     constexpr int SB = MOIST ? 12 : 9;
     w[SB] = gr[3][2];
-    if (MOIST) w[SB + 1] = gr[GQ][2];
+    if (MOIST) w[SB + 1] = sJ[2][GQ][t];
     const int nw = SB + (P.subsidence ? (MOIST ? 2 : 1) : 0);
     if (act) {
 #pragma unroll
@@ -412,6 +653,20 @@ __device__ __forceinline__ void flux1(const Th& o, double pr, R F[][3])
     F[3][2] += pp;
 }
 
+// normal inviscid flux n.F1 from primitive quantities
+template <typename R, bool MOIST>
+__device__ __forceinline__ void flux1_normal(R rho, const R u[3], R pp, R ep, R rq, const R n[3], R out[])
+{
+    const R un = u[0] * n[0] + u[1] * n[1] + u[2] * n[2];
+    const R m = rho * un;
+    out[0] = m;
+    out[1] = m * u[0] + pp * n[0];
+    out[2] = m * u[1] + pp * n[1];
+    out[3] = m * u[2] + pp * n[2];
+    out[4] = ep * un;
+    if (MOIST) out[5] = rq * un;
+}
+
 // normal component of the stored diffusive flux
 template <typename R, bool MOIST>
 __device__ __forceinline__ void f2_normal(const R* w, const R u[3], const R n[3], R out[])
@@ -429,13 +684,144 @@ __device__ __forceinline__ void f2_normal(const R* w, const R u[3], const R n[3]
     }
 }
 
+// data of one face task: own face node state, neighbour state and
+// diffusive flux (loaded before they are needed)
+template <typename R, bool MOIST, bool VISC>
+struct FaceLoad {
+    static constexpr int NV = MOIST ? 6 : 5;
+    static constexpr int NW = MOIST ? 12 : 9;
+    int dir, sd, own, nbl, en, ezn;
+    R Ym[NV], Yp[NV], wp[VISC ? NW : 1];
+    double prp;
+};
+
+template <typename R, bool MOIST, bool VISC>
+__device__ __forceinline__ void face_load(const KParams& P, const R* __restrict__ Y, const R* __restrict__ F2,
+                                          int task, int e, int ex, int ey, int ez, FaceLoad<R, MOIST, VISC>& f)
+{
+    constexpr int NV = FaceLoad<R, MOIST, VISC>::NV;
+    constexpr int NW = FaceLoad<R, MOIST, VISC>::NW;
+    face_task(task, f.dir, f.sd, f.own, f.nbl);
+    f.en = nbr_elem(P, ex, ey, ez, f.dir, f.sd ? 1 : -1, f.ezn);
+    const int eo = f.en >= 0 ? f.en : e;  // walls read their own node twice
+    const int ezo = f.en >= 0 ? f.ezn : ez;
+    const int64_t nn = P.nn;
+    const int64_t onode = (int64_t)e * NP + f.own;
+    const int64_t np = (int64_t)eo * NP + f.nbl;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) f.Ym[v] = Y[v * nn + onode];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) f.Yp[v] = Y[v * nn + np];
+    if (VISC) {
+#pragma unroll
+        for (int q = 0; q < NW; ++q) f.wp[q] = F2[q * nn + np];
+    }
+    f.prp = P.pr[ref_index(P, eo, ezo, f.nbl / (NQ * NQ), f.nbl)];
+}
+
+// numerical flux of one face task; writes lift (n.F^- - n.F^*) over the
+// task's own-node entries of sG (the divergence is already done)
+template <typename R, bool MOIST, bool WARP, bool VISC>
+__device__ __forceinline__ void face_flux(const KParams& P, const FaceLoad<R, MOIST, VISC>& f, int e, int ex, int ey,
+                                          int ez, R (*sG)[BLOCK], R (*sP)[BLOCK])
+{
+    constexpr int NV = MOIST ? 6 : 5;
+    const int64_t nn = P.nn;
+    const int dir = f.dir, sd = f.sd, own = f.own, nbl = f.nbl, en = f.en;
+    const int side = sd ? 1 : -1;
+    const int64_t onode = (int64_t)e * NP + own;
+    R n[3], lift;
+    face_normal<R, WARP>(P, onode, dir, side, n, lift);
+    const R cJ = WARP ? ((const R*)P.metrics)[9 * nn + onode] * (R)(1.0 / WN) : (R)(1.0 / WN);
+    const R um[3] = {sP[0][own], sP[1][own], sP[2][own]};
+    const R cm = sP[3][own];
+    const R unm = um[0] * n[0] + um[1] * n[1] + um[2] * n[2];
+    R liftFm[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) liftFm[v] = (R)side * sG[v * 3 + dir][own] * cJ;
+    R contrib[NV];
+    if (en >= 0) {
+        const int ezn = f.ezn;
+        const int kn = nbl / (NQ * NQ);
+        Th tp;
+        thermo<MOIST>((double)f.Yp[0], (double)f.Yp[1], (double)f.Yp[2], (double)f.Yp[3], (double)f.Yp[4],
+                      MOIST ? (double)f.Yp[NV - 1] : 0.0, node_z(P, en, ezn, kn, nbl), P.g, tp);
+        const R up[3] = {(R)tp.u, (R)tp.v, (R)tp.w};
+        R fp[NV];
+        flux1_normal<R, MOIST>((R)tp.rho, up, (R)(tp.p - f.prp), (R)(tp.rho * tp.e + tp.p), (R)(tp.rho * tp.qt), n,
+                               fp);
+        if (VISC) {
+            R fp2[NV];
+            f2_normal<R, MOIST>(f.wp, up, n, fp2);
+#pragma unroll
+            for (int v = 0; v < NV; ++v) fp[v] += fp2[v];
+        }
+        const R unp = up[0] * n[0] + up[1] * n[1] + up[2] * n[2];
+        const R lm = fabs(unm) + cm, lp = fabs(unp) + (R)tp.c;
+        const R lam = lm > lp ? lm : lp;
+#pragma unroll
+        for (int v = 0; v < NV; ++v)
+            contrib[v] = (R)0.5 * (liftFm[v] - lift * fp[v]) - (R)0.5 * lift * lam * (f.Ym[v] - f.Yp[v]);
+    } else {
+        // reflecting ghost u+ = u- - 2 (n.u-) n with rho, rho e, rho q
+        // mirrored: the Rusanov flux of (Y-, ghost) plus the prescribed wall
+        // diffusive flux
+        Th tm;
+        const int ko = own / (NQ * NQ);
+        thermo<MOIST>((double)f.Ym[0], (double)f.Ym[1], (double)f.Ym[2], (double)f.Ym[3], (double)f.Ym[4],
+                      MOIST ? (double)f.Ym[NV - 1] : 0.0, node_z(P, e, ez, ko, own), P.g, tm);
+        const R rho = f.Ym[0];
+        // on a wall the "neighbour" slot holds this element's mirrored node,
+        // whose reference pressure is not this node's: read this node's
+        const double pro = P.pr[ref_index(P, e, ez, ko, own)];
+        const R pp = (R)(tm.p - pro), ep = (R)(tm.rho * tm.e + tm.p);
+        const R rq = MOIST ? f.Ym[NV - 1] : (R)0;
+        const R ug[3] = {um[0] - (R)2 * unm * n[0], um[1] - (R)2 * unm * n[1], um[2] - (R)2 * unm * n[2]};
+        R f1m[NV], f1g[NV];
+        flux1_normal<R, MOIST>(rho, um, pp, ep, rq, n, f1m);
+        flux1_normal<R, MOIST>(rho, ug, pp, ep, rq, n, f1g);
+        const R lam = fabs(unm) + cm;
+        R jumpY[NV];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) jumpY[v] = (R)0;
+        const R mn = f.Ym[1] * n[0] + f.Ym[2] * n[1] + f.Ym[3] * n[2];
+        jumpY[1] = (R)2 * mn * n[0];
+        jumpY[2] = (R)2 * mn * n[1];
+        jumpY[3] = (R)2 * mn * n[2];
+        R f2s[NV];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) f2s[v] = (R)0;
+        if (VISC && P.sfc_flux && dir == 2 && sd == 0) {
+            // prescribed upward surface fluxes; the outward normal is -z
+            const double qf = MOIST ? P.qt_flux : 0.0;
+            f2s[4] = (R)(-(double)rho * (Phys::cpd * P.theta_flux + Phys::Lv0 * qf));
+            if (MOIST) {
+                f2s[0] = (R)(-(double)rho * qf);
+                f2s[NV - 1] = f2s[0];
+            }
+        }
+#pragma unroll
+        for (int v = 0; v < NV; ++v)
+            contrib[v] = liftFm[v] - lift * ((R)0.5 * (f1m[v] + f1g[v]) + (R)0.5 * lam * jumpY[v] + f2s[v]);
+    }
+#pragma unroll
+    for (int v = 0; v < NV; ++v) sG[v * 3 + dir][own] = contrib[v];
+}
+
 // MODE 0: out = R; MODE 1: LSRK stage; MODE 2: first LSRK stage (A = 0, dQ not read)
 template <typename R, bool MOIST, bool WARP, bool VISC, int MODE>
 __global__ __launch_bounds__(BLOCK) void k_tend(const KParams P, const R* __restrict__ Y, const R* __restrict__ F2,
                                                 R* __restrict__ out, R* __restrict__ dQ, R A, R B, R dt)
 {
     constexpr int NV = MOIST ? 6 : 5;
+    constexpr int NW = MOIST ? 12 : 9;
+    constexpr int NWS = NW + (MOIST ? 2 : 1);  // with the subsidence words
+    // contravariant total flux J a^d . F per (variable, direction); after the
+    // divergence each face task overwrites its own-node entry with the lift
+    // of (n.F^- - n.F^*)
     __shared__ R sG[NV * 3][BLOCK];
+    __shared__ R sP[4][BLOCK];  // u, v, w, c
+    __shared__ R sR[NV][BLOCK];
 
     const int e = elem_of_block(blockIdx.x, P.n_elem);
     const int t = threadIdx.x;
@@ -444,64 +830,75 @@ __global__ __launch_bounds__(BLOCK) void k_tend(const KParams P, const R* __rest
     const int i = tt % NQ, j = (tt / NQ) % NQ, k = tt / (NQ * NQ);
     const int ex = e % P.ne0, ey = (e / P.ne0) % P.ne1, ez = e / (P.ne0 * P.ne1);
     const int64_t nn = P.nn;
-    const int64_t node = (int64_t)e * NP + tt;
+    const int64_t ebase = (int64_t)e * NP;
+    const int64_t node = ebase + tt;
 
-    R Yr[NV];
-    double Yv[NV];
+    // every global load of the first face task and of the own node is
+    // issued up front, so their latencies overlap
+    FaceLoad<R, MOIST, VISC> ft0;
+    face_load<R, MOIST, VISC>(P, Y, F2, t, e, ex, ey, ez, ft0);
+
+    // phase A: own node
+    R Yr[NV], dq_old[NV], w[NWS];
 #pragma unroll
-    for (int v = 0; v < NV; ++v) {
-        Yr[v] = Y[v * nn + node];
-        Yv[v] = (double)Yr[v];
-    }
-    const double z = node_z(P, e, ez, k, tt);
-    const int ri = ref_index(P, e, ez, k, tt);
-    const double pr = P.has_ref ? P.pr[ri] : 0.0;
-    const double rr = P.has_ref ? P.rhor[ri] : 0.0;
-    Th th;
-    thermo<MOIST>(Yv[0], Yv[1], Yv[2], Yv[3], Yv[4], MOIST ? Yv[5] : 0.0, z, P.g, th);
-    R F1[NV][3];
-    flux1<R, MOIST>(th, pr, F1);
-    R w[14];
-    const R um[3] = {(R)th.u, (R)th.v, (R)th.w};
+    for (int v = 0; v < NV; ++v) Yr[v] = Y[v * nn + node];
     if (VISC) {
-        const int nw = (MOIST ? 12 : 9) + (P.subsidence ? (MOIST ? 2 : 1) : 0);
+        const int nw = P.subsidence ? NWS : NW;
 #pragma unroll
-        for (int q = 0; q < 14; ++q) {
-            if (q < nw) w[q] = F2[q * nn + node];
-            else w[q] = (R)0;
-        }
+        for (int q = 0; q < NWS; ++q) w[q] = q < nw ? F2[q * nn + node] : (R)0;
     }
-
-    Metric<R> M;
-    load_metric<R, WARP>(P, node, M);
-    // contravariant total flux J a^d . F (Cartesian: (2/h_d) F_d, J folded)
+    if (MODE == 1) {
 #pragma unroll
-    for (int v = 0; v < NV; ++v) {
-        R F[3] = {F1[v][0], F1[v][1], F1[v][2]};
+        for (int v = 0; v < NV; ++v) dq_old[v] = dQ[v * nn + node];
+    }
+    const int ri = ref_index(P, e, ez, k, tt);
+    const double pr = P.pr[ri];
+    const double rr = P.rhor[ri];
+    const double z = node_z(P, e, ez, k, tt);
+    R Jam[3][3];
+    if (WARP) {
+        const R* m = (const R*)P.metrics;
+#pragma unroll
+        for (int q = 0; q < 9; ++q) Jam[q / 3][q % 3] = m[(int64_t)q * nn + node];
+    }
+    double rho_d, mom_d[3];
+    {
+        Th th;
+        thermo<MOIST>((double)Yr[0], (double)Yr[1], (double)Yr[2], (double)Yr[3], (double)Yr[4],
+                      MOIST ? (double)Yr[NV - 1] : 0.0, z, P.g, th);
+        rho_d = th.rho;
+        mom_d[0] = (double)Yr[1]; mom_d[1] = (double)Yr[2]; mom_d[2] = (double)Yr[3];
+        R F[NV][3];
+        flux1<R, MOIST>(th, pr, F);
+        const R um[3] = {(R)th.u, (R)th.v, (R)th.w};
+        sP[0][t] = um[0]; sP[1][t] = um[1]; sP[2][t] = um[2];
+        sP[3][t] = (R)th.c;
         if (VISC) {
-            if (v == 0 && MOIST) { F[0] += w[9]; F[1] += w[10]; F[2] += w[11]; }
-            if (v == 1) { F[0] += w[0]; F[1] += w[3]; F[2] += w[4]; }
-            if (v == 2) { F[0] += w[3]; F[1] += w[1]; F[2] += w[5]; }
-            if (v == 3) { F[0] += w[4]; F[1] += w[5]; F[2] += w[2]; }
-            if (v == 4) { F[0] += w[6]; F[1] += w[7]; F[2] += w[8]; }
-            if (MOIST && v >= 1 && v <= 3) {
-                const R uu = um[v - 1];
-                F[0] += w[9] * uu; F[1] += w[10] * uu; F[2] += w[11] * uu;
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                const R nd[3] = {d == 0 ? (R)1 : (R)0, d == 1 ? (R)1 : (R)0, d == 2 ? (R)1 : (R)0};
+                R f2[NV];
+                f2_normal<R, MOIST>(w, um, nd, f2);
+#pragma unroll
+                for (int v = 0; v < NV; ++v) F[v][d] += f2[v];
             }
-            if (MOIST && v == 5) { F[0] += w[9]; F[1] += w[10]; F[2] += w[11]; }
         }
 #pragma unroll
-        for (int d = 0; d < 3; ++d) {
-            R G;
-            if (WARP) G = M.Ja[d][0] * F[0] + M.Ja[d][1] * F[1] + M.Ja[d][2] * F[2];
-            else G = (R)(2.0 / (d == 0 ? P.h0 : (d == 1 ? P.h1 : P.h2))) * F[d];
-            sG[v * 3 + d][t] = G;
-        }
+        for (int v = 0; v < NV; ++v)
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                R G;
+                if (WARP) G = Jam[d][0] * F[v][0] + Jam[d][1] * F[v][1] + Jam[d][2] * F[v][2];
+                else G = (R)(d == 0 ? P.r2h0 : (d == 1 ? P.r2h1 : P.r2h2)) * F[v][d];
+                sG[v * 3 + d][t] = G;
+            }
     }
     __syncthreads();
 
-    R Rv[NV];
-#pragma unroll
+    // phase B: strong-form divergence with the 1-D GLL matrix, one variable
+    // at a time into LDS (unrolled over variables the compiler keeps every
+    // tile load in flight and runs out of registers)
+#pragma unroll 1
     for (int v = 0; v < NV; ++v) {
         R s = 0;
 #pragma unroll
@@ -510,130 +907,55 @@ __global__ __launch_bounds__(BLOCK) void k_tend(const KParams P, const R* __rest
             s += dmat<R>(j, l) * sG[v * 3 + 1][i + NQ * (l + NQ * k)];
             s += dmat<R>(k, l) * sG[v * 3 + 2][i + NQ * (j + NQ * l)];
         }
-        Rv[v] = WARP ? -s * M.invJ : -s;
+        sR[v][t] = -s;
     }
+    __syncthreads();
 
-    // faces owned by this element: lift (n.F^- - n.F^*)
+    // phase C: face tasks.  lift (n.F^- - n.F^*): n.F^- comes from the
+    // contravariant flux already in LDS (lift n.F = side G^dir / (J w_N)).
+    // The first task's loads were issued at kernel entry (ft0).
+    face_flux<R, MOIST, WARP, VISC>(P, ft0, e, ex, ey, ez, sG, sP);
+    if (t + BLOCK < 150) {
+        FaceLoad<R, MOIST, VISC> ft1;
+        face_load<R, MOIST, VISC>(P, Y, F2, t + BLOCK, e, ex, ey, ez, ft1);
+        face_flux<R, MOIST, WARP, VISC>(P, ft1, e, ex, ey, ez, sG, sP);
+    }
+    __syncthreads();
+
+    // phase D: gather the face terms of this node, metric factor, sources
+    R Rv[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) Rv[v] = sR[v][t];
     const int idx[3] = {i, j, k};
+    if (WARP) {
+        const R invJ = ((const R*)P.metrics)[9 * nn + node];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) Rv[v] *= invJ;
+    }
 #pragma unroll
     for (int dir = 0; dir < 3; ++dir) {
+        if (idx[dir] != 0 && idx[dir] != NQ - 1) continue;
 #pragma unroll
-        for (int sd = 0; sd < 2; ++sd) {
-            const int side = sd ? 1 : -1;
-            if (idx[dir] != (sd ? NQ - 1 : 0)) continue;
-            R n[3], lift;
-            face_geom<R, WARP>(P, M, dir, side, n, lift);
-            R fm1[NV], fm2[NV];
-#pragma unroll
-            for (int v = 0; v < NV; ++v) fm1[v] = F1[v][0] * n[0] + F1[v][1] * n[1] + F1[v][2] * n[2];
-            if (VISC) f2_normal<R, MOIST>(w, um, n, fm2);
-            const R unm = um[0] * n[0] + um[1] * n[1] + um[2] * n[2];
-            const int en = nbr_elem(P, ex, ey, ez, dir, side);
-            R fstar[NV];
-            if (en >= 0) {
-                int m3[3] = {i, j, k};
-                m3[dir] = sd ? 0 : NQ - 1;
-                const int tn = m3[0] + NQ * (m3[1] + NQ * m3[2]);
-                const int64_t np = (int64_t)en * NP + tn;
-                R Ypr[NV];
-                double Yp[NV];
-#pragma unroll
-                for (int v = 0; v < NV; ++v) {
-                    Ypr[v] = Y[v * nn + np];
-                    Yp[v] = (double)Ypr[v];
-                }
-                const int ezn = en / (P.ne0 * P.ne1);
-                const double zp = node_z(P, en, ezn, m3[2], tn);
-                const double prp = P.has_ref ? P.pr[ref_index(P, en, ezn, m3[2], tn)] : 0.0;
-                Th tp;
-                thermo<MOIST>(Yp[0], Yp[1], Yp[2], Yp[3], Yp[4], MOIST ? Yp[5] : 0.0, zp, P.g, tp);
-                R Fp[NV][3];
-                flux1<R, MOIST>(tp, prp, Fp);
-                const R up[3] = {(R)tp.u, (R)tp.v, (R)tp.w};
-                const R unp = up[0] * n[0] + up[1] * n[1] + up[2] * n[2];
-                const R lm = fabs(unm) + (R)th.c, lp = fabs(unp) + (R)tp.c;
-                const R lam = lm > lp ? lm : lp;
-#pragma unroll
-                for (int v = 0; v < NV; ++v) {
-                    const R fp = Fp[v][0] * n[0] + Fp[v][1] * n[1] + Fp[v][2] * n[2];
-                    fstar[v] = (R)0.5 * (fm1[v] + fp) + (R)0.5 * lam * (Yr[v] - Ypr[v]);
-                }
-                if (VISC) {
-                    R wp[14];
-                    const int nw = MOIST ? 12 : 9;
-#pragma unroll
-                    for (int q = 0; q < 12; ++q) {
-                        if (q < nw) wp[q] = F2[q * nn + np];
-                        else wp[q] = (R)0;
-                    }
-                    R fp2[NV];
-                    f2_normal<R, MOIST>(wp, up, n, fp2);
-#pragma unroll
-                    for (int v = 0; v < NV; ++v) fstar[v] += (R)0.5 * (fm2[v] + fp2[v]);
-                }
-            } else {
-                // reflecting ghost u+ = u- - 2 (n.u-) n; rho, rho e, rho q mirrored
-                R Ypr[NV];
-#pragma unroll
-                for (int v = 0; v < NV; ++v) Ypr[v] = Yr[v];
-                const double mn = Yv[1] * (double)n[0] + Yv[2] * (double)n[1] + Yv[3] * (double)n[2];
-                double Yg[NV];
-#pragma unroll
-                for (int v = 0; v < NV; ++v) Yg[v] = Yv[v];
-                Yg[1] = Yv[1] - 2.0 * mn * (double)n[0];
-                Yg[2] = Yv[2] - 2.0 * mn * (double)n[1];
-                Yg[3] = Yv[3] - 2.0 * mn * (double)n[2];
-                Ypr[1] = (R)Yg[1]; Ypr[2] = (R)Yg[2]; Ypr[3] = (R)Yg[3];
-                Th tp;
-                thermo<MOIST>(Yg[0], Yg[1], Yg[2], Yg[3], Yg[4], MOIST ? Yg[5] : 0.0, z, P.g, tp);
-                R Fp[NV][3];
-                flux1<R, MOIST>(tp, pr, Fp);
-                const R up[3] = {(R)tp.u, (R)tp.v, (R)tp.w};
-                const R unp = up[0] * n[0] + up[1] * n[1] + up[2] * n[2];
-                const R lm = fabs(unm) + (R)th.c, lp = fabs(unp) + (R)tp.c;
-                const R lam = lm > lp ? lm : lp;
-#pragma unroll
-                for (int v = 0; v < NV; ++v) {
-                    const R fp = Fp[v][0] * n[0] + Fp[v][1] * n[1] + Fp[v][2] * n[2];
-                    fstar[v] = (R)0.5 * (fm1[v] + fp) + (R)0.5 * lam * (Yr[v] - Ypr[v]);
-                }
-                if (VISC && P.sfc_flux && dir == 2 && sd == 0) {
-                    // prescribed upward surface fluxes; the outward normal is -z
-                    const double qf = MOIST ? P.qt_flux : 0.0;
-                    fstar[4] += (R)(-th.rho * (Phys::cpd * P.theta_flux + Phys::Lv0 * qf));
-                    if (MOIST) {
-                        fstar[0] += (R)(-th.rho * qf);
-                        fstar[5] += (R)(-th.rho * qf);
-                    }
-                }
-            }
-#pragma unroll
-            for (int v = 0; v < NV; ++v) {
-                const R fm = VISC ? fm1[v] + fm2[v] : fm1[v];
-                Rv[v] += lift * (fm - fstar[v]);
-            }
-        }
+        for (int v = 0; v < NV; ++v) Rv[v] += sG[v * 3 + dir][t];
     }
-
-    // sources
-    Rv[3] -= (R)((th.rho - rr) * P.g);
+    Rv[3] -= (R)((rho_d - rr) * P.g);
     if (P.f_cor != 0.0) {
-        Rv[1] += (R)(P.f_cor * (Yv[2] - th.rho * P.v_g));
-        Rv[2] -= (R)(P.f_cor * (Yv[1] - th.rho * P.u_g));
+        Rv[1] += (R)(P.f_cor * (mom_d[1] - rho_d * P.v_g));
+        Rv[2] -= (R)(P.f_cor * (mom_d[0] - rho_d * P.u_g));
     }
     if (P.sponge && z > P.sp_zs) {
-        const double zeta = (z - P.sp_zs) / (P.sp_ztop - P.sp_zs);
+        const double zeta = (z - P.sp_zs) * P.sp_inv;
         const double tau = P.sp_alpha * pow(sin(0.5 * M_PI * zeta), P.sp_gamma);
-        Rv[1] -= (R)(tau * (Yv[1] - th.rho * P.sp_u0));
-        Rv[2] -= (R)(tau * (Yv[2] - th.rho * P.sp_u1));
-        Rv[3] -= (R)(tau * (Yv[3] - th.rho * P.sp_u2));
+        Rv[1] -= (R)(tau * (mom_d[0] - rho_d * P.sp_u0));
+        Rv[2] -= (R)(tau * (mom_d[1] - rho_d * P.sp_u1));
+        Rv[3] -= (R)(tau * (mom_d[2] - rho_d * P.sp_u2));
     }
     if (VISC && P.subsidence) {
         const double zz = z < P.sub_ztop ? z : P.sub_ztop;
-        const double ws = -P.sub_w0 * sin(M_PI * zz / P.sub_ztop);
-        const int b = MOIST ? 12 : 9;
-        Rv[4] -= (R)(th.rho * ws) * w[b];
-        if (MOIST) Rv[5] -= (R)(th.rho * ws) * w[b + 1];
+        const double ws = -P.sub_w0 * sin(M_PI * zz * P.sub_inv);
+        const R rws = (R)(rho_d * ws);
+        Rv[4] -= rws * w[NW];
+        if (MOIST) Rv[NV - 1] -= rws * w[NW + 1];
     }
 
     if (!act) return;
@@ -643,7 +965,7 @@ __global__ __launch_bounds__(BLOCK) void k_tend(const KParams P, const R* __rest
         if (MODE == 0) {
             out[a] = Rv[v];
         } else {
-            const R dq = MODE == 1 ? A * dQ[a] + dt * Rv[v] : dt * Rv[v];
+            const R dq = MODE == 1 ? A * dq_old[v] + dt * Rv[v] : dt * Rv[v];
             dQ[a] = dq;
             out[a] = Yr[v] + B * dq;
         }
@@ -661,7 +983,10 @@ static hipError_t launch_typed(cm_model* m, const void* Y, void* out, void* dQ, 
     const bool visc = m->desc.closure != CM_CLOSURE_NONE;
     if (visc) {
         cm_model::ProfRec* r = prof_begin(m, 0, s);
-        hipLaunchKernelGGL((k_grad<R, MOIST, WARP>), grid, block, 0, s, P, y, F2);
+        if (m->desc.closure == CM_CLOSURE_MLP)
+            hipLaunchKernelGGL((k_grad<R, MOIST, WARP, true>), grid, block, 0, s, P, y, F2);
+        else
+            hipLaunchKernelGGL((k_grad<R, MOIST, WARP, false>), grid, block, 0, s, P, y, F2);
         prof_end(r, s);
     }
     cm_model::ProfRec* rt = prof_begin(m, 1, s);

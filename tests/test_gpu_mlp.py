@@ -1,0 +1,148 @@
+"""GPU checks of the learned closure: BF16-MFMA inference against the oracle
+network with bfloat16 operands, hand-written backward against the FP64
+oracle gradient, training lowers the loss, and the fused closure inside the
+gradient kernel against the oracle right-hand side."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2110_00853_amd import binding as B
+from paper_2110_00853_amd import workloads as W
+from parity import hmin, rhs_errors
+
+pytestmark = pytest.mark.gpu
+
+
+def _params(seed):
+    rng = np.random.default_rng(seed)
+    p = np.zeros(9282)
+    off = 0
+    for nout, nin in ((64, 12), (64, 64), (64, 64), (2, 64)):
+        p[off:off + nout * nin] = rng.uniform(-1, 1, nout * nin) / np.sqrt(nin)
+        off += nout * nin
+        p[off:off + nout] = rng.uniform(-0.1, 0.1, nout)
+        off += nout
+    return p.astype(np.float32).astype(np.float64)
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+
+    assert t.cuda.is_available()
+    return t
+
+
+def test_mfma_inference_matches_bf16_oracle(torch):
+    p = _params(1)
+    rng = np.random.default_rng(2)
+    X = rng.normal(size=(3000, 12)).astype(np.float32)
+    net = B.MLP(seed=0)
+    net.set_params(p)
+    out = net.infer(torch.from_numpy(X).cuda()).cpu().numpy().astype(np.float64)
+    ref16 = oracle.mlp_forward(p, X.astype(np.float64), bf16=True)
+    ref64 = oracle.mlp_forward(p, X.astype(np.float64))
+    scale = np.abs(ref64).max()
+    e16 = np.abs(out - ref16) / scale
+    e64 = np.abs(out - ref64).max() / scale
+    print("vs bf16 oracle: median %.2e  99%% %.2e  max %.2e; vs fp64 max %.2e" % (
+        np.median(e16), np.quantile(e16, 0.99), e16.max(), e64))
+    assert np.median(e16) < 1e-5 and np.quantile(e16, 0.99) < 1e-3
+    assert e64 < 5e-2
+
+
+def test_backward_matches_fp64_gradient(torch):
+    p = _params(3)
+    rng = np.random.default_rng(4)
+    X = rng.normal(size=(2048, 12)).astype(np.float32)
+    T = rng.normal(size=(2048, 2)).astype(np.float32)
+    net = B.MLP(seed=0)
+    net.set_params(p)
+    g = net.grads(torch.from_numpy(X).cuda(), torch.from_numpy(T).cuda()).astype(np.float64)
+    _, gref = oracle.mlp_grad(p, X.astype(np.float64), T.astype(np.float64))
+    rel = np.linalg.norm(g - gref) / np.linalg.norm(gref)
+    cos = g @ gref / (np.linalg.norm(g) * np.linalg.norm(gref))
+    print("grad rel L2 %.3e cosine %.6f" % (rel, cos))
+    assert rel < 3e-2 and cos > 0.999
+    # each layer separately
+    off = 0
+    for nout, nin in ((64, 12), (64, 64), (64, 64), (2, 64)):
+        for n in (nout * nin, nout):
+            seg = slice(off, off + n)
+            r = np.linalg.norm(g[seg] - gref[seg]) / np.linalg.norm(gref[seg])
+            assert r < 5e-2, (off, r)
+            off += n
+
+
+def test_training_reduces_loss(torch):
+    """Regress a smooth synthetic map; loss falls by more than 10x."""
+    rng = np.random.default_rng(5)
+    X = rng.normal(size=(8192, 12)).astype(np.float32)
+    T = np.stack([np.tanh(X[:, 0] - 0.5 * X[:, 3]) + 0.1 * X[:, 9],
+                  0.5 * np.sin(X[:, 1]) * X[:, 10]], axis=1).astype(np.float32)
+    Xd, Td = torch.from_numpy(X).cuda(), torch.from_numpy(T).cuda()
+    net = B.MLP(seed=7, lr=3e-3)
+    l0 = net.train_step(Xd, Td)
+    for _ in range(300):
+        l = net.train_step(Xd, Td, want_loss=False)
+    l1 = net.train_step(Xd, Td)
+    print("loss %.4e -> %.4e" % (l0, l1))
+    assert np.isfinite(l1) and l1 < 0.1 * l0
+    # the trained parameters reproduce the loss on the oracle (FP64 forward)
+    p = net.params().astype(np.float64)
+    o = oracle.mlp_forward(p, X.astype(np.float64))
+    assert np.mean(np.sum((o - T) ** 2, axis=1)) < 0.2 * l0
+
+
+def _features(c, Y, Yref):
+    """Raw closure inputs at every node from the oracle's BR1 gradients."""
+    om = oracle.Model(oracle.Grid(c["grid"]), c["model"], Yref)
+    grad, _ = om.gradients(Y)
+    gu = grad[:3]                                  # [i][j][node] = d u_i / d x_j
+    z = oracle.Grid(c["grid"]).coords()[2]
+    T, p, ql, thv = oracle.thermo_nodes(Y, z, c["model"]["g"])
+    N2 = c["model"]["g"] / thv * grad[-1, 2]
+    h = (np.array(c["grid"]["hi"]) - np.array(c["grid"]["lo"])) / np.array(c["grid"]["ne"])
+    Delta = np.cbrt(np.prod(h / 4.0))
+    S = 0.5 * (gu + gu.transpose(1, 0, 2))
+    SS = 2 * np.sum(S * S, axis=(0, 1))
+    nu = np.array([oracle.smagorinsky(gu[:, :, n], N2[n], c["model"]["Cs"], Delta, 1 / 3, True)
+                   for n in range(Y.shape[1])])
+    raw = np.concatenate([gu.reshape(9, -1), N2[None], np.full((1, Y.shape[1]), Delta),
+                          ((nu / (0.1 * Delta)) ** 2)[None]]).T
+    return raw
+
+
+def test_fused_closure_rhs_matches_oracle(torch):
+    """The gradient kernel's fused BF16-MFMA network, with fallback to
+    Smagorinsky out of the training range, against the oracle RHS with the
+    same bf16 rounding points."""
+    c = W.case("learned_32", ne=(3, 2, 4), hi=(600.0, 400.0, 800.0))
+    Y, Yref, _ = W.perturbed_state(c, seed=9, amp_u=6.0, amp_T=2.0)
+    raw = _features(c, Y, Yref)
+    mean = raw.mean(axis=0)
+    std = raw.std(axis=0)
+    std[std == 0] = 1.0
+    Xs = (raw - mean) / std
+    lo, hi = np.quantile(Xs, 0.02, axis=0), np.quantile(Xs, 0.98, axis=0)  # some nodes fall back
+    p = _params(11)
+    p[-2:] = [-1.0, 0.2]                            # modest nu / Pr_t
+    norm = np.concatenate([mean, std, lo, hi]).astype(np.float32)
+    # float32 copies so both sides see identical numbers
+    mean, std, lo, hi = (norm[12 * q:12 * (q + 1)].astype(np.float64) for q in range(4))
+    om = oracle.Model(oracle.Grid(c["grid"]), c["model"], Yref)
+    om.set_mlp(p, mean, std, lo, hi, use_fallback=True, bf16=True)
+    Rref = om.rhs(Y)
+    nfb_ref = om.mlp_fallbacks()
+    g = B.Grid(c["grid"])
+    m = B.Model(g, c["model"], Yref)
+    m.set_mlp(p.astype(np.float32), norm)
+    Yd = m.new_state(Y)
+    Rd = m.new_state()
+    m.rhs(Yd, Rd)
+    nfb = m.mlp_fallbacks()
+    Rg = Rd.cpu().numpy()
+    err = rhs_errors(Rg, Rref, Y, hmin(c["grid"]))
+    print("fused mlp closure rhs errors", err, "fallbacks", nfb, nfb_ref)
+    assert abs(nfb - nfb_ref) <= max(2, 0.01 * nfb_ref)
+    assert np.all(err < 1e-4), err
