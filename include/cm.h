@@ -156,6 +156,14 @@ CM_API cm_status cm_model_set_mlp(cm_model* model, const float* params_host, con
  * Synchronises the stream. */
 CM_API cm_status cm_model_mlp_fallbacks(cm_model* model, int64_t* count, void* hip_stream);
 
+/* Closure inputs as the gradient pass computes them, for training the
+ * learned closure: feat_dev (device, float64) [n_nodes][16] = grad u (9,
+ * row i = component, column j = derivative direction), N^2, Delta,
+ * (nu_SL / (0.1 Delta))^2, grad theta_v (3), theta_v.  Needs an FP64 model
+ * with the Smagorinsky closure and the Richardson factor (CM_ERR_STATE
+ * otherwise).  Asynchronous on the stream. */
+CM_API cm_status cm_model_closure_inputs(cm_model* model, const void* Y, double* feat_dev, void* hip_stream);
+
 /* dYdt = R(Y): the semi-discrete DG operator (eq. matrixProblem, strong
  * form) with F = F1 + F2, Rusanov F1*, centred F2*, BR1 gradients, closure,
  * sources.  Y and dYdt must not alias.  t is the model time (unused by the

@@ -12,7 +12,8 @@ import os
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libcm.so")
+# CM_LIB may point at another build of the same library (e.g. a variant being timed)
+LIB_PATH = os.environ.get("CM_LIB", os.path.join(HERE, "libcm.so"))
 
 CM_OK, CM_ERR_ARG, CM_ERR_HIP, CM_ERR_ALLOC, CM_ERR_UNSUPPORTED, CM_ERR_NONFINITE, CM_ERR_STATE = range(7)
 CM_FP64, CM_FP32_BULK = 0, 1
@@ -23,7 +24,8 @@ EXPORTED = [
     "cm_grid_copy_metrics", "cm_model_create", "cm_model_destroy", "cm_model_set_mlp",
     "cm_model_mlp_fallbacks", "cm_dg_rhs", "cm_lsrk_step", "cm_diagnostics", "cm_mlp_create",
     "cm_mlp_destroy", "cm_mlp_train_step", "cm_mlp_grads", "cm_mlp_infer", "cm_mlp_get_params",
-    "cm_mlp_set_params", "cm_model_profile", "cm_model_profile_read", "cm_last_error",
+    "cm_mlp_set_params", "cm_model_profile", "cm_model_profile_read", "cm_model_closure_inputs",
+    "cm_last_error",
 ]
 
 
@@ -103,6 +105,7 @@ def load():
     L.cm_mlp_get_params.argtypes = [_VP, _VP]
     L.cm_mlp_set_params.argtypes = [_VP, _VP]
     L.cm_model_profile.argtypes = [_VP, C.c_int]
+    L.cm_model_closure_inputs.argtypes = [_VP, _VP, _VP, _VP]
     L.cm_model_profile_read.argtypes = [_VP, _VP, _VP]
     for name in EXPORTED:
         if name != "cm_last_error":
@@ -277,6 +280,16 @@ class Model:
         if p.size != 9282 or nrm.size != 48:
             raise ValueError("need 9282 parameters and 48 normalisation values")
         _check(load().cm_model_set_mlp(self.h, _np_ptr(p), _np_ptr(nrm)))
+
+    def closure_inputs(self, Y, out=None, stream=None):
+        """Raw closure inputs per node [n_nodes, 16] (see cm_model_closure_inputs)."""
+        import torch
+
+        self._chk(Y)
+        if out is None:
+            out = torch.empty((self.grid.n_nodes, 16), dtype=torch.float64, device=Y.device)
+        _check(load().cm_model_closure_inputs(self.h, Y.data_ptr(), out.data_ptr(), _stream_ptr(stream)))
+        return out
 
     def profile(self, enable: bool = True):
         """Bracket every kernel launch with hipEvents (see cm_model_profile)."""

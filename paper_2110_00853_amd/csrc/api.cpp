@@ -401,6 +401,7 @@ cm_status cm_model_create(const cm_grid* g, const cm_model_desc* desc, const dou
     k.nf = m->nf;
     k.mlp_frag = nullptr; k.mlp_bias = nullptr; k.mlp_norm = nullptr;
     k.mlp_fallback_on = 1; k.mlp_fallbacks = m->d_fallbacks;
+    k.feat_out = nullptr;
     if (e == hipSuccess && Yref) {
         // push the background through the device thermodynamics
         const int64_t nref = m->ref_per_node ? nn : (int64_t)g->desc.ne[2] * NQ;
@@ -494,6 +495,21 @@ cm_status cm_model_profile_read(cm_model* m, double* ms, int64_t* count)
         ms[r.kind] += t;
         count[r.kind] += 1;
     }
+    return CM_OK;
+}
+
+cm_status cm_model_closure_inputs(cm_model* m, const void* Y, double* feat, void* stream)
+{
+    if (!m || !Y || !feat) { set_error("cm_model_closure_inputs: null argument"); return CM_ERR_ARG; }
+    if (m->desc.closure != CM_CLOSURE_SMAG || !m->desc.richardson) {
+        set_error("cm_model_closure_inputs: needs the Smagorinsky closure with the Richardson factor");
+        return CM_ERR_STATE;
+    }
+    CM_TRY_HIP(hipSetDevice(m->grid->device), "hipSetDevice");
+    m->kp.feat_out = feat;
+    hipError_t e = launch_grad_only(m, Y, (hipStream_t)stream);
+    m->kp.feat_out = nullptr;
+    CM_TRY_HIP(e, "cm_model_closure_inputs");
     return CM_OK;
 }
 

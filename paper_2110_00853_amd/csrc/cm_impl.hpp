@@ -68,6 +68,7 @@ struct KParams {
     const double* mlp_norm;     // mean[12], std[12], lo[12], hi[12]
     int mlp_fallback_on;
     unsigned long long* mlp_fallbacks;
+    double* feat_out;           // when set, the gradient pass also writes the closure inputs [nn][16]
 };
 
 }  // namespace cm
@@ -123,6 +124,7 @@ cm_status hip_fail(hipError_t e, const char* where);
 hipError_t launch_reference(const cm_model* m, const double* Yref_dev, hipStream_t s);
 hipError_t launch_rhs(cm_model* m, const void* Y, void* out, void* dQ, int mode, double A, double B,
                       double dt, hipStream_t s);
+hipError_t launch_grad_only(cm_model* m, const void* Y, hipStream_t s);
 hipError_t upload_constants(const cm_grid* g);
 // event brackets around one launch when profiling is on
 cm_model::ProfRec* prof_begin(cm_model* m, int kind, hipStream_t s);

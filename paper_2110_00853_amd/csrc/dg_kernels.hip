@@ -600,6 +600,23 @@ __global__ __launch_bounds__(BLOCK) void k_grad(const KParams P, const R* __rest
             if ((threadIdx.x & 63) == 0 && nfb) atomicAdd(P.mlp_fallbacks, nfb);
         }
     }
+    if (!MLP && P.feat_out != nullptr && act) {
+        // closure inputs for training: grad u (9), N^2, Delta, TKE estimate
+        // (nu_SL / (0.1 Delta))^2, grad theta_v (3), theta_v
+        double* f = P.feat_out + node * 16;
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+            for (int b = 0; b < 3; ++b) f[3 * a + b] = (double)gr[a][b];
+        f[9] = P.g / (double)sg[GT][t] * (double)sJ[2][GT][t];
+        f[10] = P.Delta;
+        const double kk = (double)nu / (0.1 * P.Delta);
+        f[11] = kk * kk;
+        f[12] = (double)sJ[0][GT][t];
+        f[13] = (double)sJ[1][GT][t];
+        f[14] = (double)sJ[2][GT][t];
+        f[15] = (double)sg[GT][t];
+    }
     const R rho = (R)th.rho;
     const R Dt = MLP ? nu * frcp(Prt) : nu * (R)P.invPrt;
     const R c2 = (R)(-2.0) * rho * nu;
@@ -833,12 +850,9 @@ __global__ __launch_bounds__(BLOCK) void k_tend(const KParams P, const R* __rest
     const int64_t ebase = (int64_t)e * NP;
     const int64_t node = ebase + tt;
 
-    // every global load of the first face task and of the own node is
-    // issued up front, so their latencies overlap
-    FaceLoad<R, MOIST, VISC> ft0;
-    face_load<R, MOIST, VISC>(P, Y, F2, t, e, ex, ey, ez, ft0);
-
-    // phase A: own node
+    // phase A: own node (loads first; the first face task's loads follow so
+    // their latency overlaps phase A, while the in-order load counter lets
+    // phase A start as soon as the own-node data is in)
     R Yr[NV], dq_old[NV], w[NWS];
 #pragma unroll
     for (int v = 0; v < NV; ++v) Yr[v] = Y[v * nn + node];
@@ -861,6 +875,10 @@ __global__ __launch_bounds__(BLOCK) void k_tend(const KParams P, const R* __rest
 #pragma unroll
         for (int q = 0; q < 9; ++q) Jam[q / 3][q % 3] = m[(int64_t)q * nn + node];
     }
+#ifndef CM_NO_FACE_PREFETCH
+    FaceLoad<R, MOIST, VISC> ft0;
+    face_load<R, MOIST, VISC>(P, Y, F2, t, e, ex, ey, ez, ft0);
+#endif
     double rho_d, mom_d[3];
     {
         Th th;
@@ -914,6 +932,10 @@ __global__ __launch_bounds__(BLOCK) void k_tend(const KParams P, const R* __rest
     // phase C: face tasks.  lift (n.F^- - n.F^*): n.F^- comes from the
     // contravariant flux already in LDS (lift n.F = side G^dir / (J w_N)).
     // The first task's loads were issued at kernel entry (ft0).
+#ifdef CM_NO_FACE_PREFETCH
+    FaceLoad<R, MOIST, VISC> ft0;
+    face_load<R, MOIST, VISC>(P, Y, F2, t, e, ex, ey, ez, ft0);
+#endif
     face_flux<R, MOIST, WARP, VISC>(P, ft0, e, ex, ey, ez, sG, sP);
     if (t + BLOCK < 150) {
         FaceLoad<R, MOIST, VISC> ft1;
@@ -1004,6 +1026,25 @@ static hipError_t launch_typed(cm_model* m, const void* Y, void* out, void* dQ, 
     }
 #undef CM_TEND
     prof_end(rt, s);
+    return hipGetLastError();
+}
+
+hipError_t launch_grad_only(cm_model* m, const void* Y, hipStream_t s)
+{
+    const KParams& P = m->kp;
+    const bool moist = m->desc.nvar == 6;
+    const bool warp = m->grid->desc.topo == 1;
+    if (m->desc.precision != CM_FP64) return hipErrorInvalidValue;
+    const dim3 grid(P.n_elem), block(BLOCK);
+    double* F2 = (double*)m->d_F2;
+    const double* y = (const double*)Y;
+    if (moist) {
+        if (warp) hipLaunchKernelGGL((k_grad<double, true, true, false>), grid, block, 0, s, P, y, F2);
+        else hipLaunchKernelGGL((k_grad<double, true, false, false>), grid, block, 0, s, P, y, F2);
+    } else {
+        if (warp) hipLaunchKernelGGL((k_grad<double, false, true, false>), grid, block, 0, s, P, y, F2);
+        else hipLaunchKernelGGL((k_grad<double, false, false, false>), grid, block, 0, s, P, y, F2);
+    }
     return hipGetLastError();
 }
 

@@ -169,20 +169,24 @@ def constant_N(z, theta_sfc=300.0, Nbv=0.01, p_sfc=1.0e5, g=_G):
     return p, T
 
 
-def _moist_T_from_thetal(p, thl, qt):
+def _moist_T_from_thetal(p, thl, qt, T_guess=None, half_width=None, iters=100):
     """Temperature from liquid-water potential temperature at pressure p:
-    T = Pi theta_l + L_v0 q_l(T)/c_pd (fixed point, then bisection)."""
+    the root of T - Pi theta_l - L_v0 q_l(T)/c_pd by bisection (bracket
+    [Pi theta_l, Pi theta_l + L_v0 q_t/c_pd + 1], or T_guess +- half_width)."""
     Pi = (p / _P0) ** _KAPPA
-    lo = Pi * thl
-    hi = lo + _LV0 * qt / _CPD + 1.0
+    if T_guess is None:
+        lo = Pi * thl
+        hi = lo + _LV0 * qt / _CPD + 1.0
+    else:
+        lo, hi = T_guess - half_width, T_guess + half_width
 
     def resid(T):
-        rho_s = (p - pvsat(T)) / (_RD * (1.0 - qt) * T)
-        qv = pvsat(T) / (rho_s * _RV * T)
+        ps = pvsat(T)
+        qv = ps * _RD * (1.0 - qt) / ((p - ps) * _RV)   # p_v*/(rho_s R_v T), rho_s = (p - p_v*)/(R_d (1-q_t) T)
         ql = np.maximum(qt - qv, 0.0)
         return T - Pi * thl - _LV0 * ql / _CPD
 
-    for _ in range(100):
+    for _ in range(iters):
         mid = 0.5 * (lo + hi)
         r = resid(mid)
         lo = np.where(r < 0.0, mid, lo)
@@ -201,11 +205,12 @@ def shallow_cumulus_profiles(zq):
     return thl, qt
 
 
-def moist_hydrostatic(z, g=_G, p_sfc=_P0, nsub=20):
+def moist_hydrostatic(z, g=_G, p_sfc=_P0, nsub=4):
     """Integrate dp/dz = -rho g for the shallow-cumulus profiles (RK4 over the
-    sorted unique node heights, nsub substeps per interval)."""
+    sorted unique node heights, nsub substeps per interval); returns p, T, q_t
+    at every height in z."""
     z = np.asarray(z, float)
-    levels = np.unique(np.concatenate([[0.0], z]))
+    levels, inv = np.unique(np.concatenate([[0.0], z]), return_inverse=True)
 
     def dpdz(zz, pp):
         thl, qt = shallow_cumulus_profiles(np.array([zz]))
@@ -228,11 +233,10 @@ def moist_hydrostatic(z, g=_G, p_sfc=_P0, nsub=20):
             p = p + hstep / 6 * (k1 + 2 * k2 + 2 * k3 + k4)
             zz += hstep
         pl[a] = p
-    idx = np.searchsorted(levels, z)
-    pz = pl[idx]
-    thl, qt = shallow_cumulus_profiles(z)
-    T = _moist_T_from_thetal(pz, thl, qt)
-    return pz, T, qt
+    thl_l, qt_l = shallow_cumulus_profiles(levels)
+    T_l = _moist_T_from_thetal(pl, thl_l, qt_l)
+    idx = inv[1:]
+    return pl[idx], T_l[idx], qt_l[idx]
 
 
 # --------------------------------------------------------------------------
@@ -378,7 +382,11 @@ def initial_state(c: dict, xyz=None):
         dq = np.where(low, rng.uniform(-0.025e-3, 0.025e-3, n), 0.0)
         thl, qt0 = shallow_cumulus_profiles(z)
         qtp = qt0 + dq
-        Tp = _moist_T_from_thetal(p, thl + dth, qtp)
+        Tp = T.copy()
+        if low.any():
+            # perturbations change T by well under a kelvin: bisection in T +- 1 K
+            Tp[low] = _moist_T_from_thetal(p[low], thl[low] + dth[low], qtp[low], T_guess=T[low],
+                                           half_width=1.0, iters=32)
         Y = state_from_primitives(p, Tp, u, zero, zero, z, qt=qtp, g=g)
         cmax = float(np.max(np.abs(u) + sound_speed_dry(Tp)))
         return Y, Yref, cfl_dt(grid, cmax)

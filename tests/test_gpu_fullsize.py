@@ -1,0 +1,35 @@
+"""Parity at the full benchmark sizes, in the configuration bench.py times:
+the FP64 tendency of every node against the oracle (dry bubble 32^3,
+moist shallow convection 64x64x30, warped Agnesi flow 96x16x50), and the
+FP32-bulk tendency error against the same oracle (stated, bounded)."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2110_00853_amd import binding as B
+from paper_2110_00853_amd import workloads as W
+from parity import hmin, rhs_errors
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("name", ["bubble_32", "agnesi_96", "moist_64"])
+def test_full_size_rhs_matches_oracle(name):
+    import torch
+
+    c = W.case(name)
+    Y, Yref, dt = W.initial_state(c)
+    Rref = oracle.Model(oracle.Grid(c["grid"]), c["model"], Yref).rhs(Y)
+    g = B.Grid(c["grid"])
+    out = {}
+    for prec in ("fp64", "fp32"):
+        m = B.Model(g, c["model"], Yref, precision=prec)
+        Yd = m.new_state(Y)
+        Rd = m.new_state()
+        m.rhs(Yd, Rd)
+        torch.cuda.synchronize()
+        out[prec] = rhs_errors(Rd.cpu().numpy().astype(np.float64), Rref, Y, hmin(c["grid"]))
+        del m, Yd, Rd
+    print(name, "full-size rhs errors fp64", out["fp64"], "fp32-bulk", out["fp32"])
+    assert np.all(out["fp64"] < 1e-11), out["fp64"]
+    assert np.all(np.isfinite(out["fp32"])) and np.all(out["fp32"] < 5e-2), out["fp32"]
