@@ -1,9 +1,12 @@
 // C ABI entry points: grid and model objects, argument checks, dispatch to
 // the HIP kernels, error reporting.
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
 #include <new>
+#include <utility>
+#include <vector>
 
 #include "cm_impl.hpp"
 
@@ -153,6 +156,34 @@ using namespace cm;
         if (_e != hipSuccess) return hip_fail(_e, where); \
     } while (0)
 
+// Traversal table of the elements.  Blocks are dealt round-robin to the
+// eight XCDs, so XCD x works on the contiguous index range
+// [x q + min(x, r), +q + (x < r)) of n = 8 q + r elements; inside that range
+// the elements are visited in column tiles of TX x TY elements in (x, y)
+// over all layers of the range, so that most face neighbours of the
+// elements in flight on an XCD are in flight there too (shared L2).
+static void element_order(const cm_grid_desc& d, std::vector<int>& ord)
+{
+    constexpr int TX = 8, TY = 4;
+    const int64_t ne0 = d.ne[0], ne1 = d.ne[1], ne2 = d.ne[2];
+    const int64_t n = ne0 * ne1 * ne2, q = n / 8, r = n % 8;
+    const int64_t ntx = (ne0 + TX - 1) / TX;
+    ord.resize(n);
+    std::vector<std::pair<int64_t, int>> keyed;
+    for (int64_t x = 0; x < 8; ++x) {
+        const int64_t g0 = x * q + std::min(x, r), gs = q + (x < r ? 1 : 0);
+        keyed.resize(gs);
+        for (int64_t s = 0; s < gs; ++s) {
+            const int64_t e = g0 + s;
+            const int64_t ex = e % ne0, ey = (e / ne0) % ne1, ez = e / (ne0 * ne1);
+            const int64_t key = (((ey / TY * ntx + ex / TX) * ne2 + ez) * TY + ey % TY) * TX + ex % TX;
+            keyed[s] = {key, (int)e};
+        }
+        std::sort(keyed.begin(), keyed.end());
+        for (int64_t s = 0; s < gs; ++s) ord[g0 + s] = keyed[s].second;
+    }
+}
+
 extern "C" {
 
 const char* cm_last_error(void) { return g_err.c_str(); }
@@ -193,6 +224,13 @@ cm_status cm_grid_create(const cm_grid_desc* desc, int hip_device, cm_grid** out
         return CM_ERR_ALLOC;
     }
     hipError_t e = hipSetDevice(hip_device);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&g->n_cu, hipDeviceAttributeMultiprocessorCount, hip_device);
+    if (e == hipSuccess) {
+        std::vector<int> ord;
+        element_order(*desc, ord);
+        e = hipMalloc(&g->d_order, sizeof(int) * ord.size());
+        if (e == hipSuccess) e = hipMemcpy(g->d_order, ord.data(), sizeof(int) * ord.size(), hipMemcpyHostToDevice);
+    }
     if (e == hipSuccess && desc->topo == 1) {
         const int64_t nn = g->n_nodes;
         std::vector<double> m64(10 * nn);
@@ -225,6 +263,7 @@ cm_status cm_grid_destroy(cm_grid* g)
     if (g->d_metrics64) (void)hipFree(g->d_metrics64);
     if (g->d_metrics32) (void)hipFree(g->d_metrics32);
     if (g->d_z) (void)hipFree(g->d_z);
+    if (g->d_order) (void)hipFree(g->d_order);
     delete g;
     return CM_OK;
 }
@@ -374,6 +413,7 @@ cm_status cm_model_create(const cm_grid* g, const cm_model_desc* desc, const dou
     k.ne0 = g->desc.ne[0]; k.ne1 = g->desc.ne[1]; k.ne2 = g->desc.ne[2];
     k.per0 = g->desc.periodic[0] != 0; k.per1 = g->desc.periodic[1] != 0; k.per2 = g->desc.periodic[2] != 0;
     k.n_elem = (int)g->n_elem;
+    k.order = g->d_order;
     k.nn = nn;
     k.lo0 = g->desc.lo[0]; k.lo1 = g->desc.lo[1]; k.lo2 = g->desc.lo[2];
     k.h0 = g->h[0]; k.h1 = g->h[1]; k.h2 = g->h[2];

@@ -35,6 +35,7 @@ struct KParams {
     int ne0, ne1, ne2;
     int per0, per1, per2;
     int n_elem;
+    const int* order;           // per-XCD element traversal table [n_elem]
     int64_t nn;                 // nodes
     double lo0, lo1, lo2;
     double h0, h1, h2;          // element extents (Cartesian metrics)
@@ -84,6 +85,8 @@ struct cm_grid {
     double* d_metrics64 = nullptr;  // warped only: [10][nn]
     float* d_metrics32 = nullptr;
     double* d_z = nullptr;          // warped only: node heights
+    int* d_order = nullptr;         // element traversal table [n_elem]
+    int n_cu = 0;                   // compute units of the device
     double dmin = 0.0;
 };
 

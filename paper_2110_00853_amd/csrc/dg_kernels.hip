@@ -14,7 +14,8 @@
 //             dQ = A dQ + dt R, Y_new = Y + B dQ).
 // State layout [var][element][node], node = i + 5 j + 25 k, coalesced per
 // (variable, element) as a 125-word run.  Blocks are mapped to elements so
-// that each of the eight XCDs walks one contiguous range of elements.
+// that each of the eight XCDs walks one contiguous range of elements in a
+// tiled order.
 #include <cmath>
 
 #include "cm_impl.hpp"
@@ -71,14 +72,18 @@ __device__ __forceinline__ double fsqrt(double x)
 __device__ __forceinline__ float fsqrt(float x) { return sqrtf(x); }
 
 // ---------------------------------------------------------------------------
-// block -> element: blocks are dealt round-robin to the eight XCDs; give each
-// XCD one contiguous run of elements so neighbours share its L2.
+// block -> element: blocks are dealt round-robin to the eight XCDs, and XCD
+// x owns the contiguous index range [x q + min(x, r), +q + (x < r)) of the
+// n = 8 q + r elements, visited in the order of the grid's traversal table
+// (column tiles, so face neighbours share the XCD's L2)
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ int elem_of_block(int b, int n)
+__device__ __forceinline__ int elem_of_block(const KParams& P, int b)
 {
-    const int q = n >> 3;
-    if (b < (q << 3)) return (b & 7) * q + (b >> 3);
-    return b;
+    const int n = P.n_elem, q = n >> 3, r = n & 7;
+    int x, s;
+    if (b < (q << 3)) { x = b & 7; s = b >> 3; }
+    else { x = b - (q << 3); s = q; }
+    return P.order[x * q + (x < r ? x : r) + s];
 }
 
 // neighbour element across face (dir, side), -1 at a wall; ezn receives the
@@ -445,7 +450,7 @@ __global__ __launch_bounds__(BLOCK) void k_grad(const KParams P, const R* __rest
     __shared__ R sg[NG][BLOCK];        // gradient variables of the element
     __shared__ R sJ[3][NG][BLOCK];     // lift * (g* - g^-) per face direction
 
-    const int e = elem_of_block(blockIdx.x, P.n_elem);
+    const int e = elem_of_block(P, blockIdx.x);
     const int t = threadIdx.x;
     const bool act = t < NP;
     const int tt = act ? t : NP - 1;
@@ -701,37 +706,67 @@ __device__ __forceinline__ void f2_normal(const R* w, const R u[3], const R n[3]
     }
 }
 
-// data of one face task: own face node state, neighbour state and
-// diffusive flux (loaded before they are needed)
-template <typename R, bool MOIST, bool VISC>
+// normal component of a neighbour's stored diffusive flux on a flat mesh,
+// n = side e_dir, from the dir column of the flux (the words face_load keeps)
+template <typename R, bool MOIST>
+__device__ __forceinline__ void f2_normal_axis(const R* wq, const R u[3], R side, R out[])
+{
+    out[0] = MOIST ? side * wq[4] : (R)0;
+    out[1] = side * wq[0];
+    out[2] = side * wq[1];
+    out[3] = side * wq[2];
+    out[4] = side * wq[3];
+    if (MOIST) {
+        out[1] += out[0] * u[0];
+        out[2] += out[0] * u[1];
+        out[3] += out[0] * u[2];
+        out[5] = out[0];
+    }
+}
+
+// data of one face task: the neighbour's state, diffusive flux (all words on
+// warped meshes; on flat meshes only the column of the face direction:
+// tau_{x,dir}, tau_{y,dir}, tau_{z,dir}, energy and water flux along dir)
+// and reference pressure, loaded before they are needed; the own node's
+// state comes from LDS
+template <typename R, bool MOIST, bool WARP, bool VISC>
 struct FaceLoad {
     static constexpr int NV = MOIST ? 6 : 5;
     static constexpr int NW = MOIST ? 12 : 9;
+    static constexpr int NWF = WARP ? NW : (MOIST ? 5 : 4);
     int dir, sd, own, nbl, en, ezn;
-    R Ym[NV], Yp[NV], wp[VISC ? NW : 1];
+    R Yp[NV], wp[VISC ? NWF : 1];
     double prp;
 };
 
-template <typename R, bool MOIST, bool VISC>
+template <typename R, bool MOIST, bool WARP, bool VISC>
 __device__ __forceinline__ void face_load(const KParams& P, const R* __restrict__ Y, const R* __restrict__ F2,
-                                          int task, int e, int ex, int ey, int ez, FaceLoad<R, MOIST, VISC>& f)
+                                          int task, int e, int ex, int ey, int ez,
+                                          FaceLoad<R, MOIST, WARP, VISC>& f)
 {
-    constexpr int NV = FaceLoad<R, MOIST, VISC>::NV;
-    constexpr int NW = FaceLoad<R, MOIST, VISC>::NW;
+    constexpr int NV = FaceLoad<R, MOIST, WARP, VISC>::NV;
+    constexpr int NW = FaceLoad<R, MOIST, WARP, VISC>::NW;
     face_task(task, f.dir, f.sd, f.own, f.nbl);
     f.en = nbr_elem(P, ex, ey, ez, f.dir, f.sd ? 1 : -1, f.ezn);
     const int eo = f.en >= 0 ? f.en : e;  // walls read their own node twice
     const int ezo = f.en >= 0 ? f.ezn : ez;
     const int64_t nn = P.nn;
-    const int64_t onode = (int64_t)e * NP + f.own;
     const int64_t np = (int64_t)eo * NP + f.nbl;
-#pragma unroll
-    for (int v = 0; v < NV; ++v) f.Ym[v] = Y[v * nn + onode];
 #pragma unroll
     for (int v = 0; v < NV; ++v) f.Yp[v] = Y[v * nn + np];
     if (VISC) {
+        if (WARP) {
 #pragma unroll
-        for (int q = 0; q < NW; ++q) f.wp[q] = F2[q * nn + np];
+            for (int q = 0; q < NW; ++q) f.wp[q] = F2[q * nn + np];
+        } else {
+            // symmetric tau stored as xx yy zz xy xz yz: tau_{c,dir} is word
+            // c when c = dir, else 2 + c + dir
+            const int d = f.dir;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) f.wp[c] = F2[(c == d ? c : 2 + c + d) * nn + np];
+            f.wp[3] = F2[(6 + d) * nn + np];
+            if (MOIST) f.wp[4] = F2[(9 + d) * nn + np];
+        }
     }
     f.prp = P.pr[ref_index(P, eo, ezo, f.nbl / (NQ * NQ), f.nbl)];
 }
@@ -739,8 +774,8 @@ __device__ __forceinline__ void face_load(const KParams& P, const R* __restrict_
 // numerical flux of one face task; writes lift (n.F^- - n.F^*) over the
 // task's own-node entries of sG (the divergence is already done)
 template <typename R, bool MOIST, bool WARP, bool VISC>
-__device__ __forceinline__ void face_flux(const KParams& P, const FaceLoad<R, MOIST, VISC>& f, int e, int ex, int ey,
-                                          int ez, R (*sG)[BLOCK], R (*sP)[BLOCK])
+__device__ __forceinline__ void face_flux(const KParams& P, const FaceLoad<R, MOIST, WARP, VISC>& f, int e, int ex,
+                                          int ey, int ez, R (*sG)[BLOCK], R (*sP)[BLOCK], R (*sY)[BLOCK])
 {
     constexpr int NV = MOIST ? 6 : 5;
     const int64_t nn = P.nn;
@@ -753,6 +788,9 @@ __device__ __forceinline__ void face_flux(const KParams& P, const FaceLoad<R, MO
     const R um[3] = {sP[0][own], sP[1][own], sP[2][own]};
     const R cm = sP[3][own];
     const R unm = um[0] * n[0] + um[1] * n[1] + um[2] * n[2];
+    R Ym[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) Ym[v] = sY[v][own];
     R liftFm[NV];
 #pragma unroll
     for (int v = 0; v < NV; ++v) liftFm[v] = (R)side * sG[v * 3 + dir][own] * cJ;
@@ -769,7 +807,8 @@ __device__ __forceinline__ void face_flux(const KParams& P, const FaceLoad<R, MO
                                fp);
         if (VISC) {
             R fp2[NV];
-            f2_normal<R, MOIST>(f.wp, up, n, fp2);
+            if (WARP) f2_normal<R, MOIST>(f.wp, up, n, fp2);
+            else f2_normal_axis<R, MOIST>(f.wp, up, (R)side, fp2);
 #pragma unroll
             for (int v = 0; v < NV; ++v) fp[v] += fp2[v];
         }
@@ -778,21 +817,21 @@ __device__ __forceinline__ void face_flux(const KParams& P, const FaceLoad<R, MO
         const R lam = lm > lp ? lm : lp;
 #pragma unroll
         for (int v = 0; v < NV; ++v)
-            contrib[v] = (R)0.5 * (liftFm[v] - lift * fp[v]) - (R)0.5 * lift * lam * (f.Ym[v] - f.Yp[v]);
+            contrib[v] = (R)0.5 * (liftFm[v] - lift * fp[v]) - (R)0.5 * lift * lam * (Ym[v] - f.Yp[v]);
     } else {
         // reflecting ghost u+ = u- - 2 (n.u-) n with rho, rho e, rho q
         // mirrored: the Rusanov flux of (Y-, ghost) plus the prescribed wall
         // diffusive flux
         Th tm;
         const int ko = own / (NQ * NQ);
-        thermo<MOIST>((double)f.Ym[0], (double)f.Ym[1], (double)f.Ym[2], (double)f.Ym[3], (double)f.Ym[4],
-                      MOIST ? (double)f.Ym[NV - 1] : 0.0, node_z(P, e, ez, ko, own), P.g, tm);
-        const R rho = f.Ym[0];
+        thermo<MOIST>((double)Ym[0], (double)Ym[1], (double)Ym[2], (double)Ym[3], (double)Ym[4],
+                      MOIST ? (double)Ym[NV - 1] : 0.0, node_z(P, e, ez, ko, own), P.g, tm);
+        const R rho = Ym[0];
         // on a wall the "neighbour" slot holds this element's mirrored node,
         // whose reference pressure is not this node's: read this node's
         const double pro = P.pr[ref_index(P, e, ez, ko, own)];
         const R pp = (R)(tm.p - pro), ep = (R)(tm.rho * tm.e + tm.p);
-        const R rq = MOIST ? f.Ym[NV - 1] : (R)0;
+        const R rq = MOIST ? Ym[NV - 1] : (R)0;
         const R ug[3] = {um[0] - (R)2 * unm * n[0], um[1] - (R)2 * unm * n[1], um[2] - (R)2 * unm * n[2]};
         R f1m[NV], f1g[NV];
         flux1_normal<R, MOIST>(rho, um, pp, ep, rq, n, f1m);
@@ -801,7 +840,7 @@ __device__ __forceinline__ void face_flux(const KParams& P, const FaceLoad<R, MO
         R jumpY[NV];
 #pragma unroll
         for (int v = 0; v < NV; ++v) jumpY[v] = (R)0;
-        const R mn = f.Ym[1] * n[0] + f.Ym[2] * n[1] + f.Ym[3] * n[2];
+        const R mn = Ym[1] * n[0] + Ym[2] * n[1] + Ym[3] * n[2];
         jumpY[1] = (R)2 * mn * n[0];
         jumpY[2] = (R)2 * mn * n[1];
         jumpY[3] = (R)2 * mn * n[2];
@@ -838,9 +877,9 @@ __global__ __launch_bounds__(BLOCK) void k_tend(const KParams P, const R* __rest
     // of (n.F^- - n.F^*)
     __shared__ R sG[NV * 3][BLOCK];
     __shared__ R sP[4][BLOCK];  // u, v, w, c
-    __shared__ R sR[NV][BLOCK];
+    __shared__ R sY[NV][BLOCK]; // own state, for the face tasks
 
-    const int e = elem_of_block(blockIdx.x, P.n_elem);
+    const int e = elem_of_block(P, blockIdx.x);
     const int t = threadIdx.x;
     const bool act = t < NP;
     const int tt = act ? t : NP - 1;
@@ -875,10 +914,8 @@ __global__ __launch_bounds__(BLOCK) void k_tend(const KParams P, const R* __rest
 #pragma unroll
         for (int q = 0; q < 9; ++q) Jam[q / 3][q % 3] = m[(int64_t)q * nn + node];
     }
-#ifndef CM_NO_FACE_PREFETCH
-    FaceLoad<R, MOIST, VISC> ft0;
-    face_load<R, MOIST, VISC>(P, Y, F2, t, e, ex, ey, ez, ft0);
-#endif
+    FaceLoad<R, MOIST, WARP, VISC> ft0;
+    face_load<R, MOIST, WARP, VISC>(P, Y, F2, t, e, ex, ey, ez, ft0);
     double rho_d, mom_d[3];
     {
         Th th;
@@ -891,6 +928,8 @@ __global__ __launch_bounds__(BLOCK) void k_tend(const KParams P, const R* __rest
         const R um[3] = {(R)th.u, (R)th.v, (R)th.w};
         sP[0][t] = um[0]; sP[1][t] = um[1]; sP[2][t] = um[2];
         sP[3][t] = (R)th.c;
+#pragma unroll
+        for (int v = 0; v < NV; ++v) sY[v][t] = Yr[v];
         if (VISC) {
 #pragma unroll
             for (int d = 0; d < 3; ++d) {
@@ -914,8 +953,12 @@ __global__ __launch_bounds__(BLOCK) void k_tend(const KParams P, const R* __rest
     __syncthreads();
 
     // phase B: strong-form divergence with the 1-D GLL matrix, one variable
-    // at a time into LDS (unrolled over variables the compiler keeps every
-    // tile load in flight and runs out of registers)
+    // at a time (unrolled over variables the compiler keeps every tile load
+    // in flight and runs out of registers); the result goes to its register
+    // by a select, not an indexed write
+    R Rv[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) Rv[v] = 0;
 #pragma unroll 1
     for (int v = 0; v < NV; ++v) {
         R s = 0;
@@ -925,29 +968,23 @@ __global__ __launch_bounds__(BLOCK) void k_tend(const KParams P, const R* __rest
             s += dmat<R>(j, l) * sG[v * 3 + 1][i + NQ * (l + NQ * k)];
             s += dmat<R>(k, l) * sG[v * 3 + 2][i + NQ * (j + NQ * l)];
         }
-        sR[v][t] = -s;
+#pragma unroll
+        for (int u = 0; u < NV; ++u) Rv[u] = u == v ? -s : Rv[u];
     }
     __syncthreads();
 
     // phase C: face tasks.  lift (n.F^- - n.F^*): n.F^- comes from the
     // contravariant flux already in LDS (lift n.F = side G^dir / (J w_N)).
     // The first task's loads were issued at kernel entry (ft0).
-#ifdef CM_NO_FACE_PREFETCH
-    FaceLoad<R, MOIST, VISC> ft0;
-    face_load<R, MOIST, VISC>(P, Y, F2, t, e, ex, ey, ez, ft0);
-#endif
-    face_flux<R, MOIST, WARP, VISC>(P, ft0, e, ex, ey, ez, sG, sP);
+    face_flux<R, MOIST, WARP, VISC>(P, ft0, e, ex, ey, ez, sG, sP, sY);
     if (t + BLOCK < 150) {
-        FaceLoad<R, MOIST, VISC> ft1;
-        face_load<R, MOIST, VISC>(P, Y, F2, t + BLOCK, e, ex, ey, ez, ft1);
-        face_flux<R, MOIST, WARP, VISC>(P, ft1, e, ex, ey, ez, sG, sP);
+        FaceLoad<R, MOIST, WARP, VISC> ft1;
+        face_load<R, MOIST, WARP, VISC>(P, Y, F2, t + BLOCK, e, ex, ey, ez, ft1);
+        face_flux<R, MOIST, WARP, VISC>(P, ft1, e, ex, ey, ez, sG, sP, sY);
     }
     __syncthreads();
 
     // phase D: gather the face terms of this node, metric factor, sources
-    R Rv[NV];
-#pragma unroll
-    for (int v = 0; v < NV; ++v) Rv[v] = sR[v][t];
     const int idx[3] = {i, j, k};
     if (WARP) {
         const R invJ = ((const R*)P.metrics)[9 * nn + node];

@@ -47,3 +47,20 @@ def state_errors(Yg, Yref):
 
 def hmin(grid):
     return float(min((np.array(grid["hi"], float) - np.array(grid["lo"], float)) / np.array(grid["ne"], float)))
+
+
+def rounding_floor(rhs, Y, h, draws=2, seed=1):
+    """How far the oracle's own tendency moves, in the rhs_errors metric,
+    when every input word is perturbed by at most one unit in the last place
+    (random sign, a third left unchanged).  Two FP64 implementations that
+    differ only in rounding cannot be expected to agree much closer than
+    this; where it exceeds the 1e-11 target (moist states, whose pressure
+    and temperature come out of the saturation adjustment), the tolerance is
+    a small multiple of it."""
+    R0 = rhs(Y)
+    rng = np.random.default_rng(seed)
+    fl = np.zeros(Y.shape[0])
+    for _ in range(draws):
+        Yp = Y * (1.0 + 2.2e-16 * rng.choice([-1.0, 0.0, 1.0], size=Y.shape))
+        fl = np.maximum(fl, rhs_errors(rhs(Yp), R0, Y, h))
+    return R0, fl
