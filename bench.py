@@ -8,12 +8,17 @@ correction, FP64.  Inputs are synthetic and resident in HBM before timing.
 
 Prints ONE JSON line: DOF-updates/s = nodes x vars x 5 stages x steps / t,
 the roofline of the dominant kernel (tendency pass) from hipEvents around
-every launch in the timed region, the FP32-bulk variant, and the FP64 CPU
-oracle timed on this host on whole steps of the same workload.
+every launch in the timed region, the FP32-bulk variant, the learned-closure
+variant (fused BF16 network in the gradient pass), and the FP64 CPU oracle
+timed on this host on whole steps of the same workload.  The HBM traffic of
+the tendency pass comes from the rocprofv3 counter summary under profiles/
+when that summary was taken on the current kernel source (same SHA-256),
+else it is null.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -23,6 +28,23 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, vendor figure
+KERNEL_SRC = os.path.join(ROOT, "paper_2110_00853_amd", "csrc", "dg_kernels.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_tend_bubble32_fp64.json")
+MLP_WEIGHTS = os.path.join(ROOT, "paper_2110_00853_amd", "data", "mlp_bubble64_to_32.npz")
+
+
+def measured_traffic(case: str):
+    """Counter-derived HBM bytes per tendency launch, if the summary matches
+    the kernel source being timed."""
+    if case != "bubble_32" or not os.path.exists(TRAFFIC_FILE):
+        return None
+    with open(KERNEL_SRC, "rb") as f:
+        sha = hashlib.sha256(f.read()).hexdigest()
+    with open(TRAFFIC_FILE) as f:
+        t = json.load(f)
+    if t.get("kernel_source_sha256") != sha:
+        return None
+    return t["hbm_bytes_per_launch"]
 
 
 def alg_bytes(nvar: int, nf: int, s: int):
@@ -52,8 +74,10 @@ def run(args):
     grid = B.Grid(c["grid"], device=0)
     nn, nvar = grid.n_nodes, c["model"]["nvar"]
 
-    def timed(precision: str, steps: int, warmup: int):
-        m = B.Model(grid, c["model"], Yref, precision=precision)
+    def timed(precision: str, steps: int, warmup: int, model=None, mlp=None):
+        m = B.Model(grid, model or c["model"], Yref, precision=precision)
+        if mlp is not None:
+            m.set_mlp(*mlp)
         Ya, Yb, dQ = m.new_state(Y0), m.new_state(), m.new_state()
         stream = torch.cuda.current_stream()
         t = 0.0
@@ -118,7 +142,7 @@ def run(args):
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": None,
+            "traffic": measured_traffic(args.case),
             "avg_launch_us": tend_avg_s * 1e6,
             "alg_bytes_per_launch": tend_bytes,
             "grad_kernel": {"avg_launch_us": grad_avg_s * 1e6,
@@ -143,12 +167,47 @@ def run(args):
             "note": "warmup+steps LSRK54 steps from the same initial state; max-norm error per variable",
         }
         del m32, Y32
+    if not args.no_learned and c["model"].get("closure") == "smag":
+        params, norm, origin = mlp_weights(B, grid, c, Yref, Y0)
+        mdl = dict(c["model"], closure="mlp")
+        mL, YL, msL, _, profL, _ = timed("fp64", args.steps, args.warmup, model=mdl, mlp=(params, norm))
+        vL = nn * nvar * 5 * args.steps / (msL * 1e-3)
+        fb = mL.mlp_fallbacks() / float(nn * 5 * (args.steps + args.warmup))
+        gL_ms, gL_n = profL["grad"]
+        out["learned_closure"] = {
+            "value": vL, "ms_per_step": msL / args.steps, "speedup_vs_fp64_smagorinsky": vL / value,
+            "grad_kernel_avg_launch_us": gL_ms * 1e3 / gL_n,
+            "fallback_fraction": fb, "weights": origin,
+            "note": "FP64 state and fluxes; 12-64-64-64-2 SiLU network in BF16 MFMA (FP32 accumulate) "
+                    "fused into the gradient pass, Smagorinsky-Lilly fallback",
+        }
+        del mL, YL
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(c, Y0, Yref, nn, nvar, dt)
     return out
 
 
-def cpu_baseline(c, Y0, Yref, nn, nvar, dt, budget_s=10.0, max_steps=6):
+def mlp_weights(B, grid, c, Yref, Y0):
+    """Trained weights of the learned closure if the package holds them,
+    else a seeded random initialisation standardised on this state's inputs
+    (the cost of the fused network does not depend on its weights)."""
+    import numpy as np
+    import torch
+
+    if os.path.exists(MLP_WEIGHTS):
+        z = np.load(MLP_WEIGHTS)
+        return z["params"], z["norm"], "trained: 2x coarse-grained 64^3 bubble run"
+    m = B.Model(grid, dict(c["model"], closure="smag", richardson=True), Yref)
+    f = m.closure_inputs(m.new_state(Y0))[:, :12]
+    mean, std = f.mean(0), f.std(0)
+    std = torch.where(std > 0, std, torch.ones_like(std))
+    xn = (f - mean) / std
+    norm = torch.cat([mean, std, xn.min(0).values, xn.max(0).values]).cpu().numpy()
+    del m, f, xn
+    return B.MLP(seed=0).params(), norm, "seeded random initialisation"
+
+
+def cpu_baseline(c, Y0, Yref, nn, nvar, dt, budget_s=15.0, max_steps=40):
     """The FP64 oracle on this host, as it stands: whole LSRK54 steps of the
     same workload, repeated until about budget_s seconds of CPU work."""
     import oracle
@@ -183,6 +242,7 @@ def main():
     ap.add_argument("--ne", default=None, help="override element counts, e.g. 16,16,16")
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 1 GiB device copy (for scaling HBM byte counters)")
     args = ap.parse_args()

@@ -298,93 +298,102 @@ __device__ __forceinline__ void face_normal(const KParams& P, int64_t node, int 
 
 // ---------------------------------------------------------------------------
 // learned closure: fused BF16-MFMA forward of the 12-64-64-64-2 SiLU network
-// for the 128 rows (nodes) of one element.  Wave w owns rows 64w..64w+63
-// (four 16-row tiles).  Inputs sX [128][20] and activations sH [128][68]
-// are bf16 in LDS (rows padded against bank conflicts); the B operands are
-// the pre-packed weight fragments; outputs sO [128][2] FP32.
+// for the 64 nodes (rows) of one wave, in the transposed form
+// Z^T = W Z_prev^T: the pre-packed weight tiles are the A operands and the
+// activations the B operands.  A layer's accumulator tile holds, per lane,
+// four consecutive hidden units of one node, which after bias, SiLU and
+// conversion to bf16 is the next layer's B operand as it stands, so the
+// layers chain in registers with no LDS traffic or barrier between them.
+// Inputs sX [128][20] bf16 in LDS (each wave reads only its own rows).
 // ---------------------------------------------------------------------------
-constexpr int MLP_XS = 20, MLP_HS = 68;
+constexpr int MLP_XS = 20;
 
-__device__ __forceinline__ void mlp_layer_epilogue(const f32x4 (&acc)[4][4], const float* __restrict__ bias,
-                                                   uint16_t (*sH)[MLP_HS], int row0, int lane)
+typedef __bf16 bf16x2v __attribute__((ext_vector_type(2)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
+
+// SiLU from the hardware exp2 and reciprocal estimates (FP32, a few ulp;
+// the result is rounded to bf16 next)
+__device__ __forceinline__ float silu_fast(float z)
 {
-    const int r = lane & 15, kq = (lane >> 4) * 4;
-#pragma unroll
-    for (int rt = 0; rt < 4; ++rt)
-#pragma unroll
-        for (int ct = 0; ct < 4; ++ct) {
-            const float b = bias[16 * ct + r];
-#pragma unroll
-            for (int q = 0; q < 4; ++q) sH[row0 + 16 * rt + kq + q][16 * ct + r] = f2bf(silu_f(acc[rt][ct][q] + b));
-        }
+    return z * __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(-1.4426950408889634f * z));
 }
 
-__device__ void mlp_forward_element(const KParams& P, uint16_t (*sX)[MLP_XS], uint16_t (*sH)[MLP_HS],
-                                    float (*sO)[2])
+// bias + SiLU of one accumulator tile, rounded to bf16 (nearest even)
+__device__ __forceinline__ bf16x4 act_bf16(const f32x4& d, const float4& b)
 {
-    const int lane = threadIdx.x & 63, row0 = (threadIdx.x >> 6) * 64;
+    const f32x2 lo = {silu_fast(d[0] + b.x), silu_fast(d[1] + b.y)};
+    const f32x2 hi = {silu_fast(d[2] + b.z), silu_fast(d[3] + b.w)};
+    const u32x2 u = {__builtin_bit_cast(unsigned, __builtin_convertvector(lo, bf16x2v)),
+                     __builtin_bit_cast(unsigned, __builtin_convertvector(hi, bf16x2v))};
+    return __builtin_bit_cast(bf16x4, u);
+}
+
+// raw outputs (o0, o1) of the node of this lane; row0 = first row of the wave
+__device__ __forceinline__ void mlp_forward_wave(const KParams& P, const uint16_t (*sX)[MLP_XS], int row0, float& o0,
+                                                 float& o1)
+{
+    const int lane = threadIdx.x & 63;
     const int r = lane & 15, kq = (lane >> 4) * 4;
     const bf16x4* frag = (const bf16x4*)P.mlp_frag;
-    f32x4 acc[4][4];
+    const float* bias = P.mlp_bias;
+    bf16x4 h[4][4];  // activations [hidden tile][node tile]
     // layer 1: K = 16 (12 inputs, zero padded)
+    bf16x4 xin[4];
 #pragma unroll
-    for (int ct = 0; ct < 4; ++ct) {
-        const bf16x4 b = frag[(0 * 4 + ct) * 64 + lane];
+    for (int nt = 0; nt < 4; ++nt) xin[nt] = *(const bf16x4*)&sX[row0 + 16 * nt + r][kq];
 #pragma unroll
-        for (int rt = 0; rt < 4; ++rt) {
-            const bf16x4 a = *(const bf16x4*)&sX[row0 + 16 * rt + r][kq];
-            acc[rt][ct] = mfma16(a, b, f32x4{0.0f, 0.0f, 0.0f, 0.0f});
-        }
+    for (int ht = 0; ht < 4; ++ht) {
+        const bf16x4 a = frag[ht * 64 + lane];
+        const float4 b = *(const float4*)&bias[16 * ht + kq];
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt)
+            h[ht][nt] = act_bf16(mfma16(a, xin[nt], f32x4{0.0f, 0.0f, 0.0f, 0.0f}), b);
     }
-    __syncthreads();
-    mlp_layer_epilogue(acc, P.mlp_bias, sH, row0, lane);
-    __syncthreads();
     // layers 2 and 3: K = 64
-#pragma unroll 1
+#pragma unroll
     for (int layer = 0; layer < 2; ++layer) {
-        const int fbase = FRAG_L1 + layer * FRAG_L2;
+        f32x4 acc[4][4];
 #pragma unroll
-        for (int rt = 0; rt < 4; ++rt)
+        for (int ht = 0; ht < 4; ++ht)
 #pragma unroll
-            for (int ct = 0; ct < 4; ++ct) acc[rt][ct] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+            for (int nt = 0; nt < 4; ++nt) acc[ht][nt] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
-        for (int ks = 0; ks < 4; ++ks) {
-            bf16x4 a[4];
+        for (int ht = 0; ht < 4; ++ht)
 #pragma unroll
-            for (int rt = 0; rt < 4; ++rt) a[rt] = *(const bf16x4*)&sH[row0 + 16 * rt + r][16 * ks + kq];
+            for (int ks = 0; ks < 4; ++ks) {
+                const bf16x4 a = frag[(FRAG_L1 + layer * FRAG_L2 + 4 * ht + ks) * 64 + lane];
 #pragma unroll
-            for (int ct = 0; ct < 4; ++ct) {
-                const bf16x4 b = frag[(fbase + ks * 4 + ct) * 64 + lane];
-#pragma unroll
-                for (int rt = 0; rt < 4; ++rt) acc[rt][ct] = mfma16(a[rt], b, acc[rt][ct]);
+                for (int nt = 0; nt < 4; ++nt) acc[ht][nt] = mfma16(a, h[ks][nt], acc[ht][nt]);
             }
-        }
-        __syncthreads();
-        mlp_layer_epilogue(acc, P.mlp_bias + 64 * (layer + 1), sH, row0, lane);
-        __syncthreads();
-    }
-    // layer 4: N = 2 (one 16-column tile, zero padded)
-    f32x4 o[4];
 #pragma unroll
-    for (int rt = 0; rt < 4; ++rt) o[rt] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
-    const int f4 = FRAG_L1 + FRAG_L2 + FRAG_L3;
+        for (int ht = 0; ht < 4; ++ht) {
+            const float4 b = *(const float4*)&bias[64 * (layer + 1) + 16 * ht + kq];
+#pragma unroll
+            for (int nt = 0; nt < 4; ++nt) h[ht][nt] = act_bf16(acc[ht][nt], b);
+        }
+    }
+    // layer 4: one 16-row output tile (rows 0 and 1 real)
+    f32x4 out[4];
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt) out[nt] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
     for (int ks = 0; ks < 4; ++ks) {
-        const bf16x4 b = frag[(f4 + ks) * 64 + lane];
+        const bf16x4 a = frag[(FRAG_L1 + FRAG_L2 + FRAG_L3 + ks) * 64 + lane];
 #pragma unroll
-        for (int rt = 0; rt < 4; ++rt) {
-            const bf16x4 a = *(const bf16x4*)&sH[row0 + 16 * rt + r][16 * ks + kq];
-            o[rt] = mfma16(a, b, o[rt]);
-        }
+        for (int nt = 0; nt < 4; ++nt) out[nt] = mfma16(a, h[ks][nt], out[nt]);
     }
-    if (r < 2) {
-        const float b = P.mlp_bias[192 + r];
+    // lane r < 16 holds rows 0..3 of node 16 nt + r: move outputs 0 and 1 to
+    // the lane that owns the node (16 nt + r)
+    float v0 = 0.0f, v1 = 0.0f;
 #pragma unroll
-        for (int rt = 0; rt < 4; ++rt)
-#pragma unroll
-            for (int q = 0; q < 4; ++q) sO[row0 + 16 * rt + kq + q][r] = o[rt][q] + b;
+    for (int nt = 0; nt < 4; ++nt) {
+        const float s0 = __shfl(out[nt][0], r);
+        const float s1 = __shfl(out[nt][1], r);
+        if ((lane >> 4) == nt) { v0 = s0; v1 = s1; }
     }
-    __syncthreads();
+    o0 = v0 + bias[192];
+    o1 = v1 + bias[193];
 }
 
 __device__ __forceinline__ double softplus_d(double x) { return x > 30.0 ? x : log1p(exp(x)); }
@@ -565,8 +574,6 @@ __global__ __launch_bounds__(BLOCK) void k_grad(const KParams P, const R* __rest
             // filter width, TKE estimate (nu_SL / (0.1 Delta))^2), fused
             // network on the element's nodes, Smagorinsky fallback
             __shared__ uint16_t sX[BLOCK][MLP_XS];
-            __shared__ uint16_t sH[BLOCK][MLP_HS];
-            __shared__ float sO[BLOCK][2];
             double raw[12];
 #pragma unroll
             for (int a = 0; a < 3; ++a)
@@ -588,14 +595,15 @@ __global__ __launch_bounds__(BLOCK) void k_grad(const KParams P, const R* __rest
 #pragma unroll
             for (int q = 12; q < MLP_XS; ++q) sX[t][q] = 0;
             __syncthreads();
-            mlp_forward_element(P, sX, sH, sO);
+            float o0, o1;
+            mlp_forward_wave(P, sX, (threadIdx.x >> 6) * 64, o0, o1);
             double SSd = 0.0;
 #pragma unroll
             for (int a = 0; a < 3; ++a)
 #pragma unroll
                 for (int b = 0; b < 3; ++b) SSd += 2.0 * (double)S[a][b] * (double)S[a][b];
-            const double nu_m = P.Delta * P.Delta * sqrt(SSd) * softplus_d((double)sO[t][0]);
-            const double pr_m = 0.1 + softplus_d((double)sO[t][1]);
+            const double nu_m = P.Delta * P.Delta * sqrt(SSd) * softplus_d((double)o0);
+            const double pr_m = 0.1 + softplus_d((double)o1);
             const bool fb = P.mlp_fallback_on && (out_of_range || !isfinite(nu_m) || !isfinite(pr_m));
             if (!fb) {
                 nu = (R)nu_m;
@@ -768,7 +776,10 @@ __device__ __forceinline__ void face_load(const KParams& P, const R* __restrict_
             if (MOIST) f.wp[4] = F2[(9 + d) * nn + np];
         }
     }
-    f.prp = P.pr[ref_index(P, eo, ezo, f.nbl / (NQ * NQ), f.nbl)];
+    // reference pressure of the neighbour node; on a wall the neighbour slot
+    // holds this element's mirrored node, and the flux needs this node's
+    const int rn = f.en >= 0 ? f.nbl : f.own;
+    f.prp = P.pr[ref_index(P, eo, ezo, rn / (NQ * NQ), rn)];
 }
 
 // numerical flux of one face task; writes lift (n.F^- - n.F^*) over the
@@ -827,10 +838,7 @@ __device__ __forceinline__ void face_flux(const KParams& P, const FaceLoad<R, MO
         thermo<MOIST>((double)Ym[0], (double)Ym[1], (double)Ym[2], (double)Ym[3], (double)Ym[4],
                       MOIST ? (double)Ym[NV - 1] : 0.0, node_z(P, e, ez, ko, own), P.g, tm);
         const R rho = Ym[0];
-        // on a wall the "neighbour" slot holds this element's mirrored node,
-        // whose reference pressure is not this node's: read this node's
-        const double pro = P.pr[ref_index(P, e, ez, ko, own)];
-        const R pp = (R)(tm.p - pro), ep = (R)(tm.rho * tm.e + tm.p);
+        const R pp = (R)(tm.p - f.prp), ep = (R)(tm.rho * tm.e + tm.p);
         const R rq = MOIST ? Ym[NV - 1] : (R)0;
         const R ug[3] = {um[0] - (R)2 * unm * n[0], um[1] - (R)2 * unm * n[1], um[2] - (R)2 * unm * n[2]};
         R f1m[NV], f1g[NV];
@@ -864,78 +872,91 @@ __device__ __forceinline__ void face_flux(const KParams& P, const FaceLoad<R, MO
     for (int v = 0; v < NV; ++v) sG[v * 3 + dir][own] = contrib[v];
 }
 
-// MODE 0: out = R; MODE 1: LSRK stage; MODE 2: first LSRK stage (A = 0, dQ not read)
+// own-node data of one element
 template <typename R, bool MOIST, bool WARP, bool VISC, int MODE>
-__global__ __launch_bounds__(BLOCK) void k_tend(const KParams P, const R* __restrict__ Y, const R* __restrict__ F2,
-                                                R* __restrict__ out, R* __restrict__ dQ, R A, R B, R dt)
+struct OwnLoad {
+    static constexpr int NV = MOIST ? 6 : 5;
+    static constexpr int NW = MOIST ? 12 : 9;
+    static constexpr int NWS = NW + (MOIST ? 2 : 1);  // with the subsidence words
+    R Yr[NV];
+    R w[VISC ? NWS : 1];
+    R dq[MODE == 1 ? NV : 1];
+    R Jam[WARP ? 9 : 1];
+    double pr, rr;
+};
+
+template <typename R, bool MOIST, bool WARP, bool VISC, int MODE>
+__device__ __forceinline__ void own_load(const KParams& P, const R* __restrict__ Y, const R* __restrict__ F2,
+                                         const R* __restrict__ dQ, int e, int ez, int tt,
+                                         OwnLoad<R, MOIST, WARP, VISC, MODE>& o)
+{
+    using O = OwnLoad<R, MOIST, WARP, VISC, MODE>;
+    const int64_t nn = P.nn;
+    const int64_t node = (int64_t)e * NP + tt;
+#pragma unroll
+    for (int v = 0; v < O::NV; ++v) o.Yr[v] = Y[v * nn + node];
+    if (VISC) {
+        const int nw = P.subsidence ? O::NWS : O::NW;
+#pragma unroll
+        for (int q = 0; q < O::NWS; ++q) o.w[q] = q < nw ? F2[q * nn + node] : (R)0;
+    }
+    if (MODE == 1) {
+#pragma unroll
+        for (int v = 0; v < O::NV; ++v) o.dq[v] = dQ[v * nn + node];
+    }
+    const int ri = ref_index(P, e, ez, tt / (NQ * NQ), tt);
+    o.pr = P.pr[ri];
+    o.rr = P.rhor[ri];
+    if (WARP) {
+        const R* m = (const R*)P.metrics;
+#pragma unroll
+        for (int q = 0; q < 9; ++q) o.Jam[q] = m[(int64_t)q * nn + node];
+    }
+}
+
+// the tendency of one element from its loaded data: thermodynamics ->
+// contravariant flux in LDS -> divergence -> face tasks -> sources ->
+// epilogue.  MODE 0: out = R; MODE 1: LSRK stage; MODE 2: first LSRK stage
+// (A = 0, dQ not read).  The second face task (t + BLOCK < 150) is loaded
+// here unless the caller already did (ft1_loaded).
+template <typename R, bool MOIST, bool WARP, bool VISC, int MODE>
+__device__ __forceinline__ void tend_element(const KParams& P, int e, int t,
+                                             const OwnLoad<R, MOIST, WARP, VISC, MODE>& o,
+                                             const FaceLoad<R, MOIST, WARP, VISC>& ft0,
+                                             FaceLoad<R, MOIST, WARP, VISC>& ft1, bool ft1_loaded,
+                                             R (*sG)[BLOCK], R (*sP)[BLOCK], R (*sY)[BLOCK],
+                                             const R* __restrict__ Y, const R* __restrict__ F2,
+                                             R* __restrict__ out, R* __restrict__ dQ, R A, R B, R dt)
 {
     constexpr int NV = MOIST ? 6 : 5;
     constexpr int NW = MOIST ? 12 : 9;
-    constexpr int NWS = NW + (MOIST ? 2 : 1);  // with the subsidence words
-    // contravariant total flux J a^d . F per (variable, direction); after the
-    // divergence each face task overwrites its own-node entry with the lift
-    // of (n.F^- - n.F^*)
-    __shared__ R sG[NV * 3][BLOCK];
-    __shared__ R sP[4][BLOCK];  // u, v, w, c
-    __shared__ R sY[NV][BLOCK]; // own state, for the face tasks
-
-    const int e = elem_of_block(P, blockIdx.x);
-    const int t = threadIdx.x;
     const bool act = t < NP;
     const int tt = act ? t : NP - 1;
     const int i = tt % NQ, j = (tt / NQ) % NQ, k = tt / (NQ * NQ);
     const int ex = e % P.ne0, ey = (e / P.ne0) % P.ne1, ez = e / (P.ne0 * P.ne1);
     const int64_t nn = P.nn;
-    const int64_t ebase = (int64_t)e * NP;
-    const int64_t node = ebase + tt;
-
-    // phase A: own node (loads first; the first face task's loads follow so
-    // their latency overlaps phase A, while the in-order load counter lets
-    // phase A start as soon as the own-node data is in)
-    R Yr[NV], dq_old[NV], w[NWS];
-#pragma unroll
-    for (int v = 0; v < NV; ++v) Yr[v] = Y[v * nn + node];
-    if (VISC) {
-        const int nw = P.subsidence ? NWS : NW;
-#pragma unroll
-        for (int q = 0; q < NWS; ++q) w[q] = q < nw ? F2[q * nn + node] : (R)0;
-    }
-    if (MODE == 1) {
-#pragma unroll
-        for (int v = 0; v < NV; ++v) dq_old[v] = dQ[v * nn + node];
-    }
-    const int ri = ref_index(P, e, ez, k, tt);
-    const double pr = P.pr[ri];
-    const double rr = P.rhor[ri];
+    const int64_t node = (int64_t)e * NP + tt;
     const double z = node_z(P, e, ez, k, tt);
-    R Jam[3][3];
-    if (WARP) {
-        const R* m = (const R*)P.metrics;
-#pragma unroll
-        for (int q = 0; q < 9; ++q) Jam[q / 3][q % 3] = m[(int64_t)q * nn + node];
-    }
-    FaceLoad<R, MOIST, WARP, VISC> ft0;
-    face_load<R, MOIST, WARP, VISC>(P, Y, F2, t, e, ex, ey, ez, ft0);
     double rho_d, mom_d[3];
     {
         Th th;
-        thermo<MOIST>((double)Yr[0], (double)Yr[1], (double)Yr[2], (double)Yr[3], (double)Yr[4],
-                      MOIST ? (double)Yr[NV - 1] : 0.0, z, P.g, th);
+        thermo<MOIST>((double)o.Yr[0], (double)o.Yr[1], (double)o.Yr[2], (double)o.Yr[3], (double)o.Yr[4],
+                      MOIST ? (double)o.Yr[NV - 1] : 0.0, z, P.g, th);
         rho_d = th.rho;
-        mom_d[0] = (double)Yr[1]; mom_d[1] = (double)Yr[2]; mom_d[2] = (double)Yr[3];
+        mom_d[0] = (double)o.Yr[1]; mom_d[1] = (double)o.Yr[2]; mom_d[2] = (double)o.Yr[3];
         R F[NV][3];
-        flux1<R, MOIST>(th, pr, F);
+        flux1<R, MOIST>(th, o.pr, F);
         const R um[3] = {(R)th.u, (R)th.v, (R)th.w};
         sP[0][t] = um[0]; sP[1][t] = um[1]; sP[2][t] = um[2];
         sP[3][t] = (R)th.c;
 #pragma unroll
-        for (int v = 0; v < NV; ++v) sY[v][t] = Yr[v];
+        for (int v = 0; v < NV; ++v) sY[v][t] = o.Yr[v];
         if (VISC) {
 #pragma unroll
             for (int d = 0; d < 3; ++d) {
                 const R nd[3] = {d == 0 ? (R)1 : (R)0, d == 1 ? (R)1 : (R)0, d == 2 ? (R)1 : (R)0};
                 R f2[NV];
-                f2_normal<R, MOIST>(w, um, nd, f2);
+                f2_normal<R, MOIST>(o.w, um, nd, f2);
 #pragma unroll
                 for (int v = 0; v < NV; ++v) F[v][d] += f2[v];
             }
@@ -945,7 +966,7 @@ __global__ __launch_bounds__(BLOCK) void k_tend(const KParams P, const R* __rest
 #pragma unroll
             for (int d = 0; d < 3; ++d) {
                 R G;
-                if (WARP) G = Jam[d][0] * F[v][0] + Jam[d][1] * F[v][1] + Jam[d][2] * F[v][2];
+                if (WARP) G = o.Jam[3 * d] * F[v][0] + o.Jam[3 * d + 1] * F[v][1] + o.Jam[3 * d + 2] * F[v][2];
                 else G = (R)(d == 0 ? P.r2h0 : (d == 1 ? P.r2h1 : P.r2h2)) * F[v][d];
                 sG[v * 3 + d][t] = G;
             }
@@ -978,8 +999,7 @@ __global__ __launch_bounds__(BLOCK) void k_tend(const KParams P, const R* __rest
     // The first task's loads were issued at kernel entry (ft0).
     face_flux<R, MOIST, WARP, VISC>(P, ft0, e, ex, ey, ez, sG, sP, sY);
     if (t + BLOCK < 150) {
-        FaceLoad<R, MOIST, WARP, VISC> ft1;
-        face_load<R, MOIST, WARP, VISC>(P, Y, F2, t + BLOCK, e, ex, ey, ez, ft1);
+        if (!ft1_loaded) face_load<R, MOIST, WARP, VISC>(P, Y, F2, t + BLOCK, e, ex, ey, ez, ft1);
         face_flux<R, MOIST, WARP, VISC>(P, ft1, e, ex, ey, ez, sG, sP, sY);
     }
     __syncthreads();
@@ -997,7 +1017,7 @@ __global__ __launch_bounds__(BLOCK) void k_tend(const KParams P, const R* __rest
 #pragma unroll
         for (int v = 0; v < NV; ++v) Rv[v] += sG[v * 3 + dir][t];
     }
-    Rv[3] -= (R)((rho_d - rr) * P.g);
+    Rv[3] -= (R)((rho_d - o.rr) * P.g);
     if (P.f_cor != 0.0) {
         Rv[1] += (R)(P.f_cor * (mom_d[1] - rho_d * P.v_g));
         Rv[2] -= (R)(P.f_cor * (mom_d[0] - rho_d * P.u_g));
@@ -1013,8 +1033,8 @@ __global__ __launch_bounds__(BLOCK) void k_tend(const KParams P, const R* __rest
         const double zz = z < P.sub_ztop ? z : P.sub_ztop;
         const double ws = -P.sub_w0 * sin(M_PI * zz * P.sub_inv);
         const R rws = (R)(rho_d * ws);
-        Rv[4] -= rws * w[NW];
-        if (MOIST) Rv[NV - 1] -= rws * w[NW + 1];
+        Rv[4] -= rws * o.w[NW];
+        if (MOIST) Rv[NV - 1] -= rws * o.w[NW + 1];
     }
 
     if (!act) return;
@@ -1024,12 +1044,41 @@ __global__ __launch_bounds__(BLOCK) void k_tend(const KParams P, const R* __rest
         if (MODE == 0) {
             out[a] = Rv[v];
         } else {
-            const R dq = MODE == 1 ? A * dq_old[v] + dt * Rv[v] : dt * Rv[v];
+            const R dq = MODE == 1 ? A * o.dq[v] + dt * Rv[v] : dt * Rv[v];
             dQ[a] = dq;
-            out[a] = Yr[v] + B * dq;
+            out[a] = o.Yr[v] + B * dq;
         }
     }
 }
+
+// contravariant total flux J a^d . F per (variable, direction); after the
+// divergence each face task overwrites its own-node entry with the lift of
+// (n.F^- - n.F^*)
+#define CM_TEND_LDS                          \
+    __shared__ R sG[NV * 3][BLOCK];          \
+    __shared__ R sP[4][BLOCK]; /* u v w c */ \
+    __shared__ R sY[NV][BLOCK]; /* own state, for the face tasks */
+
+// one element per block: own loads first, then the first face task's, so
+// that their latency overlaps phase A
+template <typename R, bool MOIST, bool WARP, bool VISC, int MODE>
+__global__ __launch_bounds__(BLOCK) void k_tend(const KParams P, const R* __restrict__ Y, const R* __restrict__ F2,
+                                                R* __restrict__ out, R* __restrict__ dQ, R A, R B, R dt)
+{
+    constexpr int NV = MOIST ? 6 : 5;
+    CM_TEND_LDS
+    const int e = elem_of_block(P, blockIdx.x);
+    const int t = threadIdx.x;
+    const int tt = t < NP ? t : NP - 1;
+    const int ex = e % P.ne0, ey = (e / P.ne0) % P.ne1, ez = e / (P.ne0 * P.ne1);
+    OwnLoad<R, MOIST, WARP, VISC, MODE> o;
+    own_load<R, MOIST, WARP, VISC, MODE>(P, Y, F2, dQ, e, ez, tt, o);
+    FaceLoad<R, MOIST, WARP, VISC> ft0, ft1;
+    face_load<R, MOIST, WARP, VISC>(P, Y, F2, t, e, ex, ey, ez, ft0);
+    tend_element<R, MOIST, WARP, VISC, MODE>(P, e, t, o, ft0, ft1, false, sG, sP, sY, Y, F2, out, dQ, A, B, dt);
+}
+
+#undef CM_TEND_LDS
 
 template <typename R, bool MOIST, bool WARP>
 static hipError_t launch_typed(cm_model* m, const void* Y, void* out, void* dQ, int mode, double A, double B,

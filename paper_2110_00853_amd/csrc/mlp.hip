@@ -413,17 +413,20 @@ cm_status cm_model_set_mlp(cm_model* m, const float* params, const float* norm)
             return CM_ERR_ARG;
         }
     CM_TRY_HIP(hipSetDevice(m->grid->device), "hipSetDevice");
+    // A-operand tiles of W [out][in] for the transposed forward: fragment
+    // (layer, output tile ht, k step ks), lane l, element q holds
+    // W[16 ht + l % 16][16 ks + 4 (l / 16) + q] (zero outside the matrix)
     std::vector<uint16_t> frag((size_t)FRAG_TOTAL * 64 * 4, 0);
-    struct L { int off, nin, nout, ks, ct; } layers[4] = {
-        {OFF_W1, MLP_NI, MLP_NH, 1, 4}, {OFF_W2, MLP_NH, MLP_NH, 4, 4},
-        {OFF_W3, MLP_NH, MLP_NH, 4, 4}, {OFF_W4, MLP_NH, MLP_NO, 4, 1}};
+    struct L { int off, nin, nout, ht, ks; } layers[4] = {
+        {OFF_W1, MLP_NI, MLP_NH, 4, 1}, {OFF_W2, MLP_NH, MLP_NH, 4, 4},
+        {OFF_W3, MLP_NH, MLP_NH, 4, 4}, {OFF_W4, MLP_NH, MLP_NO, 1, 4}};
     int f = 0;
     for (const L& l : layers)
-        for (int ks = 0; ks < l.ks; ++ks)
-            for (int ct = 0; ct < l.ct; ++ct, ++f)
+        for (int ht = 0; ht < l.ht; ++ht)
+            for (int ks = 0; ks < l.ks; ++ks, ++f)
                 for (int lane = 0; lane < 64; ++lane)
                     for (int q = 0; q < 4; ++q) {
-                        const int j = ct * 16 + (lane & 15);
+                        const int j = ht * 16 + (lane & 15);
                         const int k = ks * 16 + 4 * (lane >> 4) + q;
                         const float w = (j < l.nout && k < l.nin) ? params[l.off + j * l.nin + k] : 0.0f;
                         frag[((size_t)f * 64 + lane) * 4 + q] = f2bf(w);

@@ -24,8 +24,9 @@ constexpr int OFF_B3 = OFF_W3 + MLP_NH * MLP_NH;
 constexpr int OFF_W4 = OFF_B3 + MLP_NH;
 constexpr int OFF_B4 = OFF_W4 + MLP_NO * MLP_NH;
 
-// packed B fragments of the four layers for the fused inference: per layer,
-// per (k step, column tile), 64 lanes x 4 bf16
+// packed A fragments (weight tiles) of the four layers for the fused
+// inference in transposed form: per layer, per (output tile, k step),
+// 64 lanes x 4 bf16
 constexpr int FRAG_L1 = 4, FRAG_L2 = 16, FRAG_L3 = 16, FRAG_L4 = 4;
 constexpr int FRAG_TOTAL = FRAG_L1 + FRAG_L2 + FRAG_L3 + FRAG_L4;
 
