@@ -164,7 +164,11 @@ using namespace cm;
 // elements in flight on an XCD are in flight there too (shared L2).
 static void element_order(const cm_grid_desc& d, std::vector<int>& ord)
 {
-    constexpr int TX = 8, TY = 4;
+#ifndef CM_ORDER_TX
+#define CM_ORDER_TX 8
+#define CM_ORDER_TY 4
+#endif
+    constexpr int TX = CM_ORDER_TX, TY = CM_ORDER_TY;
     const int64_t ne0 = d.ne[0], ne1 = d.ne[1], ne2 = d.ne[2];
     const int64_t n = ne0 * ne1 * ne2, q = n / 8, r = n % 8;
     const int64_t ntx = (ne0 + TX - 1) / TX;
@@ -176,7 +180,11 @@ static void element_order(const cm_grid_desc& d, std::vector<int>& ord)
         for (int64_t s = 0; s < gs; ++s) {
             const int64_t e = g0 + s;
             const int64_t ex = e % ne0, ey = (e / ne0) % ne1, ez = e / (ne0 * ne1);
+#ifdef CM_ORDER_LINEAR
+            const int64_t key = e;
+#else
             const int64_t key = (((ey / TY * ntx + ex / TX) * ne2 + ez) * TY + ey % TY) * TX + ex % TX;
+#endif
             keyed[s] = {key, (int)e};
         }
         std::sort(keyed.begin(), keyed.end());

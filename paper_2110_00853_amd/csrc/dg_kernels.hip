@@ -654,7 +654,7 @@ __global__ __launch_bounds__(BLOCK) void k_grad(const KParams P, const R* __rest
     if (act) {
 #pragma unroll
         for (int q = 0; q < 14; ++q)
-            if (q < nw) F2[q * nn + node] = w[q];
+            if (q < nw) __builtin_nontemporal_store(w[q], &F2[q * nn + node]);
     }
 }
 
@@ -902,7 +902,7 @@ __device__ __forceinline__ void own_load(const KParams& P, const R* __restrict__
     }
     if (MODE == 1) {
 #pragma unroll
-        for (int v = 0; v < O::NV; ++v) o.dq[v] = dQ[v * nn + node];
+        for (int v = 0; v < O::NV; ++v) o.dq[v] = __builtin_nontemporal_load(&dQ[v * nn + node]);
     }
     const int ri = ref_index(P, e, ez, tt / (NQ * NQ), tt);
     o.pr = P.pr[ri];
@@ -1042,11 +1042,11 @@ __device__ __forceinline__ void tend_element(const KParams& P, int e, int t,
     for (int v = 0; v < NV; ++v) {
         const int64_t a = v * nn + node;
         if (MODE == 0) {
-            out[a] = Rv[v];
+            __builtin_nontemporal_store(Rv[v], &out[a]);
         } else {
             const R dq = MODE == 1 ? A * o.dq[v] + dt * Rv[v] : dt * Rv[v];
-            dQ[a] = dq;
-            out[a] = o.Yr[v] + B * dq;
+            __builtin_nontemporal_store(dq, &dQ[a]);
+            __builtin_nontemporal_store(o.Yr[v] + B * dq, &out[a]);
         }
     }
 }
