@@ -9,8 +9,9 @@ correction, FP64.  Inputs are synthetic and resident in HBM before timing.
 Prints ONE JSON line: DOF-updates/s = nodes x vars x 5 stages x steps / t,
 the roofline of the dominant kernel (tendency pass) from hipEvents around
 every launch in the timed region, the FP32-bulk variant, the learned-closure
-variant (fused BF16 network in the gradient pass), and the FP64 CPU oracle
-timed on this host on whole steps of the same workload.  The HBM traffic of
+variant (fused BF16 network in the gradient pass), the moist shallow-convection
+(64x64x30) and warped Agnesi-mountain (96x16x50) setups in FP64 and FP32-bulk,
+and the FP64 CPU oracle timed on this host on whole steps of the main workload.  The HBM traffic of
 the tendency pass comes from the rocprofv3 counter summary under profiles/
 when that summary was taken on the current kernel source (same SHA-256),
 else it is null.
@@ -182,9 +183,57 @@ def run(args):
                     "fused into the gradient pass, Smagorinsky-Lilly fallback",
         }
         del mL, YL
+    if not args.no_setups:
+        out["other_setups"] = {name: other_setup(name, args.setup_steps, 2) for name in ("moist_64", "agnesi_96")}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(c, Y0, Yref, nn, nvar, dt)
     return out
+
+
+def other_setup(name: str, steps: int, warmup: int):
+    """FP64 and FP32-bulk throughput of another named setup (same step, same
+    timing as the main line, fewer steps)."""
+    import torch
+
+    from paper_2110_00853_amd import binding as B
+    from paper_2110_00853_amd import workloads as W
+
+    c = W.case(name)
+    t0 = time.perf_counter()
+    Y0, Yref, dt = W.initial_state(c)
+    t_ic = time.perf_counter() - t0
+    grid = B.Grid(c["grid"], device=0)
+    nn, nvar = grid.n_nodes, c["model"]["nvar"]
+    res = {"n_nodes": nn, "nvar": nvar, "elements": c["grid"]["ne"], "steps": steps, "ic_seconds": t_ic}
+    for prec in ("fp64", "fp32"):
+        m = B.Model(grid, c["model"], Yref, precision=prec)
+        Ya, Yb, dQ = m.new_state(Y0), m.new_state(), m.new_state()
+        stream = torch.cuda.current_stream()
+        t = 0.0
+        for _ in range(warmup):
+            m.lsrk_step(Ya, Yb, dQ, t, dt, stream)
+            Ya, Yb = Yb, Ya
+            t += dt
+        m.profile(True)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for _ in range(steps):
+            m.lsrk_step(Ya, Yb, dQ, t, dt, stream)
+            Ya, Yb = Yb, Ya
+            t += dt
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        prof = m.profile_read()
+        m.profile(False)
+        d = m.diagnostics(Ya, dt)
+        res[prec] = {"value": nn * nvar * 5 * steps / (ms * 1e-3), "ms_per_step": ms / steps,
+                     "tend_avg_us": prof["tend"][0] * 1e3 / prof["tend"][1],
+                     "grad_avg_us": prof["grad"][0] * 1e3 / max(prof["grad"][1], 1),
+                     "n_nonfinite": d["n_nonfinite"]}
+        del m, Ya, Yb, dQ
+    return res
 
 
 def mlp_weights(B, grid, c, Yref, Y0):
@@ -243,6 +292,8 @@ def main():
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-learned", action="store_true")
+    ap.add_argument("--no-setups", action="store_true", help="skip the moist and mountain setups")
+    ap.add_argument("--setup-steps", type=int, default=20)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 1 GiB device copy (for scaling HBM byte counters)")
     args = ap.parse_args()

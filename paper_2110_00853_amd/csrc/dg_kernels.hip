@@ -261,6 +261,12 @@ __device__ __forceinline__ R smagorinsky(const KParams& P, const R S[3][3], R N2
 // instead of masked passes over the owners.  Task -> (direction, side, own
 // node, mirrored node in the neighbour).
 // ---------------------------------------------------------------------------
+constexpr int NFT = 150;  // face-node tasks per element: 6 faces x 25 nodes
+
+#ifndef CM_GRAD_WPE
+#define CM_GRAD_WPE 5
+#endif
+
 __device__ __forceinline__ void face_task(int task, int& dir, int& sd, int& own, int& nbr)
 {
     dir = task / 50;
@@ -416,10 +422,10 @@ __device__ __forceinline__ void grad_load(const KParams& P, const R* __restrict_
     for (int v = 0; v < (MOIST ? 6 : 5); ++v) f.Yp[v] = Y[v * P.nn + np];
 }
 
-// lift * (g* - g^-) of one face task into sJ[dir][q][own]
+// lift * (g* - g^-) of one face task into sL[q][task]
 template <typename R, bool MOIST, bool WARP>
-__device__ __forceinline__ void grad_face(const KParams& P, const GradLoad<R, MOIST>& f, int e, bool need_thv,
-                                          R (*sg)[BLOCK], R (*sJ)[MOIST ? 6 : 5][BLOCK])
+__device__ __forceinline__ void grad_face(const KParams& P, const GradLoad<R, MOIST>& f, int task, int e,
+                                          bool need_thv, R (*sg)[BLOCK], R (*sL)[NFT])
 {
     constexpr int NG = MOIST ? 6 : 5;
     constexpr int GQ = 4, GT = MOIST ? 5 : 4;
@@ -444,20 +450,20 @@ __device__ __forceinline__ void grad_face(const KParams& P, const GradLoad<R, MO
         for (int q = 0; q < NG; ++q) jump[q] = (R)0;
     }
 #pragma unroll
-    for (int q = 0; q < NG; ++q) sJ[f.dir][q][f.own] = jump[q];
+    for (int q = 0; q < NG; ++q) sL[q][task] = jump[q];
 }
 
 // ---------------------------------------------------------------------------
 // gradient + closure pass
 // ---------------------------------------------------------------------------
 template <typename R, bool MOIST, bool WARP, bool MLP>
-__global__ __launch_bounds__(BLOCK) void k_grad(const KParams P, const R* __restrict__ Y, R* __restrict__ F2)
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(MLP || MOIST || WARP ? 1 : CM_GRAD_WPE))) void k_grad(const KParams P, const R* __restrict__ Y, R* __restrict__ F2)
 {
     constexpr int NV = MOIST ? 6 : 5;
     constexpr int NG = MOIST ? 6 : 5;  // u v w h [qt] thv
     constexpr int GQ = 4, GT = MOIST ? 5 : 4;
     __shared__ R sg[NG][BLOCK];        // gradient variables of the element
-    __shared__ R sJ[3][NG][BLOCK];     // lift * (g* - g^-) per face direction
+    __shared__ R sL[NG][NFT];          // lift * (g* - g^-) per face task
 
     const int e = elem_of_block(P, blockIdx.x);
     const int t = threadIdx.x;
@@ -488,18 +494,18 @@ __global__ __launch_bounds__(BLOCK) void k_grad(const KParams P, const R* __rest
 
     // phase B: face tasks -> lift * (g* - g^-), centred g* (walls: 0); the
     // first task's neighbour state was loaded at kernel entry
-    grad_face<R, MOIST, WARP>(P, g0, e, need_thv, sg, sJ);
+    grad_face<R, MOIST, WARP>(P, g0, t, e, need_thv, sg, sL);
     if (t + BLOCK < 150) {
         GradLoad<R, MOIST> g1;
         grad_load<R, MOIST>(P, Y, t + BLOCK, e, ex, ey, ez, g1);
-        grad_face<R, MOIST, WARP>(P, g1, e, need_thv, sg, sJ);
+        grad_face<R, MOIST, WARP>(P, g1, t + BLOCK, e, need_thv, sg, sL);
     }
     __syncthreads();
 
     // phase C: per gradient variable, volume derivative by the 1-D GLL matrix
     // along each direction, chain rule, plus the lifts of the faces this node
-    // lies on; the physical gradient replaces this node's lift entries in
-    // LDS (sJ[c][q][t] = d g_q / d x_c), which only this lane touches now
+    // lies on; the physical gradient G[q][c] = d g_q / d x_c stays in
+    // registers (a select per variable, not an indexed write)
     R Ja[3][3], invJ = (R)0;
     if (WARP) {
         const R* m = (const R*)P.metrics;
@@ -523,6 +529,13 @@ __global__ __launch_bounds__(BLOCK) void k_grad(const KParams P, const R* __rest
         }
     }
     const bool onf[3] = {i == 0 || i == NQ - 1, j == 0 || j == NQ - 1, k == 0 || k == NQ - 1};
+    // face task of this node's face in each direction (task = 50 dir + 25 side + a + 5 b)
+    const int ftask[3] = {(i ? 25 : 0) + j + NQ * k, 50 + (j ? 25 : 0) + i + NQ * k, 100 + (k ? 25 : 0) + i + NQ * j};
+    R G[NG][3];
+#pragma unroll
+    for (int q = 0; q < NG; ++q)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) G[q][c] = 0;
 #pragma unroll 1
     for (int q = 0; q < NG; ++q) {
         R d0 = 0, d1 = 0, d2 = 0;
@@ -544,18 +557,29 @@ __global__ __launch_bounds__(BLOCK) void k_grad(const KParams P, const R* __rest
 #pragma unroll
         for (int dir = 0; dir < 3; ++dir) {
             if (!onf[dir]) continue;
-            const R jv = sJ[dir][q][t];
+            const R jv = sL[q][ftask[dir]];
 #pragma unroll
             for (int c = 0; c < 3; ++c) gc[c] += jv * nrm[dir][c];
         }
+        if (q == GT && P.feat_out != nullptr && act) {
+            // grad theta_v for the closure-input export (only its z part is
+            // kept in registers)
+            double* f = P.feat_out + node * 16;
+            f[12] = (double)gc[0];
+            f[13] = (double)gc[1];
+            f[14] = (double)gc[2];
+        }
 #pragma unroll
-        for (int c = 0; c < 3; ++c) sJ[c][q][t] = gc[c];
+        for (int qq = 0; qq < NG; ++qq)
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+                if (qq != GT || c == 2) G[qq][c] = qq == q ? gc[c] : G[qq][c];
     }
     R gr[4][3];   // velocity gradient and grad h_tot
 #pragma unroll
     for (int q = 0; q < 4; ++q)
 #pragma unroll
-        for (int c = 0; c < 3; ++c) gr[q][c] = sJ[c][q][t];
+        for (int c = 0; c < 3; ++c) gr[q][c] = G[q][c];
 
     // closure and diffusive flux
     R S[3][3];
@@ -567,7 +591,7 @@ __global__ __launch_bounds__(BLOCK) void k_grad(const KParams P, const R* __rest
     if (P.closure == CM_CLOSURE_CONST) {
         nu = (R)P.nu;
     } else if (P.closure == CM_CLOSURE_SMAG || P.closure == CM_CLOSURE_MLP) {
-        const R N2 = P.richardson || MLP ? (R)P.g * frcp(sg[GT][t]) * sJ[2][GT][t] : (R)0;
+        const R N2 = P.richardson || MLP ? (R)P.g * frcp(sg[GT][t]) * G[GT][2] : (R)0;
         nu = smagorinsky<R>(P, S, N2);
         if (MLP) {
             // learned closure: standardised inputs (velocity gradient, N^2,
@@ -621,13 +645,10 @@ __global__ __launch_bounds__(BLOCK) void k_grad(const KParams P, const R* __rest
         for (int a = 0; a < 3; ++a)
 #pragma unroll
             for (int b = 0; b < 3; ++b) f[3 * a + b] = (double)gr[a][b];
-        f[9] = P.g / (double)sg[GT][t] * (double)sJ[2][GT][t];
+        f[9] = P.g / (double)sg[GT][t] * (double)G[GT][2];
         f[10] = P.Delta;
         const double kk = (double)nu / (0.1 * P.Delta);
         f[11] = kk * kk;
-        f[12] = (double)sJ[0][GT][t];
-        f[13] = (double)sJ[1][GT][t];
-        f[14] = (double)sJ[2][GT][t];
         f[15] = (double)sg[GT][t];
     }
     const R rho = (R)th.rho;
@@ -636,20 +657,20 @@ __global__ __launch_bounds__(BLOCK) void k_grad(const KParams P, const R* __rest
     R w[14] = {};
     w[0] = c2 * S[0][0]; w[1] = c2 * S[1][1]; w[2] = c2 * S[2][2];
     w[3] = c2 * S[0][1]; w[4] = c2 * S[0][2]; w[5] = c2 * S[1][2];
-    const R u0 = (R)th.u, u1 = (R)th.v, u2 = (R)th.w;
+    const R u0 = sg[0][t], u1 = sg[1][t], u2 = sg[2][t];  // (R) u, v, w of this node
     const R rDt = rho * Dt;
     w[6] = u0 * w[0] + u1 * w[3] + u2 * w[4] - rDt * gr[3][0];
     w[7] = u0 * w[3] + u1 * w[1] + u2 * w[5] - rDt * gr[3][1];
     w[8] = u0 * w[4] + u1 * w[5] + u2 * w[2] - rDt * gr[3][2];
     if (MOIST) {
-        w[9] = -rDt * sJ[0][GQ][t];
-        w[10] = -rDt * sJ[1][GQ][t];
-        w[11] = -rDt * sJ[2][GQ][t];
+        w[9] = -rDt * G[GQ][0];
+        w[10] = -rDt * G[GQ][1];
+        w[11] = -rDt * G[GQ][2];
     }
     // subsidence needs d/dz of h_tot (and q_t) in the tendency pass
     constexpr int SB = MOIST ? 12 : 9;
     w[SB] = gr[3][2];
-    if (MOIST) w[SB + 1] = sJ[2][GQ][t];
+    if (MOIST) w[SB + 1] = G[GQ][2];
     const int nw = SB + (P.subsidence ? (MOIST ? 2 : 1) : 0);
     if (act) {
 #pragma unroll

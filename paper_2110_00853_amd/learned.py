@@ -135,7 +135,7 @@ def sgs_targets(Yc, ruu, rth, rthu, feat, Delta, nu_min_ratio=1e-4):
 
 
 def run_pipeline(fine_ne=64, t_train=(60.0, 90.0, 120.0, 150.0, 180.0), t_eval=240.0, train_steps=3000,
-                 batch=8192, seed=0, out_json=None, log=print):
+                 batch=8192, seed=0, out_json=None, out_npz=None, n_holdout=10000, log=print):
     """The whole pipeline at one resolution; returns a dict of results."""
     import torch
 
@@ -204,6 +204,15 @@ def run_pipeline(fine_ne=64, t_train=(60.0, 90.0, 120.0, 150.0, 180.0), t_eval=2
     params = net.params()
     norm = np.concatenate([mean, std, lo, hi]).astype(np.float32)
 
+    # held-out samples: the evaluation snapshot (not trained on), raw inputs
+    # and targets, for the a-priori comparison with Smagorinsky-Lilly
+    Yc, ruu, rth, rthu = snaps[t_eval]
+    feat = feat_model.closure_inputs(feat_model.new_state(Yc)).cpu().numpy()
+    Th, mask = sgs_targets(Yc, ruu, rth, rthu, feat, Delta)
+    sel = np.flatnonzero(mask)
+    sel = rng.choice(sel, size=min(n_holdout, sel.size), replace=False)
+    X_hold, T_hold = feat[sel, :12], Th[sel]
+
     # a-posteriori: coarse runs from the filtered initial state
     Yc0 = snaps[0.0][0]
     Yc_eval = snaps[t_eval][0]
@@ -251,6 +260,10 @@ def run_pipeline(fine_ne=64, t_train=(60.0, 90.0, 120.0, 150.0, 180.0), t_eval=2
     if out_json:
         with open(out_json, "w") as f:
             json.dump(results, f)
+    if out_npz:
+        np.savez_compressed(out_npz, params=params, norm=norm, X_holdout=X_hold.astype(np.float32),
+                            T_holdout=T_hold.astype(np.float32), Delta=np.float64(Delta),
+                            Prt=np.float64(cc["model"]["Prt"]), Cs=np.float64(cc["model"]["Cs"]))
     return results
 
 
@@ -262,4 +275,5 @@ def coarse_grain_state(Yf, ne_fine):
 if __name__ == "__main__":
     fine = int(sys.argv[1]) if len(sys.argv) > 1 else 64
     out = sys.argv[2] if len(sys.argv) > 2 else None
-    run_pipeline(fine_ne=fine, out_json=out, log=lambda s: print(s, flush=True))
+    npz = sys.argv[3] if len(sys.argv) > 3 else None
+    run_pipeline(fine_ne=fine, out_json=out, out_npz=npz, log=lambda s: print(s, flush=True))
