@@ -554,12 +554,19 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(MLP || MO
             gc[1] = (R)P.r2h1 * d1;
             gc[2] = (R)P.r2h2 * d2;
         }
+        // lifts of the faces this node lies on (read for every node and
+        // zeroed off the faces: no divergent branches); on flat meshes the
+        // normal is -e_dir / +e_dir on the low / high face
 #pragma unroll
         for (int dir = 0; dir < 3; ++dir) {
-            if (!onf[dir]) continue;
-            const R jv = sL[q][ftask[dir]];
+            const R jl = sL[q][ftask[dir]];
+            const R jv = onf[dir] ? jl : (R)0;
+            if (WARP) {
 #pragma unroll
-            for (int c = 0; c < 3; ++c) gc[c] += jv * nrm[dir][c];
+                for (int c = 0; c < 3; ++c) gc[c] += jv * nrm[dir][c];
+            } else {
+                gc[dir] += idx[dir] == 0 ? -jv : jv;
+            }
         }
         if (q == GT && P.feat_out != nullptr && act) {
             // grad theta_v for the closure-input export (only its z part is
@@ -817,12 +824,25 @@ __device__ __forceinline__ void face_flux(const KParams& P, const FaceLoad<R, MO
     R n[3], lift;
     face_normal<R, WARP>(P, onode, dir, side, n, lift);
     const R cJ = WARP ? ((const R*)P.metrics)[9 * nn + onode] * (R)(1.0 / WN) : (R)(1.0 / WN);
-    const R um[3] = {sP[0][own], sP[1][own], sP[2][own]};
-    const R cm = sP[3][own];
-    const R unm = um[0] * n[0] + um[1] * n[1] + um[2] * n[2];
     R Ym[NV];
 #pragma unroll
     for (int v = 0; v < NV; ++v) Ym[v] = sY[v][own];
+    // own node's velocity and sound speed: from LDS in the moist case (the
+    // saturation adjustment is too costly to repeat), recomputed from the
+    // own state otherwise (the same FP64 arithmetic as phase A, so the same
+    // values, and 4 KB less LDS per block)
+    Th to;
+    R um[3], cm;
+    if (MOIST) {
+        um[0] = sP[0][own]; um[1] = sP[1][own]; um[2] = sP[2][own];
+        cm = sP[3][own];
+    } else {
+        thermo<false>((double)Ym[0], (double)Ym[1], (double)Ym[2], (double)Ym[3], (double)Ym[4], 0.0,
+                      node_z(P, e, ez, own / (NQ * NQ), own), P.g, to);
+        um[0] = (R)to.u; um[1] = (R)to.v; um[2] = (R)to.w;
+        cm = (R)to.c;
+    }
+    const R unm = um[0] * n[0] + um[1] * n[1] + um[2] * n[2];
     R liftFm[NV];
 #pragma unroll
     for (int v = 0; v < NV; ++v) liftFm[v] = (R)side * sG[v * 3 + dir][own] * cJ;
@@ -854,10 +874,10 @@ __device__ __forceinline__ void face_flux(const KParams& P, const FaceLoad<R, MO
         // reflecting ghost u+ = u- - 2 (n.u-) n with rho, rho e, rho q
         // mirrored: the Rusanov flux of (Y-, ghost) plus the prescribed wall
         // diffusive flux
-        Th tm;
-        const int ko = own / (NQ * NQ);
-        thermo<MOIST>((double)Ym[0], (double)Ym[1], (double)Ym[2], (double)Ym[3], (double)Ym[4],
-                      MOIST ? (double)Ym[NV - 1] : 0.0, node_z(P, e, ez, ko, own), P.g, tm);
+        Th tm = to;
+        if (MOIST)
+            thermo<MOIST>((double)Ym[0], (double)Ym[1], (double)Ym[2], (double)Ym[3], (double)Ym[4],
+                          (double)Ym[NV - 1], node_z(P, e, ez, own / (NQ * NQ), own), P.g, tm);
         const R rho = Ym[0];
         const R pp = (R)(tm.p - f.prp), ep = (R)(tm.rho * tm.e + tm.p);
         const R rq = MOIST ? Ym[NV - 1] : (R)0;
@@ -968,8 +988,10 @@ __device__ __forceinline__ void tend_element(const KParams& P, int e, int t,
         R F[NV][3];
         flux1<R, MOIST>(th, o.pr, F);
         const R um[3] = {(R)th.u, (R)th.v, (R)th.w};
-        sP[0][t] = um[0]; sP[1][t] = um[1]; sP[2][t] = um[2];
-        sP[3][t] = (R)th.c;
+        if (MOIST) {
+            sP[0][t] = um[0]; sP[1][t] = um[1]; sP[2][t] = um[2];
+            sP[3][t] = (R)th.c;
+        }
 #pragma unroll
         for (int v = 0; v < NV; ++v) sY[v][t] = o.Yr[v];
         if (VISC) {
@@ -1034,9 +1056,13 @@ __device__ __forceinline__ void tend_element(const KParams& P, int e, int t,
     }
 #pragma unroll
     for (int dir = 0; dir < 3; ++dir) {
-        if (idx[dir] != 0 && idx[dir] != NQ - 1) continue;
+        // read for every node, added on the face nodes only (no divergent branch)
+        const bool on = idx[dir] == 0 || idx[dir] == NQ - 1;
 #pragma unroll
-        for (int v = 0; v < NV; ++v) Rv[v] += sG[v * 3 + dir][t];
+        for (int v = 0; v < NV; ++v) {
+            const R fv = sG[v * 3 + dir][t];
+            Rv[v] += on ? fv : (R)0;
+        }
     }
     Rv[3] -= (R)((rho_d - o.rr) * P.g);
     if (P.f_cor != 0.0) {
@@ -1077,7 +1103,7 @@ __device__ __forceinline__ void tend_element(const KParams& P, int e, int t,
 // (n.F^- - n.F^*)
 #define CM_TEND_LDS                          \
     __shared__ R sG[NV * 3][BLOCK];          \
-    __shared__ R sP[4][BLOCK]; /* u v w c */ \
+    __shared__ R sP[MOIST ? 4 : 1][BLOCK]; /* u v w c (moist) */ \
     __shared__ R sY[NV][BLOCK]; /* own state, for the face tasks */
 
 // one element per block: own loads first, then the first face task's, so
