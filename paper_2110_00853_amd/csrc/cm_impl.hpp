@@ -70,6 +70,8 @@ struct KParams {
     int mlp_fallback_on;
     unsigned long long* mlp_fallbacks;
     double* feat_out;           // when set, the gradient pass also writes the closure inputs [nn][16]
+    double* Tn;                 // moist viscous models: temperature of every node, written by the
+                                // gradient pass and read by the tendency pass of the same stage [nn]
 };
 
 }  // namespace cm
@@ -95,6 +97,7 @@ struct cm_model {
     cm_model_desc desc{};
     int nf = 0;
     void* d_F2 = nullptr;        // [nf][nn] storage type
+    double* d_T = nullptr;       // moist viscous models: node temperature [nn] (FP64)
     double* d_pr = nullptr;
     double* d_rhor = nullptr;
     int ref_per_node = 0;

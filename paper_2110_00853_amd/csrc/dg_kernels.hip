@@ -160,6 +160,31 @@ __device__ __forceinline__ void saturation_adjust(double rho, double qt, double 
     ql = qt - qv;
 }
 
+// the moist recovery when T is already known (the saturation adjustment of
+// the same state in the gradient pass): q_v = min(q_t, q_v*(T)) is what the
+// adjustment itself returns, for the unsaturated branch as well, so the
+// result is the one thermo() gives, without the Newton iteration
+__device__ __forceinline__ void thermo_moist_T(double rho, double mx, double my, double mz, double re, double rq,
+                                               double T, Th& o)
+{
+    const double ir = frcp(rho);
+    o.rho = rho;
+    o.u = mx * ir; o.v = my * ir; o.w = mz * ir;
+    o.e = re * ir;
+    o.qt = rq * ir;
+    const double irv = frcp(rho * Phys::Rv);
+    double qv = pvsat(T) * irv * frcp(T);
+    qv = qv < o.qt ? qv : o.qt;
+    o.T = T;
+    o.ql = o.qt - qv;
+    o.qv = o.qt - o.ql;  // as thermo() forms it
+    o.Rm = Phys::Rd * (1.0 - o.qt) + Phys::Rv * o.qv;
+    const double cvm = (1.0 - o.qt) * Phys::cvd + o.qv * Phys::cvv + o.ql * Phys::cvl;
+    o.p = rho * o.Rm * o.T;
+    o.c = fsqrt((cvm + o.Rm) * frcp(cvm) * o.Rm * o.T);
+    o.h = o.e + o.p * ir;
+}
+
 template <bool MOIST>
 __device__ __forceinline__ void thermo(double rho, double mx, double my, double mz, double re, double rq, double z,
                                        double g, Th& o)
@@ -489,6 +514,9 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(MLP || MO
     }
     sg[0][t] = (R)th.u; sg[1][t] = (R)th.v; sg[2][t] = (R)th.w; sg[3][t] = (R)th.h;
     if (MOIST) sg[GQ][t] = (R)th.qt;
+    // the tendency pass of this stage takes T from here instead of repeating
+    // the saturation adjustment
+    if (MOIST && act) __builtin_nontemporal_store(th.T, &P.Tn[node]);
     sg[GT][t] = need_thv ? (R)theta_v(th) : (R)0;
     __syncthreads();
 
@@ -773,6 +801,7 @@ struct FaceLoad {
     int dir, sd, own, nbl, en, ezn;
     R Yp[NV], wp[VISC ? NWF : 1];
     double prp;
+    double Tq;  // moist viscous: T of the neighbour node (of this node on a wall)
 };
 
 template <typename R, bool MOIST, bool WARP, bool VISC>
@@ -808,6 +837,7 @@ __device__ __forceinline__ void face_load(const KParams& P, const R* __restrict_
     // holds this element's mirrored node, and the flux needs this node's
     const int rn = f.en >= 0 ? f.nbl : f.own;
     f.prp = P.pr[ref_index(P, eo, ezo, rn / (NQ * NQ), rn)];
+    if (MOIST && VISC) f.Tq = P.Tn[(int64_t)eo * NP + rn];
 }
 
 // numerical flux of one face task; writes lift (n.F^- - n.F^*) over the
@@ -851,8 +881,12 @@ __device__ __forceinline__ void face_flux(const KParams& P, const FaceLoad<R, MO
         const int ezn = f.ezn;
         const int kn = nbl / (NQ * NQ);
         Th tp;
-        thermo<MOIST>((double)f.Yp[0], (double)f.Yp[1], (double)f.Yp[2], (double)f.Yp[3], (double)f.Yp[4],
-                      MOIST ? (double)f.Yp[NV - 1] : 0.0, node_z(P, en, ezn, kn, nbl), P.g, tp);
+        if (MOIST && VISC)
+            thermo_moist_T((double)f.Yp[0], (double)f.Yp[1], (double)f.Yp[2], (double)f.Yp[3], (double)f.Yp[4],
+                           (double)f.Yp[NV - 1], f.Tq, tp);
+        else
+            thermo<MOIST>((double)f.Yp[0], (double)f.Yp[1], (double)f.Yp[2], (double)f.Yp[3], (double)f.Yp[4],
+                          MOIST ? (double)f.Yp[NV - 1] : 0.0, node_z(P, en, ezn, kn, nbl), P.g, tp);
         const R up[3] = {(R)tp.u, (R)tp.v, (R)tp.w};
         R fp[NV];
         flux1_normal<R, MOIST>((R)tp.rho, up, (R)(tp.p - f.prp), (R)(tp.rho * tp.e + tp.p), (R)(tp.rho * tp.qt), n,
@@ -875,7 +909,10 @@ __device__ __forceinline__ void face_flux(const KParams& P, const FaceLoad<R, MO
         // mirrored: the Rusanov flux of (Y-, ghost) plus the prescribed wall
         // diffusive flux
         Th tm = to;
-        if (MOIST)
+        if (MOIST && VISC)
+            thermo_moist_T((double)Ym[0], (double)Ym[1], (double)Ym[2], (double)Ym[3], (double)Ym[4],
+                           (double)Ym[NV - 1], f.Tq, tm);
+        else if (MOIST)
             thermo<MOIST>((double)Ym[0], (double)Ym[1], (double)Ym[2], (double)Ym[3], (double)Ym[4],
                           (double)Ym[NV - 1], node_z(P, e, ez, own / (NQ * NQ), own), P.g, tm);
         const R rho = Ym[0];
@@ -924,6 +961,7 @@ struct OwnLoad {
     R dq[MODE == 1 ? NV : 1];
     R Jam[WARP ? 9 : 1];
     double pr, rr;
+    double T;  // moist viscous: T from the gradient pass
 };
 
 template <typename R, bool MOIST, bool WARP, bool VISC, int MODE>
@@ -948,6 +986,7 @@ __device__ __forceinline__ void own_load(const KParams& P, const R* __restrict__
     const int ri = ref_index(P, e, ez, tt / (NQ * NQ), tt);
     o.pr = P.pr[ri];
     o.rr = P.rhor[ri];
+    if (MOIST && VISC) o.T = P.Tn[node];
     if (WARP) {
         const R* m = (const R*)P.metrics;
 #pragma unroll
@@ -981,8 +1020,12 @@ __device__ __forceinline__ void tend_element(const KParams& P, int e, int t,
     double rho_d, mom_d[3];
     {
         Th th;
-        thermo<MOIST>((double)o.Yr[0], (double)o.Yr[1], (double)o.Yr[2], (double)o.Yr[3], (double)o.Yr[4],
-                      MOIST ? (double)o.Yr[NV - 1] : 0.0, z, P.g, th);
+        if (MOIST && VISC)
+            thermo_moist_T((double)o.Yr[0], (double)o.Yr[1], (double)o.Yr[2], (double)o.Yr[3], (double)o.Yr[4],
+                           (double)o.Yr[NV - 1], o.T, th);
+        else
+            thermo<MOIST>((double)o.Yr[0], (double)o.Yr[1], (double)o.Yr[2], (double)o.Yr[3], (double)o.Yr[4],
+                          MOIST ? (double)o.Yr[NV - 1] : 0.0, z, P.g, th);
         rho_d = th.rho;
         mom_d[0] = (double)o.Yr[1]; mom_d[1] = (double)o.Yr[2]; mom_d[2] = (double)o.Yr[3];
         R F[NV][3];
