@@ -320,7 +320,8 @@ cm_status cm_model_destroy(cm_model* m)
     if (!m) return CM_OK;
     (void)hipSetDevice(m->grid->device);
     if (m->d_F2) (void)hipFree(m->d_F2);
-    if (m->d_T) (void)hipFree(m->d_T);
+    for (int q = 0; q < 2; ++q)
+        if (m->d_T[q]) (void)hipFree(m->d_T[q]);
     if (m->d_pr) (void)hipFree(m->d_pr);
     if (m->d_rhor) (void)hipFree(m->d_rhor);
     if (m->d_partials) (void)hipFree(m->d_partials);
@@ -361,7 +362,7 @@ cm_status cm_model_create(const cm_grid* g, const cm_model_desc* desc, const dou
     m->Delta = std::cbrt((g->h[0] / 4.0) * (g->h[1] / 4.0) * (g->h[2] / 4.0));
     hipError_t e = hipSuccess;
     if (m->nf > 0) e = hipMalloc(&m->d_F2, s * m->nf * nn);
-    if (e == hipSuccess && m->nf > 0 && moist) e = hipMalloc(&m->d_T, sizeof(double) * nn);
+    for (int q = 0; q < 2 && e == hipSuccess && m->nf > 0 && moist; ++q) e = hipMalloc(&m->d_T[q], sizeof(double) * nn);
     // reference state: per level when the mesh is flat and the background is
     // horizontally uniform, else per node
     m->has_ref = Yref != nullptr;
@@ -452,7 +453,9 @@ cm_status cm_model_create(const cm_grid* g, const cm_model_desc* desc, const dou
     k.mlp_frag = nullptr; k.mlp_bias = nullptr; k.mlp_norm = nullptr;
     k.mlp_fallback_on = 1; k.mlp_fallbacks = m->d_fallbacks;
     k.feat_out = nullptr;
-    k.Tn = m->d_T;
+    k.Tn = m->d_T[0];
+    k.Tnext = nullptr;
+    k.T_given = 0;
     if (e == hipSuccess && Yref) {
         // push the background through the device thermodynamics
         const int64_t nref = m->ref_per_node ? nn : (int64_t)g->desc.ne[2] * NQ;

@@ -70,8 +70,13 @@ struct KParams {
     int mlp_fallback_on;
     unsigned long long* mlp_fallbacks;
     double* feat_out;           // when set, the gradient pass also writes the closure inputs [nn][16]
-    double* Tn;                 // moist viscous models: temperature of every node, written by the
-                                // gradient pass and read by the tendency pass of the same stage [nn]
+    // moist viscous models: node temperature of the stage's input state
+    // (written by the gradient pass, or by the previous stage's tendency
+    // pass when T_given) and of its output state (written by the tendency
+    // pass when Tnext is set) [nn]
+    double* Tn;
+    double* Tnext;
+    int T_given;
 };
 
 }  // namespace cm
@@ -97,7 +102,8 @@ struct cm_model {
     cm_model_desc desc{};
     int nf = 0;
     void* d_F2 = nullptr;        // [nf][nn] storage type
-    double* d_T = nullptr;       // moist viscous models: node temperature [nn] (FP64)
+    double* d_T[2] = {nullptr, nullptr};  // moist viscous models: node temperature, ping-pong [nn]
+    int tsel = 0;                // which d_T holds the current stage input's T
     double* d_pr = nullptr;
     double* d_rhor = nullptr;
     int ref_per_node = 0;

@@ -185,6 +185,37 @@ __device__ __forceinline__ void thermo_moist_T(double rho, double mx, double my,
     o.h = o.e + o.p * ir;
 }
 
+// temperature of a moist state by the saturation adjustment, Newton
+// started from Tg when that is above T_u (a nearby solution: the previous
+// stage's temperature of the same node); unsaturated air returns T_u
+__device__ __forceinline__ double moist_T_guess(double rho, double mx, double my, double mz, double re, double rq,
+                                                double z, double g, double Tg)
+{
+    const double ir = frcp(rho);
+    const double u = mx * ir, v = my * ir, w = mz * ir;
+    const double I = re * ir - 0.5 * (u * u + v * v + w * w) - g * z;
+    const double qt = rq * ir;
+    const double Tu = Phys::T0 + (I - qt * Phys::Iv0) * frcp((1.0 - qt) * Phys::cvd + qt * Phys::cvv);
+    const double irv = frcp(rho * Phys::Rv);
+    const double qvs_u = pvsat(Tu) * irv * frcp(Tu);
+    if (qt <= qvs_u) return Tu;
+    double Tn = Tg > Tu ? Tg : Tu;
+    for (int it = 0; it < 20; ++it) {
+        const double iT = frcp(Tn);
+        const double qv = pvsat(Tn) * irv * iT;
+        const double dT = Tn - Phys::T0;
+        const double f = (1.0 - qt) * Phys::cvd * dT + qv * (Phys::cvv * dT + Phys::Iv0) + (qt - qv) * Phys::cvl * dT - I;
+        const double Lv = Phys::Lv0 + (Phys::cpv - Phys::cpl) * dT;
+        const double dqv = qv * (Lv * (1.0 / Phys::Rv) * iT * iT - iT);
+        const double cvm = (1.0 - qt) * Phys::cvd + qv * Phys::cvv + (qt - qv) * Phys::cvl;
+        const double fp = cvm + dqv * (Phys::Iv0 + (Phys::cvv - Phys::cvl) * dT);
+        const double step = f * frcp(fp);
+        Tn -= step;
+        if (fabs(step) <= 1e-13 * Tn) break;
+    }
+    return Tn;
+}
+
 template <bool MOIST>
 __device__ __forceinline__ void thermo(double rho, double mx, double my, double mz, double re, double rq, double z,
                                        double g, Th& o)
@@ -434,6 +465,7 @@ template <typename R, bool MOIST>
 struct GradLoad {
     int dir, sd, own, nbl, en, ezn;
     R Yp[MOIST ? 6 : 5];
+    double Tq;  // moist, T_given: the neighbour node's temperature
 };
 
 template <typename R, bool MOIST>
@@ -445,6 +477,7 @@ __device__ __forceinline__ void grad_load(const KParams& P, const R* __restrict_
     const int64_t np = (int64_t)(f.en >= 0 ? f.en : e) * NP + f.nbl;
 #pragma unroll
     for (int v = 0; v < (MOIST ? 6 : 5); ++v) f.Yp[v] = Y[v * P.nn + np];
+    if (MOIST && P.T_given) f.Tq = P.Tn[np];
 }
 
 // lift * (g* - g^-) of one face task into sL[q][task]
@@ -457,8 +490,12 @@ __device__ __forceinline__ void grad_face(const KParams& P, const GradLoad<R, MO
     R jump[NG];
     if (f.en >= 0) {
         Th tp;
-        thermo<MOIST>((double)f.Yp[0], (double)f.Yp[1], (double)f.Yp[2], (double)f.Yp[3], (double)f.Yp[4],
-                      MOIST ? (double)f.Yp[5] : 0.0, node_z(P, f.en, f.ezn, f.nbl / (NQ * NQ), f.nbl), P.g, tp);
+        if (MOIST && P.T_given)
+            thermo_moist_T((double)f.Yp[0], (double)f.Yp[1], (double)f.Yp[2], (double)f.Yp[3], (double)f.Yp[4],
+                           (double)f.Yp[MOIST ? 5 : 0], f.Tq, tp);
+        else
+            thermo<MOIST>((double)f.Yp[0], (double)f.Yp[1], (double)f.Yp[2], (double)f.Yp[3], (double)f.Yp[4],
+                          MOIST ? (double)f.Yp[5] : 0.0, node_z(P, f.en, f.ezn, f.nbl / (NQ * NQ), f.nbl), P.g, tp);
         R gp[NG];
         gp[0] = (R)tp.u; gp[1] = (R)tp.v; gp[2] = (R)tp.w; gp[3] = (R)tp.h;
         if (MOIST) gp[GQ] = (R)tp.qt;
@@ -510,13 +547,16 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(MLP || MO
         double Yv[NV];
 #pragma unroll
         for (int v = 0; v < NV; ++v) Yv[v] = (double)Y[v * nn + node];
-        thermo<MOIST>(Yv[0], Yv[1], Yv[2], Yv[3], Yv[4], MOIST ? Yv[5] : 0.0, node_z(P, e, ez, k, tt), P.g, th);
+        if (MOIST && P.T_given)
+            thermo_moist_T(Yv[0], Yv[1], Yv[2], Yv[3], Yv[4], Yv[MOIST ? 5 : 0], P.Tn[node], th);
+        else
+            thermo<MOIST>(Yv[0], Yv[1], Yv[2], Yv[3], Yv[4], MOIST ? Yv[5] : 0.0, node_z(P, e, ez, k, tt), P.g, th);
     }
     sg[0][t] = (R)th.u; sg[1][t] = (R)th.v; sg[2][t] = (R)th.w; sg[3][t] = (R)th.h;
     if (MOIST) sg[GQ][t] = (R)th.qt;
     // the tendency pass of this stage takes T from here instead of repeating
     // the saturation adjustment
-    if (MOIST && act) __builtin_nontemporal_store(th.T, &P.Tn[node]);
+    if (MOIST && !P.T_given && act) __builtin_nontemporal_store(th.T, &P.Tn[node]);
     sg[GT][t] = need_thv ? (R)theta_v(th) : (R)0;
     __syncthreads();
 
@@ -1135,9 +1175,18 @@ __device__ __forceinline__ void tend_element(const KParams& P, int e, int t,
             __builtin_nontemporal_store(Rv[v], &out[a]);
         } else {
             const R dq = MODE == 1 ? A * o.dq[v] + dt * Rv[v] : dt * Rv[v];
+            const R yn = o.Yr[v] + B * dq;
             __builtin_nontemporal_store(dq, &dQ[a]);
-            __builtin_nontemporal_store(o.Yr[v] + B * dq, &out[a]);
+            __builtin_nontemporal_store(yn, &out[a]);
+            if (MOIST && VISC) Rv[v] = yn;  // keep the output state for its temperature
         }
+    }
+    if (MOIST && VISC && MODE != 0 && P.Tnext != nullptr) {
+        // temperature of the output state, from the input state's as the
+        // Newton start: the next stage's passes read it instead of solving
+        const double Tnew = moist_T_guess((double)Rv[0], (double)Rv[1], (double)Rv[2], (double)Rv[3],
+                                          (double)Rv[4], (double)Rv[NV - 1], z, P.g, o.T);
+        __builtin_nontemporal_store(Tnew, &P.Tnext[node]);
     }
 }
 
@@ -1174,7 +1223,15 @@ template <typename R, bool MOIST, bool WARP>
 static hipError_t launch_typed(cm_model* m, const void* Y, void* out, void* dQ, int mode, double A, double B,
                                double dt, hipStream_t s)
 {
-    const KParams& P = m->kp;
+    KParams P = m->kp;
+    const bool moist_visc = MOIST && m->d_T[0] != nullptr;
+    if (moist_visc) {
+        // stages 2..5 of an LSRK step (mode 1) find their input state's T in
+        // d_T[tsel], written by the previous stage's tendency pass
+        P.Tn = m->d_T[m->tsel];
+        P.Tnext = mode != 0 ? m->d_T[m->tsel ^ 1] : nullptr;
+        P.T_given = mode == 1;
+    }
     const dim3 grid(P.n_elem), block(BLOCK);
     const R* y = (const R*)Y;
     R* F2 = (R*)m->d_F2;
@@ -1202,6 +1259,7 @@ static hipError_t launch_typed(cm_model* m, const void* Y, void* out, void* dQ, 
     }
 #undef CM_TEND
     prof_end(rt, s);
+    if (moist_visc && mode != 0) m->tsel ^= 1;
     return hipGetLastError();
 }
 

@@ -129,6 +129,31 @@ def test_bubble_4_hundred_steps(dev):
     assert np.all(err < STEP_TOL), err
 
 
+def test_moist_hundred_steps(dev):
+    """The small moist case (saturated nodes, surface fluxes, subsidence,
+    Coriolis) after 100 LSRK54 steps within 1e-9: the temperature the
+    tendency pass hands to the next stage must not drift from the oracle's
+    saturation adjustment."""
+    c = SMALL_CASES["moist"]
+    Y, Yref = _state(c)
+    _, _, speed = W.perturbed_state(c, seed=11, amp_u=6.0, amp_T=2.0, amp_q=1.5e-3)
+    dt = W.cfl_dt(c["grid"], speed)
+    g = B.Grid(c["grid"])
+    m = B.Model(g, c["model"], Yref)
+    Ya, Yb, dQ = m.new_state(Y), m.new_state(), m.new_state()
+    for _ in range(100):
+        m.lsrk_step(Ya, Yb, dQ, 0.0, dt)
+        Ya, Yb = Yb, Ya
+    dev.cuda.synchronize()
+    Yg = Ya.cpu().numpy()
+    Yo, _ = oracle.Model(oracle.Grid(c["grid"]), c["model"], Yref).steps(Y, dt, 100)
+    _, _, ql, _ = oracle.thermo_nodes(Yo, W.node_coords(c["grid"])[2], c["model"].get("g", 9.81))
+    err = state_errors(Yg, Yo)
+    print("moist 100-step state errors", err, "saturated nodes at the end:", int(np.sum(ql > 0)))
+    assert np.sum(ql > 0) > 0
+    assert np.all(err < STEP_TOL), err
+
+
 def test_diagnostics_match_oracle_integrals(dev):
     c = SMALL_CASES["moist"]
     Y, Yref = _state(c)
