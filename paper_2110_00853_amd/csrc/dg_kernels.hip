@@ -898,12 +898,14 @@ __device__ __forceinline__ void face_flux(const KParams& P, const FaceLoad<R, MO
 #pragma unroll
     for (int v = 0; v < NV; ++v) Ym[v] = sY[v][own];
     // own node's velocity and sound speed: from LDS in the moist case (the
-    // saturation adjustment is too costly to repeat), recomputed from the
-    // own state otherwise (the same FP64 arithmetic as phase A, so the same
+    // saturation adjustment is too costly to repeat) and with FP32 storage
+    // (LDS is not the limit there), recomputed from the own state in the
+    // dry FP64 case (the same FP64 arithmetic as phase A, so the same
     // values, and 4 KB less LDS per block)
+    constexpr bool KEEP_P = MOIST || sizeof(R) == 4;
     Th to;
     R um[3], cm;
-    if (MOIST) {
+    if (KEEP_P) {
         um[0] = sP[0][own]; um[1] = sP[1][own]; um[2] = sP[2][own];
         cm = sP[3][own];
     } else {
@@ -949,7 +951,10 @@ __device__ __forceinline__ void face_flux(const KParams& P, const FaceLoad<R, MO
         // mirrored: the Rusanov flux of (Y-, ghost) plus the prescribed wall
         // diffusive flux
         Th tm = to;
-        if (MOIST && VISC)
+        if (KEEP_P && !MOIST)
+            thermo<false>((double)Ym[0], (double)Ym[1], (double)Ym[2], (double)Ym[3], (double)Ym[4], 0.0,
+                          node_z(P, e, ez, own / (NQ * NQ), own), P.g, tm);
+        else if (MOIST && VISC)
             thermo_moist_T((double)Ym[0], (double)Ym[1], (double)Ym[2], (double)Ym[3], (double)Ym[4],
                            (double)Ym[NV - 1], f.Tq, tm);
         else if (MOIST)
@@ -1071,7 +1076,7 @@ __device__ __forceinline__ void tend_element(const KParams& P, int e, int t,
         R F[NV][3];
         flux1<R, MOIST>(th, o.pr, F);
         const R um[3] = {(R)th.u, (R)th.v, (R)th.w};
-        if (MOIST) {
+        if (MOIST || sizeof(R) == 4) {
             sP[0][t] = um[0]; sP[1][t] = um[1]; sP[2][t] = um[2];
             sP[3][t] = (R)th.c;
         }
@@ -1195,7 +1200,7 @@ __device__ __forceinline__ void tend_element(const KParams& P, int e, int t,
 // (n.F^- - n.F^*)
 #define CM_TEND_LDS                          \
     __shared__ R sG[NV * 3][BLOCK];          \
-    __shared__ R sP[MOIST ? 4 : 1][BLOCK]; /* u v w c (moist) */ \
+    __shared__ R sP[MOIST || sizeof(R) == 4 ? 4 : 1][BLOCK]; /* u v w c (moist, FP32) */ \
     __shared__ R sY[NV][BLOCK]; /* own state, for the face tasks */
 
 // one element per block: own loads first, then the first face task's, so
