@@ -149,12 +149,16 @@ __global__ __launch_bounds__(RB) void k_diag1(const DiagArgs A, const R* __restr
 }
 
 // combine the per-block partials in block order (one thread, deterministic)
-__global__ void k_diag2(const double* __restrict__ part, int nblk, double* __restrict__ out)
+// combine of the per-block partials: each thread merges a strided subset
+// (compensated sums, extrema), then a fixed pairwise tree in LDS, so the
+// result does not depend on timing
+__global__ __launch_bounds__(RB) void k_diag2(const double* __restrict__ part, int nblk, double* __restrict__ out)
 {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    __shared__ double sh[RB][NPART];
+    const int tid = threadIdx.x;
     Neu acc[4] = {{0, 0}, {0, 0}, {0, 0}, {0, 0}};
     double maxw = 0.0, maxcfl = 0.0, Tmin = INFINITY, Tmax = -INFINITY, nonfin = 0.0;
-    for (int b = 0; b < nblk; ++b) {
+    for (int b = tid; b < nblk; b += RB) {
         const double* p = part + (int64_t)b * NPART;
         for (int q = 0; q < 4; ++q) neu_merge(acc[q], Neu{p[2 * q], p[2 * q + 1]});
         maxw = fmax(maxw, p[8]);
@@ -163,8 +167,30 @@ __global__ void k_diag2(const double* __restrict__ part, int nblk, double* __res
         Tmax = fmax(Tmax, p[11]);
         nonfin += p[12];
     }
-    for (int q = 0; q < 4; ++q) out[q] = acc[q].s + acc[q].c;
-    out[4] = maxw; out[5] = maxcfl; out[6] = Tmin; out[7] = Tmax; out[8] = nonfin;
+    for (int q = 0; q < 4; ++q) { sh[tid][2 * q] = acc[q].s; sh[tid][2 * q + 1] = acc[q].c; }
+    sh[tid][8] = maxw; sh[tid][9] = maxcfl; sh[tid][10] = Tmin; sh[tid][11] = Tmax; sh[tid][12] = nonfin;
+    __syncthreads();
+    for (int half = RB / 2; half > 0; half >>= 1) {
+        if (tid < half) {
+            const double* o = sh[tid + half];
+            for (int q = 0; q < 4; ++q) {
+                Neu a{sh[tid][2 * q], sh[tid][2 * q + 1]};
+                neu_merge(a, Neu{o[2 * q], o[2 * q + 1]});
+                sh[tid][2 * q] = a.s;
+                sh[tid][2 * q + 1] = a.c;
+            }
+            sh[tid][8] = fmax(sh[tid][8], o[8]);
+            sh[tid][9] = fmax(sh[tid][9], o[9]);
+            sh[tid][10] = fmin(sh[tid][10], o[10]);
+            sh[tid][11] = fmax(sh[tid][11], o[11]);
+            sh[tid][12] += o[12];
+        }
+        __syncthreads();
+    }
+    if (tid == 0) {
+        for (int q = 0; q < 4; ++q) out[q] = sh[0][2 * q] + sh[0][2 * q + 1];
+        for (int q = 4; q < 9; ++q) out[q] = sh[0][q + 4];
+    }
 }
 
 hipError_t launch_diagnostics(const cm_model* m, const void* Y, double dt, cm_diag* outp, hipStream_t s)
@@ -197,7 +223,7 @@ hipError_t launch_diagnostics(const cm_model* m, const void* Y, double dt, cm_di
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_diag2, dim3(1), dim3(64), 0, s, part, nblk, dout);
+    hipLaunchKernelGGL(k_diag2, dim3(1), dim3(RB), 0, s, part, nblk, dout);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     double h[9];
