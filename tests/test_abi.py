@@ -45,3 +45,20 @@ def test_invalid_grid_arguments_are_rejected_on_the_host():
     assert L.cm_dg_rhs(None, None, None, 0.0, None) == B.CM_ERR_ARG
     assert L.cm_lsrk_step(None, None, None, None, 0.0, 1.0, None) == B.CM_ERR_ARG
     assert L.cm_model_create(None, None, None, C.byref(out)) == B.CM_ERR_ARG
+
+
+def test_grid_beyond_32_bit_indexing_is_rejected_on_the_host():
+    """The kernels index nodes x words in 32-bit integers: a mesh whose node
+    count times 16 words reaches 2^31 is refused before any device call."""
+    L = B.load()
+    out = C.c_void_p()
+    d = B.GridDesc()
+    d.N = 4
+    for a in range(3):
+        d.ne[a] = 256
+        d.lo[a] = 0.0
+        d.hi[a] = 1.0
+    assert L.cm_grid_create(C.byref(d), 0, C.byref(out)) == B.CM_ERR_UNSUPPORTED
+    assert b"32-bit" in L.cm_last_error()
+    assert not out.value
+

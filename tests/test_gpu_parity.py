@@ -34,6 +34,8 @@ SMALL_CASES = {
     "single_periodic": _small("bubble_32", (1, 1, 1), (200.0, 200.0, 200.0), periodic=[1, 1, 1]),
     # inviscid (no gradient pass)
     "inviscid": _small("bubble_4", (3, 2, 2), (1500.0, 1000.0, 1000.0)),
+    # one element layer: bottom and top walls on the same element, Smagorinsky
+    "one_layer": _small("bubble_32", (3, 2, 1), (600.0, 400.0, 200.0)),
 }
 SMALL_CASES["single_periodic"]["model"]["g"] = 0.0
 SMALL_CASES["inviscid"]["model"]["closure"] = "none"
