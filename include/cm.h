@@ -19,9 +19,10 @@
  *    e = ex + ne[0]*(ey + ne[1]*ez).  Element type double (CM_FP64) or
  *    float (CM_FP32_BULK), at least 16-byte aligned.  The library never
  *    frees or retains them beyond a call.
- *  - Grid and model objects own their device arrays (metrics, reference
- *    state, diffusive-flux scratch, reduction scratch) and free them on
- *    destroy.
+ *  - Grid and model objects own their device arrays (metrics, element
+ *    traversal table, reference state, diffusive-flux scratch, the node
+ *    temperatures moist viscous models carry between the passes and stages
+ *    of a step, reduction scratch) and free them on destroy.
  *  - Compute calls are asynchronous on the hipStream_t passed as void*
  *    (NULL = the default stream).  Only create/copy calls and
  *    cm_diagnostics synchronise.
@@ -121,7 +122,8 @@ typedef struct cm_mlp cm_mlp;
  * and (for warped meshes) per-node metric terms J a^d and 1/J from the
  * differentiated coordinates (Sect. 3.1 eq. mapping); uploads them to
  * hip_device.  *out owns its device arrays.
- * Errors: CM_ERR_ARG (null, ne < 1, hi <= lo), CM_ERR_UNSUPPORTED (N != 4),
+ * Errors: CM_ERR_ARG (null, ne < 1, hi <= lo), CM_ERR_UNSUPPORTED (N != 4,
+ * or 16 x n_nodes >= 2^31: the kernels index nodes x words in 32 bits),
  * CM_ERR_HIP / CM_ERR_ALLOC. */
 CM_API cm_status cm_grid_create(const cm_grid_desc* desc, int hip_device, cm_grid** out);
 CM_API cm_status cm_grid_destroy(cm_grid* grid);

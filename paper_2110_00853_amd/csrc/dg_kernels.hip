@@ -15,7 +15,10 @@
 // State layout [var][element][node], node = i + 5 j + 25 k, coalesced per
 // (variable, element) as a 125-word run.  Blocks are mapped to elements so
 // that each of the eight XCDs walks one contiguous range of elements in a
-// tiled order.
+// tiled order.  Moist viscous models do the saturation adjustment
+// once per node and stage: the gradient pass of a step's first stage solves
+// it and stores T, the tendency pass reads T and solves for its output
+// state (Newton from the input T), which the next stage's passes read.
 #include <cmath>
 
 #include "cm_impl.hpp"
