@@ -543,6 +543,15 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(MLP || MO
 
     GradLoad<R, MOIST> g0;
     grad_load<R, MOIST>(P, Y, t, e, ex, ey, ez, g0);
+    // warped meshes: this node's metric terms, loaded at entry so that their
+    // latency overlaps phases A and B
+    R Ja[3][3], invJ = (R)0;
+    if (WARP) {
+        const R* m = (const R*)P.metrics;
+#pragma unroll
+        for (int q = 0; q < 9; ++q) Ja[q / 3][q % 3] = m[(int64_t)q * nn + node];
+        invJ = m[9 * nn + node];
+    }
 
     // phase A: thermodynamics and gradient variables into LDS
     Th th;
@@ -577,13 +586,6 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(MLP || MO
     // along each direction, chain rule, plus the lifts of the faces this node
     // lies on; the physical gradient G[q][c] = d g_q / d x_c stays in
     // registers (a select per variable, not an indexed write)
-    R Ja[3][3], invJ = (R)0;
-    if (WARP) {
-        const R* m = (const R*)P.metrics;
-#pragma unroll
-        for (int q = 0; q < 9; ++q) Ja[q / 3][q % 3] = m[(int64_t)q * nn + node];
-        invJ = m[9 * nn + node];
-    }
     const int idx[3] = {i, j, k};
     R nrm[3][3];
 #pragma unroll
@@ -1007,7 +1009,7 @@ struct OwnLoad {
     R Yr[NV];
     R w[VISC ? NWS : 1];
     R dq[MODE == 1 ? NV : 1];
-    R Jam[WARP ? 9 : 1];
+    R Jam[WARP ? 10 : 1];  // J a^d (9) and 1/J
     double pr, rr;
     double T;  // moist viscous: T from the gradient pass
 };
@@ -1038,7 +1040,7 @@ __device__ __forceinline__ void own_load(const KParams& P, const R* __restrict__
     if (WARP) {
         const R* m = (const R*)P.metrics;
 #pragma unroll
-        for (int q = 0; q < 9; ++q) o.Jam[q] = m[(int64_t)q * nn + node];
+        for (int q = 0; q < 10; ++q) o.Jam[q] = m[(int64_t)q * nn + node];
     }
 }
 
@@ -1141,7 +1143,7 @@ __device__ __forceinline__ void tend_element(const KParams& P, int e, int t,
     // phase D: gather the face terms of this node, metric factor, sources
     const int idx[3] = {i, j, k};
     if (WARP) {
-        const R invJ = ((const R*)P.metrics)[9 * nn + node];
+        const R invJ = o.Jam[9];
 #pragma unroll
         for (int v = 0; v < NV; ++v) Rv[v] *= invJ;
     }
