@@ -361,8 +361,10 @@ cm_status cm_model_create(const cm_grid* g, const cm_model_desc* desc, const dou
     const size_t s = desc->precision == CM_FP64 ? 8 : 4;
     m->Delta = std::cbrt((g->h[0] / 4.0) * (g->h[1] / 4.0) * (g->h[2] / 4.0));
     hipError_t e = hipSuccess;
-    if (m->nf > 0) e = hipMalloc(&m->d_F2, s * m->nf * nn);
-    for (int q = 0; q < 2 && e == hipSuccess && m->nf > 0 && moist; ++q) e = hipMalloc(&m->d_T[q], sizeof(double) * nn);
+    const int64_t run = s == 8 ? run_nodes<double>() : run_nodes<float>();
+    if (m->nf > 0) e = hipMalloc(&m->d_F2, s * m->nf * g->n_elem * run);
+    for (int q = 0; q < 2 && e == hipSuccess && m->nf > 0 && moist; ++q)
+        e = hipMalloc(&m->d_T[q], sizeof(double) * g->n_elem * run_nodes<double>());
     // reference state: per level when the mesh is flat and the background is
     // horizontally uniform, else per node
     m->has_ref = Yref != nullptr;
@@ -450,6 +452,7 @@ cm_status cm_model_create(const cm_grid* g, const cm_model_desc* desc, const dou
     k.subsidence = desc->subsidence != 0; k.sub_w0 = desc->sub_w0; k.sub_ztop = desc->sub_ztop;
     k.sub_inv = desc->subsidence ? 1.0 / desc->sub_ztop : 0.0;
     k.nf = m->nf;
+    k.nnf = g->n_elem * (desc->precision == CM_FP64 ? run_nodes<double>() : run_nodes<float>());
     k.mlp_frag = nullptr; k.mlp_bias = nullptr; k.mlp_norm = nullptr;
     k.mlp_fallback_on = 1; k.mlp_fallbacks = m->d_fallbacks;
     k.feat_out = nullptr;

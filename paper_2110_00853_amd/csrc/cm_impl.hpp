@@ -31,6 +31,13 @@ struct Phys {
 };
 
 // Everything the kernels need, passed by value.
+// nodes per element run in the model-owned per-node arrays (stored
+// diffusive flux, carried temperatures): 125 used, padded so that every run
+// starts on a 128-byte line and the two waves of a block write whole lines
+// (nodes 0-63, 64-127); 144 (FP64) and 160 (FP32) keep the run stride off a
+// power of two
+template <typename R> constexpr int run_nodes() { return sizeof(R) == 8 ? 144 : 160; }
+
 struct KParams {
     int ne0, ne1, ne2;
     int per0, per1, per2;
@@ -63,6 +70,7 @@ struct KParams {
     int subsidence;
     double sub_w0, sub_ztop, sub_inv;
     int nf;                     // words per node of the stored diffusive flux
+    int64_t nnf;                // stride of one F2 word: n_elem x F2_RUN (padded element runs)
     // learned closure
     const uint16_t* mlp_frag;   // bf16 B fragments of the four layers
     const float* mlp_bias;      // biases: 64, 64, 64, 2 (padded to 16)

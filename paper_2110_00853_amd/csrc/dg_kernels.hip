@@ -480,7 +480,7 @@ __device__ __forceinline__ void grad_load(const KParams& P, const R* __restrict_
     const int64_t np = (int64_t)(f.en >= 0 ? f.en : e) * NP + f.nbl;
 #pragma unroll
     for (int v = 0; v < (MOIST ? 6 : 5); ++v) f.Yp[v] = Y[v * P.nn + np];
-    if (MOIST && P.T_given) f.Tq = P.Tn[np];
+    if (MOIST && P.T_given) f.Tq = P.Tn[(int64_t)(f.en >= 0 ? f.en : e) * run_nodes<double>() + f.nbl];
 }
 
 // lift * (g* - g^-) of one face task into sL[q][task]
@@ -560,7 +560,8 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(MLP || MO
 #pragma unroll
         for (int v = 0; v < NV; ++v) Yv[v] = (double)Y[v * nn + node];
         if (MOIST && P.T_given)
-            thermo_moist_T(Yv[0], Yv[1], Yv[2], Yv[3], Yv[4], Yv[MOIST ? 5 : 0], P.Tn[node], th);
+            thermo_moist_T(Yv[0], Yv[1], Yv[2], Yv[3], Yv[4], Yv[MOIST ? 5 : 0],
+                           P.Tn[(int64_t)e * run_nodes<double>() + tt], th);
         else
             thermo<MOIST>(Yv[0], Yv[1], Yv[2], Yv[3], Yv[4], MOIST ? Yv[5] : 0.0, node_z(P, e, ez, k, tt), P.g, th);
     }
@@ -568,7 +569,8 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(MLP || MO
     if (MOIST) sg[GQ][t] = (R)th.qt;
     // the tendency pass of this stage takes T from here instead of repeating
     // the saturation adjustment
-    if (MOIST && !P.T_given && act) __builtin_nontemporal_store(th.T, &P.Tn[node]);
+    if (MOIST && !P.T_given)  // every lane, whole lines (see the F2 store)
+        __builtin_nontemporal_store(act ? th.T : 0.0, &P.Tn[(int64_t)e * run_nodes<double>() + t]);
     sg[GT][t] = need_thv ? (R)theta_v(th) : (R)0;
     __syncthreads();
 
@@ -752,11 +754,11 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(MLP || MO
     w[SB] = gr[3][2];
     if (MOIST) w[SB + 1] = G[GQ][2];
     const int nw = SB + (P.subsidence ? (MOIST ? 2 : 1) : 0);
-    if (act) {
+    // every lane stores (the three beyond the element write the padding), so
+    // that each wave writes whole cache lines
 #pragma unroll
-        for (int q = 0; q < 14; ++q)
-            if (q < nw) __builtin_nontemporal_store(w[q], &F2[q * nn + node]);
-    }
+    for (int q = 0; q < 14; ++q)
+        if (q < nw) __builtin_nontemporal_store(act ? w[q] : (R)0, &F2[q * P.nnf + (int64_t)e * run_nodes<R>() + t]);
 }
 
 // ---------------------------------------------------------------------------
@@ -862,27 +864,28 @@ __device__ __forceinline__ void face_load(const KParams& P, const R* __restrict_
     const int ezo = f.en >= 0 ? f.ezn : ez;
     const int64_t nn = P.nn;
     const int64_t np = (int64_t)eo * NP + f.nbl;
+    const int64_t npf = (int64_t)eo * run_nodes<R>() + f.nbl;  // in the padded F2 runs
 #pragma unroll
     for (int v = 0; v < NV; ++v) f.Yp[v] = Y[v * nn + np];
     if (VISC) {
         if (WARP) {
 #pragma unroll
-            for (int q = 0; q < NW; ++q) f.wp[q] = F2[q * nn + np];
+            for (int q = 0; q < NW; ++q) f.wp[q] = F2[q * P.nnf + npf];
         } else {
             // symmetric tau stored as xx yy zz xy xz yz: tau_{c,dir} is word
             // c when c = dir, else 2 + c + dir
             const int d = f.dir;
 #pragma unroll
-            for (int c = 0; c < 3; ++c) f.wp[c] = F2[(c == d ? c : 2 + c + d) * nn + np];
-            f.wp[3] = F2[(6 + d) * nn + np];
-            if (MOIST) f.wp[4] = F2[(9 + d) * nn + np];
+            for (int c = 0; c < 3; ++c) f.wp[c] = F2[(c == d ? c : 2 + c + d) * P.nnf + npf];
+            f.wp[3] = F2[(6 + d) * P.nnf + npf];
+            if (MOIST) f.wp[4] = F2[(9 + d) * P.nnf + npf];
         }
     }
     // reference pressure of the neighbour node; on a wall the neighbour slot
     // holds this element's mirrored node, and the flux needs this node's
     const int rn = f.en >= 0 ? f.nbl : f.own;
     f.prp = P.pr[ref_index(P, eo, ezo, rn / (NQ * NQ), rn)];
-    if (MOIST && VISC) f.Tq = P.Tn[(int64_t)eo * NP + rn];
+    if (MOIST && VISC) f.Tq = P.Tn[(int64_t)eo * run_nodes<double>() + rn];
 }
 
 // numerical flux of one face task; writes lift (n.F^- - n.F^*) over the
@@ -1027,7 +1030,7 @@ __device__ __forceinline__ void own_load(const KParams& P, const R* __restrict__
     if (VISC) {
         const int nw = P.subsidence ? O::NWS : O::NW;
 #pragma unroll
-        for (int q = 0; q < O::NWS; ++q) o.w[q] = q < nw ? F2[q * nn + node] : (R)0;
+        for (int q = 0; q < O::NWS; ++q) o.w[q] = q < nw ? F2[q * P.nnf + (int64_t)e * run_nodes<R>() + tt] : (R)0;
     }
     if (MODE == 1) {
 #pragma unroll
@@ -1036,7 +1039,7 @@ __device__ __forceinline__ void own_load(const KParams& P, const R* __restrict__
     const int ri = ref_index(P, e, ez, tt / (NQ * NQ), tt);
     o.pr = P.pr[ri];
     o.rr = P.rhor[ri];
-    if (MOIST && VISC) o.T = P.Tn[node];
+    if (MOIST && VISC) o.T = P.Tn[(int64_t)e * run_nodes<double>() + tt];
     if (WARP) {
         const R* m = (const R*)P.metrics;
 #pragma unroll
@@ -1196,7 +1199,7 @@ __device__ __forceinline__ void tend_element(const KParams& P, int e, int t,
         // Newton start: the next stage's passes read it instead of solving
         const double Tnew = moist_T_guess((double)Rv[0], (double)Rv[1], (double)Rv[2], (double)Rv[3],
                                           (double)Rv[4], (double)Rv[NV - 1], z, P.g, o.T);
-        __builtin_nontemporal_store(Tnew, &P.Tnext[node]);
+        __builtin_nontemporal_store(Tnew, &P.Tnext[(int64_t)e * run_nodes<double>() + t]);
     }
 }
 
