@@ -364,7 +364,7 @@ cm_status cm_model_create(const cm_grid* g, const cm_model_desc* desc, const dou
     const int64_t run = s == 8 ? run_nodes<double>() : run_nodes<float>();
     if (m->nf > 0) e = hipMalloc(&m->d_F2, s * m->nf * g->n_elem * run);
     for (int q = 0; q < 2 && e == hipSuccess && m->nf > 0 && moist; ++q)
-        e = hipMalloc(&m->d_T[q], sizeof(double) * g->n_elem * run_nodes<double>());
+        e = hipMalloc(&m->d_T[q], sizeof(double) * 2 * g->n_elem * run_nodes<double>());
     // reference state: per level when the mesh is flat and the background is
     // horizontally uniform, else per node
     m->has_ref = Yref != nullptr;
@@ -459,6 +459,7 @@ cm_status cm_model_create(const cm_grid* g, const cm_model_desc* desc, const dou
     k.Tn = m->d_T[0];
     k.Tnext = nullptr;
     k.T_given = 0;
+    k.nnT = g->n_elem * run_nodes<double>();
     if (e == hipSuccess && Yref) {
         // push the background through the device thermodynamics
         const int64_t nref = m->ref_per_node ? nn : (int64_t)g->desc.ne[2] * NQ;

@@ -82,9 +82,11 @@ struct KParams {
     // (written by the gradient pass, or by the previous stage's tendency
     // pass when T_given) and of its output state (written by the tendency
     // pass when Tnext is set) [nn]
+    // Each buffer holds T at [0, nnT) and q_l at [nnT, 2 nnT), in padded runs.
     double* Tn;
     double* Tnext;
     int T_given;
+    int64_t nnT;
 };
 
 }  // namespace cm
@@ -110,7 +112,7 @@ struct cm_model {
     cm_model_desc desc{};
     int nf = 0;
     void* d_F2 = nullptr;        // [nf][nn] storage type
-    double* d_T[2] = {nullptr, nullptr};  // moist viscous models: node temperature, ping-pong [nn]
+    double* d_T[2] = {nullptr, nullptr};  // moist viscous models: node T and q_l, ping-pong
     int tsel = 0;                // which d_T holds the current stage input's T
     double* d_pr = nullptr;
     double* d_rhor = nullptr;

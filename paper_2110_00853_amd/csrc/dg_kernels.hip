@@ -163,23 +163,30 @@ __device__ __forceinline__ void saturation_adjust(double rho, double qt, double 
     ql = qt - qv;
 }
 
-// the moist recovery when T is already known (the saturation adjustment of
-// the same state in the gradient pass): q_v = min(q_t, q_v*(T)) is what the
-// adjustment itself returns, for the unsaturated branch as well, so the
-// result is the one thermo() gives, without the Newton iteration
+// q_l of a moist state at its adjusted temperature T: the adjustment's own
+// q_v = min(q_t, q_v*(T)), for the unsaturated branch as well
+__device__ __forceinline__ double moist_ql(double rho, double rq, double T)
+{
+    const double qt = rq * frcp(rho);
+    const double irv = frcp(rho * Phys::Rv);
+    double qv = pvsat(T) * irv * frcp(T);
+    qv = qv < qt ? qv : qt;
+    return qt - qv;
+}
+
+// the moist recovery when T and q_l are already known (the saturation
+// adjustment of the same state earlier in the stage or step): the same
+// values thermo() gives, without the Newton iteration or q_v*
 __device__ __forceinline__ void thermo_moist_T(double rho, double mx, double my, double mz, double re, double rq,
-                                               double T, Th& o)
+                                               double T, double ql, Th& o)
 {
     const double ir = frcp(rho);
     o.rho = rho;
     o.u = mx * ir; o.v = my * ir; o.w = mz * ir;
     o.e = re * ir;
     o.qt = rq * ir;
-    const double irv = frcp(rho * Phys::Rv);
-    double qv = pvsat(T) * irv * frcp(T);
-    qv = qv < o.qt ? qv : o.qt;
     o.T = T;
-    o.ql = o.qt - qv;
+    o.ql = ql;
     o.qv = o.qt - o.ql;  // as thermo() forms it
     o.Rm = Phys::Rd * (1.0 - o.qt) + Phys::Rv * o.qv;
     const double cvm = (1.0 - o.qt) * Phys::cvd + o.qv * Phys::cvv + o.ql * Phys::cvl;
@@ -468,7 +475,7 @@ template <typename R, bool MOIST>
 struct GradLoad {
     int dir, sd, own, nbl, en, ezn;
     R Yp[MOIST ? 6 : 5];
-    double Tq;  // moist, T_given: the neighbour node's temperature
+    double Tq, qlq;  // moist, T_given: the neighbour node's T and q_l
 };
 
 template <typename R, bool MOIST>
@@ -480,7 +487,11 @@ __device__ __forceinline__ void grad_load(const KParams& P, const R* __restrict_
     const int64_t np = (int64_t)(f.en >= 0 ? f.en : e) * NP + f.nbl;
 #pragma unroll
     for (int v = 0; v < (MOIST ? 6 : 5); ++v) f.Yp[v] = Y[v * P.nn + np];
-    if (MOIST && P.T_given) f.Tq = P.Tn[(int64_t)(f.en >= 0 ? f.en : e) * run_nodes<double>() + f.nbl];
+    if (MOIST && P.T_given) {
+        const int64_t nt = (int64_t)(f.en >= 0 ? f.en : e) * run_nodes<double>() + f.nbl;
+        f.Tq = P.Tn[nt];
+        f.qlq = P.Tn[P.nnT + nt];
+    }
 }
 
 // lift * (g* - g^-) of one face task into sL[q][task]
@@ -495,7 +506,7 @@ __device__ __forceinline__ void grad_face(const KParams& P, const GradLoad<R, MO
         Th tp;
         if (MOIST && P.T_given)
             thermo_moist_T((double)f.Yp[0], (double)f.Yp[1], (double)f.Yp[2], (double)f.Yp[3], (double)f.Yp[4],
-                           (double)f.Yp[MOIST ? 5 : 0], f.Tq, tp);
+                           (double)f.Yp[MOIST ? 5 : 0], f.Tq, f.qlq, tp);
         else
             thermo<MOIST>((double)f.Yp[0], (double)f.Yp[1], (double)f.Yp[2], (double)f.Yp[3], (double)f.Yp[4],
                           MOIST ? (double)f.Yp[5] : 0.0, node_z(P, f.en, f.ezn, f.nbl / (NQ * NQ), f.nbl), P.g, tp);
@@ -561,16 +572,20 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(MLP || MO
         for (int v = 0; v < NV; ++v) Yv[v] = (double)Y[v * nn + node];
         if (MOIST && P.T_given)
             thermo_moist_T(Yv[0], Yv[1], Yv[2], Yv[3], Yv[4], Yv[MOIST ? 5 : 0],
-                           P.Tn[(int64_t)e * run_nodes<double>() + tt], th);
+                           P.Tn[(int64_t)e * run_nodes<double>() + tt],
+                           P.Tn[P.nnT + (int64_t)e * run_nodes<double>() + tt], th);
         else
             thermo<MOIST>(Yv[0], Yv[1], Yv[2], Yv[3], Yv[4], MOIST ? Yv[5] : 0.0, node_z(P, e, ez, k, tt), P.g, th);
     }
     sg[0][t] = (R)th.u; sg[1][t] = (R)th.v; sg[2][t] = (R)th.w; sg[3][t] = (R)th.h;
     if (MOIST) sg[GQ][t] = (R)th.qt;
-    // the tendency pass of this stage takes T from here instead of repeating
-    // the saturation adjustment
-    if (MOIST && !P.T_given)  // every lane, whole lines (see the F2 store)
-        __builtin_nontemporal_store(act ? th.T : 0.0, &P.Tn[(int64_t)e * run_nodes<double>() + t]);
+    // the tendency pass of this stage takes T and q_l from here instead of
+    // repeating the saturation adjustment (every lane stores: whole lines)
+    if (MOIST && !P.T_given) {
+        const int64_t nt = (int64_t)e * run_nodes<double>() + t;
+        __builtin_nontemporal_store(act ? th.T : 0.0, &P.Tn[nt]);
+        __builtin_nontemporal_store(act ? th.ql : 0.0, &P.Tn[P.nnT + nt]);
+    }
     sg[GT][t] = need_thv ? (R)theta_v(th) : (R)0;
     __syncthreads();
 
@@ -848,7 +863,7 @@ struct FaceLoad {
     int dir, sd, own, nbl, en, ezn;
     R Yp[NV], wp[VISC ? NWF : 1];
     double prp;
-    double Tq;  // moist viscous: T of the neighbour node (of this node on a wall)
+    double Tq, qlq;  // moist viscous: T and q_l of the neighbour node (of this node on a wall)
 };
 
 template <typename R, bool MOIST, bool WARP, bool VISC>
@@ -885,7 +900,11 @@ __device__ __forceinline__ void face_load(const KParams& P, const R* __restrict_
     // holds this element's mirrored node, and the flux needs this node's
     const int rn = f.en >= 0 ? f.nbl : f.own;
     f.prp = P.pr[ref_index(P, eo, ezo, rn / (NQ * NQ), rn)];
-    if (MOIST && VISC) f.Tq = P.Tn[(int64_t)eo * run_nodes<double>() + rn];
+    if (MOIST && VISC) {
+        const int64_t nt = (int64_t)eo * run_nodes<double>() + rn;
+        f.Tq = P.Tn[nt];
+        f.qlq = P.Tn[P.nnT + nt];
+    }
 }
 
 // numerical flux of one face task; writes lift (n.F^- - n.F^*) over the
@@ -933,7 +952,7 @@ __device__ __forceinline__ void face_flux(const KParams& P, const FaceLoad<R, MO
         Th tp;
         if (MOIST && VISC)
             thermo_moist_T((double)f.Yp[0], (double)f.Yp[1], (double)f.Yp[2], (double)f.Yp[3], (double)f.Yp[4],
-                           (double)f.Yp[NV - 1], f.Tq, tp);
+                           (double)f.Yp[NV - 1], f.Tq, f.qlq, tp);
         else
             thermo<MOIST>((double)f.Yp[0], (double)f.Yp[1], (double)f.Yp[2], (double)f.Yp[3], (double)f.Yp[4],
                           MOIST ? (double)f.Yp[NV - 1] : 0.0, node_z(P, en, ezn, kn, nbl), P.g, tp);
@@ -964,7 +983,7 @@ __device__ __forceinline__ void face_flux(const KParams& P, const FaceLoad<R, MO
                           node_z(P, e, ez, own / (NQ * NQ), own), P.g, tm);
         else if (MOIST && VISC)
             thermo_moist_T((double)Ym[0], (double)Ym[1], (double)Ym[2], (double)Ym[3], (double)Ym[4],
-                           (double)Ym[NV - 1], f.Tq, tm);
+                           (double)Ym[NV - 1], f.Tq, f.qlq, tm);
         else if (MOIST)
             thermo<MOIST>((double)Ym[0], (double)Ym[1], (double)Ym[2], (double)Ym[3], (double)Ym[4],
                           (double)Ym[NV - 1], node_z(P, e, ez, own / (NQ * NQ), own), P.g, tm);
@@ -1014,7 +1033,7 @@ struct OwnLoad {
     R dq[MODE == 1 ? NV : 1];
     R Jam[WARP ? 10 : 1];  // J a^d (9) and 1/J
     double pr, rr;
-    double T;  // moist viscous: T from the gradient pass
+    double T, ql;  // moist viscous: T and q_l from earlier in the stage
 };
 
 template <typename R, bool MOIST, bool WARP, bool VISC, int MODE>
@@ -1039,7 +1058,10 @@ __device__ __forceinline__ void own_load(const KParams& P, const R* __restrict__
     const int ri = ref_index(P, e, ez, tt / (NQ * NQ), tt);
     o.pr = P.pr[ri];
     o.rr = P.rhor[ri];
-    if (MOIST && VISC) o.T = P.Tn[(int64_t)e * run_nodes<double>() + tt];
+    if (MOIST && VISC) {
+        o.T = P.Tn[(int64_t)e * run_nodes<double>() + tt];
+        o.ql = P.Tn[P.nnT + (int64_t)e * run_nodes<double>() + tt];
+    }
     if (WARP) {
         const R* m = (const R*)P.metrics;
 #pragma unroll
@@ -1075,7 +1097,7 @@ __device__ __forceinline__ void tend_element(const KParams& P, int e, int t,
         Th th;
         if (MOIST && VISC)
             thermo_moist_T((double)o.Yr[0], (double)o.Yr[1], (double)o.Yr[2], (double)o.Yr[3], (double)o.Yr[4],
-                           (double)o.Yr[NV - 1], o.T, th);
+                           (double)o.Yr[NV - 1], o.T, o.ql, th);
         else
             thermo<MOIST>((double)o.Yr[0], (double)o.Yr[1], (double)o.Yr[2], (double)o.Yr[3], (double)o.Yr[4],
                           MOIST ? (double)o.Yr[NV - 1] : 0.0, z, P.g, th);
@@ -1199,7 +1221,9 @@ __device__ __forceinline__ void tend_element(const KParams& P, int e, int t,
         // Newton start: the next stage's passes read it instead of solving
         const double Tnew = moist_T_guess((double)Rv[0], (double)Rv[1], (double)Rv[2], (double)Rv[3],
                                           (double)Rv[4], (double)Rv[NV - 1], z, P.g, o.T);
-        __builtin_nontemporal_store(Tnew, &P.Tnext[(int64_t)e * run_nodes<double>() + t]);
+        const int64_t nt = (int64_t)e * run_nodes<double>() + t;
+        __builtin_nontemporal_store(Tnew, &P.Tnext[nt]);
+        __builtin_nontemporal_store(moist_ql((double)Rv[0], (double)Rv[NV - 1], Tnew), &P.Tnext[P.nnT + nt]);
     }
 }
 
