@@ -253,10 +253,19 @@ __device__ __forceinline__ void thermo(double rho, double mx, double my, double 
     o.h = o.e + o.p * ir;
 }
 
-// virtual potential temperature theta_v = T (p0/p)^(R_d/c_pd) R_m/R_d
-__device__ __forceinline__ double theta_v(const Th& o)
+// virtual potential temperature theta_v = T (p0/p)^(R_d/c_pd) R_m/R_d, in the
+// storage precision: FP64, or with FP32-bulk storage in FP32 from the FP64
+// T and p (it only enters the Richardson number; pressure and temperature
+// themselves stay FP64)
+template <typename R> __device__ __forceinline__ R theta_v(const Th& o);
+template <> __device__ __forceinline__ double theta_v<double>(const Th& o)
 {
     return o.T * exp(Phys::kappa * log(Phys::p0 * frcp(o.p))) * (o.Rm * (1.0 / Phys::Rd));
+}
+template <> __device__ __forceinline__ float theta_v<float>(const Th& o)
+{
+    const float x = (float)(Phys::p0 / o.p);
+    return (float)o.T * __expf((float)Phys::kappa * __logf(x)) * (float)(o.Rm * (1.0 / Phys::Rd));
 }
 
 // ---------------------------------------------------------------------------
@@ -513,7 +522,7 @@ __device__ __forceinline__ void grad_face(const KParams& P, const GradLoad<R, MO
         R gp[NG];
         gp[0] = (R)tp.u; gp[1] = (R)tp.v; gp[2] = (R)tp.w; gp[3] = (R)tp.h;
         if (MOIST) gp[GQ] = (R)tp.qt;
-        gp[GT] = need_thv ? (R)theta_v(tp) : (R)0;
+        gp[GT] = need_thv ? theta_v<R>(tp) : (R)0;
         R n[3], lift;
         face_normal<R, WARP>(P, (int64_t)e * NP + f.own, f.dir, f.sd ? 1 : -1, n, lift);
 #pragma unroll
@@ -586,7 +595,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(MLP || MO
         __builtin_nontemporal_store(act ? th.T : 0.0, &P.Tn[nt]);
         __builtin_nontemporal_store(act ? th.ql : 0.0, &P.Tn[P.nnT + nt]);
     }
-    sg[GT][t] = need_thv ? (R)theta_v(th) : (R)0;
+    sg[GT][t] = need_thv ? theta_v<R>(th) : (R)0;
     __syncthreads();
 
     // phase B: face tasks -> lift * (g* - g^-), centred g* (walls: 0); the
