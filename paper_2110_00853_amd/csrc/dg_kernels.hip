@@ -611,7 +611,10 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(MLP || MO
     // phase C: per gradient variable, volume derivative by the 1-D GLL matrix
     // along each direction, chain rule, plus the lifts of the faces this node
     // lies on; the physical gradient G[q][c] = d g_q / d x_c stays in
-    // registers (a select per variable, not an indexed write)
+    // registers.  The variable loop is unrolled (no select chain) with a
+    // scheduling barrier after each variable, so that the LDS reads of one
+    // variable are not hoisted into the previous one (which would keep every
+    // tile in flight and run out of registers)
     const int idx[3] = {i, j, k};
     R nrm[3][3];
 #pragma unroll
@@ -635,7 +638,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(MLP || MO
     for (int q = 0; q < NG; ++q)
 #pragma unroll
         for (int c = 0; c < 3; ++c) G[q][c] = 0;
-#pragma unroll 1
+#pragma unroll
     for (int q = 0; q < NG; ++q) {
         R d0 = 0, d1 = 0, d2 = 0;
 #pragma unroll
@@ -675,11 +678,12 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(MLP || MO
             f[13] = (double)gc[1];
             f[14] = (double)gc[2];
         }
+        // pin the three results here, so that the arithmetic of this
+        // variable is not moved past the next one's LDS reads
+        asm volatile("" : "+v"(gc[0]), "+v"(gc[1]), "+v"(gc[2]));
 #pragma unroll
-        for (int qq = 0; qq < NG; ++qq)
-#pragma unroll
-            for (int c = 0; c < 3; ++c)
-                if (qq != GT || c == 2) G[qq][c] = qq == q ? gc[c] : G[qq][c];
+        for (int c = 0; c < 3; ++c)
+            if (q != GT || c == 2) G[q][c] = gc[c];
     }
     R gr[4][3];   // velocity gradient and grad h_tot
 #pragma unroll
@@ -1144,13 +1148,10 @@ __device__ __forceinline__ void tend_element(const KParams& P, int e, int t,
     __syncthreads();
 
     // phase B: strong-form divergence with the 1-D GLL matrix, one variable
-    // at a time (unrolled over variables the compiler keeps every tile load
-    // in flight and runs out of registers); the result goes to its register
-    // by a select, not an indexed write
+    // at a time: each variable's sum is pinned before the next variable's
+    // LDS reads, so that the compiler does not keep every tile in flight
     R Rv[NV];
 #pragma unroll
-    for (int v = 0; v < NV; ++v) Rv[v] = 0;
-#pragma unroll 1
     for (int v = 0; v < NV; ++v) {
         R s = 0;
 #pragma unroll
@@ -1159,8 +1160,8 @@ __device__ __forceinline__ void tend_element(const KParams& P, int e, int t,
             s += dmat<R>(j, l) * sG[v * 3 + 1][i + NQ * (l + NQ * k)];
             s += dmat<R>(k, l) * sG[v * 3 + 2][i + NQ * (j + NQ * l)];
         }
-#pragma unroll
-        for (int u = 0; u < NV; ++u) Rv[u] = u == v ? -s : Rv[u];
+        asm volatile("" : "+v"(s));
+        Rv[v] = -s;
     }
     __syncthreads();
 
