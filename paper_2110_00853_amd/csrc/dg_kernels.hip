@@ -197,9 +197,12 @@ __device__ __forceinline__ void thermo_moist_T(double rho, double mx, double my,
 
 // temperature of a moist state by the saturation adjustment, Newton
 // started from Tg when that is above T_u (a nearby solution: the previous
-// stage's temperature of the same node); unsaturated air returns T_u
+// stage's temperature of the same node); unsaturated air returns T_u.  ql
+// is the liquid fraction at the returned temperature, as moist_ql gives it
+// (zero for unsaturated air without a second q_v* evaluation: there
+// moist_ql's minimum picks q_t)
 __device__ __forceinline__ double moist_T_guess(double rho, double mx, double my, double mz, double re, double rq,
-                                                double z, double g, double Tg)
+                                                double z, double g, double Tg, double& ql)
 {
     const double ir = frcp(rho);
     const double u = mx * ir, v = my * ir, w = mz * ir;
@@ -208,6 +211,7 @@ __device__ __forceinline__ double moist_T_guess(double rho, double mx, double my
     const double Tu = Phys::T0 + (I - qt * Phys::Iv0) * frcp((1.0 - qt) * Phys::cvd + qt * Phys::cvv);
     const double irv = frcp(rho * Phys::Rv);
     const double qvs_u = pvsat(Tu) * irv * frcp(Tu);
+    ql = 0.0;
     if (qt <= qvs_u) return Tu;
     double Tn = Tg > Tu ? Tg : Tu;
     for (int it = 0; it < 20; ++it) {
@@ -223,6 +227,7 @@ __device__ __forceinline__ double moist_T_guess(double rho, double mx, double my
         Tn -= step;
         if (fabs(step) <= 1e-13 * Tn) break;
     }
+    ql = moist_ql(rho, rq, Tn);
     return Tn;
 }
 
@@ -338,8 +343,10 @@ __device__ __forceinline__ R smagorinsky(const KParams& P, const R S[3][3], R N2
 // ---------------------------------------------------------------------------
 constexpr int NFT = 150;  // face-node tasks per element: 6 faces x 25 nodes
 
+// waves per SIMD the dry flat gradient pass is compiled for (80 VGPRs, no
+// spills)
 #ifndef CM_GRAD_WPE
-#define CM_GRAD_WPE 5
+#define CM_GRAD_WPE 6
 #endif
 
 __device__ __forceinline__ void face_task(int task, int& dir, int& sd, int& own, int& nbr)
@@ -863,6 +870,14 @@ __device__ __forceinline__ void f2_normal_axis(const R* wq, const R u[3], R side
     }
 }
 
+// whether the tendency pass keeps the own nodes' velocity and sound speed in
+// LDS for the face tasks (moist inviscid: no carried temperature to
+// recompute them from; FP32 storage: LDS is not the limit) or recomputes them
+template <typename R, bool MOIST, bool VISC> constexpr bool tend_keeps_p()
+{
+    return (MOIST && !VISC) || sizeof(R) == 4;
+}
+
 // data of one face task: the neighbour's state, diffusive flux (all words on
 // warped meshes; on flat meshes only the column of the face direction:
 // tau_{x,dir}, tau_{y,dir}, tau_{z,dir}, energy and water flux along dir)
@@ -877,6 +892,7 @@ struct FaceLoad {
     R Yp[NV], wp[VISC ? NWF : 1];
     double prp;
     double Tq, qlq;  // moist viscous: T and q_l of the neighbour node (of this node on a wall)
+    double To, qlo;  // moist viscous: T and q_l of the own node
 };
 
 template <typename R, bool MOIST, bool WARP, bool VISC>
@@ -917,6 +933,9 @@ __device__ __forceinline__ void face_load(const KParams& P, const R* __restrict_
         const int64_t nt = (int64_t)eo * run_nodes<double>() + rn;
         f.Tq = P.Tn[nt];
         f.qlq = P.Tn[P.nnT + nt];
+        const int64_t no = (int64_t)e * run_nodes<double>() + f.own;
+        f.To = P.Tn[no];
+        f.qlo = P.Tn[P.nnT + no];
     }
 }
 
@@ -937,20 +956,25 @@ __device__ __forceinline__ void face_flux(const KParams& P, const FaceLoad<R, MO
     R Ym[NV];
 #pragma unroll
     for (int v = 0; v < NV; ++v) Ym[v] = sY[v][own];
-    // own node's velocity and sound speed: from LDS in the moist case (the
-    // saturation adjustment is too costly to repeat) and with FP32 storage
-    // (LDS is not the limit there), recomputed from the own state in the
-    // dry FP64 case (the same FP64 arithmetic as phase A, so the same
-    // values, and 4 KB less LDS per block)
-    constexpr bool KEEP_P = MOIST || sizeof(R) == 4;
+    // own node's velocity and sound speed: from LDS in the moist inviscid
+    // case (the saturation adjustment is too costly to repeat) and with FP32
+    // storage (LDS is not the limit there); recomputed from the own state in
+    // the FP64 dry and moist viscous cases (the same FP64 arithmetic as phase
+    // A, with the moist temperature that phase A used, so the same values,
+    // and 4 KB less LDS per block)
+    constexpr bool KEEP_P = tend_keeps_p<R, MOIST, VISC>();
     Th to;
     R um[3], cm;
     if (KEEP_P) {
         um[0] = sP[0][own]; um[1] = sP[1][own]; um[2] = sP[2][own];
         cm = sP[3][own];
     } else {
-        thermo<false>((double)Ym[0], (double)Ym[1], (double)Ym[2], (double)Ym[3], (double)Ym[4], 0.0,
-                      node_z(P, e, ez, own / (NQ * NQ), own), P.g, to);
+        if (MOIST)
+            thermo_moist_T((double)Ym[0], (double)Ym[1], (double)Ym[2], (double)Ym[3], (double)Ym[4],
+                           (double)Ym[NV - 1], f.To, f.qlo, to);
+        else
+            thermo<false>((double)Ym[0], (double)Ym[1], (double)Ym[2], (double)Ym[3], (double)Ym[4], 0.0,
+                          node_z(P, e, ez, own / (NQ * NQ), own), P.g, to);
         um[0] = (R)to.u; um[1] = (R)to.v; um[2] = (R)to.w;
         cm = (R)to.c;
     }
@@ -990,14 +1014,16 @@ __device__ __forceinline__ void face_flux(const KParams& P, const FaceLoad<R, MO
         // reflecting ghost u+ = u- - 2 (n.u-) n with rho, rho e, rho q
         // mirrored: the Rusanov flux of (Y-, ghost) plus the prescribed wall
         // diffusive flux
+        // (without KEEP_P, to already holds this node's thermodynamics; on a
+        // wall the neighbour slot's T and q_l are this node's)
         Th tm = to;
         if (KEEP_P && !MOIST)
             thermo<false>((double)Ym[0], (double)Ym[1], (double)Ym[2], (double)Ym[3], (double)Ym[4], 0.0,
                           node_z(P, e, ez, own / (NQ * NQ), own), P.g, tm);
-        else if (MOIST && VISC)
+        else if (KEEP_P && MOIST && VISC)
             thermo_moist_T((double)Ym[0], (double)Ym[1], (double)Ym[2], (double)Ym[3], (double)Ym[4],
                            (double)Ym[NV - 1], f.Tq, f.qlq, tm);
-        else if (MOIST)
+        else if (MOIST && !VISC)
             thermo<MOIST>((double)Ym[0], (double)Ym[1], (double)Ym[2], (double)Ym[3], (double)Ym[4],
                           (double)Ym[NV - 1], node_z(P, e, ez, own / (NQ * NQ), own), P.g, tm);
         const R rho = Ym[0];
@@ -1119,7 +1145,7 @@ __device__ __forceinline__ void tend_element(const KParams& P, int e, int t,
         R F[NV][3];
         flux1<R, MOIST>(th, o.pr, F);
         const R um[3] = {(R)th.u, (R)th.v, (R)th.w};
-        if (MOIST || sizeof(R) == 4) {
+        if (tend_keeps_p<R, MOIST, VISC>()) {
             sP[0][t] = um[0]; sP[1][t] = um[1]; sP[2][t] = um[2];
             sP[3][t] = (R)th.c;
         }
@@ -1229,11 +1255,12 @@ __device__ __forceinline__ void tend_element(const KParams& P, int e, int t,
     if (MOIST && VISC && MODE != 0 && P.Tnext != nullptr) {
         // temperature of the output state, from the input state's as the
         // Newton start: the next stage's passes read it instead of solving
+        double qlnew;
         const double Tnew = moist_T_guess((double)Rv[0], (double)Rv[1], (double)Rv[2], (double)Rv[3],
-                                          (double)Rv[4], (double)Rv[NV - 1], z, P.g, o.T);
+                                          (double)Rv[4], (double)Rv[NV - 1], z, P.g, o.T, qlnew);
         const int64_t nt = (int64_t)e * run_nodes<double>() + t;
         __builtin_nontemporal_store(Tnew, &P.Tnext[nt]);
-        __builtin_nontemporal_store(moist_ql((double)Rv[0], (double)Rv[NV - 1], Tnew), &P.Tnext[P.nnT + nt]);
+        __builtin_nontemporal_store(qlnew, &P.Tnext[P.nnT + nt]);
     }
 }
 
@@ -1242,7 +1269,7 @@ __device__ __forceinline__ void tend_element(const KParams& P, int e, int t,
 // (n.F^- - n.F^*)
 #define CM_TEND_LDS                          \
     __shared__ R sG[NV * 3][BLOCK];          \
-    __shared__ R sP[MOIST || sizeof(R) == 4 ? 4 : 1][BLOCK]; /* u v w c (moist, FP32) */ \
+    __shared__ R sP[tend_keeps_p<R, MOIST, VISC>() ? 4 : 1][BLOCK]; /* u v w c */ \
     __shared__ R sY[NV][BLOCK]; /* own state, for the face tasks */
 
 // one element per block: own loads first, then the first face task's, so
