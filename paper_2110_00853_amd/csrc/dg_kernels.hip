@@ -1174,12 +1174,12 @@ __device__ __forceinline__ void own_load(const KParams& P, const R* __restrict__
 // contravariant flux in LDS -> divergence -> face tasks -> sources ->
 // epilogue.  MODE 0: out = R; MODE 1: LSRK stage; MODE 2: first LSRK stage
 // (A = 0, dQ not read).  The second face task (t + BLOCK < 150) is loaded
-// here unless the caller already did (ft1_loaded).
+// just before it is needed: loaded earlier, its registers stay live through
+// the divergence and cost a wave per SIMD (measured slower).
 template <typename R, bool MOIST, bool WARP, bool VISC, int MODE>
 __device__ __forceinline__ void tend_element(const KParams& P, int e, int t,
                                              const OwnLoad<R, MOIST, WARP, VISC, MODE>& o,
                                              const FaceLoad<R, MOIST, WARP, VISC>& ft0,
-                                             FaceLoad<R, MOIST, WARP, VISC>& ft1, bool ft1_loaded,
                                              R (*sG)[BLOCK], R (*sP)[BLOCK], R (*sY)[BLOCK],
                                              const R* __restrict__ Y, const R* __restrict__ F2,
                                              R* __restrict__ out, R* __restrict__ dQ, R A, R B, R dt)
@@ -1257,8 +1257,9 @@ __device__ __forceinline__ void tend_element(const KParams& P, int e, int t,
     // contravariant flux already in LDS (lift n.F = side G^dir / (J w_N)).
     // The first task's loads were issued at kernel entry (ft0).
     face_flux<R, MOIST, WARP, VISC>(P, ft0, e, ex, ey, ez, sG, sP, sY);
-    if (t + BLOCK < 150) {
-        if (!ft1_loaded) face_load<R, MOIST, WARP, VISC>(P, Y, F2, t + BLOCK, e, ex, ey, ez, ft1);
+    if (t + BLOCK < NFT) {
+        FaceLoad<R, MOIST, WARP, VISC> ft1;
+        face_load<R, MOIST, WARP, VISC>(P, Y, F2, t + BLOCK, e, ex, ey, ez, ft1);
         face_flux<R, MOIST, WARP, VISC>(P, ft1, e, ex, ey, ez, sG, sP, sY);
     }
     __syncthreads();
@@ -1348,9 +1349,9 @@ __global__ __launch_bounds__(BLOCK) void k_tend(const KParams P, const R* __rest
     const int ex = e % P.ne0, ey = (e / P.ne0) % P.ne1, ez = e / (P.ne0 * P.ne1);
     OwnLoad<R, MOIST, WARP, VISC, MODE> o;
     own_load<R, MOIST, WARP, VISC, MODE>(P, Y, F2, dQ, e, ez, tt, o);
-    FaceLoad<R, MOIST, WARP, VISC> ft0, ft1;
+    FaceLoad<R, MOIST, WARP, VISC> ft0;
     face_load<R, MOIST, WARP, VISC>(P, Y, F2, t, e, ex, ey, ez, ft0);
-    tend_element<R, MOIST, WARP, VISC, MODE>(P, e, t, o, ft0, ft1, false, sG, sP, sY, Y, F2, out, dQ, A, B, dt);
+    tend_element<R, MOIST, WARP, VISC, MODE>(P, e, t, o, ft0, sG, sP, sY, Y, F2, out, dQ, A, B, dt);
 }
 
 #undef CM_TEND_LDS
