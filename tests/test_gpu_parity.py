@@ -36,9 +36,16 @@ SMALL_CASES = {
     "inviscid": _small("bubble_4", (3, 2, 2), (1500.0, 1000.0, 1000.0)),
     # one element layer: bottom and top walls on the same element, Smagorinsky
     "one_layer": _small("bubble_32", (3, 2, 1), (600.0, 400.0, 200.0)),
+    # moist on a warped mesh (moist and metric terms together)
+    "moist_warped": _small("moist_64", (4, 2, 5), (1500.0, 500.0, 3000.0), topo=1, topo_a=300.0, topo_xc=750.0,
+                           topo_h=200.0),
+    # moist inviscid: no carried temperature, saturation adjustment at every
+    # node and face node of the tendency pass
+    "moist_inviscid": _small("moist_64", (3, 2, 4), (300.0, 200.0, 2000.0)),
 }
 SMALL_CASES["single_periodic"]["model"]["g"] = 0.0
 SMALL_CASES["inviscid"]["model"]["closure"] = "none"
+SMALL_CASES["moist_inviscid"]["model"]["closure"] = "none"
 
 
 def _state(c, seed=11):
@@ -91,7 +98,7 @@ def test_rhs_fp64_matches_oracle(dev, name):
     assert np.all(err < RHS_TOL), err
 
 
-@pytest.mark.parametrize("name", ["bubble_4", "moist", "warped"])
+@pytest.mark.parametrize("name", ["bubble_4", "moist", "warped", "moist_warped", "moist_inviscid"])
 def test_lsrk_step_matches_oracle(dev, name):
     c = SMALL_CASES[name]
     Y, Yref = _state(c)
@@ -207,7 +214,7 @@ def test_conservation_on_gpu_closed_box(dev):
 
 def test_fp32_bulk_rhs_error_is_stated(dev):
     """FP32-bulk tendency against the FP64 oracle: error stated, bounded."""
-    for name in ("smag_ragged", "moist", "warped"):
+    for name in ("smag_ragged", "moist", "warped", "moist_warped"):
         c = SMALL_CASES[name]
         Y, Yref = _state(c)
         g = B.Grid(c["grid"])
