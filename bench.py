@@ -157,8 +157,8 @@ def run(args):
     if not args.no_fp32:
         m32, Y32, ms32, _, prof32, _ = timed("fp32", args.steps, args.warmup)
         v32 = nn * nvar * 5 * args.steps / (ms32 * 1e-3)
-        a = Y64.cpu().numpy()
-        b = Y32.cpu().numpy().astype(np.float64)
+        a = m64.to_numpy(Y64)
+        b = m32.to_numpy(Y32).astype(np.float64)
         err = [float(np.abs(a[v] - b[v]).max() / np.abs(a[v]).max()) for v in range(nvar)]
         g32, tf32, to32 = alg_bytes(nvar, nf, 4)
         t32_ms, t32_n = prof32["tend"]

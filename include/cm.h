@@ -14,11 +14,16 @@
  *
  * Conventions for every call:
  *  - State buffers (Y, Y_alt, dQ, dYdt) are caller-owned DEVICE memory on
- *    the grid's device, contiguous, layout [nvar][n_nodes]; element-major
- *    node order: node = 125*e + i + 5*(j + 5*k), i along x, and
- *    e = ex + ne[0]*(ey + ne[1]*ez).  Element type double (CM_FP64) or
- *    float (CM_FP32_BULK), at least 16-byte aligned.  The library never
- *    frees or retains them beyond a call.
+ *    the grid's device, contiguous, layout [nvar][state_stride] with
+ *    state_stride = 160*n_elem (cm_grid_info): element-major runs of 160
+ *    slots, slot = 160*e + i + 5*(j + 5*k) for the node (i, j, k) of
+ *    element e = ex + ne[0]*(ey + ne[1]*ez), i along x.  Slots 125..159 of a
+ *    run are padding: never read as nodes, and written as zeros (125..127)
+ *    or left untouched (128..159) in outputs.  The padding puts every
+ *    element run on a 128-byte line in both precisions, so the kernels
+ *    stream whole lines.  Element type double (CM_FP64) or float
+ *    (CM_FP32_BULK), at least 16-byte aligned (256-byte for whole lines).
+ *    The library never frees or retains them beyond a call.
  *  - Grid and model objects own their device arrays (metrics, element
  *    traversal table, reference state, diffusive-flux scratch, the node
  *    temperatures moist viscous models carry between the passes and stages
@@ -84,6 +89,7 @@ typedef struct {
     int N;
     int warped;
     double dmin_node;    /* minimum distance between adjacent GLL nodes [m] */
+    int64_t state_stride; /* slots per variable in a state buffer: 160 * n_elem */
 } cm_grid_info;
 
 /* Physics of one model (Sects. 2, 4, App. A).  Units SI. */

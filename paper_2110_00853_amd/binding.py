@@ -43,7 +43,7 @@ class GridDesc(C.Structure):
 
 class GridInfo(C.Structure):
     _fields_ = [("n_elem", C.c_int64), ("n_nodes", C.c_int64), ("N", C.c_int), ("warped", C.c_int),
-                ("dmin_node", C.c_double)]
+                ("dmin_node", C.c_double), ("state_stride", C.c_int64)]
 
 
 class ModelDesc(C.Structure):
@@ -155,6 +155,10 @@ class Grid:
         info = GridInfo()
         _check(load().cm_grid_query(self.h, C.byref(info)))
         self.n_elem, self.n_nodes, self.dmin = info.n_elem, info.n_nodes, info.dmin_node
+        # state buffers: [nvar][state_stride], element runs of srun slots
+        # (the element's 125 nodes, then padding)
+        self.state_stride = info.state_stride
+        self.srun = info.state_stride // info.n_elem
 
     def __del__(self):
         if getattr(self, "h", None) and _lib is not None:
@@ -242,16 +246,33 @@ class Model:
         for t in ts:
             if not t.is_cuda:
                 raise ValueError("state tensors must live on the GPU")
-            if t.dtype != self.dtype or tuple(t.shape) != (self.nvar, self.grid.n_nodes) or not t.is_contiguous():
+            if t.dtype != self.dtype or tuple(t.shape) != (self.nvar, self.grid.state_stride) or not t.is_contiguous():
                 raise ValueError("state tensor must be contiguous %s of shape (%d, %d)"
-                                 % (self.dtype, self.nvar, self.grid.n_nodes))
+                                 % (self.dtype, self.nvar, self.grid.state_stride))
 
     def new_state(self, Y: np.ndarray | None = None):
+        """A device state buffer [nvar, state_stride]; from a node-ordered
+        array Y [nvar, n_nodes] if given (padding slots zero)."""
         import torch
 
+        g = self.grid
+        dev = "cuda:%d" % g.device
         if Y is None:
-            return torch.empty((self.nvar, self.grid.n_nodes), dtype=self.dtype, device="cuda:%d" % self.grid.device)
-        return torch.from_numpy(np.ascontiguousarray(Y)).to(device="cuda:%d" % self.grid.device, dtype=self.dtype)
+            return torch.zeros((self.nvar, g.state_stride), dtype=self.dtype, device=dev)
+        Y = np.asarray(Y)
+        if Y.shape != (self.nvar, g.n_nodes):
+            raise ValueError("state must have shape [nvar, n_nodes] = (%d, %d)" % (self.nvar, g.n_nodes))
+        P = np.zeros((self.nvar, g.n_elem, g.srun), dtype=np.float64)
+        P[:, :, :125] = Y.reshape(self.nvar, g.n_elem, 125)
+        return torch.from_numpy(P.reshape(self.nvar, g.state_stride)).to(device=dev, dtype=self.dtype)
+
+    def to_numpy(self, T) -> np.ndarray:
+        """Node-ordered host copy [nvar, n_nodes] of a device state buffer
+        (padding slots dropped), in the buffer's precision."""
+        g = self.grid
+        self._chk(T)
+        A = T.cpu().numpy().reshape(self.nvar, g.n_elem, g.srun)[:, :, :125]
+        return np.ascontiguousarray(A).reshape(self.nvar, g.n_nodes)
 
     def rhs(self, Y, out, t: float = 0.0, stream=None):
         self._chk(Y, out)

@@ -281,6 +281,7 @@ cm_status cm_grid_query(const cm_grid* g, cm_grid_info* out)
     if (!g || !out) { set_error("cm_grid_query: null argument"); return CM_ERR_ARG; }
     out->n_elem = g->n_elem;
     out->n_nodes = g->n_nodes;
+    out->state_stride = g->n_elem * SRUN;
     out->N = 4;
     out->warped = g->desc.topo;
     out->dmin_node = g->dmin;
@@ -428,6 +429,7 @@ cm_status cm_model_create(const cm_grid* g, const cm_model_desc* desc, const dou
     k.n_elem = (int)g->n_elem;
     k.order = g->d_order;
     k.nn = nn;
+    k.nnS = g->n_elem * SRUN;
     k.lo0 = g->desc.lo[0]; k.lo1 = g->desc.lo[1]; k.lo2 = g->desc.lo[2];
     k.h0 = g->h[0]; k.h1 = g->h[1]; k.h2 = g->h[2];
     k.r2h0 = 2.0 / g->h[0]; k.r2h1 = 2.0 / g->h[1]; k.r2h2 = 2.0 / g->h[2];

@@ -38,12 +38,20 @@ struct Phys {
 // power of two
 template <typename R> constexpr int run_nodes() { return sizeof(R) == 8 ? 144 : 160; }
 
+// slots per element in the state buffers (Y, dQ, dY/dt): the element's 125
+// nodes, then padding, so that every element run starts on a 128-byte line
+// in both precisions (1280 / 640 bytes) and a block's stores cover whole
+// lines (the lanes beyond the element write zeros); a stride off a power of
+// two
+constexpr int SRUN = 160;
+
 struct KParams {
     int ne0, ne1, ne2;
     int per0, per1, per2;
     int n_elem;
     const int* order;           // per-XCD element traversal table [n_elem]
     int64_t nn;                 // nodes
+    int64_t nnS;                // stride of one state variable: n_elem x SRUN
     double lo0, lo1, lo2;
     double h0, h1, h2;          // element extents (Cartesian metrics)
     double r2h0, r2h1, r2h2;    // 2 / h_d

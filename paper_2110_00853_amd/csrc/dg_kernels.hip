@@ -562,9 +562,9 @@ __device__ __forceinline__ void grad_load(const KParams& P, const R* __restrict_
 {
     face_task(task, f.dir, f.sd, f.own, f.nbl);
     f.en = nbr_elem(P, ex, ey, ez, f.dir, f.sd ? 1 : -1, f.ezn);
-    const int64_t np = (int64_t)(f.en >= 0 ? f.en : e) * NP + f.nbl;
+    const int64_t np = (int64_t)(f.en >= 0 ? f.en : e) * SRUN + f.nbl;  // state slot
 #pragma unroll
-    for (int v = 0; v < (MOIST ? 6 : 5); ++v) f.Yp[v] = Y[v * P.nn + np];
+    for (int v = 0; v < (MOIST ? 6 : 5); ++v) f.Yp[v] = Y[v * P.nnS + np];
     if (MOIST && P.T_given) {
         const int64_t nt = (int64_t)(f.en >= 0 ? f.en : e) * run_nodes<double>() + f.nbl;
         f.Tq = P.Tn[nt];
@@ -646,8 +646,9 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(MLP || MO
     Th th;
     {
         double Yv[NV];
+        const int64_t slot = (int64_t)e * SRUN + tt;
 #pragma unroll
-        for (int v = 0; v < NV; ++v) Yv[v] = (double)Y[v * nn + node];
+        for (int v = 0; v < NV; ++v) Yv[v] = (double)Y[v * P.nnS + slot];
         if (MOIST && P.T_given)
             thermo_moist_T(Yv[0], Yv[1], Yv[2], Yv[3], Yv[4], Yv[MOIST ? 5 : 0],
                            P.Tn[(int64_t)e * run_nodes<double>() + tt],
@@ -969,10 +970,10 @@ __device__ __forceinline__ void face_load(const KParams& P, const R* __restrict_
     const int eo = f.en >= 0 ? f.en : e;  // walls read their own node twice
     const int ezo = f.en >= 0 ? f.ezn : ez;
     const int64_t nn = P.nn;
-    const int64_t np = (int64_t)eo * NP + f.nbl;
+    const int64_t np = (int64_t)eo * SRUN + f.nbl;             // state slot
     const int64_t npf = (int64_t)eo * run_nodes<R>() + f.nbl;  // in the padded F2 runs
 #pragma unroll
-    for (int v = 0; v < NV; ++v) f.Yp[v] = Y[v * nn + np];
+    for (int v = 0; v < NV; ++v) f.Yp[v] = Y[v * P.nnS + np];
     if (VISC) {
         if (WARP) {
 #pragma unroll
@@ -1145,8 +1146,9 @@ __device__ __forceinline__ void own_load(const KParams& P, const R* __restrict__
     using O = OwnLoad<R, MOIST, WARP, VISC, MODE>;
     const int64_t nn = P.nn;
     const int64_t node = (int64_t)e * NP + tt;
+    const int64_t slot = (int64_t)e * SRUN + tt;  // in the state buffers
 #pragma unroll
-    for (int v = 0; v < O::NV; ++v) o.Yr[v] = Y[v * nn + node];
+    for (int v = 0; v < O::NV; ++v) o.Yr[v] = Y[v * P.nnS + slot];
     if (VISC) {
         const int nw = P.subsidence ? O::NWS : O::NW;
 #pragma unroll
@@ -1154,7 +1156,7 @@ __device__ __forceinline__ void own_load(const KParams& P, const R* __restrict__
     }
     if (MODE == 1) {
 #pragma unroll
-        for (int v = 0; v < O::NV; ++v) o.dq[v] = __builtin_nontemporal_load(&dQ[v * nn + node]);
+        for (int v = 0; v < O::NV; ++v) o.dq[v] = __builtin_nontemporal_load(&dQ[v * P.nnS + slot]);
     }
     const int ri = ref_index(P, e, ez, tt / (NQ * NQ), tt);
     o.pr = P.pr[ri];
@@ -1301,20 +1303,23 @@ __device__ __forceinline__ void tend_element(const KParams& P, int e, int t,
         if (MOIST) Rv[NV - 1] -= rws * o.w[NW + 1];
     }
 
-    if (!act) return;
+    // every lane stores (the three beyond the element write zeros into the
+    // padding), so that each wave writes whole lines of its element run
+    const int64_t slot = (int64_t)e * SRUN + t;
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
-        const int64_t a = v * nn + node;
+        const int64_t a = v * P.nnS + slot;
         if (MODE == 0) {
-            __builtin_nontemporal_store(Rv[v], &out[a]);
+            __builtin_nontemporal_store(act ? Rv[v] : (R)0, &out[a]);
         } else {
             const R dq = MODE == 1 ? A * o.dq[v] + dt * Rv[v] : dt * Rv[v];
             const R yn = o.Yr[v] + B * dq;
-            __builtin_nontemporal_store(dq, &dQ[a]);
-            __builtin_nontemporal_store(yn, &out[a]);
+            __builtin_nontemporal_store(act ? dq : (R)0, &dQ[a]);
+            __builtin_nontemporal_store(act ? yn : (R)0, &out[a]);
             if (MOIST && VISC) Rv[v] = yn;  // keep the output state for its temperature
         }
     }
+    if (!act) return;
     if (MOIST && VISC && MODE != 0 && P.Tnext != nullptr) {
         // temperature of the output state, from the input state's as the
         // Newton start: the next stage's passes read it instead of solving

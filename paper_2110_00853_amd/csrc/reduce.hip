@@ -75,6 +75,7 @@ __device__ void temp_sound(double rho, double mx, double my, double mz, double r
 
 struct DiagArgs {
     int64_t nn;
+    int64_t nnS;             // state stride (n_elem x SRUN slots per variable)
     int ne0, ne1;
     double lo2, h2, zg[NQ];
     double w[NQ];
@@ -92,17 +93,18 @@ __global__ __launch_bounds__(RB) void k_diag1(const DiagArgs A, const R* __restr
     double maxw = 0.0, maxcfl = 0.0, Tmin = INFINITY, Tmax = -INFINITY, nonfin = 0.0;
     const int64_t stride = (int64_t)gridDim.x * RB;
     for (int64_t n = (int64_t)blockIdx.x * RB + threadIdx.x; n < A.nn; n += stride) {
+        const int t = (int)(n % NP);
+        const int64_t e = n / NP;
+        const int64_t slot = e * SRUN + t;  // the node's slot in the state buffer
         double y[NV];
         bool fin = true;
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
-            y[v] = (double)Y[v * A.nn + n];
+            y[v] = (double)Y[v * A.nnS + slot];
             if (!isfinite(y[v])) { nonfin += 1.0; fin = false; }
         }
         if (!fin) continue;
-        const int t = (int)(n % NP);
         const int i = t % NQ, j = (t / NQ) % NQ, k = t / (NQ * NQ);
-        const int64_t e = n / NP;
         const double J = A.invJ ? 1.0 / A.invJ[n] : A.Jc;
         const double wJ = A.w[i] * A.w[j] * A.w[k] * J;
         const double z = A.zn ? A.zn[n] : A.lo2 + ((double)(e / ((int64_t)A.ne0 * A.ne1)) + A.zg[k]) * A.h2;
@@ -198,6 +200,7 @@ hipError_t launch_diagnostics(const cm_model* m, const void* Y, double dt, cm_di
     const cm_grid* g = m->grid;
     DiagArgs A;
     A.nn = g->n_nodes;
+    A.nnS = g->n_elem * SRUN;
     A.ne0 = g->desc.ne[0];
     A.ne1 = g->desc.ne[1];
     A.lo2 = g->desc.lo[2];

@@ -168,7 +168,7 @@ def run_pipeline(fine_ne=64, t_train=(60.0, 90.0, 120.0, 150.0, 180.0), t_eval=2
             if nsteps % 2000 == 0:
                 torch.cuda.synchronize()
                 log("fine run: step %d  t = %.1f s  (%.0f s elapsed)" % (nsteps, t, time.time() - t_start))
-        Yh = Ya.cpu().numpy()
+        Yh = mf.to_numpy(Ya)
         snaps[tw] = filtered(Yh, xyz_f[2], cf["grid"]["ne"])
         d = mf.diagnostics(Ya, dt_f)
         log("snapshot t = %.1f s  max|w| %.3f  (%.0f s elapsed)" % (t, d["max_abs_w"], time.time() - t_start))
@@ -243,7 +243,7 @@ def run_pipeline(fine_ne=64, t_train=(60.0, 90.0, 120.0, 150.0, 180.0), t_eval=2
             tt += dt_c
         torch.cuda.synchronize()
         el = time.time() - t0
-        Y = Ya.cpu().numpy()
+        Y = m.to_numpy(Ya)
         th = _theta(Y, xyz_c[2])
         w = Y[3] / Y[0]
         e_th = float(np.linalg.norm(th - th_ref) / np.linalg.norm(th_ref - th_bg))

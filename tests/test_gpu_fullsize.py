@@ -33,7 +33,7 @@ def test_full_size_rhs_matches_oracle(name):
         Rd = m.new_state()
         m.rhs(Yd, Rd)
         torch.cuda.synchronize()
-        out[prec] = rhs_errors(Rd.cpu().numpy().astype(np.float64), Rref, Y, hmin(c["grid"]))
+        out[prec] = rhs_errors(m.to_numpy(Rd).astype(np.float64), Rref, Y, hmin(c["grid"]))
         del m, Yd, Rd
     print(name, "full-size rhs errors fp64", out["fp64"], "oracle 1-ulp floor", floor, "fp32-bulk", out["fp32"])
     assert np.all(out["fp64"] < tol), (out["fp64"], tol)

@@ -141,7 +141,7 @@ def test_fused_closure_rhs_matches_oracle(torch):
     Rd = m.new_state()
     m.rhs(Yd, Rd)
     nfb = m.mlp_fallbacks()
-    Rg = Rd.cpu().numpy()
+    Rg = m.to_numpy(Rd)
     err = rhs_errors(Rg, Rref, Y, hmin(c["grid"]))
     print("fused mlp closure rhs errors", err, "fallbacks", nfb, nfb_ref)
     assert abs(nfb - nfb_ref) <= max(2, 0.01 * nfb_ref)

@@ -90,7 +90,7 @@ def test_rhs_fp64_matches_oracle(dev, name):
     Rd = m.new_state()
     m.rhs(Yd, Rd)
     dev.cuda.synchronize()
-    Rg = Rd.cpu().numpy()
+    Rg = m.to_numpy(Rd)
     Rref = oracle.Model(oracle.Grid(c["grid"]), c["model"], Yref).rhs(Y)
     err = rhs_errors(Rg, Rref, Y, hmin(c["grid"]))
     print(name, "rhs errors per variable", err)
@@ -112,7 +112,7 @@ def test_lsrk_step_matches_oracle(dev, name):
         m.lsrk_step(Ya, Yb, dQ, 0.0, dt)
         Ya, Yb = Yb, Ya
     dev.cuda.synchronize()
-    Yg = Ya.cpu().numpy()
+    Yg = m.to_numpy(Ya)
     Yo, _ = oracle.Model(oracle.Grid(c["grid"]), c["model"], Yref).steps(Y, dt, nsteps)
     err = state_errors(Yg, Yo)
     print(name, "state errors after", nsteps, "steps", err)
@@ -130,7 +130,7 @@ def test_bubble_4_hundred_steps(dev):
         m.lsrk_step(Ya, Yb, dQ, 0.0, dt)
         Ya, Yb = Yb, Ya
     dev.cuda.synchronize()
-    Yg = Ya.cpu().numpy()
+    Yg = m.to_numpy(Ya)
     Yo, _ = oracle.Model(oracle.Grid(c["grid"]), c["model"], Yref).steps(Y, dt, 100)
     err = state_errors(Yg, Yo)
     change = np.array([np.abs(Yo[v] - Y[v]).max() for v in range(5)])
@@ -154,7 +154,7 @@ def test_moist_hundred_steps(dev):
         m.lsrk_step(Ya, Yb, dQ, 0.0, dt)
         Ya, Yb = Yb, Ya
     dev.cuda.synchronize()
-    Yg = Ya.cpu().numpy()
+    Yg = m.to_numpy(Ya)
     Yo, _ = oracle.Model(oracle.Grid(c["grid"]), c["model"], Yref).steps(Y, dt, 100)
     _, _, ql, _ = oracle.thermo_nodes(Yo, W.node_coords(c["grid"])[2], c["model"].get("g", 9.81))
     err = state_errors(Yg, Yo)
@@ -209,7 +209,7 @@ def test_conservation_on_gpu_closed_box(dev):
     d1 = m.diagnostics(Ya)
     for k in ("mass", "energy", "water"):
         assert abs(d1[k] - d0[k]) / abs(d0[k]) < 1e-14, (k, d0[k], d1[k])
-    assert np.abs(Ya.cpu().numpy() - Y).max() > 1e-4
+    assert np.abs(m.to_numpy(Ya) - Y).max() > 1e-4
 
 
 def test_fp32_bulk_rhs_error_is_stated(dev):
@@ -223,7 +223,7 @@ def test_fp32_bulk_rhs_error_is_stated(dev):
         Rd = m.new_state()
         m.rhs(Yd, Rd)
         dev.cuda.synchronize()
-        Rg = Rd.cpu().numpy().astype(np.float64)
+        Rg = m.to_numpy(Rd).astype(np.float64)
         Rref = oracle.Model(oracle.Grid(c["grid"]), c["model"], Yref).rhs(Y)
         err = rhs_errors(Rg, Rref, Y, hmin(c["grid"]))
         print(name, "fp32-bulk rhs errors per variable", err)
