@@ -36,14 +36,20 @@ struct Phys {
 // starts on a 128-byte line and the two waves of a block write whole lines
 // (nodes 0-63, 64-127); 144 (FP64) and 160 (FP32) keep the run stride off a
 // power of two
-template <typename R> constexpr int run_nodes() { return sizeof(R) == 8 ? 144 : 160; }
+#ifndef CM_F2RUN64
+#define CM_F2RUN64 144
+#endif
+template <typename R> constexpr int run_nodes() { return sizeof(R) == 8 ? CM_F2RUN64 : 160; }
 
 // slots per element in the state buffers (Y, dQ, dY/dt): the element's 125
 // nodes, then padding, so that every element run starts on a 128-byte line
 // in both precisions (1280 / 640 bytes) and a block's stores cover whole
 // lines (the lanes beyond the element write zeros); a stride off a power of
 // two
-constexpr int SRUN = 160;
+#ifndef CM_SRUN
+#define CM_SRUN 160
+#endif
+constexpr int SRUN = CM_SRUN;
 
 struct KParams {
     int ne0, ne1, ne2;
