@@ -228,3 +228,34 @@ def test_fp32_bulk_rhs_error_is_stated(dev):
         err = rhs_errors(Rg, Rref, Y, hmin(c["grid"]))
         print(name, "fp32-bulk rhs errors per variable", err)
         assert np.all(np.isfinite(Rg)) and np.all(err < 5e-2), err
+
+
+def test_state_padding_contract(dev):
+    """State buffers hold element runs of 160 slots: the padding of an input
+    is never read (NaN there changes nothing), and outputs get zeros in
+    slots 125..127 and leave 128..159 untouched."""
+    torch = dev
+    c = SMALL_CASES["smag_ragged"]
+    Y, Yref = _state(c)
+    g = B.Grid(c["grid"])
+    assert g.state_stride == 160 * g.n_elem and g.srun == 160
+    m = B.Model(g, c["model"], Yref)
+    Yd = m.new_state(Y)
+    R0 = m.new_state()
+    m.rhs(Yd, R0)
+    Ynan = Yd.clone().view(m.nvar, g.n_elem, 160)
+    Ynan[:, :, 125:] = float("nan")
+    R1 = torch.full((m.nvar, g.state_stride), float("nan"), dtype=torch.float64, device=Yd.device)
+    m.rhs(Ynan.view(m.nvar, g.state_stride), R1)
+    Ya = torch.full_like(R1, float("nan"))
+    dQ = torch.full_like(R1, float("nan"))
+    m.lsrk_step(Ynan.view(m.nvar, g.state_stride), Ya, dQ, 0.0, 0.01)
+    torch.cuda.synchronize()
+    r0 = R0.view(m.nvar, g.n_elem, 160).cpu().numpy()
+    r1 = R1.view(m.nvar, g.n_elem, 160).cpu().numpy()
+    assert np.array_equal(r0[:, :, :125], r1[:, :, :125])      # bit-identical tendency
+    for T in (R1, Ya, dQ):
+        a = T.view(m.nvar, g.n_elem, 160).cpu().numpy()
+        assert np.all(np.isfinite(a[:, :, :125]))
+        assert np.all(a[:, :, 125:128] == 0.0)
+        assert np.all(np.isnan(a[:, :, 128:]))
