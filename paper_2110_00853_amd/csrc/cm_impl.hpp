@@ -101,6 +101,12 @@ struct KParams {
     double* Tnext;
     int T_given;
     int64_t nnT;
+    // per-variable / per-word array bases of the current launch (filled on
+    // the host): state input, output, dQ, stored diffusive flux
+    const void* Ys[6];
+    void* outs[6];
+    void* dQs[6];
+    void* F2s[14];
 };
 
 }  // namespace cm

@@ -74,6 +74,17 @@ __device__ __forceinline__ double fsqrt(double x)
 }
 __device__ __forceinline__ float fsqrt(float x) { return sqrtf(x); }
 
+// element of a per-variable (or per-word) array whose base comes with the
+// launch parameters: with the byte offset in 32 bits the access takes the
+// base from scalar registers and one 32-bit vector offset that all the
+// variables share, instead of a 64-bit address per lane and variable (the
+// offsets fit: the grid size is capped so that 16 x n_nodes < 2^31)
+template <typename T> __device__ __forceinline__ __attribute__((address_space(1))) T* gptr(const void* base,
+                                                                                         uint32_t byte_off)
+{
+    return (__attribute__((address_space(1))) T*)((__attribute__((address_space(1))) char*)base + byte_off);
+}
+
 // FP64 natural logarithm and exponential for the thermodynamics (theta_v
 // and the saturation vapour pressure), each about an ulp from the correctly
 // rounded result (checked on the host against extended precision).  The
@@ -562,9 +573,9 @@ __device__ __forceinline__ void grad_load(const KParams& P, const R* __restrict_
 {
     face_task(task, f.dir, f.sd, f.own, f.nbl);
     f.en = nbr_elem(P, ex, ey, ez, f.dir, f.sd ? 1 : -1, f.ezn);
-    const int64_t np = (int64_t)(f.en >= 0 ? f.en : e) * SRUN + f.nbl;  // state slot
+    const uint32_t soff = (uint32_t)((f.en >= 0 ? f.en : e) * SRUN + f.nbl) * (uint32_t)sizeof(R);
 #pragma unroll
-    for (int v = 0; v < (MOIST ? 6 : 5); ++v) f.Yp[v] = Y[v * P.nnS + np];
+    for (int v = 0; v < (MOIST ? 6 : 5); ++v) f.Yp[v] = *gptr<const R>(P.Ys[v], soff);
     if (MOIST && P.T_given) {
         const int64_t nt = (int64_t)(f.en >= 0 ? f.en : e) * run_nodes<double>() + f.nbl;
         f.Tq = P.Tn[nt];
@@ -646,9 +657,9 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(MLP || MO
     Th th;
     {
         double Yv[NV];
-        const int64_t slot = (int64_t)e * SRUN + tt;
+        const uint32_t soff = (uint32_t)(e * SRUN + tt) * (uint32_t)sizeof(R);
 #pragma unroll
-        for (int v = 0; v < NV; ++v) Yv[v] = (double)Y[v * P.nnS + slot];
+        for (int v = 0; v < NV; ++v) Yv[v] = (double)*gptr<const R>(P.Ys[v], soff);
         if (MOIST && P.T_given)
             thermo_moist_T(Yv[0], Yv[1], Yv[2], Yv[3], Yv[4], Yv[MOIST ? 5 : 0],
                            P.Tn[(int64_t)e * run_nodes<double>() + tt],
@@ -856,7 +867,9 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(MLP || MO
     // that each wave writes whole cache lines
 #pragma unroll
     for (int q = 0; q < 14; ++q)
-        if (q < nw) __builtin_nontemporal_store(act ? w[q] : (R)0, &F2[q * P.nnf + (int64_t)e * run_nodes<R>() + t]);
+        if (q < nw)
+            __builtin_nontemporal_store(act ? w[q] : (R)0,
+                                        gptr<R>(P.F2s[q], (uint32_t)(e * run_nodes<R>() + t) * (uint32_t)sizeof(R)));
 }
 
 // ---------------------------------------------------------------------------
@@ -970,10 +983,10 @@ __device__ __forceinline__ void face_load(const KParams& P, const R* __restrict_
     const int eo = f.en >= 0 ? f.en : e;  // walls read their own node twice
     const int ezo = f.en >= 0 ? f.ezn : ez;
     const int64_t nn = P.nn;
-    const int64_t np = (int64_t)eo * SRUN + f.nbl;             // state slot
+    const uint32_t soff = (uint32_t)(eo * SRUN + f.nbl) * (uint32_t)sizeof(R);  // state slot, bytes
     const int64_t npf = (int64_t)eo * run_nodes<R>() + f.nbl;  // in the padded F2 runs
 #pragma unroll
-    for (int v = 0; v < NV; ++v) f.Yp[v] = Y[v * P.nnS + np];
+    for (int v = 0; v < NV; ++v) f.Yp[v] = *gptr<const R>(P.Ys[v], soff);
     if (VISC) {
         if (WARP) {
 #pragma unroll
@@ -1146,17 +1159,18 @@ __device__ __forceinline__ void own_load(const KParams& P, const R* __restrict__
     using O = OwnLoad<R, MOIST, WARP, VISC, MODE>;
     const int64_t nn = P.nn;
     const int64_t node = (int64_t)e * NP + tt;
-    const int64_t slot = (int64_t)e * SRUN + tt;  // in the state buffers
+    const uint32_t soff = (uint32_t)(e * SRUN + tt) * (uint32_t)sizeof(R);  // byte offset in the state buffers
 #pragma unroll
-    for (int v = 0; v < O::NV; ++v) o.Yr[v] = Y[v * P.nnS + slot];
+    for (int v = 0; v < O::NV; ++v) o.Yr[v] = *gptr<const R>(P.Ys[v], soff);
     if (VISC) {
         const int nw = P.subsidence ? O::NWS : O::NW;
+        const uint32_t foff = (uint32_t)(e * run_nodes<R>() + tt) * (uint32_t)sizeof(R);
 #pragma unroll
-        for (int q = 0; q < O::NWS; ++q) o.w[q] = q < nw ? F2[q * P.nnf + (int64_t)e * run_nodes<R>() + tt] : (R)0;
+        for (int q = 0; q < O::NWS; ++q) o.w[q] = q < nw ? *gptr<const R>(P.F2s[q], foff) : (R)0;
     }
     if (MODE == 1) {
 #pragma unroll
-        for (int v = 0; v < O::NV; ++v) o.dq[v] = __builtin_nontemporal_load(&dQ[v * P.nnS + slot]);
+        for (int v = 0; v < O::NV; ++v) o.dq[v] = __builtin_nontemporal_load(gptr<const R>(P.dQs[v], soff));
     }
     const int ri = ref_index(P, e, ez, tt / (NQ * NQ), tt);
     o.pr = P.pr[ri];
@@ -1305,17 +1319,16 @@ __device__ __forceinline__ void tend_element(const KParams& P, int e, int t,
 
     // every lane stores (the three beyond the element write zeros into the
     // padding), so that each wave writes whole lines of its element run
-    const int64_t slot = (int64_t)e * SRUN + t;
+    const uint32_t soff = (uint32_t)(e * SRUN + t) * (uint32_t)sizeof(R);
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
-        const int64_t a = v * P.nnS + slot;
         if (MODE == 0) {
-            __builtin_nontemporal_store(act ? Rv[v] : (R)0, &out[a]);
+            __builtin_nontemporal_store(act ? Rv[v] : (R)0, gptr<R>(P.outs[v], soff));
         } else {
             const R dq = MODE == 1 ? A * o.dq[v] + dt * Rv[v] : dt * Rv[v];
             const R yn = o.Yr[v] + B * dq;
-            __builtin_nontemporal_store(act ? dq : (R)0, &dQ[a]);
-            __builtin_nontemporal_store(act ? yn : (R)0, &out[a]);
+            __builtin_nontemporal_store(act ? dq : (R)0, gptr<R>(P.dQs[v], soff));
+            __builtin_nontemporal_store(act ? yn : (R)0, gptr<R>(P.outs[v], soff));
             if (MOIST && VISC) Rv[v] = yn;  // keep the output state for its temperature
         }
     }
@@ -1361,11 +1374,24 @@ __global__ __launch_bounds__(BLOCK) void k_tend(const KParams P, const R* __rest
 
 #undef CM_TEND_LDS
 
+// per-variable and per-word bases of one launch's arrays
+template <typename R>
+static void set_bases(KParams& P, const void* Y, void* out, void* dQ, void* F2)
+{
+    for (int v = 0; v < 6; ++v) {
+        P.Ys[v] = Y ? (const void*)((const R*)Y + v * P.nnS) : nullptr;
+        P.outs[v] = out ? (void*)((R*)out + v * P.nnS) : nullptr;
+        P.dQs[v] = dQ ? (void*)((R*)dQ + v * P.nnS) : nullptr;
+    }
+    for (int q = 0; q < 14; ++q) P.F2s[q] = F2 ? (void*)((R*)F2 + q * P.nnf) : nullptr;
+}
+
 template <typename R, bool MOIST, bool WARP>
 static hipError_t launch_typed(cm_model* m, const void* Y, void* out, void* dQ, int mode, double A, double B,
                                double dt, hipStream_t s)
 {
     KParams P = m->kp;
+    set_bases<R>(P, Y, out, dQ, m->d_F2);
     const bool moist_visc = MOIST && m->d_T[0] != nullptr;
     if (moist_visc) {
         // stages 2..5 of an LSRK step (mode 1) find their input state's T in
@@ -1407,7 +1433,8 @@ static hipError_t launch_typed(cm_model* m, const void* Y, void* out, void* dQ, 
 
 hipError_t launch_grad_only(cm_model* m, const void* Y, hipStream_t s)
 {
-    const KParams& P = m->kp;
+    KParams P = m->kp;
+    set_bases<double>(P, Y, nullptr, nullptr, m->d_F2);
     const bool moist = m->desc.nvar == 6;
     const bool warp = m->grid->desc.topo == 1;
     if (m->desc.precision != CM_FP64) return hipErrorInvalidValue;
