@@ -12,8 +12,11 @@
 //             xi1/xi2/xi3 -> Rusanov / centred face fluxes with the
 //             neighbour's face nodes -> sources -> epilogue (write R, or
 //             dQ = A dQ + dt R, Y_new = Y + B dQ).
-// State layout [var][element][node], node = i + 5 j + 25 k, coalesced per
-// (variable, element) as a 125-word run.  Blocks are mapped to elements so
+// State layout [var][element][slot], slot = i + 5 j + 25 k, each (variable,
+// element) a line-aligned run of SRUN slots (125 nodes, then padding that
+// the epilogue fills with zeros so that stores cover whole lines); the
+// per-variable bases of a launch come with its parameters and every lane
+// addresses its node by a 32-bit byte offset.  Blocks are mapped to elements so
 // that each of the eight XCDs walks one contiguous range of elements in a
 // tiled order.  Moist viscous models do the saturation adjustment
 // once per node and stage: the gradient pass of a step's first stage solves
@@ -568,7 +571,7 @@ struct GradLoad {
 };
 
 template <typename R, bool MOIST>
-__device__ __forceinline__ void grad_load(const KParams& P, const R* __restrict__ Y, int task, int e, int ex, int ey,
+__device__ __forceinline__ void grad_load(const KParams& P, int task, int e, int ex, int ey,
                                           int ez, GradLoad<R, MOIST>& f)
 {
     face_task(task, f.dir, f.sd, f.own, f.nbl);
@@ -622,7 +625,7 @@ __device__ __forceinline__ void grad_face(const KParams& P, const GradLoad<R, MO
 // gradient + closure pass
 // ---------------------------------------------------------------------------
 template <typename R, bool MOIST, bool WARP, bool MLP>
-__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(MLP || MOIST || WARP ? 1 : CM_GRAD_WPE))) void k_grad(const KParams P, const R* __restrict__ Y, R* __restrict__ F2)
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(MLP || MOIST || WARP ? 1 : CM_GRAD_WPE))) void k_grad(const KParams P)
 {
     constexpr int NV = MOIST ? 6 : 5;
     constexpr int NG = MOIST ? 6 : 5;  // u v w h [qt] thv
@@ -642,7 +645,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(MLP || MO
     const bool need_thv = (P.closure == CM_CLOSURE_SMAG && P.richardson) || MLP;
 
     GradLoad<R, MOIST> g0;
-    grad_load<R, MOIST>(P, Y, t, e, ex, ey, ez, g0);
+    grad_load<R, MOIST>(P, t, e, ex, ey, ez, g0);
     // warped meshes: this node's metric terms, loaded at entry so that their
     // latency overlaps phases A and B
     R Ja[3][3], invJ = (R)0;
@@ -684,7 +687,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(MLP || MO
     grad_face<R, MOIST, WARP>(P, g0, t, e, need_thv, sg, sL);
     if (t + BLOCK < 150) {
         GradLoad<R, MOIST> g1;
-        grad_load<R, MOIST>(P, Y, t + BLOCK, e, ex, ey, ez, g1);
+        grad_load<R, MOIST>(P, t + BLOCK, e, ex, ey, ez, g1);
         grad_face<R, MOIST, WARP>(P, g1, t + BLOCK, e, need_thv, sg, sL);
     }
     __syncthreads();
@@ -972,7 +975,7 @@ struct FaceLoad {
 };
 
 template <typename R, bool MOIST, bool WARP, bool VISC>
-__device__ __forceinline__ void face_load(const KParams& P, const R* __restrict__ Y, const R* __restrict__ F2,
+__device__ __forceinline__ void face_load(const KParams& P, const R* __restrict__ F2,
                                           int task, int e, int ex, int ey, int ez,
                                           FaceLoad<R, MOIST, WARP, VISC>& f)
 {
@@ -982,7 +985,6 @@ __device__ __forceinline__ void face_load(const KParams& P, const R* __restrict_
     f.en = nbr_elem(P, ex, ey, ez, f.dir, f.sd ? 1 : -1, f.ezn);
     const int eo = f.en >= 0 ? f.en : e;  // walls read their own node twice
     const int ezo = f.en >= 0 ? f.ezn : ez;
-    const int64_t nn = P.nn;
     const uint32_t soff = (uint32_t)(eo * SRUN + f.nbl) * (uint32_t)sizeof(R);  // state slot, bytes
     const int64_t npf = (int64_t)eo * run_nodes<R>() + f.nbl;  // in the padded F2 runs
 #pragma unroll
@@ -1018,8 +1020,8 @@ __device__ __forceinline__ void face_load(const KParams& P, const R* __restrict_
 // numerical flux of one face task; writes lift (n.F^- - n.F^*) over the
 // task's own-node entries of sG (the divergence is already done)
 template <typename R, bool MOIST, bool WARP, bool VISC>
-__device__ __forceinline__ void face_flux(const KParams& P, const FaceLoad<R, MOIST, WARP, VISC>& f, int e, int ex,
-                                          int ey, int ez, R (*sG)[BLOCK], R (*sP)[BLOCK], R (*sY)[BLOCK])
+__device__ __forceinline__ void face_flux(const KParams& P, const FaceLoad<R, MOIST, WARP, VISC>& f, int e, int ez,
+                                          R (*sG)[BLOCK], R (*sP)[BLOCK], R (*sY)[BLOCK])
 {
     constexpr int NV = MOIST ? 6 : 5;
     const int64_t nn = P.nn;
@@ -1152,8 +1154,7 @@ struct OwnLoad {
 };
 
 template <typename R, bool MOIST, bool WARP, bool VISC, int MODE>
-__device__ __forceinline__ void own_load(const KParams& P, const R* __restrict__ Y, const R* __restrict__ F2,
-                                         const R* __restrict__ dQ, int e, int ez, int tt,
+__device__ __forceinline__ void own_load(const KParams& P, int e, int ez, int tt,
                                          OwnLoad<R, MOIST, WARP, VISC, MODE>& o)
 {
     using O = OwnLoad<R, MOIST, WARP, VISC, MODE>;
@@ -1197,8 +1198,7 @@ __device__ __forceinline__ void tend_element(const KParams& P, int e, int t,
                                              const OwnLoad<R, MOIST, WARP, VISC, MODE>& o,
                                              const FaceLoad<R, MOIST, WARP, VISC>& ft0,
                                              R (*sG)[BLOCK], R (*sP)[BLOCK], R (*sY)[BLOCK],
-                                             const R* __restrict__ Y, const R* __restrict__ F2,
-                                             R* __restrict__ out, R* __restrict__ dQ, R A, R B, R dt)
+                                             const R* __restrict__ F2, R A, R B, R dt)
 {
     constexpr int NV = MOIST ? 6 : 5;
     constexpr int NW = MOIST ? 12 : 9;
@@ -1206,8 +1206,6 @@ __device__ __forceinline__ void tend_element(const KParams& P, int e, int t,
     const int tt = act ? t : NP - 1;
     const int i = tt % NQ, j = (tt / NQ) % NQ, k = tt / (NQ * NQ);
     const int ex = e % P.ne0, ey = (e / P.ne0) % P.ne1, ez = e / (P.ne0 * P.ne1);
-    const int64_t nn = P.nn;
-    const int64_t node = (int64_t)e * NP + tt;
     const double z = node_z(P, e, ez, k, tt);
     double rho_d, mom_d[3];
     {
@@ -1272,11 +1270,11 @@ __device__ __forceinline__ void tend_element(const KParams& P, int e, int t,
     // phase C: face tasks.  lift (n.F^- - n.F^*): n.F^- comes from the
     // contravariant flux already in LDS (lift n.F = side G^dir / (J w_N)).
     // The first task's loads were issued at kernel entry (ft0).
-    face_flux<R, MOIST, WARP, VISC>(P, ft0, e, ex, ey, ez, sG, sP, sY);
+    face_flux<R, MOIST, WARP, VISC>(P, ft0, e, ez, sG, sP, sY);
     if (t + BLOCK < NFT) {
         FaceLoad<R, MOIST, WARP, VISC> ft1;
-        face_load<R, MOIST, WARP, VISC>(P, Y, F2, t + BLOCK, e, ex, ey, ez, ft1);
-        face_flux<R, MOIST, WARP, VISC>(P, ft1, e, ex, ey, ez, sG, sP, sY);
+        face_load<R, MOIST, WARP, VISC>(P, F2, t + BLOCK, e, ex, ey, ez, ft1);
+        face_flux<R, MOIST, WARP, VISC>(P, ft1, e, ez, sG, sP, sY);
     }
     __syncthreads();
 
@@ -1356,8 +1354,7 @@ __device__ __forceinline__ void tend_element(const KParams& P, int e, int t,
 // one element per block: own loads first, then the first face task's, so
 // that their latency overlaps phase A
 template <typename R, bool MOIST, bool WARP, bool VISC, int MODE>
-__global__ __launch_bounds__(BLOCK) void k_tend(const KParams P, const R* __restrict__ Y, const R* __restrict__ F2,
-                                                R* __restrict__ out, R* __restrict__ dQ, R A, R B, R dt)
+__global__ __launch_bounds__(BLOCK) void k_tend(const KParams P, const R* __restrict__ F2, R A, R B, R dt)
 {
     constexpr int NV = MOIST ? 6 : 5;
     CM_TEND_LDS
@@ -1366,10 +1363,10 @@ __global__ __launch_bounds__(BLOCK) void k_tend(const KParams P, const R* __rest
     const int tt = t < NP ? t : NP - 1;
     const int ex = e % P.ne0, ey = (e / P.ne0) % P.ne1, ez = e / (P.ne0 * P.ne1);
     OwnLoad<R, MOIST, WARP, VISC, MODE> o;
-    own_load<R, MOIST, WARP, VISC, MODE>(P, Y, F2, dQ, e, ez, tt, o);
+    own_load<R, MOIST, WARP, VISC, MODE>(P, e, ez, tt, o);
     FaceLoad<R, MOIST, WARP, VISC> ft0;
-    face_load<R, MOIST, WARP, VISC>(P, Y, F2, t, e, ex, ey, ez, ft0);
-    tend_element<R, MOIST, WARP, VISC, MODE>(P, e, t, o, ft0, sG, sP, sY, Y, F2, out, dQ, A, B, dt);
+    face_load<R, MOIST, WARP, VISC>(P, F2, t, e, ex, ey, ez, ft0);
+    tend_element<R, MOIST, WARP, VISC, MODE>(P, e, t, o, ft0, sG, sP, sY, F2, A, B, dt);
 }
 
 #undef CM_TEND_LDS
@@ -1401,21 +1398,19 @@ static hipError_t launch_typed(cm_model* m, const void* Y, void* out, void* dQ, 
         P.T_given = mode == 1;
     }
     const dim3 grid(P.n_elem), block(BLOCK);
-    const R* y = (const R*)Y;
-    R* F2 = (R*)m->d_F2;
+    const R* F2 = (const R*)m->d_F2;
     const bool visc = m->desc.closure != CM_CLOSURE_NONE;
     if (visc) {
         cm_model::ProfRec* r = prof_begin(m, 0, s);
         if (m->desc.closure == CM_CLOSURE_MLP)
-            hipLaunchKernelGGL((k_grad<R, MOIST, WARP, true>), grid, block, 0, s, P, y, F2);
+            hipLaunchKernelGGL((k_grad<R, MOIST, WARP, true>), grid, block, 0, s, P);
         else
-            hipLaunchKernelGGL((k_grad<R, MOIST, WARP, false>), grid, block, 0, s, P, y, F2);
+            hipLaunchKernelGGL((k_grad<R, MOIST, WARP, false>), grid, block, 0, s, P);
         prof_end(r, s);
     }
     cm_model::ProfRec* rt = prof_begin(m, 1, s);
 #define CM_TEND(V, MD)                                                                                      \
-    hipLaunchKernelGGL((k_tend<R, MOIST, WARP, V, MD>), grid, block, 0, s, P, y, (const R*)F2, (R*)out, (R*)dQ, \
-                       (R)A, (R)B, (R)dt)
+    hipLaunchKernelGGL((k_tend<R, MOIST, WARP, V, MD>), grid, block, 0, s, P, F2, (R)A, (R)B, (R)dt)
     if (visc) {
         if (mode == 0) CM_TEND(true, 0);
         else if (mode == 1) CM_TEND(true, 1);
@@ -1439,14 +1434,12 @@ hipError_t launch_grad_only(cm_model* m, const void* Y, hipStream_t s)
     const bool warp = m->grid->desc.topo == 1;
     if (m->desc.precision != CM_FP64) return hipErrorInvalidValue;
     const dim3 grid(P.n_elem), block(BLOCK);
-    double* F2 = (double*)m->d_F2;
-    const double* y = (const double*)Y;
     if (moist) {
-        if (warp) hipLaunchKernelGGL((k_grad<double, true, true, false>), grid, block, 0, s, P, y, F2);
-        else hipLaunchKernelGGL((k_grad<double, true, false, false>), grid, block, 0, s, P, y, F2);
+        if (warp) hipLaunchKernelGGL((k_grad<double, true, true, false>), grid, block, 0, s, P);
+        else hipLaunchKernelGGL((k_grad<double, true, false, false>), grid, block, 0, s, P);
     } else {
-        if (warp) hipLaunchKernelGGL((k_grad<double, false, true, false>), grid, block, 0, s, P, y, F2);
-        else hipLaunchKernelGGL((k_grad<double, false, false, false>), grid, block, 0, s, P, y, F2);
+        if (warp) hipLaunchKernelGGL((k_grad<double, false, true, false>), grid, block, 0, s, P);
+        else hipLaunchKernelGGL((k_grad<double, false, false, false>), grid, block, 0, s, P);
     }
     return hipGetLastError();
 }
