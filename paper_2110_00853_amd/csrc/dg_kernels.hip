@@ -398,17 +398,16 @@ __device__ __forceinline__ R smagorinsky(const KParams& P, const R S[3][3], R N2
 #pragma unroll
         for (int b = 0; b < 3; ++b) SS += (R)2 * S[a][b] * S[a][b];
     if (!(SS > (R)0)) return (R)0;
-    R fb = (R)1;
+    const R cd = (R)(P.Cs * P.Delta);
     if (P.richardson) {
         const R Ri = N2 * frcp(SS);
         if (Ri > (R)0) {
-            R a = (R)1 - Ri * (R)P.invPrt;
-            a = a > (R)0 ? a : (R)0;
-            fb = a > (R)0 ? fsqrt(fsqrt(a)) : (R)0;
+            // sqrt|S|^2 (1 - Ri/Pr_t)^(1/4) as one fourth root of |S|^4 (1 - Ri/Pr_t)
+            const R a = (R)1 - Ri * (R)P.invPrt;
+            return a > (R)0 ? cd * cd * fsqrt(fsqrt(SS * SS * a)) : (R)0;
         }
     }
-    const R cd = (R)(P.Cs * P.Delta);
-    return cd * cd * fsqrt(SS) * fb;
+    return cd * cd * fsqrt(SS);
 }
 
 // ---------------------------------------------------------------------------
@@ -624,8 +623,9 @@ __device__ __forceinline__ void grad_face(const KParams& P, const GradLoad<R, MO
 // ---------------------------------------------------------------------------
 // gradient + closure pass
 // ---------------------------------------------------------------------------
-template <typename R, bool MOIST, bool WARP, bool MLP>
-__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(MLP || MOIST || WARP ? 1 : CM_GRAD_WPE))) void k_grad(const KParams P)
+// FEAT: also export the closure inputs per node (P.feat_out), for training
+template <typename R, bool MOIST, bool WARP, bool MLP, bool FEAT = false>
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(MLP || MOIST || WARP || FEAT ? 1 : CM_GRAD_WPE))) void k_grad(const KParams P)
 {
     constexpr int NV = MOIST ? 6 : 5;
     constexpr int NG = MOIST ? 6 : 5;  // u v w h [qt] thv
@@ -724,6 +724,19 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(MLP || MO
         for (int c = 0; c < 3; ++c) G[q][c] = 0;
 #pragma unroll
     for (int q = 0; q < NG; ++q) {
+        if (q == GT && !WARP && !FEAT) {
+            // only d theta_v / dz enters (through N^2): on flat meshes that is
+            // the derivative along xi_3 and the lifts of the z faces
+            R d2 = 0;
+#pragma unroll
+            for (int l = 0; l < NQ; ++l) d2 += dmat<R>(k, l) * sg[q][i + NQ * (j + NQ * l)];
+            const R jl = sL[q][ftask[2]];
+            const R jv = onf[2] ? jl : (R)0;
+            R gz = (R)P.r2h2 * d2 + (idx[2] == 0 ? -jv : jv);
+            asm volatile("" : "+v"(gz));
+            G[q][2] = gz;
+            continue;
+        }
         R d0 = 0, d1 = 0, d2 = 0;
 #pragma unroll
         for (int l = 0; l < NQ; ++l) {
@@ -754,7 +767,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(MLP || MO
                 gc[dir] += idx[dir] == 0 ? -jv : jv;
             }
         }
-        if (q == GT && P.feat_out != nullptr && act) {
+        if (FEAT && q == GT && act) {
             // grad theta_v for the closure-input export (only its z part is
             // kept in registers)
             double* f = P.feat_out + node * 16;
@@ -831,7 +844,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(MLP || MO
             if ((threadIdx.x & 63) == 0 && nfb) atomicAdd(P.mlp_fallbacks, nfb);
         }
     }
-    if (!MLP && P.feat_out != nullptr && act) {
+    if (FEAT && !MLP && act) {
         // closure inputs for training: grad u (9), N^2, Delta, TKE estimate
         // (nu_SL / (0.1 Delta))^2, grad theta_v (3), theta_v
         double* f = P.feat_out + node * 16;
@@ -1435,11 +1448,11 @@ hipError_t launch_grad_only(cm_model* m, const void* Y, hipStream_t s)
     if (m->desc.precision != CM_FP64) return hipErrorInvalidValue;
     const dim3 grid(P.n_elem), block(BLOCK);
     if (moist) {
-        if (warp) hipLaunchKernelGGL((k_grad<double, true, true, false>), grid, block, 0, s, P);
-        else hipLaunchKernelGGL((k_grad<double, true, false, false>), grid, block, 0, s, P);
+        if (warp) hipLaunchKernelGGL((k_grad<double, true, true, false, true>), grid, block, 0, s, P);
+        else hipLaunchKernelGGL((k_grad<double, true, false, false, true>), grid, block, 0, s, P);
     } else {
-        if (warp) hipLaunchKernelGGL((k_grad<double, false, true, false>), grid, block, 0, s, P);
-        else hipLaunchKernelGGL((k_grad<double, false, false, false>), grid, block, 0, s, P);
+        if (warp) hipLaunchKernelGGL((k_grad<double, false, true, false, true>), grid, block, 0, s, P);
+        else hipLaunchKernelGGL((k_grad<double, false, false, false, true>), grid, block, 0, s, P);
     }
     return hipGetLastError();
 }
