@@ -588,7 +588,7 @@ __device__ __forceinline__ void grad_load(const KParams& P, int task, int e, int
 // lift * (g* - g^-) of one face task into sL[q][task]
 template <typename R, bool MOIST, bool WARP>
 __device__ __forceinline__ void grad_face(const KParams& P, const GradLoad<R, MOIST>& f, int task, int e,
-                                          bool need_thv, R (*sg)[BLOCK], R (*sL)[NFT])
+                                          bool need_thv, bool thv_all_faces, R (*sg)[BLOCK], R (*sL)[NFT])
 {
     constexpr int NG = MOIST ? 6 : 5;
     constexpr int GQ = 4, GT = MOIST ? 5 : 4;
@@ -604,7 +604,10 @@ __device__ __forceinline__ void grad_face(const KParams& P, const GradLoad<R, MO
         R gp[NG];
         gp[0] = (R)tp.u; gp[1] = (R)tp.v; gp[2] = (R)tp.w; gp[3] = (R)tp.h;
         if (MOIST) gp[GQ] = (R)tp.qt;
-        gp[GT] = need_thv ? theta_v<R>(tp) : (R)0;
+        // theta_v: all faces when every component of its gradient is formed,
+        // else (flat mesh, only d/dz used) the z faces only
+        const bool thv_here = need_thv && (thv_all_faces || f.dir == 2);
+        gp[GT] = thv_here ? theta_v<R>(tp) : (R)0;
         R n[3], lift;
         face_normal<R, WARP>(P, (int64_t)e * NP + f.own, f.dir, f.sd ? 1 : -1, n, lift);
 #pragma unroll
@@ -612,6 +615,7 @@ __device__ __forceinline__ void grad_face(const KParams& P, const GradLoad<R, MO
             const R gm = sg[q][f.own];
             jump[q] = lift * ((R)0.5 * (gm + gp[q]) - gm);
         }
+        if (!thv_here) jump[GT] = (R)0;
     } else {
 #pragma unroll
         for (int q = 0; q < NG; ++q) jump[q] = (R)0;
@@ -684,11 +688,11 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(MLP || MO
 
     // phase B: face tasks -> lift * (g* - g^-), centred g* (walls: 0); the
     // first task's neighbour state was loaded at kernel entry
-    grad_face<R, MOIST, WARP>(P, g0, t, e, need_thv, sg, sL);
+    grad_face<R, MOIST, WARP>(P, g0, t, e, need_thv, WARP || FEAT, sg, sL);
     if (t + BLOCK < 150) {
         GradLoad<R, MOIST> g1;
         grad_load<R, MOIST>(P, t + BLOCK, e, ex, ey, ez, g1);
-        grad_face<R, MOIST, WARP>(P, g1, t + BLOCK, e, need_thv, sg, sL);
+        grad_face<R, MOIST, WARP>(P, g1, t + BLOCK, e, need_thv, WARP || FEAT, sg, sL);
     }
     __syncthreads();
 
