@@ -184,10 +184,36 @@ __device__ __forceinline__ int nbr_elem(const KParams& P, int ex, int ey, int ez
     return c0 + P.ne0 * (c1 + P.ne1 * c2);
 }
 
+// (1 + xi_k)/2 of this lane's k, selected from the launch parameters' scalar
+// copies: an indexed read of the parameter array would be a vector load,
+// and waiting for it waits for every load issued before it (the element's
+// own data and its face gathers)
+__device__ __forceinline__ double zgll_of(const KParams& P, int k)
+{
+    double z0 = P.zgll[0], z1 = P.zgll[1], z2 = P.zgll[2], z3 = P.zgll[3], z4 = P.zgll[4];
+    // held opaque in scalar registers, or the compiler turns the selects
+    // back into one indexed load
+    asm volatile("" : "+s"(z0), "+s"(z1), "+s"(z2), "+s"(z3), "+s"(z4));
+    double z = z0;
+    z = k == 1 ? z1 : z;
+    z = k == 2 ? z2 : z;
+    z = k == 3 ? z3 : z;
+    z = k == 4 ? z4 : z;
+    return z;
+}
+
+// node height; WARP fixed at compile time in the passes (a flat-mesh
+// kernel then carries no per-node height load whose register a later wait
+// would have to cover), from the launch parameters elsewhere
+template <bool WARP>
 __device__ __forceinline__ double node_z(const KParams& P, int e, int ez, int k, int t)
 {
-    if (P.warped) return P.zn[(int64_t)e * NP + t];
-    return P.lo2 + ((double)ez + P.zgll[k]) * P.h2;
+    if (WARP) return P.zn[(int64_t)e * NP + t];
+    return P.lo2 + ((double)ez + zgll_of(P, k)) * P.h2;
+}
+__device__ __forceinline__ double node_z(const KParams& P, int e, int ez, int k, int t)
+{
+    return P.warped ? node_z<true>(P, e, ez, k, t) : node_z<false>(P, e, ez, k, t);
 }
 
 __device__ __forceinline__ int ref_index(const KParams& P, int e, int ez, int k, int t)
@@ -361,7 +387,7 @@ __global__ void k_reference(KParams P, const double* __restrict__ Yr, int64_t nr
     double z;
     if (!P.ref_per_node) {
         const int ez = (int)(r / NQ), k = (int)(r % NQ);
-        z = P.lo2 + ((double)ez + P.zgll[k]) * P.h2;
+        z = P.lo2 + ((double)ez + zgll_of(P, k)) * P.h2;
     } else {
         const int e = (int)(r / NP), t = (int)(r % NP);
         const int ez = e / (P.ne0 * P.ne1);
@@ -600,7 +626,7 @@ __device__ __forceinline__ void grad_face(const KParams& P, const GradLoad<R, MO
                            (double)f.Yp[MOIST ? 5 : 0], f.Tq, f.qlq, tp);
         else
             thermo<MOIST>((double)f.Yp[0], (double)f.Yp[1], (double)f.Yp[2], (double)f.Yp[3], (double)f.Yp[4],
-                          MOIST ? (double)f.Yp[5] : 0.0, node_z(P, f.en, f.ezn, f.nbl / (NQ * NQ), f.nbl), P.g, tp);
+                          MOIST ? (double)f.Yp[5] : 0.0, node_z<WARP>(P, f.en, f.ezn, f.nbl / (NQ * NQ), f.nbl), P.g, tp);
         R gp[NG];
         gp[0] = (R)tp.u; gp[1] = (R)tp.v; gp[2] = (R)tp.w; gp[3] = (R)tp.h;
         if (MOIST) gp[GQ] = (R)tp.qt;
@@ -672,7 +698,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(MLP || MO
                            P.Tn[(int64_t)e * run_nodes<double>() + tt],
                            P.Tn[P.nnT + (int64_t)e * run_nodes<double>() + tt], th);
         else
-            thermo<MOIST>(Yv[0], Yv[1], Yv[2], Yv[3], Yv[4], MOIST ? Yv[5] : 0.0, node_z(P, e, ez, k, tt), P.g, th);
+            thermo<MOIST>(Yv[0], Yv[1], Yv[2], Yv[3], Yv[4], MOIST ? Yv[5] : 0.0, node_z<WARP>(P, e, ez, k, tt), P.g, th);
     }
     sg[0][t] = (R)th.u; sg[1][t] = (R)th.v; sg[2][t] = (R)th.w; sg[3][t] = (R)th.h;
     if (MOIST) sg[GQ][t] = (R)th.qt;
@@ -1069,7 +1095,7 @@ __device__ __forceinline__ void face_flux(const KParams& P, const FaceLoad<R, MO
                            (double)Ym[NV - 1], f.To, f.qlo, to);
         else
             thermo<false>((double)Ym[0], (double)Ym[1], (double)Ym[2], (double)Ym[3], (double)Ym[4], 0.0,
-                          node_z(P, e, ez, own / (NQ * NQ), own), P.g, to);
+                          node_z<WARP>(P, e, ez, own / (NQ * NQ), own), P.g, to);
         um[0] = (R)to.u; um[1] = (R)to.v; um[2] = (R)to.w;
         cm = (R)to.c;
     }
@@ -1087,7 +1113,7 @@ __device__ __forceinline__ void face_flux(const KParams& P, const FaceLoad<R, MO
                            (double)f.Yp[NV - 1], f.Tq, f.qlq, tp);
         else
             thermo<MOIST>((double)f.Yp[0], (double)f.Yp[1], (double)f.Yp[2], (double)f.Yp[3], (double)f.Yp[4],
-                          MOIST ? (double)f.Yp[NV - 1] : 0.0, node_z(P, en, ezn, kn, nbl), P.g, tp);
+                          MOIST ? (double)f.Yp[NV - 1] : 0.0, node_z<WARP>(P, en, ezn, kn, nbl), P.g, tp);
         const R up[3] = {(R)tp.u, (R)tp.v, (R)tp.w};
         R fp[NV];
         flux1_normal<R, MOIST>((R)tp.rho, up, (R)(tp.p - f.prp), (R)(tp.rho * tp.e + tp.p), (R)(tp.rho * tp.qt), n,
@@ -1114,13 +1140,13 @@ __device__ __forceinline__ void face_flux(const KParams& P, const FaceLoad<R, MO
         Th tm = to;
         if (KEEP_P && !MOIST)
             thermo<false>((double)Ym[0], (double)Ym[1], (double)Ym[2], (double)Ym[3], (double)Ym[4], 0.0,
-                          node_z(P, e, ez, own / (NQ * NQ), own), P.g, tm);
+                          node_z<WARP>(P, e, ez, own / (NQ * NQ), own), P.g, tm);
         else if (KEEP_P && MOIST && VISC)
             thermo_moist_T((double)Ym[0], (double)Ym[1], (double)Ym[2], (double)Ym[3], (double)Ym[4],
                            (double)Ym[NV - 1], f.Tq, f.qlq, tm);
         else if (MOIST && !VISC)
             thermo<MOIST>((double)Ym[0], (double)Ym[1], (double)Ym[2], (double)Ym[3], (double)Ym[4],
-                          (double)Ym[NV - 1], node_z(P, e, ez, own / (NQ * NQ), own), P.g, tm);
+                          (double)Ym[NV - 1], node_z<WARP>(P, e, ez, own / (NQ * NQ), own), P.g, tm);
         const R rho = Ym[0];
         const R pp = (R)(tm.p - f.prp), ep = (R)(tm.rho * tm.e + tm.p);
         const R rq = MOIST ? Ym[NV - 1] : (R)0;
@@ -1223,7 +1249,7 @@ __device__ __forceinline__ void tend_element(const KParams& P, int e, int t,
     const int tt = act ? t : NP - 1;
     const int i = tt % NQ, j = (tt / NQ) % NQ, k = tt / (NQ * NQ);
     const int ex = e % P.ne0, ey = (e / P.ne0) % P.ne1, ez = e / (P.ne0 * P.ne1);
-    const double z = node_z(P, e, ez, k, tt);
+    const double z = node_z<WARP>(P, e, ez, k, tt);
     double rho_d, mom_d[3];
     {
         Th th;
