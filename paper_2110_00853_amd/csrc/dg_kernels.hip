@@ -1239,7 +1239,7 @@ __device__ __forceinline__ void own_load(const KParams& P, int e, int ez, int tt
 template <typename R, bool MOIST, bool WARP, bool VISC, int MODE>
 __device__ __forceinline__ void tend_element(const KParams& P, int e, int t,
                                              const OwnLoad<R, MOIST, WARP, VISC, MODE>& o,
-                                             const FaceLoad<R, MOIST, WARP, VISC>& ft0,
+                                             const FaceLoad<R, MOIST, WARP, VISC>& ft0, R dval,
                                              R (*sG)[BLOCK], R (*sP)[BLOCK], R (*sY)[BLOCK],
                                              const R* __restrict__ F2, R A, R B, R dt)
 {
@@ -1287,9 +1287,13 @@ __device__ __forceinline__ void tend_element(const KParams& P, int e, int t,
                 R G;
                 if (WARP) G = o.Jam[3 * d] * F[v][0] + o.Jam[3 * d + 1] * F[v][1] + o.Jam[3 * d + 2] * F[v][2];
                 else G = (R)(d == 0 ? P.r2h0 : (d == 1 ? P.r2h1 : P.r2h2)) * F[v][d];
-                sG[v * 3 + d][t] = G;
+                if (act) sG[v * 3 + d][t] = G;
             }
     }
+    // the differentiation matrix into the unused slots 125, 126 of sG:
+    // D[r][c] at sG[3c + r % 3][125 + r / 3] (its load was issued first, so
+    // phase B waits for no global load)
+    if (t < NQ * NQ) sG[(t % NQ) * 3 + (t / NQ) % 3][NP + (t / NQ) / 3] = dval;
     __syncthreads();
 
     // phase B: strong-form divergence with the 1-D GLL matrix, one variable
@@ -1301,9 +1305,9 @@ __device__ __forceinline__ void tend_element(const KParams& P, int e, int t,
         R s = 0;
 #pragma unroll
         for (int l = 0; l < NQ; ++l) {
-            s += dmat<R>(i, l) * sG[v * 3 + 0][l + NQ * (j + NQ * k)];
-            s += dmat<R>(j, l) * sG[v * 3 + 1][i + NQ * (l + NQ * k)];
-            s += dmat<R>(k, l) * sG[v * 3 + 2][i + NQ * (j + NQ * l)];
+            s += sG[l * 3 + i % 3][NP + i / 3] * sG[v * 3 + 0][l + NQ * (j + NQ * k)];
+            s += sG[l * 3 + j % 3][NP + j / 3] * sG[v * 3 + 1][i + NQ * (l + NQ * k)];
+            s += sG[l * 3 + k % 3][NP + k / 3] * sG[v * 3 + 2][i + NQ * (j + NQ * l)];
         }
         asm volatile("" : "+v"(s));
         Rv[v] = -s;
@@ -1406,10 +1410,11 @@ __global__ __launch_bounds__(BLOCK) void k_tend(const KParams P, const R* __rest
     const int tt = t < NP ? t : NP - 1;
     const int ex = e % P.ne0, ey = (e / P.ne0) % P.ne1, ez = e / (P.ne0 * P.ne1);
     OwnLoad<R, MOIST, WARP, VISC, MODE> o;
+    const R dval = dmat<R>(t < NQ * NQ ? t / NQ : 0, t < NQ * NQ ? t % NQ : 0);
     own_load<R, MOIST, WARP, VISC, MODE>(P, e, ez, tt, o);
     FaceLoad<R, MOIST, WARP, VISC> ft0;
     face_load<R, MOIST, WARP, VISC>(P, F2, t, e, ex, ey, ez, ft0);
-    tend_element<R, MOIST, WARP, VISC, MODE>(P, e, t, o, ft0, sG, sP, sY, F2, A, B, dt);
+    tend_element<R, MOIST, WARP, VISC, MODE>(P, e, t, o, ft0, dval, sG, sP, sY, F2, A, B, dt);
 }
 
 #undef CM_TEND_LDS
