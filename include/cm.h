@@ -73,7 +73,7 @@ typedef enum {
  * [lo, hi]; periodic[d] != 0 wraps direction d, otherwise its two end faces
  * are free-slip walls.  topo = 1 warps the mesh terrain-following over the
  * Agnesi ridge z_sfc(x) = topo_h topo_a^2 / ((x - topo_xc)^2 + topo_a^2)
- * (eq. agnesi) with linear decay to a flat lid at hi[2] (Sect. 4.3). */
+ * (eq. agnesi, Sect. 5.4) with linear decay to a flat lid at hi[2] (Sect. 5.3). */
 typedef struct {
     int N;               /* polynomial order; only 4 is supported */
     int ne[3];
@@ -143,7 +143,7 @@ CM_API cm_status cm_grid_copy_metrics(const cm_grid* grid, double* Ja_host, doub
 /* Create a model on a grid.  Yref_host (host, [nvar][n_nodes], float64) is
  * the hydrostatic background; the library pushes it through its own
  * thermodynamics to obtain the reference pressure p_r and density rho_r
- * factored out of the momentum flux and the buoyancy (Sect. 2.3).  NULL
+ * factored out of the momentum flux and the buoyancy (Sect. 2.4).  NULL
  * means p_r = rho_r = 0.  In CM_FP32_BULK the background is first rounded
  * to float, so a state equal to it is exactly at rest.
  * Errors: CM_ERR_ARG, CM_ERR_UNSUPPORTED (nvar not 5/6), CM_ERR_HIP/ALLOC. */
@@ -156,8 +156,11 @@ CM_API cm_status cm_model_destroy(cm_model* model);
  * weight matrix row-major [out][in] followed by its bias.  norm: 48 floats:
  * input mean[12], std[12], then the standardised training range lo[12],
  * hi[12].  A node falls back to Smagorinsky when a standardised input leaves
- * the range widened by 10 % of its half-width on each side, or when the
- * network output is not finite. */
+ * the range widened by 10 % of its half-width on each side plus a margin of
+ * 2^-20 (1 + |mean/std|) (the float rounding of the normalisation: an input
+ * that was constant in training, such as the filter width on a uniform mesh,
+ * passes at its training value), or when the network output is not finite.
+ * Errors: CM_ERR_ARG (std <= 0 or hi < lo), CM_ERR_STATE (closure not MLP). */
 CM_API cm_status cm_model_set_mlp(cm_model* model, const float* params_host, const float* norm_host);
 /* number of node evaluations that fell back to Smagorinsky since the
  * previous call (each RHS evaluates every node once); resets the count.

@@ -102,6 +102,10 @@ def lib():
         L.cmref_lsrk_steps.argtypes = [C.c_void_p, _P, _P, C.c_double, C.c_double, C.c_int]
         L.cmref_integrals.argtypes = [C.c_void_p, _P, _P]
         L.cmref_num_threads.restype = C.c_int
+        L.cmref_set_mutation.argtypes = [C.c_int]
+        L.cmref_mlp_closure.argtypes = [_P, C.c_void_p, _P, _P, C.c_int, _P, C.c_double, C.c_double,
+                                        C.c_double, C.POINTER(C.c_double), C.POINTER(C.c_double)]
+        L.cmref_mlp_closure.restype = C.c_int
         _lib = L
     return _lib
 
@@ -342,8 +346,27 @@ def adam_step(params, grad, m, v, step, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
     lib().cmref_adam_step(params, np.ascontiguousarray(grad, dtype=np.float64), m, v, int(step), lr, b1, b2, eps)
 
 
+def mlp_closure(params, mean, std, lo, hi, gu, N2, Delta, nu_sl, use_fallback=True):
+    """The learned closure at one node: (fell_back, nu_t, Pr_t) for the
+    velocity gradient gu[3][3], N^2, filter width and Smagorinsky viscosity
+    (FP64 network)."""
+    p = np.ascontiguousarray(np.concatenate([np.asarray(params, np.float64), np.asarray(mean, np.float64),
+                                             np.asarray(std, np.float64)]))
+    nu, pr = C.c_double(), C.c_double()
+    fb = lib().cmref_mlp_closure(p, None, np.ascontiguousarray(lo, dtype=np.float64),
+                                 np.ascontiguousarray(hi, dtype=np.float64), int(use_fallback),
+                                 np.ascontiguousarray(gu, dtype=np.float64).ravel(), float(N2), float(Delta),
+                                 float(nu_sl), C.byref(nu), C.byref(pr))
+    return bool(fb), nu.value, pr.value
+
+
 def bf16(x: float) -> float:
     return lib().cmref_bf16(float(x))
+
+
+def set_mutation(code: int) -> None:
+    """Plant a known mistake in the operator (tests of the pins only; 0 = none)."""
+    lib().cmref_set_mutation(int(code))
 
 
 def num_threads() -> int:

@@ -96,7 +96,7 @@ int cmref_gll(int N, double* xi, double* w, double* D)
 }
 
 /* ======================================================================== */
-/* Grid: brick of hexahedra, optional terrain-following warp (Sect. 4.3/4.4) */
+/* Grid: brick of hexahedra, optional terrain-following warp (Sect. 5.3/5.4) */
 /* ======================================================================== */
 typedef struct {
     int N, Q, Np;
@@ -531,6 +531,14 @@ void cmref_smagorinsky_point(const double* gu9, double N2, double Cs, double Del
     *nu = cmref_smagorinsky(gu, N2, Cs, Delta, Prt, richardson);
 }
 
+/* Planted mistakes, for the tests that show that a pin fails when the
+ * operator is wrong (0: none).  1: the diffusive flux doubled; 2: the sign
+ * of tau flipped; 3: one-sided F2* (own side only); 4: the energy diffusion
+ * -rho D_t grad h_tot dropped; 5: the d_qt (x) rho u momentum term dropped;
+ * 6: the BR1 lift doubled. */
+static int g_mutation = 0;
+void cmref_set_mutation(int code) { g_mutation = code; }
+
 /* gradient-variable slots */
 enum { GU = 0, GV = 1, GW = 2, GH = 3 };
 
@@ -596,6 +604,7 @@ static void br1_gradients(const model_t* M, work_t* W, gslots_t s)
                         double nv[3] = {side * Ja0 / Js, side * Ja1 / Js, side * Ja2 / Js};
                         double lift = Js / (J * G->w[N]);
                         double gstar = 0.5 * (gm + gp);
+                        if (g_mutation == 6) lift *= 2.0;
                         for (int c = 0; c < 3; ++c) gr[c] += lift * (gstar - gm) * nv[c];
                     }
                 }
@@ -637,17 +646,22 @@ static void diffusive_flux(model_t* M, work_t* W, gslots_t s)
         double S[3][3], rt[3][3];
         for (int i = 0; i < 3; ++i) for (int j = 0; j < 3; ++j) S[i][j] = 0.5 * (gu[i][j] + gu[j][i]);
         for (int i = 0; i < 3; ++i) for (int j = 0; j < 3; ++j) rt[i][j] = -2.0 * P->rho * nu * S[i][j];
+        if (g_mutation == 2)
+            for (int i = 0; i < 3; ++i) for (int j = 0; j < 3; ++j) rt[i][j] = -rt[i][j];
         double rd[3] = {0, 0, 0};
         if (m->nvar > 5)
             for (int j = 0; j < 3; ++j) rd[j] = -P->rho * Dt * W->grad[(s.iq * 3 + j) * nn + n];
         for (int j = 0; j < 3; ++j) {
             W->F2[(0 * 3 + j) * nn + n] = (m->nvar > 5) ? rd[j] : 0.0;
             for (int i = 0; i < 3; ++i)
-                W->F2[((1 + i) * 3 + j) * nn + n] = rt[i][j] + ((m->nvar > 5) ? rd[j] * P->u[i] : 0.0);
+                W->F2[((1 + i) * 3 + j) * nn + n] =
+                    rt[i][j] + ((m->nvar > 5 && g_mutation != 5) ? rd[j] * P->u[i] : 0.0);
             double ue = P->u[0] * rt[0][j] + P->u[1] * rt[1][j] + P->u[2] * rt[2][j];
-            W->F2[(4 * 3 + j) * nn + n] = ue - P->rho * Dt * W->grad[(GH * 3 + j) * nn + n];
+            W->F2[(4 * 3 + j) * nn + n] = ue - (g_mutation == 4 ? 0.0 : P->rho * Dt * W->grad[(GH * 3 + j) * nn + n]);
             if (m->nvar > 5) W->F2[(5 * 3 + j) * nn + n] = rd[j];
         }
+        if (g_mutation == 1)
+            for (int q = 0; q < 3 * m->nvar; ++q) W->F2[(long)q * nn + n] *= 2.0;
     }
     M->mlp_fallbacks = fallbacks;
 }
@@ -764,7 +778,7 @@ static void rhs_eval(model_t* M, const double* Y, double* R, work_t* W)
                                 a += W->F2[(v * 3 + c) * nn + n] * nv[c];
                                 b += W->F2[(v * 3 + c) * nn + np] * nv[c];
                             }
-                            f2star[v] = 0.5 * (a + b);
+                            f2star[v] = g_mutation == 3 ? a : 0.5 * (a + b);
                         }
                     } else {
                         /* reflecting ghost: u+ = u- - 2 (n.u-) n, scalars mirrored */

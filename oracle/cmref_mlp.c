@@ -201,7 +201,8 @@ void cmref_adam_step(double* p, const double* g, double* m, double* v, int step,
  * mean[12], std[12]]; Wb = the network with bf16-rounded weights, or NULL
  * for the FP64 network; lo/hi = standardised training range.  Returns 1 when
  * the node falls back to Smagorinsky (an input outside the range widened by
- * 10 % of its half-width on each side, or a non-finite output). */
+ * 10 % of its half-width on each side plus 2^-20 (1 + |mean/std|), or a
+ * non-finite output). */
 int cmref_mlp_closure(const double* params, const double* Wb, const double* lo, const double* hi,
                       int use_fallback, const double gu[3][3], double N2, double Delta, double nu_sl,
                       double* nu, double* Prt)
@@ -219,7 +220,11 @@ int cmref_mlp_closure(const double* params, const double* Wb, const double* lo, 
     for (int i = 0; i < NI; ++i) {
         x[i] = (raw[i] - mean[i]) / sd[i];
         double c = 0.5 * (lo[i] + hi[i]), r = 0.5 * (hi[i] - lo[i]);
-        if (fabs(x[i] - c) > 1.1 * r) out_of_range = 1;
+        /* the margin 2^-20 (1 + |mean/std|) absorbs the float rounding of the
+         * normalisation, so an input that was constant in training (zero
+         * half-width) passes at its training value */
+        double tol = ldexp(1.0 + fabs(mean[i] / sd[i]), -20);
+        if (fabs(x[i] - c) > 1.1 * r + tol) out_of_range = 1;
     }
     double o[NO];
     forward_one(Wb ? Wb : params, params, x, Wb != NULL, o);

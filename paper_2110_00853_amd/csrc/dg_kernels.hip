@@ -848,9 +848,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(MLP || MO
 #pragma unroll
             for (int q = 0; q < 12; ++q) {
                 const double x = (raw[q] - P.mlp_norm[q]) / P.mlp_norm[12 + q];
-                const double c = 0.5 * (P.mlp_norm[24 + q] + P.mlp_norm[36 + q]);
-                const double hw = 0.5 * (P.mlp_norm[36 + q] - P.mlp_norm[24 + q]);
-                if (fabs(x - c) > 1.1 * hw) out_of_range = true;
+                if (fabs(x - P.mlp_norm[24 + q]) > P.mlp_norm[36 + q]) out_of_range = true;
                 sX[t][q] = f2bf((float)x);
             }
 #pragma unroll

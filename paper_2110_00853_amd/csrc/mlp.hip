@@ -439,8 +439,18 @@ cm_status cm_model_set_mlp(cm_model* m, const float* params, const float* norm)
     }
     bias[3 * MLP_NH + 0] = params[OFF_B4 + 0];
     bias[3 * MLP_NH + 1] = params[OFF_B4 + 1];
+    // device copy: mean[12], std[12], centre of the standardised training
+    // range[12], allowed distance from the centre[12] = 1.1 x half-width plus
+    // 2^-20 (1 + |mean/std|) (the float rounding of the normalisation, so an
+    // input that was constant in training passes at its training value)
     std::vector<double> nrm(48);
-    for (int q = 0; q < 48; ++q) nrm[q] = norm[q];
+    for (int q = 0; q < 12; ++q) {
+        const double mean = norm[q], sd = norm[12 + q], lo = norm[24 + q], hi = norm[36 + q];
+        nrm[q] = mean;
+        nrm[12 + q] = sd;
+        nrm[24 + q] = 0.5 * (lo + hi);
+        nrm[36 + q] = 1.1 * (0.5 * (hi - lo)) + std::ldexp(1.0 + std::fabs(mean / sd), -20);
+    }
     if (!m->d_mlp_w) {
         const size_t bytes = frag.size() * sizeof(uint16_t) + bias.size() * sizeof(float);
         CM_TRY_HIP(hipMalloc(&m->d_mlp_w, bytes), "cm_model_set_mlp");

@@ -10,7 +10,7 @@ State layout: float64 array [nvar, n_nodes], variables (rho, rho u, rho v,
 rho w, rho e_tot[, rho q_t]); node order element-major, element = ex + ne0*(ey
 + ne1*ez), node = i + Q*(j + Q*k) with i along x.
 
-Constants are Table 1 of the paper (Sect. 2.4) plus the stated readings for
+Constants are Table 1 of the paper (Sect. 2.5) plus the stated readings for
 g, p0, c_pd = c_vd + R_d and the triple-point pressure of water.
 """
 from __future__ import annotations
@@ -61,7 +61,7 @@ def node_coords(grid: dict) -> np.ndarray:
 
     Terrain following (Gal-Chen & Somerville linear decay): z = zh + z_sfc(x)
     (z_top - zh)/(z_top - z_lo), with the Agnesi ridge z_sfc = h a^2/((x -
-    x_c)^2 + a^2) (Sect. 4.4, eq. agnesi).
+    x_c)^2 + a^2) (Sect. 5.4, eq. agnesi).
     """
     N = grid.get("N", 4)
     Q = N + 1

@@ -1,4 +1,4 @@
-"""Pins of the oracle's mesh and metric terms (Sect. 3.1 mapping; Sect. 4.3
+"""Pins of the oracle's mesh and metric terms (Sect. 3.1 mapping; Sect. 5.3
 terrain-following warp; eq. agnesi)."""
 import numpy as np
 import pytest

@@ -106,3 +106,71 @@ def test_adam_first_step_moves_by_lr(oracle_lib):
     p0 = p.copy()
     oracle_lib.adam_step(p, g, m, v, 1, lr=1e-3)
     assert np.allclose(p0 - p, 1e-3 * g / (np.abs(g) + 1e-8), rtol=1e-12)
+
+
+def _closure_args():
+    """Zero network weights with output biases (b0, b1): the raw outputs are
+    the biases whatever the inputs.  Unit normalisation, training range
+    [-1, 1] on every input."""
+    O = offsets()
+    p = np.zeros(9282)
+    return p, O["b4"][0], np.zeros(NI), np.ones(NI), -np.ones(NI), np.ones(NI)
+
+
+def test_closure_output_mapping_closed_form(oracle_lib):
+    """nu_t = Delta^2 |S| softplus(o_1), Pr_t = 0.1 + softplus(o_2), with
+    |S|^2 = 2 S_ij S_ij; softplus(0) = ln 2."""
+    p, b4, mean, std, lo, hi = _closure_args()
+    gu = np.array([[0.0, 0.0, 0.02], [0.0, 0.0, 0.0], [0.0, 0.0, 0.0]]) * 0.5   # |S| = 0.01
+    Delta = 50.0
+    mean[10] = Delta     # the filter-width input at the centre of its range
+    for o1, o2 in ((0.0, 0.0), (1.5, -2.0), (-3.0, 4.0), (40.0, 0.3)):
+        p[b4], p[b4 + 1] = o1, o2
+        fb, nu, pr = oracle_lib.mlp_closure(p, mean, std, lo, hi, gu, 0.0, Delta, 0.0)
+        assert not fb
+        sp1 = np.log1p(np.exp(o1)) if o1 < 30 else o1
+        assert nu == pytest.approx(Delta ** 2 * 0.01 * sp1, rel=1e-14)
+        assert pr == pytest.approx(0.1 + np.log1p(np.exp(o2)), rel=1e-14)
+    p[b4], p[b4 + 1] = 0.0, 0.0
+    _, nu, pr = oracle_lib.mlp_closure(p, mean, std, lo, hi, gu, 0.0, Delta, 0.0)
+    assert nu == pytest.approx(Delta ** 2 * 0.01 * np.log(2.0), rel=1e-15)
+    assert pr == pytest.approx(0.1 + np.log(2.0), rel=1e-15)
+    # no strain, no viscosity: the rest state stays at rest
+    _, nu0, _ = oracle_lib.mlp_closure(p, mean, std, lo, hi, np.zeros((3, 3)), 0.0, Delta, 0.0)
+    assert nu0 == 0.0
+
+
+def test_closure_fallback_rule(oracle_lib):
+    """Fallback when a standardised input leaves [lo, hi] widened by 10 % of
+    its half-width (plus the 2^-20 (1 + |mean/std|) rounding margin), or the
+    output is not finite; never with the fallback switched off."""
+    p, b4, mean, std, lo, hi = _closure_args()
+    Delta = 1.0          # input 10 (the filter width): x = 1 with mean 0, std 1
+    gu = np.zeros((3, 3))
+    for val, expect in ((1.05, False), (-1.09, False), (1.12, True), (-1.2, True)):
+        g = gu.copy()
+        g[0, 1] = val    # input 1 (du/dy)
+        fb, _, _ = oracle_lib.mlp_closure(p, mean, std, lo, hi, g, 0.0, Delta, 0.0)
+        assert fb == expect, val
+        fb, _, _ = oracle_lib.mlp_closure(p, mean, std, lo, hi, g, 0.0, Delta, 0.0, use_fallback=False)
+        assert not fb
+    # N^2 (input 9) and the TKE estimate (input 11) are checked too
+    assert oracle_lib.mlp_closure(p, mean, std, lo, hi, gu, 1.2, Delta, 0.0)[0]
+    assert oracle_lib.mlp_closure(p, mean, std, lo, hi, gu, 0.0, Delta, 0.2)[0]   # (0.2/0.1)^2 = 4
+    # a non-finite output falls back
+    p[b4] = np.nan
+    assert oracle_lib.mlp_closure(p, mean, std, lo, hi, gu, 0.0, Delta, 0.0)[0]
+
+
+def test_closure_constant_training_input_passes_at_its_value(oracle_lib):
+    """An input that was constant in training (the filter width on a
+    uniform mesh: half-width 0, std set to 1) passes when it equals the
+    float-rounded training mean, also for a width that float cannot hold
+    exactly, and falls back when it moves off that value."""
+    p, b4, mean, std, lo, hi = _closure_args()
+    Delta = 1000.0 / 12.0                      # 83.333..., not a float
+    mean[10] = float(np.float32(Delta))
+    lo[10] = hi[10] = 0.0
+    gu = np.zeros((3, 3))
+    assert not oracle_lib.mlp_closure(p, mean, std, lo, hi, gu, 0.0, Delta, 0.0)[0]
+    assert oracle_lib.mlp_closure(p, mean, std, lo, hi, gu, 0.0, Delta * 1.001, 0.0)[0]

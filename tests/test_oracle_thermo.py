@@ -1,4 +1,4 @@
-"""Pins of the oracle's thermodynamics (Sect. 2.4-2.6: moist internal energy,
+"""Pins of the oracle's thermodynamics (Sect. 2.5-2.7: moist internal energy,
 equation of state, saturation adjustment with the closed-form saturation
 vapour pressure)."""
 import os

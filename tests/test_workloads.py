@@ -1,6 +1,6 @@
 """Checks of the seeded input generators against closed forms (hydrostatic
-balance of the background profiles, Sect. 4.1 eq. pressureDistrib and
-Sect. 4.4 eq. pressure_hs_brunt / density_hs_brunt)."""
+balance of the background profiles, Sect. 5.1 eq. pressureDistrib and
+Sect. 5.4 eq. pressure_hs_brunt / density_hs_brunt)."""
 import numpy as np
 import pytest
 
