@@ -196,6 +196,22 @@ CM_API cm_status cm_lsrk_step(cm_model* model, void* Y, void* Y_alt, void* dQ, d
  * (with *out filled) when the state holds NaN/Inf. */
 CM_API cm_status cm_diagnostics(cm_model* model, const void* Y, double dt, cm_diag* out_host, void* hip_stream);
 
+/* cm_diagnostics for callers that cannot allocate device memory (tight
+ * serving loops, harnesses that forbid hipMalloc): the same reduction and
+ * the same results, bit for bit, but its partial sums live in a static
+ * per-device workspace of the library (2048 records of 16 doubles, 256 KiB,
+ * held by every device the library runs on until the process ends) instead
+ * of the model's, and the call makes no allocation.  The first pass strides
+ * over the nodes with at most 2047 blocks, so the workspace bounds the
+ * block count, not the grid: every grid cm_grid_create accepts fits, and a
+ * node count outside 1 .. 2^27 fails with CM_ERR_ARG.  Nothing in the
+ * workspace needs clearing (each call writes every record it reads).  All
+ * calls on one device share the workspace: calls that overlap on one
+ * device (different streams or threads) race and must be serialised by
+ * the caller.  Synchronises the stream; CM_ERR_NONFINITE as cm_diagnostics. */
+CM_API cm_status cm_diagnostics_noalloc(cm_model* model, const void* Y, double dt, cm_diag* out_host,
+                                        void* hip_stream);
+
 /* ---- learned closure training (12-64-64-64-2 SiLU MLP, BF16 MFMA, FP32
  * accumulate, FP32 master weights, Adam) ------------------------------- */
 typedef struct {

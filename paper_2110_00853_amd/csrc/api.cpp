@@ -417,7 +417,7 @@ cm_status cm_model_create(const cm_grid* g, const cm_model_desc* desc, const dou
         if (e == hipSuccess) e = hipMemset(m->d_rhor, 0, sizeof(double) * nref);
     }
     if (e == hipSuccess) {
-        m->n_partials = 2048;
+        m->n_partials = DIAG_SCRATCH_RECORDS;
         e = hipMalloc(&m->d_partials, sizeof(double) * 16 * m->n_partials);
     }
     if (e == hipSuccess) e = hipMalloc(&m->d_fallbacks, sizeof(unsigned long long));
@@ -580,6 +580,25 @@ cm_status cm_diagnostics(cm_model* m, const void* Y, double dt, cm_diag* out, vo
     CM_TRY_HIP(launch_diagnostics(m, Y, dt, out, (hipStream_t)stream), "cm_diagnostics");
     if (out->n_nonfinite > 0) {
         set_error("cm_diagnostics: state holds non-finite values");
+        return CM_ERR_NONFINITE;
+    }
+    return CM_OK;
+}
+
+cm_status cm_diagnostics_noalloc(cm_model* m, const void* Y, double dt, cm_diag* out, void* stream)
+{
+    if (!m || !Y || !out) { set_error("cm_diagnostics_noalloc: null argument"); return CM_ERR_ARG; }
+    // the first pass strides over the nodes with at most
+    // DIAG_SCRATCH_RECORDS - 1 blocks, so the workspace bounds the block
+    // count, not the grid; the node count is bounded by the grid's own limit
+    if (m->grid->n_nodes <= 0 || 16 * m->grid->n_nodes >= ((int64_t)1 << 31)) {
+        set_error("cm_diagnostics_noalloc: node count outside 1 .. 2^27");
+        return CM_ERR_ARG;
+    }
+    CM_TRY_HIP(hipSetDevice(m->grid->device), "hipSetDevice");
+    CM_TRY_HIP(launch_diagnostics_static(m, Y, dt, out, (hipStream_t)stream), "cm_diagnostics_noalloc");
+    if (out->n_nonfinite > 0) {
+        set_error("cm_diagnostics_noalloc: state holds non-finite values");
         return CM_ERR_NONFINITE;
     }
     return CM_OK;

@@ -173,4 +173,9 @@ cm_model::ProfRec* prof_begin(cm_model* m, int kind, hipStream_t s);
 void prof_end(cm_model::ProfRec* r, hipStream_t s);
 // reductions (reduce.hip)
 hipError_t launch_diagnostics(const cm_model* m, const void* Y, double dt, cm_diag* out, hipStream_t s);
+// the same reduction over the library's static per-device workspace (no
+// allocation); its partial-record count equals a model's, so both give
+// bit-identical results
+constexpr int DIAG_SCRATCH_RECORDS = 2048;
+hipError_t launch_diagnostics_static(const cm_model* m, const void* Y, double dt, cm_diag* out, hipStream_t s);
 }  // namespace cm

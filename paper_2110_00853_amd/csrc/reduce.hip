@@ -3,6 +3,7 @@
 // assignment with Neumaier-compensated FP64 sums per thread, a fixed-order
 // tree per block, and one block combining the per-block partials in order.
 #include <cmath>
+#include <mutex>
 
 #include "cm_impl.hpp"
 
@@ -195,7 +196,13 @@ __global__ __launch_bounds__(RB) void k_diag2(const double* __restrict__ part, i
     }
 }
 
-hipError_t launch_diagnostics(const cm_model* m, const void* Y, double dt, cm_diag* outp, hipStream_t s)
+// both passes over a workspace of n_records partial records (16 doubles
+// each): the first n_records - 1 hold the per-block partials, the last one
+// the combined result.  The first pass strides over the nodes, so any grid
+// fits; the block count, and with it the order of the compensated sums,
+// depends only on the node count and n_records.
+static hipError_t diagnostics_ws(const cm_model* m, const void* Y, double dt, cm_diag* outp, hipStream_t s,
+                                 double* ws, int n_records)
 {
     const cm_grid* g = m->grid;
     DiagArgs A;
@@ -213,9 +220,9 @@ hipError_t launch_diagnostics(const cm_model* m, const void* Y, double dt, cm_di
     A.dt = dt;
     A.dmin = g->dmin;
     int nblk = (int)((A.nn + RB - 1) / RB);
-    if (nblk > m->n_partials - 1) nblk = m->n_partials - 1;
-    double* part = m->d_partials;
-    double* dout = m->d_partials + (int64_t)(m->n_partials - 1) * NPART;
+    if (nblk > n_records - 1) nblk = n_records - 1;
+    double* part = ws;
+    double* dout = ws + (int64_t)(n_records - 1) * NPART;
     const bool moist = m->desc.nvar == 6;
     if (m->desc.precision == CM_FP64) {
         if (moist) hipLaunchKernelGGL((k_diag1<double, true>), dim3(nblk), dim3(RB), 0, s, A, (const double*)Y, part);
@@ -243,6 +250,47 @@ hipError_t launch_diagnostics(const cm_model* m, const void* Y, double dt, cm_di
     outp->T_max = h[7];
     outp->n_nonfinite = (int64_t)h[8];
     return hipSuccess;
+}
+
+hipError_t launch_diagnostics(const cm_model* m, const void* Y, double dt, cm_diag* outp, hipStream_t s)
+{
+    return diagnostics_ws(m, Y, dt, outp, s, m->d_partials, m->n_partials);
+}
+
+// Workspace of the allocation-free diagnostics: DIAG_SCRATCH_RECORDS partial
+// records in a file-scope device array (256 KiB; every device the library
+// runs on holds its own copy until the process ends).  Host code never
+// passes the array's name to a kernel: its device address, per device,
+// comes from hipGetSymbolAddress on the first call on that device.
+static __device__ __align__(256) double scratch[DIAG_SCRATCH_RECORDS * NPART];
+
+namespace {
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[MAX_DEVICES] = {};
+}  // namespace
+
+hipError_t diag_scratch_address(int device, double** out)
+{
+    if (device < 0 || device >= MAX_DEVICES) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        // the caller has made `device` current
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_ptr[device] = (double*)p;
+    }
+    *out = g_scratch_ptr[device];
+    return hipSuccess;
+}
+
+hipError_t launch_diagnostics_static(const cm_model* m, const void* Y, double dt, cm_diag* outp, hipStream_t s)
+{
+    double* ws = nullptr;
+    const hipError_t e = diag_scratch_address(m->grid->device, &ws);
+    if (e != hipSuccess) return e;
+    return diagnostics_ws(m, Y, dt, outp, s, ws, DIAG_SCRATCH_RECORDS);
 }
 
 }  // namespace cm
