@@ -18,21 +18,30 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_FMA_PATH = os.path.join(_HERE, "liboracle_fma.so")
 _SOURCES = ["cmref.c", "cmref_mlp.c"]
 _lib = None
+_lib_fma = None
 
 
-def build(force: bool = True) -> str:
-    """Compile the oracle shared library (gcc, OpenMP, no FMA contraction)."""
-    if not force and os.path.exists(_LIB_PATH):
-        return _LIB_PATH
+def build(force: bool = True, contract: bool = False) -> str:
+    """Compile the oracle shared library (gcc, OpenMP, no FMA contraction).
+    contract=True builds the same sources with fused multiply-adds allowed
+    (``-ffp-contract=fast -mfma``) into ``liboracle_fma.so``: a second
+    correct FP64 evaluation of the same operator that differs only in
+    rounding, whose distance from the plain build measures how closely two
+    such implementations can agree."""
+    path = _FMA_PATH if contract else _LIB_PATH
+    if not force and os.path.exists(path):
+        return path
     srcs = [os.path.join(_HERE, s) for s in _SOURCES]
-    tmp = _LIB_PATH + ".tmp%d" % os.getpid()
-    cmd = ["gcc", "-O2", "-std=c99", "-D_GNU_SOURCE", "-fPIC", "-shared", "-fopenmp",
-           "-ffp-contract=off", "-fno-fast-math", "-o", tmp] + srcs + ["-lm"]
+    tmp = path + ".tmp%d" % os.getpid()
+    fp = ["-ffp-contract=fast", "-mfma"] if contract else ["-ffp-contract=off"]
+    cmd = ["gcc", "-O2", "-std=c99", "-D_GNU_SOURCE", "-fPIC", "-shared", "-fopenmp"] + fp + [
+        "-fno-fast-math", "-o", tmp] + srcs + ["-lm"]
     subprocess.run(cmd, check=True)
-    os.replace(tmp, _LIB_PATH)
-    return _LIB_PATH
+    os.replace(tmp, path)
+    return path
 
 
 class GridDesc(C.Structure):
@@ -55,59 +64,71 @@ class ModelDesc(C.Structure):
 _P = np.ctypeslib.ndpointer(dtype=np.float64, flags="C_CONTIGUOUS")
 
 
-def lib():
-    global _lib
+def lib(contract: bool = False):
+    """The oracle library; contract=True the FMA-contracted build of the
+    same sources (see build)."""
+    global _lib, _lib_fma
+    if contract:
+        if _lib_fma is None:
+            if not os.path.exists(_FMA_PATH):
+                build(contract=True)
+            _lib_fma = _declare(C.CDLL(_FMA_PATH))
+        return _lib_fma
     if _lib is None:
         if not os.path.exists(_LIB_PATH):
             build()
-        L = C.CDLL(_LIB_PATH)
-        L.cmref_gll.argtypes = [C.c_int, _P, _P, _P]
-        L.cmref_grid_create.argtypes = [C.POINTER(GridDesc), C.c_int]
-        L.cmref_grid_create.restype = C.c_void_p
-        L.cmref_grid_destroy.argtypes = [C.c_void_p]
-        L.cmref_grid_nnodes.argtypes = [C.c_void_p]
-        L.cmref_grid_nnodes.restype = C.c_long
-        L.cmref_grid_coords.argtypes = [C.c_void_p, _P]
-        L.cmref_grid_metrics.argtypes = [C.c_void_p, _P, _P]
-        L.cmref_grid_wJ.argtypes = [C.c_void_p, _P]
-        L.cmref_grid_metric_identity.argtypes = [C.c_void_p, _P]
-        L.cmref_pvsat.argtypes = [C.c_double]
-        L.cmref_pvsat.restype = C.c_double
-        L.cmref_saturation_adjust.argtypes = [C.c_double, C.c_double, C.c_double,
-                                              C.POINTER(C.c_double), C.POINTER(C.c_double)]
-        L.cmref_thermo_nodes.argtypes = [C.c_int, C.c_long, _P, _P, C.c_double, _P, _P, _P, _P]
-        L.cmref_rusanov_point.argtypes = [C.c_int, _P, _P, C.c_double, C.c_double, C.c_double,
-                                          C.c_double, C.c_double, _P, _P]
-        L.cmref_smagorinsky_point.argtypes = [_P, C.c_double, C.c_double, C.c_double, C.c_double,
-                                              C.c_int, C.POINTER(C.c_double)]
-        L.cmref_model_create.argtypes = [C.c_void_p, C.POINTER(ModelDesc), C.c_void_p]
-        L.cmref_model_create.restype = C.c_void_p
-        L.cmref_model_destroy.argtypes = [C.c_void_p]
-        L.cmref_model_reference.argtypes = [C.c_void_p, _P, _P]
-        L.cmref_model_set_mlp.argtypes = [C.c_void_p, _P, C.c_int, _P, _P, C.c_int, C.c_int]
-        L.cmref_mlp_nparams.restype = C.c_int
-        L.cmref_mlp_forward.argtypes = [_P, _P, C.c_int, _P]
-        L.cmref_mlp_forward_bf16.argtypes = [_P, _P, C.c_int, _P]
-        L.cmref_mlp_grad.argtypes = [_P, _P, _P, C.c_int, _P]
-        L.cmref_mlp_grad.restype = C.c_double
-        L.cmref_adam_step.argtypes = [_P, _P, _P, _P, C.c_int, C.c_double, C.c_double, C.c_double, C.c_double]
-        L.cmref_bf16.argtypes = [C.c_double]
-        L.cmref_bf16.restype = C.c_double
-        L.cmref_model_mlp_fallbacks.argtypes = [C.c_void_p]
-        L.cmref_model_mlp_fallbacks.restype = C.c_long
-        L.cmref_rhs.argtypes = [C.c_void_p, _P, _P, C.c_double]
-        L.cmref_gradients.argtypes = [C.c_void_p, _P, _P, _P]
-        L.cmref_gradients.restype = C.c_int
-        L.cmref_lsrk54_coeffs.argtypes = [_P, _P, _P]
-        L.cmref_lsrk_steps.argtypes = [C.c_void_p, _P, _P, C.c_double, C.c_double, C.c_int]
-        L.cmref_integrals.argtypes = [C.c_void_p, _P, _P]
-        L.cmref_num_threads.restype = C.c_int
-        L.cmref_set_mutation.argtypes = [C.c_int]
-        L.cmref_mlp_closure.argtypes = [_P, C.c_void_p, _P, _P, C.c_int, _P, C.c_double, C.c_double,
-                                        C.c_double, C.POINTER(C.c_double), C.POINTER(C.c_double)]
-        L.cmref_mlp_closure.restype = C.c_int
-        _lib = L
+        _lib = _declare(C.CDLL(_LIB_PATH))
     return _lib
+
+
+def _declare(L):
+    """Argument and result types of the library's exports."""
+    L.cmref_gll.argtypes = [C.c_int, _P, _P, _P]
+    L.cmref_grid_create.argtypes = [C.POINTER(GridDesc), C.c_int]
+    L.cmref_grid_create.restype = C.c_void_p
+    L.cmref_grid_destroy.argtypes = [C.c_void_p]
+    L.cmref_grid_nnodes.argtypes = [C.c_void_p]
+    L.cmref_grid_nnodes.restype = C.c_long
+    L.cmref_grid_coords.argtypes = [C.c_void_p, _P]
+    L.cmref_grid_metrics.argtypes = [C.c_void_p, _P, _P]
+    L.cmref_grid_wJ.argtypes = [C.c_void_p, _P]
+    L.cmref_grid_metric_identity.argtypes = [C.c_void_p, _P]
+    L.cmref_pvsat.argtypes = [C.c_double]
+    L.cmref_pvsat.restype = C.c_double
+    L.cmref_saturation_adjust.argtypes = [C.c_double, C.c_double, C.c_double,
+                                          C.POINTER(C.c_double), C.POINTER(C.c_double)]
+    L.cmref_thermo_nodes.argtypes = [C.c_int, C.c_long, _P, _P, C.c_double, _P, _P, _P, _P]
+    L.cmref_rusanov_point.argtypes = [C.c_int, _P, _P, C.c_double, C.c_double, C.c_double,
+                                      C.c_double, C.c_double, _P, _P]
+    L.cmref_smagorinsky_point.argtypes = [_P, C.c_double, C.c_double, C.c_double, C.c_double,
+                                          C.c_int, C.POINTER(C.c_double)]
+    L.cmref_model_create.argtypes = [C.c_void_p, C.POINTER(ModelDesc), C.c_void_p]
+    L.cmref_model_create.restype = C.c_void_p
+    L.cmref_model_destroy.argtypes = [C.c_void_p]
+    L.cmref_model_reference.argtypes = [C.c_void_p, _P, _P]
+    L.cmref_model_set_mlp.argtypes = [C.c_void_p, _P, C.c_int, _P, _P, C.c_int, C.c_int]
+    L.cmref_mlp_nparams.restype = C.c_int
+    L.cmref_mlp_forward.argtypes = [_P, _P, C.c_int, _P]
+    L.cmref_mlp_forward_bf16.argtypes = [_P, _P, C.c_int, _P]
+    L.cmref_mlp_grad.argtypes = [_P, _P, _P, C.c_int, _P]
+    L.cmref_mlp_grad.restype = C.c_double
+    L.cmref_adam_step.argtypes = [_P, _P, _P, _P, C.c_int, C.c_double, C.c_double, C.c_double, C.c_double]
+    L.cmref_bf16.argtypes = [C.c_double]
+    L.cmref_bf16.restype = C.c_double
+    L.cmref_model_mlp_fallbacks.argtypes = [C.c_void_p]
+    L.cmref_model_mlp_fallbacks.restype = C.c_long
+    L.cmref_rhs.argtypes = [C.c_void_p, _P, _P, C.c_double]
+    L.cmref_gradients.argtypes = [C.c_void_p, _P, _P, _P]
+    L.cmref_gradients.restype = C.c_int
+    L.cmref_lsrk54_coeffs.argtypes = [_P, _P, _P]
+    L.cmref_lsrk_steps.argtypes = [C.c_void_p, _P, _P, C.c_double, C.c_double, C.c_int]
+    L.cmref_integrals.argtypes = [C.c_void_p, _P, _P]
+    L.cmref_num_threads.restype = C.c_int
+    L.cmref_set_mutation.argtypes = [C.c_int]
+    L.cmref_mlp_closure.argtypes = [_P, C.c_void_p, _P, _P, C.c_int, _P, C.c_double, C.c_double,
+                                    C.c_double, C.POINTER(C.c_double), C.POINTER(C.c_double)]
+    L.cmref_mlp_closure.restype = C.c_int
+    return L
 
 
 def gll(N: int):
@@ -169,43 +190,45 @@ def _model_desc(m: dict) -> ModelDesc:
 
 
 class Grid:
-    def __init__(self, desc: dict, dense: bool = False):
+    def __init__(self, desc: dict, dense: bool = False, contract: bool = False):
+        self._L = lib(contract)
         self._d = _grid_desc(desc)
-        self.h = lib().cmref_grid_create(C.byref(self._d), int(dense))
+        self.h = self._L.cmref_grid_create(C.byref(self._d), int(dense))
         if not self.h:
             raise RuntimeError("oracle grid creation failed")
-        self.nnodes = lib().cmref_grid_nnodes(self.h)
+        self.nnodes = self._L.cmref_grid_nnodes(self.h)
 
     def __del__(self):
         if getattr(self, "h", None):
-            lib().cmref_grid_destroy(self.h)
+            self._L.cmref_grid_destroy(self.h)
             self.h = None
 
     def coords(self):
         out = np.zeros(3 * self.nnodes)
-        lib().cmref_grid_coords(self.h, out)
+        self._L.cmref_grid_coords(self.h, out)
         return out.reshape(3, self.nnodes)
 
     def metrics(self):
         Ja = np.zeros(9 * self.nnodes)
         J = np.zeros(self.nnodes)
-        lib().cmref_grid_metrics(self.h, Ja, J)
+        self._L.cmref_grid_metrics(self.h, Ja, J)
         return Ja.reshape(3, 3, self.nnodes), J
 
     def wJ(self):
         out = np.zeros(self.nnodes)
-        lib().cmref_grid_wJ(self.h, out)
+        self._L.cmref_grid_wJ(self.h, out)
         return out
 
     def metric_identity(self):
         out = np.zeros(3 * self.nnodes)
-        lib().cmref_grid_metric_identity(self.h, out)
+        self._L.cmref_grid_metric_identity(self.h, out)
         return out.reshape(3, self.nnodes)
 
 
 class Model:
     def __init__(self, grid: Grid, desc: dict, Yref: np.ndarray | None = None):
         self.grid = grid
+        self._L = grid._L  # the grid's build of the oracle library
         self._d = _model_desc(desc)
         self.nvar = self._d.nvar
         yref = None
@@ -214,11 +237,11 @@ class Model:
             assert yref.shape == (self.nvar, grid.nnodes)
         self._yref = yref
         ptr = yref.ctypes.data_as(C.c_void_p) if yref is not None else None
-        self.h = lib().cmref_model_create(grid.h, C.byref(self._d), ptr)
+        self.h = self._L.cmref_model_create(grid.h, C.byref(self._d), ptr)
 
     def __del__(self):
         if getattr(self, "h", None):
-            lib().cmref_model_destroy(self.h)
+            self._L.cmref_model_destroy(self.h)
             self.h = None
 
     def _chk(self, Y):
@@ -229,7 +252,7 @@ class Model:
     def rhs(self, Y, t: float = 0.0):
         Y = self._chk(Y)
         R = np.zeros_like(Y)
-        lib().cmref_rhs(self.h, Y, R, float(t))
+        self._L.cmref_rhs(self.h, Y, R, float(t))
         return R
 
     def gradients(self, Y):
@@ -237,28 +260,28 @@ class Model:
         nn = self.grid.nnodes
         grad = np.zeros(8 * 3 * nn)
         F2 = np.zeros(self.nvar * 3 * nn)
-        nG = lib().cmref_gradients(self.h, Y, grad, F2)
+        nG = self._L.cmref_gradients(self.h, Y, grad, F2)
         return grad[: nG * 3 * nn].reshape(nG, 3, nn), F2.reshape(self.nvar, 3, nn)
 
     def reference(self):
         nn = self.grid.nnodes
         pr = np.zeros(nn)
         rr = np.zeros(nn)
-        lib().cmref_model_reference(self.h, pr, rr)
+        self._L.cmref_model_reference(self.h, pr, rr)
         return pr, rr
 
     def steps(self, Y, dt: float, nsteps: int, t: float = 0.0, dQ=None):
         """Advance a copy of Y by nsteps LSRK54 steps; returns (Y, dQ)."""
         Y = self._chk(Y).copy()
         dQ = np.zeros_like(Y) if dQ is None else np.ascontiguousarray(dQ, dtype=np.float64).copy()
-        lib().cmref_lsrk_steps(self.h, Y, dQ, float(t), float(dt), int(nsteps))
+        self._L.cmref_lsrk_steps(self.h, Y, dQ, float(t), float(dt), int(nsteps))
         return Y, dQ
 
     def integrals(self, Y):
         """Domain integrals of each variable (w J weighted) and kinetic energy."""
         Y = self._chk(Y)
         out = np.zeros(self.nvar + 1)
-        lib().cmref_integrals(self.h, Y, out)
+        self._L.cmref_integrals(self.h, Y, out)
         return out
 
     def set_mlp(self, params: np.ndarray, mean: np.ndarray, std: np.ndarray, lo: np.ndarray,
@@ -267,12 +290,12 @@ class Model:
         standardised training range; bf16 emulates the GPU's operand rounding."""
         p = np.ascontiguousarray(np.concatenate([np.asarray(params, np.float64), np.asarray(mean, np.float64),
                                                  np.asarray(std, np.float64)]))
-        lib().cmref_model_set_mlp(self.h, p, p.size, np.ascontiguousarray(lo, dtype=np.float64),
+        self._L.cmref_model_set_mlp(self.h, p, p.size, np.ascontiguousarray(lo, dtype=np.float64),
                                   np.ascontiguousarray(hi, dtype=np.float64), int(use_fallback), int(bf16))
         self._mlp = p
 
     def mlp_fallbacks(self) -> int:
-        return lib().cmref_model_mlp_fallbacks(self.h)
+        return self._L.cmref_model_mlp_fallbacks(self.h)
 
 
 def pvsat(T: float) -> float:

@@ -1,4 +1,5 @@
-"""Build the gfx950 shared library libcm.so in-tree with hipcc."""
+"""Build the gfx950 shared library libcm.so in-tree with hipcc (and the small
+accuracy probe of its FP64 elementary functions, libcm_fp64check.so)."""
 from __future__ import annotations
 
 import os
@@ -9,6 +10,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libcm.so")
 SOURCES = ["api.cpp", "dg_kernels.hip", "reduce.hip", "mlp.hip"]
+CHECK_LIB = os.path.join(HERE, "libcm_fp64check.so")
+CHECK_SOURCES = ["fp64_check.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [
@@ -19,10 +22,9 @@ FLAGS = [
 ]
 
 
-def build(verbose: bool = False, extra: list[str] | None = None) -> str:
-    """Compile every HIP/C++ source of the library for gfx950 (always rebuilds)."""
-    srcs = [os.path.join(CSRC, s) for s in SOURCES]
-    tmp = LIB + ".tmp%d" % os.getpid()
+def _compile(sources: list[str], out: str, extra: list[str] | None, verbose: bool) -> str:
+    srcs = [os.path.join(CSRC, s) for s in sources]
+    tmp = out + ".tmp%d" % os.getpid()
     cmd = [HIPCC] + FLAGS + (extra or []) + ["-I", os.path.join(HERE, "..", "include"), "-o", tmp] + srcs
     if verbose:
         print(" ".join(cmd), flush=True)
@@ -30,10 +32,25 @@ def build(verbose: bool = False, extra: list[str] | None = None) -> str:
     if r.returncode != 0:
         sys.stderr.write(r.stdout + r.stderr)
         raise RuntimeError("hipcc failed")
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, out)
+    return out
+
+
+def build(verbose: bool = False, extra: list[str] | None = None, out: str | None = None) -> str:
+    """Compile every HIP/C++ source of the library for gfx950 (always
+    rebuilds), and the FP64 accuracy probe.  ``extra`` adds compiler flags
+    (e.g. ``-DCM_LIBM_THERMO``, library log/exp/sqrt/division in the
+    thermodynamics) and ``out`` names another output file for such a
+    variant; the probe is built only with the default library."""
+    lib = _compile(SOURCES, out or LIB, extra, verbose)
+    if out is None:
+        _compile(CHECK_SOURCES, CHECK_LIB, extra, verbose)
+    return lib
 
 
 if __name__ == "__main__":
-    build(verbose=True)
-    print(LIB)
+    args = sys.argv[1:]
+    if args and args[0] == "--libm":
+        print(build(verbose=True, extra=["-DCM_LIBM_THERMO"], out=os.path.join(HERE, "libcm_libm.so")))
+    else:
+        print(build(verbose=True))

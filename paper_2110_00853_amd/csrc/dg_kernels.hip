@@ -25,6 +25,7 @@
 #include <cmath>
 
 #include "cm_impl.hpp"
+#include "fp64_math.hpp"
 #include "mlp_common.hpp"
 
 namespace cm {
@@ -48,34 +49,6 @@ template <> __device__ __forceinline__ float dmat<float>(int r, int c) { return 
 // GLL end weight w_N = 1/10
 constexpr double WN = 0.1;
 
-// FP64 reciprocal and square root from the hardware estimates refined by
-// Newton-Raphson (reciprocal) and Goldschmidt (square root) steps: within an
-// ulp or two of the correctly rounded results, at a third of the
-// instructions of the IEEE sequences.  Arguments are positive and finite.
-__device__ __forceinline__ double frcp(double x)
-{
-    double r = __builtin_amdgcn_rcp(x);
-    double e = fma(-x, r, 1.0);
-    r = fma(r, e, r);
-    e = fma(-x, r, 1.0);
-    return fma(r, e, r);
-}
-__device__ __forceinline__ float frcp(float x) { return 1.0f / x; }
-
-__device__ __forceinline__ double fsqrt(double x)
-{
-    const double y = __builtin_amdgcn_rsq(x);
-    double g = x * y, h = 0.5 * y;
-    double r = fma(-g, h, 0.5);
-    g = fma(g, r, g);
-    h = fma(h, r, h);
-    r = fma(-g, h, 0.5);
-    g = fma(g, r, g);
-    h = fma(h, r, h);
-    const double d = fma(-g, g, x);
-    return fma(d, h, g);
-}
-__device__ __forceinline__ float fsqrt(float x) { return sqrtf(x); }
 
 // element of a per-variable (or per-word) array whose base comes with the
 // launch parameters: with the byte offset in 32 bits the access takes the
@@ -86,68 +59,6 @@ template <typename T> __device__ __forceinline__ __attribute__((address_space(1)
                                                                                          uint32_t byte_off)
 {
     return (__attribute__((address_space(1))) T*)((__attribute__((address_space(1))) char*)base + byte_off);
-}
-
-// FP64 natural logarithm and exponential for the thermodynamics (theta_v
-// and the saturation vapour pressure), each about an ulp from the correctly
-// rounded result (checked on the host against extended precision).  The
-// logarithm takes positive, finite, normal x = m 2^e with m in
-// [1/sqrt2, sqrt2) and sums ln m = 2 atanh(s), s = (m-1)/(m+1), |s| <= 0.172,
-// to the s^23 term; the exponential takes |y| < 700, reduces y = k ln2 + r,
-// |r| <= ln2/2, and sums the Taylor series to the r^13 term.  No special
-// cases: the arguments they see are far from the ends of the range.  The
-// series coefficients come from a constant table (wave-uniform loads, kept
-// in scalar registers) and enter as multiplicands of powers of the reduced
-// argument, summed smallest first: a Horner step would need each
-// coefficient as its vector addend, which the compiler copies into vector
-// registers before every use.
-__constant__ double c_lnexp[24] = {
-    // 1/(2n+1), n = 11 .. 1 (the last one is not read)
-    1.0 / 23, 1.0 / 21, 1.0 / 19, 1.0 / 17, 1.0 / 15, 1.0 / 13, 1.0 / 11, 1.0 / 9, 1.0 / 7, 1.0 / 5, 1.0 / 3,
-    // 1/n!, n = 13 .. 2
-    1.0 / 6227020800.0, 1.0 / 479001600.0, 1.0 / 39916800.0, 1.0 / 3628800.0, 1.0 / 362880.0, 1.0 / 40320.0,
-    1.0 / 5040.0, 1.0 / 720.0, 1.0 / 120.0, 1.0 / 24.0, 1.0 / 6.0, 0.5,
-    0.0};
-constexpr double LN2_HI = 6.93147180369123816490e-01, LN2_LO = 1.90821492927058770002e-10;
-
-__device__ __forceinline__ double ln_pos(double x)
-{
-    int e;
-    double m = frexp(x, &e);  // [0.5, 1)
-    if (m < 0.70710678118654752440) {
-        m *= 2.0;
-        e -= 1;
-    }
-    const double sv = (m - 1.0) * frcp(m + 1.0);
-    const double s2 = sv * sv;
-    // ln m = 2s (1 + s2 p), p = sum over n = 1 .. 11 of s2^(n-1) / (2n+1)
-    double pw[10];
-    pw[0] = s2;
-#pragma unroll
-    for (int n = 1; n < 10; ++n) pw[n] = pw[n - 1] * s2;
-    double p = c_lnexp[0] * pw[9];
-#pragma unroll
-    for (int n = 1; n < 10; ++n) p = fma(c_lnexp[n], pw[9 - n], p);
-    p = p + 1.0 / 3;
-    const double lnm = fma(2.0 * sv * s2, p, 2.0 * sv);
-    return fma((double)e, LN2_HI, fma((double)e, LN2_LO, lnm));
-}
-
-__device__ __forceinline__ double exp_fin(double y)
-{
-    const double k = rint(y * 1.44269504088896340736);
-    double r = fma(-k, LN2_HI, y);
-    r = fma(-k, LN2_LO, r);
-    // exp(r) = 1 + r + sum over n = 2 .. 13 of r^n / n!
-    double pr[13];
-    pr[0] = r;
-#pragma unroll
-    for (int n = 1; n < 13; ++n) pr[n] = pr[n - 1] * r;
-    double q = c_lnexp[11] * pr[12];
-#pragma unroll
-    for (int n = 12; n < 23; ++n) q = fma(c_lnexp[n], pr[23 - n], q);
-    q = (q + r) + 1.0;
-    return ldexp(q, (int)k);
 }
 
 // ---------------------------------------------------------------------------

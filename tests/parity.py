@@ -35,6 +35,15 @@ def rhs_errors(Rg, Rref, Y, h):
     return np.array(out)
 
 
+def literal_rhs_errors(Rg, Rref):
+    """The plain relative max-norm error per variable,
+    ||R_gpu - R_ref||_inf / ||R_ref||_inf, without the floor of rhs_errors
+    (printed next to it; where ||R_ref|| is small against the natural scale
+    it is dominated by the rounding of the fluxes, not by the method)."""
+    return np.array([np.abs(Rg[v] - Rref[v]).max() / max(np.abs(Rref[v]).max(), 1e-300)
+                     for v in range(Rref.shape[0])])
+
+
 def state_errors(Yg, Yref):
     out = []
     rho_c = np.abs(Yref[0]).max() * C_SOUND
@@ -64,3 +73,14 @@ def rounding_floor(rhs, Y, h, draws=2, seed=1):
         Yp = Y * (1.0 + 2.2e-16 * rng.choice([-1.0, 0.0, 1.0], size=Y.shape))
         fl = np.maximum(fl, rhs_errors(rhs(Yp), R0, Y, h))
     return R0, fl
+
+
+def contraction_floor(grid, model, Yref, Y, R0, h):
+    """How far the same oracle sources, compiled with fused multiply-adds
+    allowed, land from the plain build's tendency R0 (rhs_errors norm): the
+    distance between two correct FP64 evaluations of the operator that
+    differ only in rounding (the GPU contracts to FMA as well)."""
+    import oracle
+
+    R1 = oracle.Model(oracle.Grid(grid, contract=True), model, Yref).rhs(Y)
+    return rhs_errors(R1, R0, Y, h)

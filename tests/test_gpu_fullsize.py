@@ -1,20 +1,32 @@
 """Parity at the full benchmark sizes, in the configuration bench.py times:
 the FP64 tendency of every node against the oracle (dry bubble 32^3,
-moist shallow convection 64x64x30, warped Agnesi flow 96x16x50), and the
-FP32-bulk tendency error against the same oracle (stated, bounded).
+moist shallow convection 64x64x30, warped Agnesi flow 96x16x50), two whole
+LSRK54 steps of the 32^3 bubble, and the FP32-bulk tendency error against
+the same oracle (stated, bounded).
 
-The FP64 bar is 1e-11 relative per variable, or four times the oracle's own
-movement under one-ulp input perturbations where that is larger (the moist
-momentum tendencies, whose floor is about 1.2e-11)."""
+Tendency bar: 1e-11 relative per variable in the norm of parity.rhs_errors
+(max-norm error over max(||R_ref||, 1e-3 x the natural tendency scale)).
+Where the oracle itself moves by more than that when every input word is
+perturbed by one ulp (the moist momentum tendencies: pressure and
+temperature come out of the saturation adjustment, and the vertical
+pressure gradient of a nearly hydrostatic column cancels to ~1e-4 of its
+terms), the bar is four times that floor; no second FP64 implementation can
+do better there.  A second measure of that floor is the distance between
+the oracle and the same oracle sources compiled with FMA contraction: the
+GPU must stay within 1.5 times it wherever it exceeds 1e-11 (on the moist
+state the contracted oracle moves 2.45e-11 in rho w, the GPU 2.22e-11).
+The plain relative max-norm error is printed beside it."""
 import numpy as np
 import pytest
 
 import oracle
 from paper_2110_00853_amd import binding as B
 from paper_2110_00853_amd import workloads as W
-from parity import hmin, rhs_errors, rounding_floor
+from parity import contraction_floor, hmin, literal_rhs_errors, rhs_errors, rounding_floor, state_errors
 
 pytestmark = pytest.mark.gpu
+
+STEP_TOL = 1e-9
 
 
 @pytest.mark.parametrize("name", ["bubble_32", "agnesi_96", "moist_64"])
@@ -23,18 +35,50 @@ def test_full_size_rhs_matches_oracle(name):
 
     c = W.case(name)
     Y, Yref, dt = W.initial_state(c)
+    print("full-size rhs:", name, flush=True)
     Rref, floor = rounding_floor(oracle.Model(oracle.Grid(c["grid"]), c["model"], Yref).rhs, Y, hmin(c["grid"]))
+    cfloor = contraction_floor(c["grid"], c["model"], Yref, Y, Rref, hmin(c["grid"]))
     tol = np.maximum(1e-11, 4.0 * floor)
     g = B.Grid(c["grid"])
-    out = {}
+    out, lit = {}, {}
     for prec in ("fp64", "fp32"):
         m = B.Model(g, c["model"], Yref, precision=prec)
         Yd = m.new_state(Y)
         Rd = m.new_state()
         m.rhs(Yd, Rd)
         torch.cuda.synchronize()
-        out[prec] = rhs_errors(m.to_numpy(Rd).astype(np.float64), Rref, Y, hmin(c["grid"]))
+        Rg = m.to_numpy(Rd).astype(np.float64)
+        out[prec] = rhs_errors(Rg, Rref, Y, hmin(c["grid"]))
+        lit[prec] = literal_rhs_errors(Rg, Rref)
         del m, Yd, Rd
-    print(name, "full-size rhs errors fp64", out["fp64"], "oracle 1-ulp floor", floor, "fp32-bulk", out["fp32"])
+    print(name, "full-size rhs errors fp64", out["fp64"], "plain relative", lit["fp64"],
+          "oracle 1-ulp floor", floor, "oracle vs FMA-contracted oracle", cfloor, "fp32-bulk", out["fp32"])
     assert np.all(out["fp64"] < tol), (out["fp64"], tol)
+    assert np.all(out["fp64"] <= np.maximum(1e-11, 1.5 * cfloor)), (out["fp64"], cfloor)
     assert np.all(np.isfinite(out["fp32"])) and np.all(out["fp32"] < 5e-2), out["fp32"]
+
+
+def test_full_size_two_lsrk_steps_match_oracle():
+    """Two LSRK54 steps of the 32^3 bubble (4.1M nodes, Smagorinsky-Lilly +
+    Richardson, FP64) in the launch configuration bench.py times."""
+    import torch
+
+    c = W.case("bubble_32")
+    Y, Yref, dt = W.initial_state(c)
+    print("full-size 2 steps: bubble_32", flush=True)
+    Yo, _ = oracle.Model(oracle.Grid(c["grid"]), c["model"], Yref).steps(Y, dt, 2)
+    g = B.Grid(c["grid"])
+    m = B.Model(g, c["model"], Yref)
+    Ya, Yb, dQ = m.new_state(Y), m.new_state(), m.new_state()
+    t = 0.0
+    for _ in range(2):
+        m.lsrk_step(Ya, Yb, dQ, t, dt)
+        Ya, Yb = Yb, Ya
+        t += dt
+    torch.cuda.synchronize()
+    Yg = m.to_numpy(Ya)
+    err = state_errors(Yg, Yo)
+    moved = np.array([np.abs(Yo[v] - Y[v]).max() for v in range(Y.shape[0])])
+    rel_change = np.array([np.abs(Yg[v] - Yo[v]).max() for v in range(Y.shape[0])]) / np.maximum(moved, 1e-300)
+    print("2-step state errors", err, "relative to the change over the 2 steps", rel_change)
+    assert np.all(err < STEP_TOL), err
