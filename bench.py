@@ -35,10 +35,11 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_tend_bubble32_fp64.json
 MLP_WEIGHTS = os.path.join(ROOT, "paper_2110_00853_amd", "data", "mlp_bubble64_to_32.npz")
 
 
-def measured_traffic(case: str):
-    """Counter-derived HBM bytes per tendency launch, if the summary matches
-    the kernel source being timed."""
-    if case != "bubble_32" or not os.path.exists(TRAFFIC_FILE):
+def measured_traffic(case: str, ne=None):
+    """Counter-derived HBM bytes per tendency launch, if the summary was
+    taken on this workload (the 32^3 bubble at its own element counts) and on
+    the kernel source being timed; else None."""
+    if case != "bubble_32" or ne is not None or not os.path.exists(TRAFFIC_FILE):
         return None
     with open(KERNEL_SRC, "rb") as f:
         sha = hashlib.sha256(f.read()).hexdigest()
@@ -144,7 +145,7 @@ def run(args):
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": measured_traffic(args.case),
+            "traffic": measured_traffic(args.case, args.ne),
             "avg_launch_us": tend_avg_s * 1e6,
             "alg_bytes_per_launch": tend_bytes,
             "grad_kernel": {"avg_launch_us": grad_avg_s * 1e6,
@@ -228,6 +229,12 @@ def other_setup(name: str, steps: int, warmup: int):
     grid = B.Grid(c["grid"], device=0)
     nn, nvar = grid.n_nodes, c["model"]["nvar"]
     res = {"n_nodes": nn, "nvar": nvar, "elements": c["grid"]["ne"], "steps": steps, "ic_seconds": t_ic}
+    # algorithmic words per node and stage: 5 nv state words, the stored
+    # diffusive flux written once and read once, and on warped meshes the
+    # per-node metric terms (10) and face metrics (about 4.8) read in both
+    # passes
+    nf_words = {5: 9, 6: 12}[nvar]
+    metric_words = 2 * (10 + 4.8) if c["grid"].get("topo") == 1 else 0
     for prec in ("fp64", "fp32"):
         m = B.Model(grid, c["model"], Yref, precision=prec)
         Ya, Yb, dQ = m.new_state(Y0), m.new_state(), m.new_state()
@@ -251,7 +258,11 @@ def other_setup(name: str, steps: int, warmup: int):
         prof = m.profile_read()
         m.profile(False)
         d = m.diagnostics(Ya, dt)
+        sb = 8 if prec == "fp64" else 4
+        b_alg = (5 * nvar + 2 * nf_words + metric_words) * sb  # bytes per node and stage
         res[prec] = {"value": nn * nvar * 5 * steps / (ms * 1e-3), "ms_per_step": ms / steps,
+                     "alg_bytes_per_node_stage": b_alg,
+                     "roofline_frac": nn * 5 * steps * b_alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
                      "tend_avg_us": prof["tend"][0] * 1e3 / prof["tend"][1],
                      "grad_avg_us": prof["grad"][0] * 1e3 / max(prof["grad"][1], 1),
                      "n_nonfinite": d["n_nonfinite"]}
@@ -279,9 +290,22 @@ def mlp_weights(B, grid, c, Yref, Y0):
     return B.MLP(seed=0).params(), norm, "seeded random initialisation"
 
 
-def cpu_baseline(c, Y0, Yref, nn, nvar, dt, budget_s=15.0, max_steps=40):
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(c, Y0, Yref, nn, nvar, dt, budget_s=15.0, max_steps=40, one_thread_s=5.0):
     """The FP64 oracle on this host, as it stands: whole LSRK54 steps of the
-    same workload, repeated until about budget_s seconds of CPU work."""
+    same workload, repeated until about budget_s seconds of CPU work, with
+    all the host threads it gets; then right-hand-side evaluations on one
+    thread for about one_thread_s seconds (a fifth of a step each)."""
     import oracle
 
     og = oracle.Grid(c["grid"])
@@ -295,13 +319,27 @@ def cpu_baseline(c, Y0, Yref, nn, nvar, dt, budget_s=15.0, max_steps=40):
         if time.perf_counter() - t0 >= budget_s:
             break
     t = time.perf_counter() - t0
+    threads = oracle.num_threads()
+    oracle.set_num_threads(1)
+    n1 = 0
+    t1 = time.perf_counter()
+    while True:
+        om.rhs(Y0)
+        n1 += 1
+        if time.perf_counter() - t1 >= one_thread_s:
+            break
+    t1 = time.perf_counter() - t1
+    oracle.set_num_threads(threads)
     return {
         "value": nn * nvar * 5 * steps / t,
         "unit": "DOF-updates/s",
-        "cores": oracle.num_threads(),
+        "cores": threads,
         "kind": "oracle",
+        "cpu": cpu_model(),
         "sample": "%d LSRK54 step(s) of the same workload (%d nodes x %d vars x 5 stages), %.1f s"
                   % (steps, nn, nvar, t),
+        "one_thread": {"value": nn * nvar * n1 / t1, "unit": "DOF-updates/s",
+                       "sample": "%d right-hand-side evaluation(s), %.1f s" % (n1, t1)},
     }
 
 

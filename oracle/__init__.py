@@ -124,6 +124,7 @@ def _declare(L):
     L.cmref_lsrk_steps.argtypes = [C.c_void_p, _P, _P, C.c_double, C.c_double, C.c_int]
     L.cmref_integrals.argtypes = [C.c_void_p, _P, _P]
     L.cmref_num_threads.restype = C.c_int
+    L.cmref_set_num_threads.argtypes = [C.c_int]
     L.cmref_set_mutation.argtypes = [C.c_int]
     L.cmref_mlp_closure.argtypes = [_P, C.c_void_p, _P, _P, C.c_int, _P, C.c_double, C.c_double,
                                     C.c_double, C.POINTER(C.c_double), C.POINTER(C.c_double)]
@@ -394,3 +395,8 @@ def set_mutation(code: int) -> None:
 
 def num_threads() -> int:
     return lib().cmref_num_threads()
+
+
+def set_num_threads(n: int) -> None:
+    """Thread count of the oracle's parallel loops from now on."""
+    lib().cmref_set_num_threads(int(n))

@@ -937,3 +937,13 @@ int cmref_num_threads(void)
     return 1;
 #endif
 }
+
+/* thread count of the following parallel loops (timing on one thread) */
+void cmref_set_num_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}

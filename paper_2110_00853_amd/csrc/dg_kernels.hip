@@ -973,7 +973,7 @@ __device__ __forceinline__ void face_load(const KParams& P, const R* __restrict_
 // task's own-node entries of sG (the divergence is already done)
 template <typename R, bool MOIST, bool WARP, bool VISC>
 __device__ __forceinline__ void face_flux(const KParams& P, const FaceLoad<R, MOIST, WARP, VISC>& f, int e, int ez,
-                                          R (*sG)[BLOCK], R (*sP)[BLOCK], R (*sY)[BLOCK])
+                                          R (*sG)[NP], R (*sP)[BLOCK], R (*sY)[BLOCK])
 {
     constexpr int NV = MOIST ? 6 : 5;
     const int64_t nn = P.nn;
@@ -1099,7 +1099,6 @@ struct OwnLoad {
     static constexpr int NWS = NW + (MOIST ? 2 : 1);  // with the subsidence words
     R Yr[NV];
     R w[VISC ? NWS : 1];
-    R dq[MODE == 1 ? NV : 1];
     R Jam[WARP ? 10 : 1];  // J a^d (9) and 1/J
     double pr, rr;
     double T, ql;  // moist viscous: T and q_l from earlier in the stage
@@ -1121,10 +1120,7 @@ __device__ __forceinline__ void own_load(const KParams& P, int e, int ez, int tt
 #pragma unroll
         for (int q = 0; q < O::NWS; ++q) o.w[q] = q < nw ? *gptr<const R>(P.F2s[q], foff) : (R)0;
     }
-    if (MODE == 1) {
-#pragma unroll
-        for (int v = 0; v < O::NV; ++v) o.dq[v] = __builtin_nontemporal_load(gptr<const R>(P.dQs[v], soff));
-    }
+
     const int ri = ref_index(P, e, ez, tt / (NQ * NQ), tt);
     o.pr = P.pr[ri];
     o.rr = P.rhor[ri];
@@ -1149,7 +1145,7 @@ template <typename R, bool MOIST, bool WARP, bool VISC, int MODE>
 __device__ __forceinline__ void tend_element(const KParams& P, int e, int t,
                                              const OwnLoad<R, MOIST, WARP, VISC, MODE>& o,
                                              const FaceLoad<R, MOIST, WARP, VISC>& ft0, R dval,
-                                             R (*sG)[BLOCK], R (*sP)[BLOCK], R (*sY)[BLOCK],
+                                             R (*sG)[NP], R (*sP)[BLOCK], R (*sY)[BLOCK], R* sD,
                                              const R* __restrict__ F2, R A, R B, R dt)
 {
     constexpr int NV = MOIST ? 6 : 5;
@@ -1199,10 +1195,11 @@ __device__ __forceinline__ void tend_element(const KParams& P, int e, int t,
                 if (act) sG[v * 3 + d][t] = G;
             }
     }
-    // the differentiation matrix into the unused slots 125, 126 of sG:
-    // D[r][c] at sG[3c + r % 3][125 + r / 3] (its load was issued first, so
-    // phase B waits for no global load)
-    if (t < NQ * NQ) sG[(t % NQ) * 3 + (t / NQ) % 3][NP + (t / NQ) / 3] = dval;
+    // the differentiation matrix into LDS column by column, D[r][c] at
+    // sD[5c + r]: the five rows a wave reads for one c are consecutive words,
+    // in distinct banks (its load was issued first, so phase B waits for no
+    // global load)
+    if (t < NQ * NQ) sD[(t % NQ) * NQ + t / NQ] = dval;
     __syncthreads();
 
     // phase B: strong-form divergence with the 1-D GLL matrix, one variable
@@ -1214,14 +1211,15 @@ __device__ __forceinline__ void tend_element(const KParams& P, int e, int t,
         R s = 0;
 #pragma unroll
         for (int l = 0; l < NQ; ++l) {
-            s += sG[l * 3 + i % 3][NP + i / 3] * sG[v * 3 + 0][l + NQ * (j + NQ * k)];
-            s += sG[l * 3 + j % 3][NP + j / 3] * sG[v * 3 + 1][i + NQ * (l + NQ * k)];
-            s += sG[l * 3 + k % 3][NP + k / 3] * sG[v * 3 + 2][i + NQ * (j + NQ * l)];
+            s += sD[l * NQ + i] * sG[v * 3 + 0][l + NQ * (j + NQ * k)];
+            s += sD[l * NQ + j] * sG[v * 3 + 1][i + NQ * (l + NQ * k)];
+            s += sD[l * NQ + k] * sG[v * 3 + 2][i + NQ * (j + NQ * l)];
         }
         asm volatile("" : "+v"(s));
         Rv[v] = -s;
     }
     __syncthreads();
+
 
     // phase C: face tasks.  lift (n.F^- - n.F^*): n.F^- comes from the
     // contravariant flux already in LDS (lift n.F = side G^dir / (J w_N)).
@@ -1235,6 +1233,15 @@ __device__ __forceinline__ void tend_element(const KParams& P, int e, int t,
     __syncthreads();
 
     // phase D: gather the face terms of this node, metric factor, sources
+    // the stage's dQ is loaded only now: loaded with the rest of the own
+    // data at entry, its registers stay live through phases A to C
+    // (120 instead of 110 VGPRs, 1 % slower)
+    R dqv[MODE == 1 ? NV : 1];
+    if (MODE == 1) {
+        const uint32_t doff = (uint32_t)(e * SRUN + tt) * (uint32_t)sizeof(R);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) dqv[v] = __builtin_nontemporal_load(gptr<const R>(P.dQs[v], doff));
+    }
     const int idx[3] = {i, j, k};
     if (WARP) {
         const R invJ = o.Jam[9];
@@ -1247,7 +1254,7 @@ __device__ __forceinline__ void tend_element(const KParams& P, int e, int t,
         const bool on = idx[dir] == 0 || idx[dir] == NQ - 1;
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
-            const R fv = sG[v * 3 + dir][t];
+            const R fv = sG[v * 3 + dir][tt];
             Rv[v] += on ? fv : (R)0;
         }
     }
@@ -1279,7 +1286,7 @@ __device__ __forceinline__ void tend_element(const KParams& P, int e, int t,
         if (MODE == 0) {
             __builtin_nontemporal_store(act ? Rv[v] : (R)0, gptr<R>(P.outs[v], soff));
         } else {
-            const R dq = MODE == 1 ? A * o.dq[v] + dt * Rv[v] : dt * Rv[v];
+            const R dq = MODE == 1 ? A * dqv[v] + dt * Rv[v] : dt * Rv[v];
             const R yn = o.Yr[v] + B * dq;
             __builtin_nontemporal_store(act ? dq : (R)0, gptr<R>(P.dQs[v], soff));
             __builtin_nontemporal_store(act ? yn : (R)0, gptr<R>(P.outs[v], soff));
@@ -1303,7 +1310,8 @@ __device__ __forceinline__ void tend_element(const KParams& P, int e, int t,
 // divergence each face task overwrites its own-node entry with the lift of
 // (n.F^- - n.F^*)
 #define CM_TEND_LDS                          \
-    __shared__ R sG[NV * 3][BLOCK];          \
+    __shared__ R sG[NV * 3][NP];             \
+    __shared__ R sD[NQ * NQ];                \
     __shared__ R sP[tend_keeps_p<R, MOIST, VISC>() ? 4 : 1][BLOCK]; /* u v w c */ \
     __shared__ R sY[NV][BLOCK]; /* own state, for the face tasks */
 
@@ -1323,7 +1331,7 @@ __global__ __launch_bounds__(BLOCK) void k_tend(const KParams P, const R* __rest
     own_load<R, MOIST, WARP, VISC, MODE>(P, e, ez, tt, o);
     FaceLoad<R, MOIST, WARP, VISC> ft0;
     face_load<R, MOIST, WARP, VISC>(P, F2, t, e, ex, ey, ez, ft0);
-    tend_element<R, MOIST, WARP, VISC, MODE>(P, e, t, o, ft0, dval, sG, sP, sY, F2, A, B, dt);
+    tend_element<R, MOIST, WARP, VISC, MODE>(P, e, t, o, ft0, dval, sG, sP, sY, sD, F2, A, B, dt);
 }
 
 #undef CM_TEND_LDS

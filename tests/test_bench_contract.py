@@ -43,5 +43,6 @@ def test_traffic_is_reported_only_for_the_profiled_source(tmp_path, monkeypatch)
     prof.write_text(json.dumps({"kernel_source_sha256": sha, "hbm_bytes_per_launch": 1.5e9}))
     assert bench.measured_traffic("bubble_32") == 1.5e9
     assert bench.measured_traffic("moist_64") is None  # taken on another workload
+    assert bench.measured_traffic("bubble_32", "16,16,16") is None  # other element counts
     src.write_bytes(b"kernel source, changed")
     assert bench.measured_traffic("bubble_32") is None  # stale summary
