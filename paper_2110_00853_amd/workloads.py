@@ -279,6 +279,16 @@ CASES = {
                              "u_relax": (10.0, 0.0, 0.0)}},
         "ic": {"kind": "agnesi", "u0": 10.0, "Nbv": 0.01},
     },
+    # 2.5-D density current (Sect. 5.2): [0, 25.6 km] x one 200 m element
+    # (periodic) x [0, 6.4 km], free-slip walls in x and z, 50 m effective
+    # resolution (200 m elements, N = 4), constant nu = 75 m^2/s with
+    # Pr = 1 (the classical set-up the front-location table quotes)
+    "density_current": {
+        "grid": _grid((128, 1, 32), (25600.0, 200.0, 6400.0), periodic=(0, 1, 0)),
+        "model": {"nvar": 5, "closure": "const", "nu": 75.0, "Prt": 1.0, "g": _G},
+        "ic": {"kind": "density_current", "theta0": 300.0, "theta_c": -15.0, "center": (0.0, 3000.0),
+               "radii": (4000.0, 2000.0)},
+    },
 }
 CASES["learned_32"] = copy.deepcopy(CASES["bubble_32"])
 CASES["learned_32"]["model"]["closure"] = "mlp"
@@ -327,6 +337,25 @@ def bubble_state(grid: dict, center, r0=500.0, dtheta=1.0, T_iso=300.0, g=_G, xy
     return Y, Yref, float(np.max(sound_speed_dry(Tp)))
 
 
+def density_current_state(grid: dict, theta0=300.0, theta_c=-15.0, center=(0.0, 3000.0),
+                          radii=(4000.0, 2000.0), g=_G, xyz=None):
+    """Neutral hydrostatic background (uniform theta0) plus the cold bubble
+    dtheta = theta_c/2 (1 + cos(pi r)) for r <= 1, r = |((x - x_c)/r_x,
+    (z - z_c)/r_z)| (Sect. 5.2, eq. densityCurrentEqn, reading the printed
+    radius as the usual elliptic distance), applied at fixed pressure; the
+    flow starts at rest."""
+    xyz = node_coords(grid) if xyz is None else xyz
+    z = xyz[2]
+    p, T = neutral(z, theta0, g)
+    r = np.sqrt(((xyz[0] - center[0]) / radii[0]) ** 2 + ((z - center[1]) / radii[1]) ** 2)
+    dth = np.where(r <= 1.0, 0.5 * theta_c * (1.0 + np.cos(np.pi * r)), 0.0)
+    Tp = T + dth * (p / _P0) ** _KAPPA
+    zero = np.zeros_like(z)
+    Y = state_from_primitives(p, Tp, zero, zero, zero, z, g=g)
+    Yref = state_from_primitives(p, T, zero, zero, zero, z, g=g)
+    return Y, Yref, float(np.max(sound_speed_dry(T)))
+
+
 def perturbed_state(c: dict, seed: int = 0, amp_u=5.0, amp_T=1.0, amp_q=1.0e-3, xyz=None):
     """Background of case c plus smooth random velocity / temperature (and
     moisture) perturbations: a generic state for parity tests."""
@@ -370,6 +399,10 @@ def initial_state(c: dict, xyz=None):
     zero = np.zeros_like(z)
     if ic["kind"] == "bubble":
         Y, Yref, cmax = bubble_state(grid, ic["center"], g=g, xyz=xyz)
+        return Y, Yref, cfl_dt(grid, cmax)
+    if ic["kind"] == "density_current":
+        Y, Yref, cmax = density_current_state(grid, ic["theta0"], ic["theta_c"], ic["center"], ic["radii"],
+                                              g=g, xyz=xyz)
         return Y, Yref, cfl_dt(grid, cmax)
     if ic["kind"] == "moist":
         p, T, qt = moist_hydrostatic(z, g=g)

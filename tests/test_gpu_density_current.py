@@ -1,0 +1,66 @@
+"""The 2.5-D density current (Sect. 5.2) on the GPU: a short full-grid
+segment against the oracle, and the front location at t = 900 s against the
+front-location table of App. B (50 m effective resolution, mu = 75 m^2/s:
+14767 m for DG and SEM; the 50 m entries of the table span 14535 m to
+15027 m)."""
+import math
+import time
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2110_00853_amd import binding as B
+from paper_2110_00853_amd import diagnostics as D
+from paper_2110_00853_amd import workloads as W
+from parity import state_errors
+
+pytestmark = pytest.mark.gpu
+
+PUBLISHED_DG_50M = 14767.0
+SPREAD_50M = (14535.0, 15027.0)
+
+
+def _run(c, Y, Yref, dt, nsteps):
+    import torch
+
+    g = B.Grid(c["grid"])
+    m = B.Model(g, c["model"], Yref)
+    Ya, Yb, dQ = m.new_state(Y), m.new_state(), m.new_state()
+    t = 0.0
+    for _ in range(nsteps):
+        m.lsrk_step(Ya, Yb, dQ, t, dt)
+        Ya, Yb = Yb, Ya
+        t += dt
+    torch.cuda.synchronize()
+    d = m.diagnostics(Ya, dt)
+    return m.to_numpy(Ya), d
+
+
+def test_density_current_segment_matches_oracle():
+    c = W.case("density_current")
+    Y, Yref, dt = W.initial_state(c)
+    print("density current: 20 steps against the oracle", flush=True)
+    Yg, _ = _run(c, Y, Yref, dt, 20)
+    Yo, _ = oracle.Model(oracle.Grid(c["grid"]), c["model"], Yref).steps(Y, dt, 20)
+    err = state_errors(Yg, Yo)
+    print("density current 20-step state errors", err)
+    assert np.all(err < 1e-9), err
+
+
+def test_density_current_front_at_900_s():
+    c = W.case("density_current")
+    xyz = W.node_coords(c["grid"])
+    Y, Yref, dt0 = W.initial_state(c, xyz=xyz)
+    nsteps = math.ceil(900.0 / dt0)
+    dt = 900.0 / nsteps
+    print("density current: %d LSRK54 steps of %.5f s to t = 900 s" % (nsteps, dt), flush=True)
+    t0 = time.perf_counter()
+    Yg, d = _run(c, Y, Yref, dt, nsteps)
+    wall = time.perf_counter() - t0
+    x = D.front_location(Yg, xyz)
+    thp = D.potential_temperature(Yg, xyz[2]) - 300.0
+    print("front at t = 900 s: %.1f m (published DG/SEM 50 m: %.0f m, difference %+.1f m); theta' min %.2f K; "
+          "max CFL %.3f; %.1f s wall" % (x, PUBLISHED_DG_50M, x - PUBLISHED_DG_50M, thp.min(), d["max_cfl"], wall))
+    assert d["n_nonfinite"] == 0
+    assert SPREAD_50M[0] <= x <= SPREAD_50M[1], x
