@@ -190,6 +190,16 @@ CM_API cm_status cm_dg_rhs(cm_model* model, const void* Y, void* dYdt, double t,
 CM_API cm_status cm_lsrk_step(cm_model* model, void* Y, void* Y_alt, void* dQ, double t, double dt,
                        void* hip_stream);
 
+/* One LSRK144 step (Sect. 3.2: the fourteen-stage fourth-order 2N-storage
+ * scheme of Niegemann, Diehl & Busch, the paper's integrator for its
+ * isotropic runs), the same fused stage update as cm_lsrk_step with its own
+ * coefficients.  The stages ping-pong Y -> Y_alt -> Y ...; with fourteen
+ * stages the NEW state ends in Y (Y_alt holds the thirteenth stage).  dQ need
+ * not be initialised (A_1 = 0).  Y, Y_alt, dQ must be distinct.  Errors as
+ * cm_lsrk_step. */
+CM_API cm_status cm_lsrk144_step(cm_model* model, void* Y, void* Y_alt, void* dQ, double t, double dt,
+                                 void* hip_stream);
+
 /* Conservation and health diagnostics (Sect. 6): compensated (Neumaier) FP64
  * integrals in a deterministic two-stage reduction, extrema, CFL and a
  * non-finite count.  Synchronises the stream.  Returns CM_ERR_NONFINITE

@@ -122,6 +122,8 @@ def _declare(L):
     L.cmref_gradients.restype = C.c_int
     L.cmref_lsrk54_coeffs.argtypes = [_P, _P, _P]
     L.cmref_lsrk_steps.argtypes = [C.c_void_p, _P, _P, C.c_double, C.c_double, C.c_int]
+    L.cmref_lsrk144_coeffs.argtypes = [_P, _P, _P]
+    L.cmref_lsrk144_steps.argtypes = [C.c_void_p, _P, _P, C.c_double, C.c_double, C.c_int]
     L.cmref_integrals.argtypes = [C.c_void_p, _P, _P]
     L.cmref_num_threads.restype = C.c_int
     L.cmref_set_num_threads.argtypes = [C.c_int]
@@ -271,11 +273,13 @@ class Model:
         self._L.cmref_model_reference(self.h, pr, rr)
         return pr, rr
 
-    def steps(self, Y, dt: float, nsteps: int, t: float = 0.0, dQ=None):
-        """Advance a copy of Y by nsteps LSRK54 steps; returns (Y, dQ)."""
+    def steps(self, Y, dt: float, nsteps: int, t: float = 0.0, dQ=None, scheme: str = "lsrk54"):
+        """Advance a copy of Y by nsteps steps of LSRK54 (or scheme="lsrk144");
+        returns (Y, dQ)."""
         Y = self._chk(Y).copy()
         dQ = np.zeros_like(Y) if dQ is None else np.ascontiguousarray(dQ, dtype=np.float64).copy()
-        self._L.cmref_lsrk_steps(self.h, Y, dQ, float(t), float(dt), int(nsteps))
+        fn = {"lsrk54": self._L.cmref_lsrk_steps, "lsrk144": self._L.cmref_lsrk144_steps}[scheme]
+        fn(self.h, Y, dQ, float(t), float(dt), int(nsteps))
         return Y, dQ
 
     def integrals(self, Y):
@@ -343,6 +347,13 @@ def lsrk54_coeffs():
 
 
 NPARAM = 9282
+
+
+def lsrk144_coeffs():
+    """A, B, C of the 14-stage LSRK (Niegemann, Diehl & Busch 2012)."""
+    A, B, Cc = np.zeros(14), np.zeros(14), np.zeros(14)
+    lib().cmref_lsrk144_coeffs(A, B, Cc)
+    return A, B, Cc
 
 
 def mlp_forward(params, X, bf16=False):

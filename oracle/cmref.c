@@ -878,26 +878,65 @@ void cmref_lsrk54_coeffs(double* A, double* B, double* C)
     for (int s = 0; s < 5; ++s) { A[s] = LSRK_A[s]; B[s] = LSRK_B[s]; C[s] = LSRK_C[s]; }
 }
 
-/* One step in place: for each stage dQ = A_s dQ + dt R(Y); Y += B_s dQ. */
-void cmref_lsrk_steps(void* h, double* Y, double* dQ, double t, double dt, int nsteps)
+/* LSRK144 (Niegemann, Diehl & Busch 2012: fourteen stages, fourth order,
+ * 2N storage, stability region fitted to DG operators), the integrator of
+ * the paper's isotropic runs (Sect. 3.2).  Coefficients as published, to
+ * sixteen digits; C_s are the stage times. */
+static const double LSRK144_A[14] = {
+    0.0, -0.7188012108672410, -0.7785331173421570, -0.0053282796654044, -0.8552979934029281,
+    -3.9564138245774565, -1.5780575380587385, -2.0837094552574054, -0.7483334182761610,
+    -0.7032861106563359, 0.0013917096117681, -0.0932075369637460, -0.9514200470875948,
+    -7.1151571693922548};
+static const double LSRK144_B[14] = {
+    0.0367762454319673, 0.3136296607553959, 0.1531848691869027, 0.0030097086818182, 0.3326293790646110,
+    0.2440251405350864, 0.3718879239592277, 0.6204126221582444, 0.1524043173028741, 0.0760894927419266,
+    0.0077604214040978, 0.0024647284755382, 0.0780348340049386, 5.5059777270269628};
+static const double LSRK144_C[14] = {
+    0.0, 0.0367762454319673, 0.1249685262725025, 0.2446177702277698, 0.2476149531070420,
+    0.2969311120382472, 0.3978149645802642, 0.5270854589440328, 0.6981269994175695,
+    0.8190890835352128, 0.8527059887098624, 0.8604711817462826, 0.8627060376969976,
+    0.8734213127600976};
+
+void cmref_lsrk144_coeffs(double* A, double* B, double* C)
 {
-    model_t* M = (model_t*)h;
+    for (int s = 0; s < 14; ++s) { A[s] = LSRK144_A[s]; B[s] = LSRK144_B[s]; C[s] = LSRK144_C[s]; }
+}
+
+/* nsteps steps in place of a 2N-storage scheme with ns stages: for each
+ * stage dQ = A_s dQ + dt R(Y); Y += B_s dQ. */
+static void lsrk_run(model_t* M, int ns, const double* A, const double* B, double* Y, double* dQ, double dt,
+                     int nsteps)
+{
     long n = (long)M->m.nvar * M->G->nnodes;
     double* R = (double*)malloc(sizeof(double) * n);
     work_t W; work_alloc(M, &W, slots(&M->m));
     for (int step = 0; step < nsteps; ++step) {
-        for (int s = 0; s < 5; ++s) {
+        for (int s = 0; s < ns; ++s) {
             rhs_eval(M, Y, R, &W);
             #pragma omp parallel for schedule(static)
             for (long i = 0; i < n; ++i) {
-                dQ[i] = LSRK_A[s] * dQ[i] + dt * R[i];
-                Y[i] = Y[i] + LSRK_B[s] * dQ[i];
+                dQ[i] = A[s] * dQ[i] + dt * R[i];
+                Y[i] = Y[i] + B[s] * dQ[i];
             }
         }
-        t += dt;
     }
     work_free(&W);
     free(R);
+}
+
+/* LSRK54 steps in place (t: model time of the first step; the sources do
+ * not depend on it) */
+void cmref_lsrk_steps(void* h, double* Y, double* dQ, double t, double dt, int nsteps)
+{
+    (void)t;
+    lsrk_run((model_t*)h, 5, LSRK_A, LSRK_B, Y, dQ, dt, nsteps);
+}
+
+/* LSRK144 steps in place */
+void cmref_lsrk144_steps(void* h, double* Y, double* dQ, double t, double dt, int nsteps)
+{
+    (void)t;
+    lsrk_run((model_t*)h, 14, LSRK144_A, LSRK144_B, Y, dQ, dt, nsteps);
 }
 
 /* ======================================================================== */

@@ -22,7 +22,8 @@ CLOSURES = {"none": 0, "const": 1, "smag": 2, "mlp": 3}
 EXPORTED = [
     "cm_grid_create", "cm_grid_destroy", "cm_grid_query", "cm_grid_copy_coords", "cm_grid_copy_wJ",
     "cm_grid_copy_metrics", "cm_model_create", "cm_model_destroy", "cm_model_set_mlp",
-    "cm_model_mlp_fallbacks", "cm_dg_rhs", "cm_lsrk_step", "cm_diagnostics", "cm_diagnostics_noalloc",
+    "cm_model_mlp_fallbacks", "cm_dg_rhs", "cm_lsrk_step", "cm_lsrk144_step", "cm_diagnostics",
+    "cm_diagnostics_noalloc",
     "cm_mlp_create",
     "cm_mlp_destroy", "cm_mlp_train_step", "cm_mlp_grads", "cm_mlp_infer", "cm_mlp_get_params",
     "cm_mlp_set_params", "cm_model_profile", "cm_model_profile_read", "cm_model_closure_inputs",
@@ -97,6 +98,7 @@ def load():
     L.cm_model_mlp_fallbacks.argtypes = [_VP, C.POINTER(C.c_int64), _VP]
     L.cm_dg_rhs.argtypes = [_VP, _VP, _VP, C.c_double, _VP]
     L.cm_lsrk_step.argtypes = [_VP, _VP, _VP, _VP, C.c_double, C.c_double, _VP]
+    L.cm_lsrk144_step.argtypes = [_VP, _VP, _VP, _VP, C.c_double, C.c_double, _VP]
     L.cm_diagnostics.argtypes = [_VP, _VP, C.c_double, C.POINTER(Diag), _VP]
     L.cm_diagnostics_noalloc.argtypes = [_VP, _VP, C.c_double, C.POINTER(Diag), _VP]
     L.cm_mlp_create.argtypes = [C.POINTER(MLPDesc), C.c_uint64, C.c_int, C.POINTER(_VP)]
@@ -287,6 +289,13 @@ class Model:
         _check(load().cm_lsrk_step(self.h, Y.data_ptr(), Y_alt.data_ptr(), dQ.data_ptr(), float(t), float(dt),
                                    _stream_ptr(stream)))
         return Y_alt
+
+    def lsrk144_step(self, Y, Y_alt, dQ, t: float, dt: float, stream=None):
+        """One LSRK144 step; the new state is in Y on return (Y_alt is scratch)."""
+        self._chk(Y, Y_alt, dQ)
+        _check(load().cm_lsrk144_step(self.h, Y.data_ptr(), Y_alt.data_ptr(), dQ.data_ptr(), float(t),
+                                      float(dt), _stream_ptr(stream)))
+        return Y
 
     def diagnostics(self, Y, dt: float = 0.0, stream=None, noalloc: bool = False) -> dict:
         """cm_diagnostics, or cm_diagnostics_noalloc (static workspace) with noalloc=True."""

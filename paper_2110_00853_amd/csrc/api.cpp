@@ -512,26 +512,51 @@ static const double LSRK_B[5] = {1432997174477.0 / 9575080441755.0, 516183667771
                                  1720146321549.0 / 2090206949498.0, 3134564353537.0 / 4481467310338.0,
                                  2277821191437.0 / 14882151754819.0};
 
-cm_status cm_lsrk_step(cm_model* m, void* Y, void* Y_alt, void* dQ, double t, double dt, void* stream)
+// Niegemann, Diehl & Busch (2012) fourteen-stage fourth-order 2N-storage
+// coefficients (sixteen digits, as published)
+static const double LSRK144_A[14] = {0.0, -0.7188012108672410, -0.7785331173421570, -0.0053282796654044,
+                                     -0.8552979934029281, -3.9564138245774565, -1.5780575380587385,
+                                     -2.0837094552574054, -0.7483334182761610, -0.7032861106563359,
+                                     0.0013917096117681, -0.0932075369637460, -0.9514200470875948,
+                                     -7.1151571693922548};
+static const double LSRK144_B[14] = {0.0367762454319673, 0.3136296607553959, 0.1531848691869027,
+                                     0.0030097086818182, 0.3326293790646110, 0.2440251405350864,
+                                     0.3718879239592277, 0.6204126221582444, 0.1524043173028741,
+                                     0.0760894927419266, 0.0077604214040978, 0.0024647284755382,
+                                     0.0780348340049386, 5.5059777270269628};
+
+// ns fused stages of a 2N-storage scheme, ping-ponging Y -> Y_alt -> Y ...
+static cm_status lsrk_run(cm_model* m, void* Y, void* Y_alt, void* dQ, double dt, int ns, const double* A,
+                          const double* B, void* stream, const char* name)
 {
-    (void)t;
-    cm_status st = check_model(m, "cm_lsrk_step");
+    cm_status st = check_model(m, name);
     if (st != CM_OK) return st;
-    if (!Y || !Y_alt || !dQ) { set_error("cm_lsrk_step: null state pointer"); return CM_ERR_ARG; }
-    if (Y == Y_alt || Y == dQ || Y_alt == dQ) { set_error("cm_lsrk_step: Y, Y_alt, dQ must be distinct"); return CM_ERR_ARG; }
-    if (!(dt > 0.0) || !std::isfinite(dt)) { set_error("cm_lsrk_step: dt must be positive and finite"); return CM_ERR_ARG; }
+    if (!Y || !Y_alt || !dQ) { set_error(std::string(name) + ": null state pointer"); return CM_ERR_ARG; }
+    if (Y == Y_alt || Y == dQ || Y_alt == dQ) { set_error(std::string(name) + ": Y, Y_alt, dQ must be distinct"); return CM_ERR_ARG; }
+    if (!(dt > 0.0) || !std::isfinite(dt)) { set_error(std::string(name) + ": dt must be positive and finite"); return CM_ERR_ARG; }
     CM_TRY_HIP(hipSetDevice(m->grid->device), "hipSetDevice");
     hipStream_t s = (hipStream_t)stream;
     void* src = Y;
     void* dst = Y_alt;
-    for (int stage = 0; stage < 5; ++stage) {
-        CM_TRY_HIP(launch_rhs(m, src, dst, dQ, stage == 0 ? 2 : 1, LSRK_A[stage], LSRK_B[stage], dt, s),
-                   "cm_lsrk_step launch");
+    for (int stage = 0; stage < ns; ++stage) {
+        CM_TRY_HIP(launch_rhs(m, src, dst, dQ, stage == 0 ? 2 : 1, A[stage], B[stage], dt, s), name);
         void* tmp = src;
         src = dst;
         dst = tmp;
     }
     return CM_OK;
+}
+
+cm_status cm_lsrk_step(cm_model* m, void* Y, void* Y_alt, void* dQ, double t, double dt, void* stream)
+{
+    (void)t;
+    return lsrk_run(m, Y, Y_alt, dQ, dt, 5, LSRK_A, LSRK_B, stream, "cm_lsrk_step");
+}
+
+cm_status cm_lsrk144_step(cm_model* m, void* Y, void* Y_alt, void* dQ, double t, double dt, void* stream)
+{
+    (void)t;
+    return lsrk_run(m, Y, Y_alt, dQ, dt, 14, LSRK144_A, LSRK144_B, stream, "cm_lsrk144_step");
 }
 
 cm_status cm_model_profile(cm_model* m, int enable)

@@ -119,6 +119,30 @@ def test_lsrk_step_matches_oracle(dev, name):
     assert np.all(err < 1e-10), err
 
 
+@pytest.mark.parametrize("name", ["bubble_4", "smag_ragged", "moist", "warped", "moist_inviscid"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_lsrk144_step_matches_oracle(dev, name, precision):
+    """LSRK144 (fourteen fused stages, new state back in the input buffer)
+    against the oracle's: FP64 at 1e-10 after 3 steps; FP32-bulk bounded at 1e-2
+    (its momenta carry the FP32 rounding of the hydrostatic balance)."""
+    c = SMALL_CASES[name]
+    Y, Yref = _state(c)
+    _, _, speed = W.perturbed_state(c, seed=11, amp_u=6.0, amp_T=2.0, amp_q=1.5e-3)
+    dt = 2.0 * W.cfl_dt(c["grid"], speed)
+    g = B.Grid(c["grid"])
+    m = B.Model(g, c["model"], Yref, precision=precision)
+    Ya, Yb, dQ = m.new_state(Y), m.new_state(), m.new_state()
+    nsteps = 3
+    for _ in range(nsteps):
+        m.lsrk144_step(Ya, Yb, dQ, 0.0, dt)
+    dev.cuda.synchronize()
+    Yg = m.to_numpy(Ya).astype(np.float64)
+    Yo, _ = oracle.Model(oracle.Grid(c["grid"]), c["model"], Yref).steps(Y, dt, nsteps, scheme="lsrk144")
+    err = state_errors(Yg, Yo)
+    print(name, precision, "LSRK144 state errors after", nsteps, "steps", err)
+    assert np.all(err < (1e-10 if precision == "fp64" else 1e-2)), err
+
+
 def test_bubble_4_hundred_steps(dev):
     """The 4^3-element dry bubble: state after 100 LSRK54 steps within 1e-9."""
     c = W.case("bubble_4")

@@ -1,5 +1,6 @@
-"""Pins of the LSRK54 integrator (Sect. 3.2: Carpenter & Kennedy low-storage
-explicit Runge-Kutta family; five stages, fourth order, 2N storage)."""
+"""Pins of the low-storage integrators (Sect. 3.2): LSRK54 (Carpenter &
+Kennedy; five stages, fourth order, 2N storage) and LSRK144 (Niegemann, Diehl
+& Busch; fourteen stages, fourth order, 2N storage)."""
 from fractions import Fraction
 
 import numpy as np
@@ -60,3 +61,66 @@ def test_empirical_temporal_order(oracle_lib):
         errs.append(np.abs(Y[1] - ref[1]).max())
     orders = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
     assert np.all(orders > 3.8), (errs, orders)
+
+
+def test_lsrk144_order_conditions(oracle_lib):
+    A, B, Cc = oracle_lib.lsrk144_coeffs()
+    assert A[0] == 0.0 and Cc[0] == 0.0 and len(A) == 14
+    a, b = butcher(A, B)
+    c = a.sum(axis=1)
+    # the published stage times are the row sums of the tableau
+    assert np.allclose(c, Cc, atol=1e-14)
+    cond = [
+        (b.sum(), 1.0), (b @ c, 1 / 2), (b @ c ** 2, 1 / 3), (b @ a @ c, 1 / 6),
+        (b @ c ** 3, 1 / 4), (b @ (c * (a @ c)), 1 / 8), (b @ a @ c ** 2, 1 / 12), (b @ a @ a @ c, 1 / 24),
+    ]
+    # sixteen published digits and |B_14| = 5.5: the conditions hold to ~1e-13
+    for val, exact in cond:
+        assert val == pytest.approx(exact, abs=2e-13)
+    # not fifth order: the first fifth-order condition fails by far more
+    assert abs(b @ c ** 4 - 1 / 5) > 1e-6
+
+
+def test_lsrk144_reaches_further_per_stage_into_the_left_half_plane(oracle_lib):
+    """The scheme's purpose (a stability region fitted to the spectra of
+    upwinded DG operators, which lie in the left half plane): along rays at
+    120, 150 and 180 degrees the largest stable |z| per stage exceeds
+    LSRK54's (on the imaginary axis itself it does not: 0.43 against 0.67)."""
+    def amp(A, B, z):
+        a, b = butcher(A, B)
+        s = len(A)
+        # R(z) = 1 + z b (I - z a)^-1 1
+        return abs(1.0 + z * b @ np.linalg.solve(np.eye(s) - z * a, np.ones(s)))
+
+    def reach(A, B, deg):
+        d = np.exp(1j * np.pi * deg / 180.0)
+        rs = np.linspace(0.01, 30.0, 6000)
+        ok = np.array([amp(A, B, r * d) <= 1.0 + 1e-12 for r in rs])
+        return rs[np.argmin(ok)] if not ok.all() else rs[-1]
+
+    A54, B54, _ = oracle_lib.lsrk54_coeffs()
+    A144, B144, _ = oracle_lib.lsrk144_coeffs()
+    for deg in (120, 150, 180):
+        r54, r144 = reach(A54, B54, deg) / 5, reach(A144, B144, deg) / 14
+        assert r144 > 1.15 * r54, (deg, r54, r144)
+    # check of the reach computation itself: LSRK54's stability polynomial
+    # is 1 + z + z^2/2 + z^3/6 + z^4/24 + z^5/200, whose real stability
+    # interval ends at the root of P(x) = -1 below zero
+    P = np.polynomial.Polynomial([2.0, 1.0, 1 / 2, 1 / 6, 1 / 24, 1 / 200])
+    x = min(r.real for r in P.roots() if abs(r.imag) < 1e-12 and r.real < 0)
+    assert abs(reach(A54, B54, 180) + x) < 0.01, (reach(A54, B54, 180), x)
+
+
+def test_lsrk144_empirical_temporal_order(oracle_lib):
+    g = {"N": 4, "ne": [2, 2, 1], "lo": [0.0, 0.0, 0.0], "hi": [4000.0, 4000.0, 2000.0], "periodic": [1, 1, 1]}
+    G = oracle_lib.Grid(g)
+    Y0, _ = W.isentropic_vortex(g, 0.0, center=(2000.0, 2000.0), L=600.0)
+    M = oracle_lib.Model(G, {"nvar": 5, "closure": "none", "g": 0.0})
+    T = 12.0
+    ref, _ = M.steps(Y0, T / 384, 384, scheme="lsrk144")
+    errs = []
+    for n in (12, 24, 48):
+        Y, _ = M.steps(Y0, T / n, n, scheme="lsrk144")
+        errs.append(np.abs(Y[1] - ref[1]).max())
+    orders = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
+    assert np.all(orders > 3.7), (errs, orders)
