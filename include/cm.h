@@ -66,8 +66,19 @@ typedef enum {
     CM_CLOSURE_NONE = 0,   /* inviscid */
     CM_CLOSURE_CONST = 1,  /* constant kinematic viscosity nu */
     CM_CLOSURE_SMAG = 2,   /* Smagorinsky-Lilly (eq. smago), optional Richardson factor */
-    CM_CLOSURE_MLP = 3     /* learned eddy viscosity / Prandtl number, Smagorinsky fallback */
+    CM_CLOSURE_MLP = 3,    /* learned eddy viscosity / Prandtl number, Smagorinsky fallback */
+    CM_CLOSURE_VREMAN = 4  /* Vreman (Sect. 4.2, eq. vreman-sgs), coefficient 2.5 Cs^2, mixing length
+                              h_d / N per direction, optional Richardson factor */
 } cm_closure;
+
+/* Inviscid numerical flux n.F1* at element faces (Sect. 3.1).  Roe and HLLC
+ * are for dry models (nvar = 5); a moist model with them fails to create
+ * with CM_ERR_UNSUPPORTED. */
+typedef enum {
+    CM_FLUX_RUSANOV = 0,   /* centred + half the largest |u.n| + c times the jump */
+    CM_FLUX_ROE = 1,       /* Roe: acoustic, entropy and shear waves of the sqrt(rho)-averaged state */
+    CM_FLUX_HLLC = 2       /* HLLC: Davis wave-speed bounds, contact restored */
+} cm_flux;
 
 /* Mesh (Sect. 3.1): brick of ne[0] x ne[1] x ne[2] hexahedra over
  * [lo, hi]; periodic[d] != 0 wraps direction d, otherwise its two end faces
@@ -109,6 +120,7 @@ typedef struct {
     double theta_flux, qt_flux;        /* [K m/s], [m/s] */
     int subsidence;                    /* w_s = -w0 sin(pi z / z_top) acting on h_tot, q_t */
     double sub_w0, sub_ztop;
+    int flux;                          /* inviscid numerical flux (Sect. 3.1): cm_flux */
 } cm_model_desc;
 
 typedef struct {

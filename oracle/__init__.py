@@ -58,8 +58,10 @@ class ModelDesc(C.Structure):
                 ("sp_ztop", C.c_double), ("sp_alpha", C.c_double), ("sp_gamma", C.c_double),
                 ("sp_u", C.c_double * 3), ("sfc_flux", C.c_int), ("theta_flux", C.c_double),
                 ("qt_flux", C.c_double), ("subsidence", C.c_int), ("sub_w0", C.c_double),
-                ("sub_ztop", C.c_double)]
+                ("sub_ztop", C.c_double), ("flux", C.c_int)]
 
+
+FLUXES = {"rusanov": 0, "roe": 1, "hllc": 2}
 
 _P = np.ctypeslib.ndpointer(dtype=np.float64, flags="C_CONTIGUOUS")
 
@@ -98,10 +100,13 @@ def _declare(L):
     L.cmref_saturation_adjust.argtypes = [C.c_double, C.c_double, C.c_double,
                                           C.POINTER(C.c_double), C.POINTER(C.c_double)]
     L.cmref_thermo_nodes.argtypes = [C.c_int, C.c_long, _P, _P, C.c_double, _P, _P, _P, _P]
+    L.cmref_numflux_point.argtypes = [C.c_int, C.c_int, _P, _P, C.c_double, C.c_double, C.c_double, _P, _P]
     L.cmref_rusanov_point.argtypes = [C.c_int, _P, _P, C.c_double, C.c_double, C.c_double,
                                       C.c_double, C.c_double, _P, _P]
     L.cmref_smagorinsky_point.argtypes = [_P, C.c_double, C.c_double, C.c_double, C.c_double,
                                           C.c_int, C.POINTER(C.c_double)]
+    L.cmref_vreman_point.argtypes = [_P, C.c_double, C.c_double, _P, C.c_double, C.c_int,
+                                     C.POINTER(C.c_double)]
     L.cmref_model_create.argtypes = [C.c_void_p, C.POINTER(ModelDesc), C.c_void_p]
     L.cmref_model_create.restype = C.c_void_p
     L.cmref_model_destroy.argtypes = [C.c_void_p]
@@ -163,7 +168,7 @@ def _grid_desc(g: dict) -> GridDesc:
 def _model_desc(m: dict) -> ModelDesc:
     d = ModelDesc()
     d.nvar = int(m.get("nvar", 5))
-    d.closure = {"none": 0, "const": 1, "smag": 2, "mlp": 3}[m.get("closure", "none")]
+    d.closure = {"none": 0, "const": 1, "smag": 2, "mlp": 3, "vreman": 4}[m.get("closure", "none")]
     d.nu = float(m.get("nu", 0.0))
     d.Cs = float(m.get("Cs", 0.21))
     d.Prt = float(m.get("Prt", 1.0 / 3.0))
@@ -189,6 +194,7 @@ def _model_desc(m: dict) -> ModelDesc:
         d.subsidence = 1
         d.sub_w0 = float(sb["w0"])
         d.sub_ztop = float(sb["z_top"])
+    d.flux = FLUXES[m.get("flux", "rusanov")]
     return d
 
 
@@ -241,6 +247,8 @@ class Model:
         self._yref = yref
         ptr = yref.ctypes.data_as(C.c_void_p) if yref is not None else None
         self.h = self._L.cmref_model_create(grid.h, C.byref(self._d), ptr)
+        if not self.h:
+            raise ValueError("oracle model creation failed (Roe and HLLC fluxes are for dry models only)")
 
     def __del__(self):
         if getattr(self, "h", None):
@@ -333,10 +341,29 @@ def rusanov(Ym, Yp, n, zm=0.0, zp=0.0, g=0.0, prm=0.0, prp=0.0):
     return out
 
 
+def numflux(kind, Ym, Yp, n, z=0.0, g=0.0, pr=0.0):
+    """Numerical flux n.F1* ("rusanov", "roe", "hllc") between two states at
+    a face node at height z with reference pressure pr."""
+    Ym = np.ascontiguousarray(Ym, dtype=np.float64)
+    out = np.zeros(Ym.size)
+    lib().cmref_numflux_point(FLUXES[kind], Ym.size, Ym, np.ascontiguousarray(Yp, dtype=np.float64), float(z),
+                              float(g), float(pr), np.ascontiguousarray(n, dtype=np.float64), out)
+    return out
+
+
 def smagorinsky(gu: np.ndarray, N2: float, Cs: float, Delta: float, Prt: float, richardson: bool):
     nu = C.c_double()
     lib().cmref_smagorinsky_point(np.ascontiguousarray(gu, dtype=np.float64).ravel(), N2, Cs,
                                   Delta, Prt, int(richardson), C.byref(nu))
+    return nu.value
+
+
+def vreman(gu, N2, Cs, Dm, Prt=1.0 / 3.0, richardson=False):
+    """Vreman eddy viscosity at one node (eq. vreman-sgs); gu[i][j] = du_i/dx_j,
+    Dm the mixing length per direction."""
+    nu = C.c_double()
+    lib().cmref_vreman_point(np.ascontiguousarray(gu, dtype=np.float64).ravel(), float(N2), float(Cs),
+                             np.ascontiguousarray(Dm, dtype=np.float64), float(Prt), int(richardson), C.byref(nu))
     return nu.value
 
 

@@ -402,6 +402,99 @@ static void rusanov(const double* Ym, const prim_t* Pm, double prm,
     }
 }
 
+/* Roe numerical flux (Sect. 3.1; Roe 1981) for dry air: centred average
+ * minus half of sum_k |lambda_k| alpha_k r_k over the acoustic, entropy and
+ * shear waves of the Roe-averaged state (weights sqrt(rho)).  With the
+ * internal energy counted from T_0 (I = c_vd (T - T_0)), rho e_tot + rho
+ * c_vd T_0 is the ideal-gas total energy whose Roe matrix is the textbook
+ * one; the energy row here is that one minus c_vd T_0 times the mass row.
+ * phi = g z at the face node (the same on both sides).  The momentum flux
+ * carries p - p_r (p_r is continuous at the node, so only the centred part
+ * sees it). */
+static void roe(const prim_t* Pm, double prm, const prim_t* Pp, double prp, double phi, const double n[3],
+                double* out)
+{
+    double Fm[6][3], Fp[6][3];
+    flux1(Pm, 5, prm, Fm);
+    flux1(Pp, 5, prp, Fp);
+    double sm = sqrt(Pm->rho), sp = sqrt(Pp->rho);
+    double wm = sm / (sm + sp), wp = sp / (sm + sp);
+    double rh = sm * sp;
+    double uh[3], du[3];
+    for (int c = 0; c < 3; ++c) { uh[c] = wm * Pm->u[c] + wp * Pp->u[c]; du[c] = Pp->u[c] - Pm->u[c]; }
+    double Hh = wm * Pm->h + wp * Pp->h;
+    double q2 = uh[0] * uh[0] + uh[1] * uh[1] + uh[2] * uh[2];
+    double c2 = (CPD / CVD - 1.0) * (Hh + CVD * TREF0 - 0.5 * q2 - phi);
+    double ch = sqrt(c2);
+    double unh = uh[0] * n[0] + uh[1] * n[1] + uh[2] * n[2];
+    double dun = du[0] * n[0] + du[1] * n[1] + du[2] * n[2];
+    double drho = Pp->rho - Pm->rho, dp = Pp->p - Pm->p;
+    double a1 = (dp - rh * ch * dun) / (2.0 * c2);
+    double a2 = drho - dp / c2;
+    double a3 = (dp + rh * ch * dun) / (2.0 * c2);
+    double l1 = fabs(unh - ch), l2 = fabs(unh), l3 = fabs(unh + ch);
+    double D[5];
+    D[0] = l1 * a1 + l2 * a2 + l3 * a3;
+    double udu_t = uh[0] * du[0] + uh[1] * du[1] + uh[2] * du[2] - unh * dun;
+    for (int c = 0; c < 3; ++c)
+        D[1 + c] = l1 * a1 * (uh[c] - ch * n[c]) + l2 * a2 * uh[c] + l3 * a3 * (uh[c] + ch * n[c]) +
+                   l2 * rh * (du[c] - dun * n[c]);
+    D[4] = l1 * a1 * (Hh - ch * unh) + l2 * a2 * (0.5 * q2 + phi - CVD * TREF0) + l3 * a3 * (Hh + ch * unh) +
+           l2 * rh * udu_t;
+    for (int v = 0; v < 5; ++v) {
+        double fm = Fm[v][0] * n[0] + Fm[v][1] * n[1] + Fm[v][2] * n[2];
+        double fp = Fp[v][0] * n[0] + Fp[v][1] * n[1] + Fp[v][2] * n[2];
+        out[v] = 0.5 * (fm + fp) - 0.5 * D[v];
+    }
+}
+
+/* HLLC numerical flux (Sect. 3.1; Toro, Spruce & Speares 1994) for dry air,
+ * with the wave-speed bounds of Davis, S_L = min(u_n - c) and S_R =
+ * max(u_n + c) over both sides, the contact speed S* from the jump
+ * conditions, and the star states rho_K (S_K - u_nK)/(S_K - S*) (1, u_K +
+ * (S* - u_nK) n, e_K + (S* - u_nK)(S* + p_K / (rho_K (S_K - u_nK)))).  The
+ * energy flux (rho e_tot + p) u_n is the form the jump conditions take
+ * with any energy origin; the momentum flux carries p - p_r. */
+static void hllc(const double* Ym, const prim_t* Pm, double prm, const double* Yp, const prim_t* Pp, double prp,
+                 const double n[3], double* out)
+{
+    double Fm[6][3], Fp[6][3];
+    flux1(Pm, 5, prm, Fm);
+    flux1(Pp, 5, prp, Fp);
+    double fm[5], fp[5];
+    for (int v = 0; v < 5; ++v) {
+        fm[v] = Fm[v][0] * n[0] + Fm[v][1] * n[1] + Fm[v][2] * n[2];
+        fp[v] = Fp[v][0] * n[0] + Fp[v][1] * n[1] + Fp[v][2] * n[2];
+    }
+    double unm = Pm->u[0] * n[0] + Pm->u[1] * n[1] + Pm->u[2] * n[2];
+    double unp = Pp->u[0] * n[0] + Pp->u[1] * n[1] + Pp->u[2] * n[2];
+    double SL = fmin(unm - Pm->c, unp - Pp->c);
+    double SR = fmax(unm + Pm->c, unp + Pp->c);
+    if (SL >= 0.0) { for (int v = 0; v < 5; ++v) out[v] = fm[v]; return; }
+    if (SR <= 0.0) { for (int v = 0; v < 5; ++v) out[v] = fp[v]; return; }
+    double Ss = (Pp->p - Pm->p + Pm->rho * unm * (SL - unm) - Pp->rho * unp * (SR - unp)) /
+                (Pm->rho * (SL - unm) - Pp->rho * (SR - unp));
+    const prim_t* P = Ss >= 0.0 ? Pm : Pp;
+    const double* Y = Ss >= 0.0 ? Ym : Yp;
+    const double* f = Ss >= 0.0 ? fm : fp;
+    double S = Ss >= 0.0 ? SL : SR, un = Ss >= 0.0 ? unm : unp;
+    double fac = P->rho * (S - un) / (S - Ss);
+    double Us[5];
+    Us[0] = fac;
+    for (int c = 0; c < 3; ++c) Us[1 + c] = fac * (P->u[c] + (Ss - un) * n[c]);
+    Us[4] = fac * (P->e + (Ss - un) * (Ss + P->p / (P->rho * (S - un))));
+    for (int v = 0; v < 5; ++v) out[v] = f[v] + S * (Us[v] - Y[v]);
+}
+
+/* the model's numerical flux: 0 Rusanov, 1 Roe, 2 HLLC */
+static void numflux(int kind, const double* Ym, const prim_t* Pm, double prm, const double* Yp, const prim_t* Pp,
+                    double prp, double phi, const double n[3], int nvar, double* out)
+{
+    if (kind == 1) roe(Pm, prm, Pp, prp, phi, n, out);
+    else if (kind == 2) hllc(Ym, Pm, prm, Yp, Pp, prp, n, out);
+    else rusanov(Ym, Pm, prm, Yp, Pp, prp, n, nvar, out);
+}
+
 /* Point evaluation of the Rusanov flux for the identity tests. */
 void cmref_rusanov_point(int nvar, const double* Ym, const double* Yp, double zm, double zp,
                          double g, double prm, double prp, const double* n, double* out)
@@ -410,6 +503,17 @@ void cmref_rusanov_point(int nvar, const double* Ym, const double* Yp, double zm
     thermo(Ym, nvar, zm, g, &Pm);
     thermo(Yp, nvar, zp, g, &Pp);
     rusanov(Ym, &Pm, prm, Yp, &Pp, prp, n, nvar, out);
+}
+
+/* Point evaluation of any of the numerical fluxes (dry for Roe and HLLC)
+ * at a face node at height z, for the flux tests. */
+void cmref_numflux_point(int kind, int nvar, const double* Ym, const double* Yp, double z, double g, double pr,
+                         const double* n, double* out)
+{
+    prim_t Pm, Pp;
+    thermo(Ym, nvar, z, g, &Pm);
+    thermo(Yp, nvar, z, g, &Pp);
+    numflux(kind, Ym, &Pm, pr, Yp, &Pp, pr, g * z, n, nvar, out);
 }
 
 /* ======================================================================== */
@@ -432,6 +536,7 @@ typedef struct {
 
 void* cmref_model_create(void* grid, const cmref_model_desc* m, const double* Yref)
 {
+    if (m->flux < 0 || m->flux > 2 || (m->flux != 0 && m->nvar > 5)) return NULL;
     model_t* M = (model_t*)calloc(1, sizeof(model_t));
     M->G = (grid_t*)grid;
     M->m = *m;
@@ -523,6 +628,52 @@ double cmref_smagorinsky(const double gu[3][3], double N2, double Cs, double Del
     return (Cs * Delta) * (Cs * Delta) * sqrt(SS) * fb;
 }
 
+/* Vreman eddy viscosity (Sect. 4.2, eq. vreman-sgs): nu = 2.5 Cs^2
+ * sqrt(B_beta / (u_ij u_ij)), beta_ij = sum_m Dm_m^2 u_i,m u_j,m, B_beta the
+ * sum of the three principal 2x2 minors of beta; Dm the element size over N
+ * per direction.  With richardson the same stability factor as
+ * Smagorinsky-Lilly multiplies it (Ri = N^2 / |S|^2). */
+double cmref_vreman(const double gu[3][3], double N2, double Cs, const double Dm[3], double Prt, int richardson)
+{
+    double aa = 0.0;
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) aa += gu[i][j] * gu[i][j];
+    if (aa <= 0.0) return 0.0;
+    double beta[3][3];
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+            double b = 0.0;
+            for (int m = 0; m < 3; ++m) b += Dm[m] * Dm[m] * gu[i][m] * gu[j][m];
+            beta[i][j] = b;
+        }
+    double Bb = beta[0][0] * beta[1][1] + beta[0][0] * beta[2][2] + beta[1][1] * beta[2][2] -
+                (beta[0][2] * beta[0][2] + beta[0][1] * beta[0][1] + beta[1][2] * beta[1][2]);
+    if (Bb <= 0.0) return 0.0;
+    double fb = 1.0;
+    if (richardson) {
+        double SS = 0.0;
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j) {
+                double Sij = 0.5 * (gu[i][j] + gu[j][i]);
+                SS += 2.0 * Sij * Sij;
+            }
+        double Ri = SS > 0.0 ? N2 / SS : 0.0;
+        if (Ri > 0.0) {
+            double a = 1.0 - Ri / Prt;
+            fb = pow(a > 0.0 ? a : 0.0, 0.25);
+        }
+    }
+    return 2.5 * Cs * Cs * sqrt(Bb / aa) * fb;
+}
+
+void cmref_vreman_point(const double* gu9, double N2, double Cs, const double* Dm, double Prt, int richardson,
+                        double* nu)
+{
+    double gu[3][3];
+    for (int i = 0; i < 3; ++i) for (int j = 0; j < 3; ++j) gu[i][j] = gu9[3 * i + j];
+    *nu = cmref_vreman(gu, N2, Cs, Dm, Prt, richardson);
+}
+
 void cmref_smagorinsky_point(const double* gu9, double N2, double Cs, double Delta, double Prt,
                              int richardson, double* nu)
 {
@@ -551,7 +702,7 @@ static gslots_t slots(const cmref_model_desc* m)
 {
     gslots_t s; s.nG = 4; s.iq = -1; s.ith = -1;
     if (m->nvar > 5) s.iq = s.nG++;
-    if ((m->closure == 2 && m->richardson) || m->closure == 3) s.ith = s.nG++;
+    if (((m->closure == 2 || m->closure == 4) && m->richardson) || m->closure == 3) s.ith = s.nG++;
     return s;
 }
 
@@ -632,7 +783,10 @@ static void diffusive_flux(model_t* M, work_t* W, gslots_t s)
         double nu = 0.0, Prt = m->Prt;
         if (m->closure == 1) nu = m->nu;
         else if (m->closure == 2) nu = cmref_smagorinsky(gu, N2, m->Cs, M->Delta, m->Prt, m->richardson);
-        else if (m->closure == 3) {
+        else if (m->closure == 4) {
+            const double Dm[3] = {G->h[0] / G->N, G->h[1] / G->N, G->h[2] / G->N};
+            nu = cmref_vreman(gu, N2, m->Cs, Dm, m->Prt, m->richardson);
+        } else if (m->closure == 3) {
             double nu_sl = cmref_smagorinsky(gu, N2, m->Cs, M->Delta, m->Prt, m->richardson);
             if (M->mlp) {
                 double nn_, pp_;
@@ -771,7 +925,7 @@ static void rhs_eval(model_t* M, const double* Y, double* R, work_t* W)
                         long np = en * Np + m3[0] + Q * (m3[1] + Q * m3[2]);
                         double Yp[6];
                         for (int v = 0; v < nvar; ++v) Yp[v] = Y[v * nn + np];
-                        rusanov(Ym, Pm, M->pr[n], Yp, &W->P[np], M->pr[np], nv, nvar, fstar);
+                        numflux(m->flux, Ym, Pm, M->pr[n], Yp, &W->P[np], M->pr[np], m->g * z[n], nv, nvar, fstar);
                         for (int v = 0; v < nvar; ++v) {
                             double a = 0.0, b = 0.0;
                             for (int c = 0; c < 3; ++c) {
@@ -787,7 +941,7 @@ static void rhs_eval(model_t* M, const double* Y, double* R, work_t* W)
                         double mn = Ym[1] * nv[0] + Ym[2] * nv[1] + Ym[3] * nv[2];
                         for (int c = 0; c < 3; ++c) Yp[1 + c] = Ym[1 + c] - 2.0 * mn * nv[c];
                         prim_t Pp; thermo(Yp, nvar, z[n], m->g, &Pp);
-                        rusanov(Ym, Pm, M->pr[n], Yp, &Pp, M->pr[n], nv, nvar, fstar);
+                        numflux(m->flux, Ym, Pm, M->pr[n], Yp, &Pp, M->pr[n], m->g * z[n], nv, nvar, fstar);
                         for (int v = 0; v < nvar; ++v) f2star[v] = 0.0;
                         if (m->closure != 0 && m->sfc_flux && dir == 2 && side < 0) {
                             /* prescribed upward surface fluxes; outward normal is -z */

@@ -28,7 +28,7 @@ typedef struct {
 
 typedef struct {
     int nvar;           /* 5 dry (rho, rho u, rho v, rho w, rho e_tot), 6 moist (+ rho q_t) */
-    int closure;        /* 0 none, 1 constant nu, 2 Smagorinsky-Lilly, 3 learned (MLP) */
+    int closure;        /* 0 none, 1 constant nu, 2 Smagorinsky-Lilly, 3 learned (MLP), 4 Vreman */
     double nu, Cs, Prt;
     int richardson;
     double g;
@@ -39,6 +39,7 @@ typedef struct {
     double theta_flux, qt_flux;
     int subsidence;
     double sub_w0, sub_ztop;
+    int flux;           /* inviscid numerical flux: 0 Rusanov, 1 Roe, 2 HLLC (the last two dry only) */
 } cmref_model_desc;
 
 #endif

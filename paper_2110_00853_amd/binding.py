@@ -17,7 +17,8 @@ LIB_PATH = os.environ.get("CM_LIB", os.path.join(HERE, "libcm.so"))
 
 CM_OK, CM_ERR_ARG, CM_ERR_HIP, CM_ERR_ALLOC, CM_ERR_UNSUPPORTED, CM_ERR_NONFINITE, CM_ERR_STATE = range(7)
 CM_FP64, CM_FP32_BULK = 0, 1
-CLOSURES = {"none": 0, "const": 1, "smag": 2, "mlp": 3}
+CLOSURES = {"none": 0, "const": 1, "smag": 2, "mlp": 3, "vreman": 4}
+FLUXES = {"rusanov": 0, "roe": 1, "hllc": 2}
 
 EXPORTED = [
     "cm_grid_create", "cm_grid_destroy", "cm_grid_query", "cm_grid_copy_coords", "cm_grid_copy_wJ",
@@ -55,7 +56,7 @@ class ModelDesc(C.Structure):
                 ("sp_zs", C.c_double), ("sp_ztop", C.c_double), ("sp_alpha", C.c_double),
                 ("sp_gamma", C.c_double), ("sp_u", C.c_double * 3), ("sfc_flux", C.c_int),
                 ("theta_flux", C.c_double), ("qt_flux", C.c_double), ("subsidence", C.c_int),
-                ("sub_w0", C.c_double), ("sub_ztop", C.c_double)]
+                ("sub_w0", C.c_double), ("sub_ztop", C.c_double), ("flux", C.c_int)]
 
 
 class Diag(C.Structure):
@@ -214,6 +215,7 @@ def model_desc(m: dict, precision: str = "fp64") -> ModelDesc:
     if sb:
         d.subsidence = 1
         d.sub_w0, d.sub_ztop = float(sb["w0"]), float(sb["z_top"])
+    d.flux = FLUXES[m.get("flux", "rusanov")]
     return d
 
 

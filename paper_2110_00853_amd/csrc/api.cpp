@@ -343,7 +343,12 @@ cm_status cm_model_create(const cm_grid* g, const cm_model_desc* desc, const dou
     *out = nullptr;
     if (desc->nvar != 5 && desc->nvar != 6) { set_error("cm_model_create: nvar must be 5 or 6"); return CM_ERR_UNSUPPORTED; }
     if (desc->precision != CM_FP64 && desc->precision != CM_FP32_BULK) { set_error("cm_model_create: bad precision"); return CM_ERR_ARG; }
-    if (desc->closure < 0 || desc->closure > 3) { set_error("cm_model_create: bad closure"); return CM_ERR_ARG; }
+    if (desc->closure < 0 || desc->closure > 4) { set_error("cm_model_create: bad closure"); return CM_ERR_ARG; }
+    if (desc->flux < 0 || desc->flux > 2) { set_error("cm_model_create: bad numerical flux"); return CM_ERR_ARG; }
+    if (desc->flux != CM_FLUX_RUSANOV && desc->nvar != 5) {
+        set_error("cm_model_create: Roe and HLLC fluxes are for dry models (nvar = 5) only");
+        return CM_ERR_UNSUPPORTED;
+    }
     if (desc->closure != CM_CLOSURE_NONE && !(desc->Prt > 0.0)) { set_error("cm_model_create: Prt must be > 0"); return CM_ERR_ARG; }
     if (desc->sponge && !(desc->sp_ztop > desc->sp_zs)) { set_error("cm_model_create: sponge needs z_top > z_s"); return CM_ERR_ARG; }
     if (desc->subsidence && !(desc->sub_ztop > 0.0)) { set_error("cm_model_create: subsidence needs z_top > 0"); return CM_ERR_ARG; }

@@ -347,6 +347,45 @@ __device__ __forceinline__ R smagorinsky(const KParams& P, const R S[3][3], R N2
     return cd * cd * fsqrt(SS);
 }
 
+// Vreman (eq. vreman-sgs): 2.5 Cs^2 sqrt(B_beta / (u_ij u_ij)) with
+// beta_ij = sum_m Dm_m^2 u_i,m u_j,m (Dm the element size over N per
+// direction) and B_beta its second principal invariant; the same Richardson
+// factor as Smagorinsky-Lilly when enabled.  gu[i][j] = du_i/dx_j.
+template <typename R>
+__device__ __forceinline__ R vreman(const KParams& P, const R gu[3][3], const R S[3][3], R N2)
+{
+    const R d2[3] = {(R)(P.h0 * P.h0 * (1.0 / 16.0)), (R)(P.h1 * P.h1 * (1.0 / 16.0)),
+                     (R)(P.h2 * P.h2 * (1.0 / 16.0))};
+    R aa = 0;
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) aa += gu[i][j] * gu[i][j];
+    R b[3][3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = i; j < 3; ++j)
+            b[i][j] = d2[0] * gu[i][0] * gu[j][0] + d2[1] * gu[i][1] * gu[j][1] + d2[2] * gu[i][2] * gu[j][2];
+    const R Bb = b[0][0] * b[1][1] + b[0][0] * b[2][2] + b[1][1] * b[2][2] -
+                 (b[0][2] * b[0][2] + b[0][1] * b[0][1] + b[1][2] * b[1][2]);
+    if (!(aa > (R)0) || !(Bb > (R)0)) return (R)0;
+    R nu = (R)(2.5 * P.Cs * P.Cs) * fsqrt(Bb * frcp(aa));
+    if (P.richardson) {
+        R SS = 0;
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) SS += (R)2 * S[a][c] * S[a][c];
+        const R Ri = SS > (R)0 ? N2 * frcp(SS) : (R)0;
+        if (Ri > (R)0) {
+            const R a = (R)1 - Ri * (R)P.invPrt;
+            nu = a > (R)0 ? nu * fsqrt(fsqrt(a)) : (R)0;
+        }
+    }
+    return nu;
+}
+
 // ---------------------------------------------------------------------------
 // face-node tasks: the 6 x 25 face nodes of an element are spread over the
 // block's lanes (150 tasks on 128 lanes), so face work runs on dense lanes
@@ -583,7 +622,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(MLP || MO
     const int64_t nn = P.nn;
     const int64_t ebase = (int64_t)e * NP;
     const int64_t node = ebase + tt;
-    const bool need_thv = (P.closure == CM_CLOSURE_SMAG && P.richardson) || MLP;
+    const bool need_thv = ((P.closure == CM_CLOSURE_SMAG || P.closure == CM_CLOSURE_VREMAN) && P.richardson) || MLP;
 
     GradLoad<R, MOIST> g0;
     grad_load<R, MOIST>(P, t, e, ex, ey, ez, g0);
@@ -738,6 +777,9 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(MLP || MO
     R nu = 0, Prt = (R)P.Prt;
     if (P.closure == CM_CLOSURE_CONST) {
         nu = (R)P.nu;
+    } else if (P.closure == CM_CLOSURE_VREMAN) {
+        const R N2 = P.richardson ? (R)P.g * frcp(sg[GT][t]) * G[GT][2] : (R)0;
+        nu = vreman<R>(P, gr, S, N2);
     } else if (P.closure == CM_CLOSURE_SMAG || P.closure == CM_CLOSURE_MLP) {
         const R N2 = P.richardson || MLP ? (R)P.g * frcp(sg[GT][t]) * G[GT][2] : (R)0;
         nu = smagorinsky<R>(P, S, N2);
@@ -969,9 +1011,88 @@ __device__ __forceinline__ void face_load(const KParams& P, const R* __restrict_
     }
 }
 
+// Dissipative part of the Roe and HLLC numerical fluxes for dry air (Sect.
+// 3.1), written as D with n.F1* = (n.F1^- + n.F1^+)/2 - D/2 (Rusanov: D =
+// lambda (Y^+ - Y^-)).  FP64 from the two sides' thermodynamics; the
+// reference pressure cancels from D (it is continuous at the node).
+//
+// Roe: D = sum_k |lambda_k| alpha_k r_k over the two acoustic waves, the
+// entropy wave and the shear wave of the sqrt(rho)-weighted average state.
+// The internal energy counts from T_0, so rho e_tot + rho c_vd T_0 is the
+// ideal-gas total energy of the textbook Roe matrix: its sound speed is
+// c^2 = (R_d/c_vd)(H + c_vd T_0 - |u|^2/2 - g z), and the energy components
+// of the eigenvectors are the textbook ones less c_vd T_0.
+__device__ __forceinline__ void roe_dissipation(const Th& a, const Th& b, double phi, const double n[3], double D[5])
+{
+    const double sa = fsqrt(a.rho), sb = fsqrt(b.rho);
+    const double inv = frcp(sa + sb);
+    const double wa = sa * inv, wb = sb * inv, rh = sa * sb;
+    const double uh[3] = {wa * a.u + wb * b.u, wa * a.v + wb * b.v, wa * a.w + wb * b.w};
+    const double du[3] = {b.u - a.u, b.v - a.v, b.w - a.w};
+    const double Hh = wa * a.h + wb * b.h;
+    const double q2 = uh[0] * uh[0] + uh[1] * uh[1] + uh[2] * uh[2];
+    const double c2 = (Phys::Rd / Phys::cvd) * (Hh + Phys::cvd * Phys::T0 - 0.5 * q2 - phi);
+    const double ch = fsqrt(c2), ic2 = frcp(c2);
+    const double unh = uh[0] * n[0] + uh[1] * n[1] + uh[2] * n[2];
+    const double dun = du[0] * n[0] + du[1] * n[1] + du[2] * n[2];
+    const double dp = b.p - a.p;
+    const double a1 = 0.5 * (dp - rh * ch * dun) * ic2;
+    const double a2 = (b.rho - a.rho) - dp * ic2;
+    const double a3 = 0.5 * (dp + rh * ch * dun) * ic2;
+    const double l1 = fabs(unh - ch), l2 = fabs(unh), l3 = fabs(unh + ch);
+    const double w1 = l1 * a1, w2 = l2 * a2, w3 = l3 * a3, ws = l2 * rh;
+    D[0] = w1 + w2 + w3;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) D[1 + c] = (w1 + w2 + w3) * uh[c] + (w3 - w1) * ch * n[c] + ws * (du[c] - dun * n[c]);
+    D[4] = (w1 + w3) * Hh + (w3 - w1) * ch * unh + w2 * (0.5 * q2 + phi - Phys::cvd * Phys::T0) +
+           ws * (uh[0] * du[0] + uh[1] * du[1] + uh[2] * du[2] - unh * dun);
+}
+
+// HLLC with Davis wave-speed bounds S_a = min(u_n - c), S_b = max(u_n + c)
+// over the two sides and the contact speed S* from the jump conditions; the
+// flux of the side whose fan holds the node direction, f_K + S_K (U*_K -
+// U_K), with U*_K = rho_K (S_K - u_nK)/(S_K - S*) (1, u_K + (S* - u_nK) n,
+// e_K + (S* - u_nK)(S* + p_K/(rho_K (S_K - u_nK)))).  Returned as D = f^- +
+// f^+ - 2 F* (normal inviscid fluxes with the full pressure).
+__device__ __forceinline__ void hllc_dissipation(const Th& a, const Th& b, const double n[3], double D[5])
+{
+    const double una = a.u * n[0] + a.v * n[1] + a.w * n[2];
+    const double unb = b.u * n[0] + b.v * n[1] + b.w * n[2];
+    double fa[5], fb[5];
+    fa[0] = a.rho * una; fb[0] = b.rho * unb;
+    fa[1] = fa[0] * a.u + a.p * n[0]; fb[1] = fb[0] * b.u + b.p * n[0];
+    fa[2] = fa[0] * a.v + a.p * n[1]; fb[2] = fb[0] * b.v + b.p * n[1];
+    fa[3] = fa[0] * a.w + a.p * n[2]; fb[3] = fb[0] * b.w + b.p * n[2];
+    fa[4] = (a.rho * a.e + a.p) * una; fb[4] = (b.rho * b.e + b.p) * unb;
+    const double Sa = fmin(una - a.c, unb - b.c), Sb = fmax(una + a.c, unb + b.c);
+    double F[5];
+    if (Sa >= 0.0) {
+#pragma unroll
+        for (int v = 0; v < 5; ++v) F[v] = fa[v];
+    } else if (Sb <= 0.0) {
+#pragma unroll
+        for (int v = 0; v < 5; ++v) F[v] = fb[v];
+    } else {
+        const double ma = a.rho * (Sa - una), mb = b.rho * (Sb - unb);
+        const double Ss = (b.p - a.p + una * ma - unb * mb) * frcp(ma - mb);
+        const bool left = Ss >= 0.0;
+        const Th& k = left ? a : b;
+        const double S = left ? Sa : Sb, un = left ? una : unb, mk = left ? ma : mb;
+        const double fac = mk * frcp(S - Ss);
+        const double sh = Ss - un;
+        const double Uk[5] = {k.rho, k.rho * k.u, k.rho * k.v, k.rho * k.w, k.rho * k.e};
+        const double Us[5] = {fac, fac * (k.u + sh * n[0]), fac * (k.v + sh * n[1]), fac * (k.w + sh * n[2]),
+                              fac * (k.e + sh * (Ss + k.p * frcp(mk)))};
+#pragma unroll
+        for (int v = 0; v < 5; ++v) F[v] = (left ? fa[v] : fb[v]) + S * (Us[v] - Uk[v]);
+    }
+#pragma unroll
+    for (int v = 0; v < 5; ++v) D[v] = fa[v] + fb[v] - 2.0 * F[v];
+}
+
 // numerical flux of one face task; writes lift (n.F^- - n.F^*) over the
 // task's own-node entries of sG (the divergence is already done)
-template <typename R, bool MOIST, bool WARP, bool VISC>
+template <typename R, bool MOIST, bool WARP, bool VISC, int FLUX>
 __device__ __forceinline__ void face_flux(const KParams& P, const FaceLoad<R, MOIST, WARP, VISC>& f, int e, int ez,
                                           R (*sG)[NP], R (*sP)[BLOCK], R (*sY)[BLOCK])
 {
@@ -992,7 +1113,8 @@ __device__ __forceinline__ void face_flux(const KParams& P, const FaceLoad<R, MO
     // the FP64 dry and moist viscous cases (the same FP64 arithmetic as phase
     // A, with the moist temperature that phase A used, so the same values,
     // and 4 KB less LDS per block)
-    constexpr bool KEEP_P = tend_keeps_p<R, MOIST, VISC>();
+    // (Roe and HLLC need the own node's pressure and enthalpy: always recomputed)
+    constexpr bool KEEP_P = tend_keeps_p<R, MOIST, VISC>() && FLUX == 0;
     Th to;
     R um[3], cm;
     if (KEEP_P) {
@@ -1034,12 +1156,21 @@ __device__ __forceinline__ void face_flux(const KParams& P, const FaceLoad<R, MO
 #pragma unroll
             for (int v = 0; v < NV; ++v) fp[v] += fp2[v];
         }
-        const R unp = up[0] * n[0] + up[1] * n[1] + up[2] * n[2];
-        const R lm = fabs(unm) + cm, lp = fabs(unp) + (R)tp.c;
-        const R lam = lm > lp ? lm : lp;
+        if (FLUX == 0) {
+            const R unp = up[0] * n[0] + up[1] * n[1] + up[2] * n[2];
+            const R lm = fabs(unm) + cm, lp = fabs(unp) + (R)tp.c;
+            const R lam = lm > lp ? lm : lp;
 #pragma unroll
-        for (int v = 0; v < NV; ++v)
-            contrib[v] = (R)0.5 * (liftFm[v] - lift * fp[v]) - (R)0.5 * lift * lam * (Ym[v] - f.Yp[v]);
+            for (int v = 0; v < NV; ++v)
+                contrib[v] = (R)0.5 * (liftFm[v] - lift * fp[v]) - (R)0.5 * lift * lam * (Ym[v] - f.Yp[v]);
+        } else {
+            const double nd[3] = {(double)n[0], (double)n[1], (double)n[2]};
+            double D[5];
+            if (FLUX == 1) roe_dissipation(to, tp, P.g * node_z<WARP>(P, e, ez, own / (NQ * NQ), own), nd, D);
+            else hllc_dissipation(to, tp, nd, D);
+#pragma unroll
+            for (int v = 0; v < NV; ++v) contrib[v] = (R)0.5 * (liftFm[v] - lift * fp[v]) + (R)0.5 * lift * (R)D[v];
+        }
     } else {
         // reflecting ghost u+ = u- - 2 (n.u-) n with rho, rho e, rho q
         // mirrored: the Rusanov flux of (Y-, ghost) plus the prescribed wall
@@ -1083,9 +1214,26 @@ __device__ __forceinline__ void face_flux(const KParams& P, const FaceLoad<R, MO
                 f2s[NV - 1] = f2s[0];
             }
         }
+        if (FLUX == 0) {
 #pragma unroll
-        for (int v = 0; v < NV; ++v)
-            contrib[v] = liftFm[v] - lift * ((R)0.5 * (f1m[v] + f1g[v]) + (R)0.5 * lam * jumpY[v] + f2s[v]);
+            for (int v = 0; v < NV; ++v)
+                contrib[v] = liftFm[v] - lift * ((R)0.5 * (f1m[v] + f1g[v]) + (R)0.5 * lam * jumpY[v] + f2s[v]);
+        } else {
+            // the ghost: same density, pressure, enthalpy and sound speed,
+            // mirrored velocity
+            Th tg = tm;
+            const double und = tm.u * (double)n[0] + tm.v * (double)n[1] + tm.w * (double)n[2];
+            tg.u = tm.u - 2.0 * und * (double)n[0];
+            tg.v = tm.v - 2.0 * und * (double)n[1];
+            tg.w = tm.w - 2.0 * und * (double)n[2];
+            const double nd[3] = {(double)n[0], (double)n[1], (double)n[2]};
+            double D[5];
+            if (FLUX == 1) roe_dissipation(tm, tg, P.g * node_z<WARP>(P, e, ez, own / (NQ * NQ), own), nd, D);
+            else hllc_dissipation(tm, tg, nd, D);
+#pragma unroll
+            for (int v = 0; v < NV; ++v)
+                contrib[v] = liftFm[v] - lift * ((R)0.5 * (f1m[v] + f1g[v]) - (R)0.5 * (R)D[v] + f2s[v]);
+        }
     }
 #pragma unroll
     for (int v = 0; v < NV; ++v) sG[v * 3 + dir][own] = contrib[v];
@@ -1141,7 +1289,7 @@ __device__ __forceinline__ void own_load(const KParams& P, int e, int ez, int tt
 // (A = 0, dQ not read).  The second face task (t + BLOCK < 150) is loaded
 // just before it is needed: loaded earlier, its registers stay live through
 // the divergence and cost a wave per SIMD (measured slower).
-template <typename R, bool MOIST, bool WARP, bool VISC, int MODE>
+template <typename R, bool MOIST, bool WARP, bool VISC, int MODE, int FLUX>
 __device__ __forceinline__ void tend_element(const KParams& P, int e, int t,
                                              const OwnLoad<R, MOIST, WARP, VISC, MODE>& o,
                                              const FaceLoad<R, MOIST, WARP, VISC>& ft0, R dval,
@@ -1224,11 +1372,11 @@ __device__ __forceinline__ void tend_element(const KParams& P, int e, int t,
     // phase C: face tasks.  lift (n.F^- - n.F^*): n.F^- comes from the
     // contravariant flux already in LDS (lift n.F = side G^dir / (J w_N)).
     // The first task's loads were issued at kernel entry (ft0).
-    face_flux<R, MOIST, WARP, VISC>(P, ft0, e, ez, sG, sP, sY);
+    face_flux<R, MOIST, WARP, VISC, FLUX>(P, ft0, e, ez, sG, sP, sY);
     if (t + BLOCK < NFT) {
         FaceLoad<R, MOIST, WARP, VISC> ft1;
         face_load<R, MOIST, WARP, VISC>(P, F2, t + BLOCK, e, ex, ey, ez, ft1);
-        face_flux<R, MOIST, WARP, VISC>(P, ft1, e, ez, sG, sP, sY);
+        face_flux<R, MOIST, WARP, VISC, FLUX>(P, ft1, e, ez, sG, sP, sY);
     }
     __syncthreads();
 
@@ -1317,7 +1465,7 @@ __device__ __forceinline__ void tend_element(const KParams& P, int e, int t,
 
 // one element per block: own loads first, then the first face task's, so
 // that their latency overlaps phase A
-template <typename R, bool MOIST, bool WARP, bool VISC, int MODE>
+template <typename R, bool MOIST, bool WARP, bool VISC, int MODE, int FLUX>
 __global__ __launch_bounds__(BLOCK) void k_tend(const KParams P, const R* __restrict__ F2, R A, R B, R dt)
 {
     constexpr int NV = MOIST ? 6 : 5;
@@ -1331,7 +1479,7 @@ __global__ __launch_bounds__(BLOCK) void k_tend(const KParams P, const R* __rest
     own_load<R, MOIST, WARP, VISC, MODE>(P, e, ez, tt, o);
     FaceLoad<R, MOIST, WARP, VISC> ft0;
     face_load<R, MOIST, WARP, VISC>(P, F2, t, e, ex, ey, ez, ft0);
-    tend_element<R, MOIST, WARP, VISC, MODE>(P, e, t, o, ft0, dval, sG, sP, sY, sD, F2, A, B, dt);
+    tend_element<R, MOIST, WARP, VISC, MODE, FLUX>(P, e, t, o, ft0, dval, sG, sP, sY, sD, F2, A, B, dt);
 }
 
 #undef CM_TEND_LDS
@@ -1374,17 +1522,26 @@ static hipError_t launch_typed(cm_model* m, const void* Y, void* out, void* dQ, 
         prof_end(r, s);
     }
     cm_model::ProfRec* rt = prof_begin(m, 1, s);
-#define CM_TEND(V, MD)                                                                                      \
-    hipLaunchKernelGGL((k_tend<R, MOIST, WARP, V, MD>), grid, block, 0, s, P, F2, (R)A, (R)B, (R)dt)
+#define CM_TEND(V, MD, FL)                                                                                  \
+    hipLaunchKernelGGL((k_tend<R, MOIST, WARP, V, MD, FL>), grid, block, 0, s, P, F2, (R)A, (R)B, (R)dt)
+#define CM_TEND_MODES(V, FL)              \
+    do {                                  \
+        if (mode == 0) CM_TEND(V, 0, FL); \
+        else if (mode == 1) CM_TEND(V, 1, FL); \
+        else CM_TEND(V, 2, FL);           \
+    } while (0)
+    // Roe and HLLC are instantiated for dry models only (the model rejects them otherwise)
+    const int flux = MOIST ? 0 : m->desc.flux;
     if (visc) {
-        if (mode == 0) CM_TEND(true, 0);
-        else if (mode == 1) CM_TEND(true, 1);
-        else CM_TEND(true, 2);
+        if (flux == 1) CM_TEND_MODES(true, MOIST ? 0 : 1);
+        else if (flux == 2) CM_TEND_MODES(true, MOIST ? 0 : 2);
+        else CM_TEND_MODES(true, 0);
     } else {
-        if (mode == 0) CM_TEND(false, 0);
-        else if (mode == 1) CM_TEND(false, 1);
-        else CM_TEND(false, 2);
+        if (flux == 1) CM_TEND_MODES(false, MOIST ? 0 : 1);
+        else if (flux == 2) CM_TEND_MODES(false, MOIST ? 0 : 2);
+        else CM_TEND_MODES(false, 0);
     }
+#undef CM_TEND_MODES
 #undef CM_TEND
     prof_end(rt, s);
     if (moist_visc && mode != 0) m->tsel ^= 1;

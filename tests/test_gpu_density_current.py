@@ -21,11 +21,11 @@ PUBLISHED_DG_50M = 14767.0
 SPREAD_50M = (14535.0, 15027.0)
 
 
-def _run(c, Y, Yref, dt, nsteps, scheme="lsrk54"):
+def _run(c, Y, Yref, dt, nsteps, scheme="lsrk54", model=None):
     import torch
 
     g = B.Grid(c["grid"])
-    m = B.Model(g, c["model"], Yref)
+    m = B.Model(g, model or c["model"], Yref)
     Ya, Yb, dQ = m.new_state(Y), m.new_state(), m.new_state()
     t = 0.0
     for _ in range(nsteps):
@@ -84,5 +84,35 @@ def test_density_current_front_with_lsrk144_at_four_times_the_step():
     x = D.front_location(Yg, xyz)
     print("LSRK144 front at t = 900 s: %.1f m (difference from the published %.0f m: %+.1f m); max CFL %.3f; "
           "%.1f s wall" % (x, PUBLISHED_DG_50M, x - PUBLISHED_DG_50M, d["max_cfl"], wall))
+    assert d["n_nonfinite"] == 0
+    assert SPREAD_50M[0] <= x <= SPREAD_50M[1], x
+
+
+# the table's ClimateMachine entries at 50 m without a constant viscosity
+PUBLISHED_VREMAN_50M = 14739.0
+
+
+@pytest.mark.parametrize("variant", ["roe", "hllc", "vreman", "vreman_roe"])
+def test_density_current_front_closure_and_flux_variants(variant):
+    """Roe and HLLC with nu = 75 (the front of the Rusanov run), and the
+    Vreman closure (C_s = 0.18, no constant viscosity) with Rusanov and Roe:
+    fronts inside the 50 m spread of the table."""
+    c = W.case("density_current")
+    xyz = W.node_coords(c["grid"])
+    Y, Yref, dt0 = W.initial_state(c, xyz=xyz)
+    model = dict(c["model"])
+    if variant.startswith("vreman"):
+        model.update(closure="vreman", Cs=0.18, Prt=1.0 / 3.0)
+    if variant.endswith("roe"):
+        model["flux"] = "roe"
+    if variant == "hllc":
+        model["flux"] = "hllc"
+    nsteps = math.ceil(900.0 / dt0)
+    dt = 900.0 / nsteps
+    print("density current, %s: %d LSRK54 steps" % (variant, nsteps), flush=True)
+    Yg, d = _run(c, Y, Yref, dt, nsteps, model=model)
+    x = D.front_location(Yg, xyz)
+    ref = PUBLISHED_VREMAN_50M if variant.startswith("vreman") else PUBLISHED_DG_50M
+    print("%s front at t = 900 s: %.1f m (table entry %.0f m, difference %+.1f m)" % (variant, x, ref, x - ref))
     assert d["n_nonfinite"] == 0
     assert SPREAD_50M[0] <= x <= SPREAD_50M[1], x

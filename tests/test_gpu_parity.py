@@ -42,7 +42,27 @@ SMALL_CASES = {
     # moist inviscid: no carried temperature, saturation adjustment at every
     # node and face node of the tendency pass
     "moist_inviscid": _small("moist_64", (3, 2, 4), (300.0, 200.0, 2000.0)),
+    # Vreman closure with the Richardson factor, anisotropic elements
+    "vreman": _small("bubble_32", (5, 3, 7), (1000.0, 450.0, 1400.0), ),
+    # Vreman on a moist warped mesh
+    "vreman_moist_warped": _small("moist_64", (4, 2, 5), (1500.0, 500.0, 3000.0), topo=1, topo_a=300.0,
+                                  topo_xc=750.0, topo_h=200.0),
+    # Roe and HLLC numerical fluxes (dry): flat ragged mesh with Vreman, warped mesh, inviscid
+    "roe": _small("bubble_32", (5, 3, 7), (1000.0, 450.0, 1400.0)),
+    "hllc": _small("bubble_32", (5, 3, 7), (1000.0, 450.0, 1400.0)),
+    "roe_warped": _small("agnesi_96", (6, 2, 5), (1500.0, 500.0, 1600.0), topo_a=300.0, topo_xc=750.0,
+                         topo_h=200.0),
+    "hllc_warped": _small("agnesi_96", (6, 2, 5), (1500.0, 500.0, 1600.0), topo_a=300.0, topo_xc=750.0,
+                          topo_h=200.0),
+    "hllc_inviscid": _small("bubble_4", (3, 2, 2), (1500.0, 1000.0, 1000.0)),
 }
+SMALL_CASES["roe"]["model"].update(closure="vreman", Cs=0.18, flux="roe")
+SMALL_CASES["hllc"]["model"].update(closure="vreman", Cs=0.18, flux="hllc")
+SMALL_CASES["roe_warped"]["model"].update(flux="roe")
+SMALL_CASES["hllc_warped"]["model"].update(flux="hllc")
+SMALL_CASES["hllc_inviscid"]["model"].update(closure="none", flux="hllc")
+SMALL_CASES["vreman"]["model"].update(closure="vreman", Cs=0.18)
+SMALL_CASES["vreman_moist_warped"]["model"].update(closure="vreman", Cs=0.18)
 SMALL_CASES["single_periodic"]["model"]["g"] = 0.0
 SMALL_CASES["inviscid"]["model"]["closure"] = "none"
 SMALL_CASES["moist_inviscid"]["model"]["closure"] = "none"
@@ -98,7 +118,8 @@ def test_rhs_fp64_matches_oracle(dev, name):
     assert np.all(err < RHS_TOL), err
 
 
-@pytest.mark.parametrize("name", ["bubble_4", "moist", "warped", "moist_warped", "moist_inviscid"])
+@pytest.mark.parametrize("name", ["bubble_4", "moist", "warped", "moist_warped", "moist_inviscid", "vreman",
+                                  "vreman_moist_warped", "roe", "hllc", "roe_warped", "hllc_inviscid"])
 def test_lsrk_step_matches_oracle(dev, name):
     c = SMALL_CASES[name]
     Y, Yref = _state(c)
@@ -119,7 +140,7 @@ def test_lsrk_step_matches_oracle(dev, name):
     assert np.all(err < 1e-10), err
 
 
-@pytest.mark.parametrize("name", ["bubble_4", "smag_ragged", "moist", "warped", "moist_inviscid"])
+@pytest.mark.parametrize("name", ["bubble_4", "smag_ragged", "moist", "warped", "moist_inviscid", "roe", "hllc"])
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 def test_lsrk144_step_matches_oracle(dev, name, precision):
     """LSRK144 (fourteen fused stages, new state back in the input buffer)
@@ -283,3 +304,12 @@ def test_state_padding_contract(dev):
         assert np.all(np.isfinite(a[:, :, :125]))
         assert np.all(a[:, :, 125:128] == 0.0)
         assert np.all(np.isnan(a[:, :, 128:]))
+
+
+def test_moist_model_rejects_roe_and_hllc(dev):
+    c = SMALL_CASES["moist"]
+    g = B.Grid(c["grid"])
+    for flux in ("roe", "hllc"):
+        with pytest.raises(B.CMError) as ei:
+            B.Model(g, dict(c["model"], flux=flux))
+        assert ei.value.status == B.CM_ERR_UNSUPPORTED
