@@ -121,6 +121,10 @@ typedef struct {
     int subsidence;                    /* w_s = -w0 sin(pi z / z_top) acting on h_tot, q_t */
     double sub_w0, sub_ztop;
     int flux;                          /* inviscid numerical flux (Sect. 3.1): cm_flux */
+    int ice;                           /* moist: the saturation adjustment splits the condensate between
+                                          liquid and ice (Sect. 2.5, 2.7): liquid fraction 1 at and above
+                                          273.15 K, 0 at and below 233 K, linear between; saturation over
+                                          the mix weighted by it.  0: all liquid.  Ignored when dry. */
 } cm_model_desc;
 
 typedef struct {

@@ -58,7 +58,7 @@ class ModelDesc(C.Structure):
                 ("sp_ztop", C.c_double), ("sp_alpha", C.c_double), ("sp_gamma", C.c_double),
                 ("sp_u", C.c_double * 3), ("sfc_flux", C.c_int), ("theta_flux", C.c_double),
                 ("qt_flux", C.c_double), ("subsidence", C.c_int), ("sub_w0", C.c_double),
-                ("sub_ztop", C.c_double), ("flux", C.c_int)]
+                ("sub_ztop", C.c_double), ("flux", C.c_int), ("ice", C.c_int)]
 
 
 FLUXES = {"rusanov": 0, "roe": 1, "hllc": 2}
@@ -99,7 +99,13 @@ def _declare(L):
     L.cmref_pvsat.restype = C.c_double
     L.cmref_saturation_adjust.argtypes = [C.c_double, C.c_double, C.c_double,
                                           C.POINTER(C.c_double), C.POINTER(C.c_double)]
-    L.cmref_thermo_nodes.argtypes = [C.c_int, C.c_long, _P, _P, C.c_double, _P, _P, _P, _P]
+    L.cmref_thermo_nodes.argtypes = [C.c_int, C.c_int, C.c_long, _P, _P, C.c_double, _P, _P, _P, _P]
+    L.cmref_pvsat_ice.argtypes = [C.c_double]
+    L.cmref_pvsat_ice.restype = C.c_double
+    L.cmref_liquid_fraction.argtypes = [C.c_double]
+    L.cmref_liquid_fraction.restype = C.c_double
+    L.cmref_saturation_adjust_phase.argtypes = [C.c_double, C.c_double, C.c_double, C.c_int, C.POINTER(C.c_double),
+                                                C.POINTER(C.c_double), C.POINTER(C.c_double)]
     L.cmref_numflux_point.argtypes = [C.c_int, C.c_int, _P, _P, C.c_double, C.c_double, C.c_double, _P, _P]
     L.cmref_rusanov_point.argtypes = [C.c_int, _P, _P, C.c_double, C.c_double, C.c_double,
                                       C.c_double, C.c_double, _P, _P]
@@ -195,6 +201,7 @@ def _model_desc(m: dict) -> ModelDesc:
         d.sub_w0 = float(sb["w0"])
         d.sub_ztop = float(sb["z_top"])
     d.flux = FLUXES[m.get("flux", "rusanov")]
+    d.ice = int(bool(m.get("ice", False)))
     return d
 
 
@@ -322,13 +329,29 @@ def saturation_adjust(rho: float, qt: float, I: float):
     return T.value, ql.value
 
 
-def thermo_nodes(Y: np.ndarray, z: np.ndarray, g: float):
-    """T, p, q_l, theta_v at every node of a state [nvar, n]."""
+def pvsat_ice(T: float) -> float:
+    return lib().cmref_pvsat_ice(float(T))
+
+
+def liquid_fraction(T: float) -> float:
+    return lib().cmref_liquid_fraction(float(T))
+
+
+def saturation_adjust_phase(rho: float, qt: float, I: float, ice: bool = True):
+    """(T, q_l, q_i) of the equilibrium state, with or without the ice phase."""
+    T, ql, qi = C.c_double(), C.c_double(), C.c_double()
+    lib().cmref_saturation_adjust_phase(float(rho), float(qt), float(I), int(ice), C.byref(T), C.byref(ql),
+                                        C.byref(qi))
+    return T.value, ql.value, qi.value
+
+
+def thermo_nodes(Y: np.ndarray, z: np.ndarray, g: float, ice: bool = False):
+    """T, p, total condensate q_l + q_i, theta_v at every node of a state [nvar, n]."""
     Y = np.ascontiguousarray(Y, dtype=np.float64)
     nvar, n = Y.shape
     z = np.ascontiguousarray(z, dtype=np.float64)
     T, p, ql, thv = (np.zeros(n) for _ in range(4))
-    lib().cmref_thermo_nodes(nvar, n, Y, z, float(g), T, p, ql, thv)
+    lib().cmref_thermo_nodes(nvar, int(ice), n, Y, z, float(g), T, p, ql, thv)
     return T, p, ql, thv
 
 

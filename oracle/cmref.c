@@ -289,47 +289,95 @@ double cmref_pvsat(double T)
     return PTRIPLE * pow(T / TREF0, dc / RV) * exp((LV0 - dc * TREF0) / RV * (1.0 / TREF0 - 1.0 / T));
 }
 
-static double qvsat(double T, double rho) { return cmref_pvsat(T) / (rho * RV * T); }
+/* Ice (Sect. 2.5, Table 1): c_vi and L_f0, I_i0 = L_f0.  The paper
+ * apportions the condensate "according to temperature" without stating
+ * how; reading: liquid fraction 1 at and above the freezing point, 0 at and
+ * below the homogeneous-nucleation temperature, linear in between. */
+static const double CVI = 2100.0, LF0 = 0.3336e6;
+static const double T_FREEZE = 273.15, T_ICENUC = 233.0;
 
-/* Equilibrium internal energy I*(T; rho, q_t), liquid-only apportioning. */
-static double Istar(double T, double rho, double qt)
+/* Saturation vapour pressure over ice, Clausius-Clapeyron with constant
+ * heat capacities: L_s(T) = L_v0 + L_f0 + (c_pv - c_vi)(T - T_0); equal to
+ * the liquid one at the triple point T_0. */
+double cmref_pvsat_ice(double T)
 {
-    double qv = qvsat(T, rho);
+    double dc = CPV - CVI;
+    return PTRIPLE * pow(T / TREF0, dc / RV) * exp((LV0 + LF0 - dc * TREF0) / RV * (1.0 / TREF0 - 1.0 / T));
+}
+
+double cmref_liquid_fraction(double T)
+{
+    if (T >= T_FREEZE) return 1.0;
+    if (T <= T_ICENUC) return 0.0;
+    return (T - T_ICENUC) / (T_FREEZE - T_ICENUC);
+}
+
+/* saturation specific humidity over the condensate mix at T: the vapour
+ * pressure weighted by the liquid fraction (liquid only without ice) */
+static double qvsat(double T, double rho, int ice)
+{
+    double pv = cmref_pvsat(T);
+    if (ice) {
+        double lam = cmref_liquid_fraction(T);
+        pv = lam * pv + (1.0 - lam) * cmref_pvsat_ice(T);
+    }
+    return pv / (rho * RV * T);
+}
+
+/* Equilibrium internal energy I*(T; rho, q_t) (eq. total_internal_energy):
+ * vapour at saturation (or all of q_t), the rest condensed, split between
+ * liquid and ice by the liquid fraction (all liquid without ice). */
+static double Istar(double T, double rho, double qt, int ice)
+{
+    double qv = qvsat(T, rho, ice);
     if (qv > qt) qv = qt;
-    double ql = qt - qv;
-    return (1.0 - qt) * CVD * (T - TREF0) + qv * (CVV * (T - TREF0) + IV0) + ql * CVL * (T - TREF0);
+    double qc = qt - qv;
+    double lam = ice ? cmref_liquid_fraction(T) : 1.0;
+    double ql = lam * qc, qi = qc - ql;
+    return (1.0 - qt) * CVD * (T - TREF0) + qv * (CVV * (T - TREF0) + IV0) + ql * CVL * (T - TREF0) +
+           qi * (CVI * (T - TREF0) - LF0);
 }
 
 /* Saturation adjustment: the root T of I*(T) - I = 0.  The oracle brackets
  * it and bisects to adjacent doubles (a different algorithm from the GPU's
- * Newton iteration, converging to the same root). */
-void cmref_saturation_adjust(double rho, double qt, double I, double* T_out, double* ql_out)
+ * Newton iteration, converging to the same root).  ql and qi at the root. */
+void cmref_saturation_adjust_phase(double rho, double qt, double I, int ice, double* T_out, double* ql_out,
+                                   double* qi_out)
 {
     double Tu = TREF0 + (I - qt * IV0) / ((1.0 - qt) * CVD + qt * CVV);
-    if (qt <= qvsat(Tu, rho)) { *T_out = Tu; *ql_out = 0.0; return; }
-    double lo = Tu, hi = Tu + LV0 * qt / CVD;
-    while (Istar(hi, rho, qt) - I < 0.0) hi += LV0 * qt / CVD;
+    if (qt <= qvsat(Tu, rho, ice)) { *T_out = Tu; *ql_out = 0.0; *qi_out = 0.0; return; }
+    double step = (LV0 + (ice ? LF0 : 0.0)) * qt / CVD;
+    double lo = Tu, hi = Tu + step;
+    while (Istar(hi, rho, qt, ice) - I < 0.0) hi += step;
     for (int it = 0; it < 200; ++it) {
         double mid = 0.5 * (lo + hi);
         if (mid <= lo || mid >= hi) break;
-        if (Istar(mid, rho, qt) - I < 0.0) lo = mid; else hi = mid;
+        if (Istar(mid, rho, qt, ice) - I < 0.0) lo = mid; else hi = mid;
     }
     /* the two adjacent doubles bracket the root; take the one with the
      * smaller residual */
-    double rl = fabs(Istar(lo, rho, qt) - I), rh = fabs(Istar(hi, rho, qt) - I);
+    double rl = fabs(Istar(lo, rho, qt, ice) - I), rh = fabs(Istar(hi, rho, qt, ice) - I);
     double T = (rl <= rh) ? lo : hi;
-    double qv = qvsat(T, rho);
+    double qv = qvsat(T, rho, ice);
     if (qv > qt) qv = qt;
-    *T_out = T; *ql_out = qt - qv;
+    double lam = ice ? cmref_liquid_fraction(T) : 1.0;
+    *T_out = T; *ql_out = lam * (qt - qv); *qi_out = (qt - qv) - *ql_out;
+}
+
+/* liquid-only adjustment (the model without ice) */
+void cmref_saturation_adjust(double rho, double qt, double I, double* T_out, double* ql_out)
+{
+    double qi;
+    cmref_saturation_adjust_phase(rho, qt, I, 0, T_out, ql_out, &qi);
 }
 
 typedef struct {
     double rho, u[3], e, qt;
-    double T, p, c, h, thv, ql, qv, Rm;
+    double T, p, c, h, thv, ql, qi, qv, Rm;
 } prim_t;
 
 /* State -> primitive/thermodynamic quantities at one node (z = height). */
-static void thermo(const double* Yn, int nvar, double z, double g, prim_t* P)
+static void thermo(const double* Yn, int nvar, int ice, double z, double g, prim_t* P)
 {
     double rho = Yn[0];
     P->rho = rho;
@@ -338,30 +386,30 @@ static void thermo(const double* Yn, int nvar, double z, double g, prim_t* P)
     P->qt = (nvar > 5) ? Yn[5] / rho : 0.0;
     double ke = 0.5 * (P->u[0] * P->u[0] + P->u[1] * P->u[1] + P->u[2] * P->u[2]);
     double I = P->e - ke - g * z;
-    double qt = P->qt, T, ql;
-    if (nvar > 5) cmref_saturation_adjust(rho, qt, I, &T, &ql);
-    else { T = TREF0 + I / CVD; ql = 0.0; }
-    double qv = qt - ql;
+    double qt = P->qt, T, ql, qi;
+    if (nvar > 5) cmref_saturation_adjust_phase(rho, qt, I, ice, &T, &ql, &qi);
+    else { T = TREF0 + I / CVD; ql = 0.0; qi = 0.0; }
+    double qv = qt - ql - qi;
     double Rm = RD * (1.0 - qt) + RV * qv;
     double p = rho * Rm * T;
-    double cvm = (1.0 - qt) * CVD + qv * CVV + ql * CVL;
+    double cvm = (1.0 - qt) * CVD + qv * CVV + ql * CVL + qi * CVI;
     double gam = (cvm + Rm) / cvm;
-    P->T = T; P->ql = ql; P->qv = qv; P->Rm = Rm; P->p = p;
+    P->T = T; P->ql = ql; P->qi = qi; P->qv = qv; P->Rm = Rm; P->p = p;
     P->c = sqrt(gam * Rm * T);
     P->h = P->e + p / rho;
     P->thv = T * pow(P00 / p, RD / CPD) * Rm / RD;
 }
 
 /* Per-node thermodynamic diagnostics for tests: T, p, q_l, theta_v. */
-void cmref_thermo_nodes(int nvar, long n, const double* Y, const double* z, double g,
+void cmref_thermo_nodes(int nvar, int ice, long n, const double* Y, const double* z, double g,
                         double* T, double* p, double* ql, double* thv)
 {
     #pragma omp parallel for schedule(static)
     for (long i = 0; i < n; ++i) {
         double Yn[6];
         for (int v = 0; v < nvar; ++v) Yn[v] = Y[v * n + i];
-        prim_t P; thermo(Yn, nvar, z[i], g, &P);
-        T[i] = P.T; p[i] = P.p; ql[i] = P.ql; thv[i] = P.thv;
+        prim_t P; thermo(Yn, nvar, ice, z[i], g, &P);
+        T[i] = P.T; p[i] = P.p; ql[i] = P.ql + P.qi; thv[i] = P.thv;
     }
 }
 
@@ -500,8 +548,8 @@ void cmref_rusanov_point(int nvar, const double* Ym, const double* Yp, double zm
                          double g, double prm, double prp, const double* n, double* out)
 {
     prim_t Pm, Pp;
-    thermo(Ym, nvar, zm, g, &Pm);
-    thermo(Yp, nvar, zp, g, &Pp);
+    thermo(Ym, nvar, 0, zm, g, &Pm);
+    thermo(Yp, nvar, 0, zp, g, &Pp);
     rusanov(Ym, &Pm, prm, Yp, &Pp, prp, n, nvar, out);
 }
 
@@ -511,8 +559,8 @@ void cmref_numflux_point(int kind, int nvar, const double* Ym, const double* Yp,
                          const double* n, double* out)
 {
     prim_t Pm, Pp;
-    thermo(Ym, nvar, z, g, &Pm);
-    thermo(Yp, nvar, z, g, &Pp);
+    thermo(Ym, nvar, 0, z, g, &Pm);
+    thermo(Yp, nvar, 0, z, g, &Pp);
     numflux(kind, Ym, &Pm, pr, Yp, &Pp, pr, g * z, n, nvar, out);
 }
 
@@ -551,7 +599,7 @@ void* cmref_model_create(void* grid, const cmref_model_desc* m, const double* Yr
         for (long i = 0; i < nn; ++i) {
             double Yn[6];
             for (int v = 0; v < m->nvar; ++v) Yn[v] = Yref[v * nn + i];
-            prim_t P; thermo(Yn, m->nvar, z[i], m->g, &P);
+            prim_t P; thermo(Yn, m->nvar, m->ice, z[i], m->g, &P);
             M->pr[i] = P.p; M->rhor[i] = P.rho;
         }
     }
@@ -840,7 +888,7 @@ static void prepare(const model_t* M, const double* Y, work_t* W, gslots_t s)
     for (long n = 0; n < nn; ++n) {
         double Yn[6];
         for (int v = 0; v < nvar; ++v) Yn[v] = Y[v * nn + n];
-        thermo(Yn, nvar, z[n], M->m.g, &W->P[n]);
+        thermo(Yn, nvar, M->m.ice, z[n], M->m.g, &W->P[n]);
         const prim_t* P = &W->P[n];
         W->gvar[GU * nn + n] = P->u[0];
         W->gvar[GV * nn + n] = P->u[1];
@@ -940,7 +988,7 @@ static void rhs_eval(model_t* M, const double* Y, double* R, work_t* W)
                         for (int v = 0; v < nvar; ++v) Yp[v] = Ym[v];
                         double mn = Ym[1] * nv[0] + Ym[2] * nv[1] + Ym[3] * nv[2];
                         for (int c = 0; c < 3; ++c) Yp[1 + c] = Ym[1 + c] - 2.0 * mn * nv[c];
-                        prim_t Pp; thermo(Yp, nvar, z[n], m->g, &Pp);
+                        prim_t Pp; thermo(Yp, nvar, m->ice, z[n], m->g, &Pp);
                         numflux(m->flux, Ym, Pm, M->pr[n], Yp, &Pp, M->pr[n], m->g * z[n], nv, nvar, fstar);
                         for (int v = 0; v < nvar; ++v) f2star[v] = 0.0;
                         if (m->closure != 0 && m->sfc_flux && dir == 2 && side < 0) {

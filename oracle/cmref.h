@@ -40,6 +40,7 @@ typedef struct {
     int subsidence;
     double sub_w0, sub_ztop;
     int flux;           /* inviscid numerical flux: 0 Rusanov, 1 Roe, 2 HLLC (the last two dry only) */
+    int ice;            /* moist: condensate split between liquid and ice by temperature (else all liquid) */
 } cmref_model_desc;
 
 #endif

@@ -56,7 +56,7 @@ class ModelDesc(C.Structure):
                 ("sp_zs", C.c_double), ("sp_ztop", C.c_double), ("sp_alpha", C.c_double),
                 ("sp_gamma", C.c_double), ("sp_u", C.c_double * 3), ("sfc_flux", C.c_int),
                 ("theta_flux", C.c_double), ("qt_flux", C.c_double), ("subsidence", C.c_int),
-                ("sub_w0", C.c_double), ("sub_ztop", C.c_double), ("flux", C.c_int)]
+                ("sub_w0", C.c_double), ("sub_ztop", C.c_double), ("flux", C.c_int), ("ice", C.c_int)]
 
 
 class Diag(C.Structure):
@@ -216,6 +216,7 @@ def model_desc(m: dict, precision: str = "fp64") -> ModelDesc:
         d.subsidence = 1
         d.sub_w0, d.sub_ztop = float(sb["w0"]), float(sb["z_top"])
     d.flux = FLUXES[m.get("flux", "rusanov")]
+    d.ice = int(bool(m.get("ice", False)))
     return d
 
 

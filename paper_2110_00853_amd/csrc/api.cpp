@@ -345,6 +345,10 @@ cm_status cm_model_create(const cm_grid* g, const cm_model_desc* desc, const dou
     if (desc->precision != CM_FP64 && desc->precision != CM_FP32_BULK) { set_error("cm_model_create: bad precision"); return CM_ERR_ARG; }
     if (desc->closure < 0 || desc->closure > 4) { set_error("cm_model_create: bad closure"); return CM_ERR_ARG; }
     if (desc->flux < 0 || desc->flux > 2) { set_error("cm_model_create: bad numerical flux"); return CM_ERR_ARG; }
+    if (desc->ice && desc->nvar == 6 && desc->closure == CM_CLOSURE_MLP) {
+        set_error("cm_model_create: the learned closure is not built with the ice phase");
+        return CM_ERR_UNSUPPORTED;
+    }
     if (desc->flux != CM_FLUX_RUSANOV && desc->nvar != 5) {
         set_error("cm_model_create: Roe and HLLC fluxes are for dry models (nvar = 5) only");
         return CM_ERR_UNSUPPORTED;
@@ -457,6 +461,7 @@ cm_status cm_model_create(const cm_grid* g, const cm_model_desc* desc, const dou
     k.sp_inv = desc->sponge ? 1.0 / (desc->sp_ztop - desc->sp_zs) : 0.0;
     k.sfc_flux = desc->sfc_flux != 0; k.theta_flux = desc->theta_flux; k.qt_flux = desc->qt_flux;
     k.subsidence = desc->subsidence != 0; k.sub_w0 = desc->sub_w0; k.sub_ztop = desc->sub_ztop;
+    k.ice = desc->nvar == 6 && desc->ice != 0;
     k.sub_inv = desc->subsidence ? 1.0 / desc->sub_ztop : 0.0;
     k.nf = m->nf;
     k.nnf = g->n_elem * (desc->precision == CM_FP64 ? run_nodes<double>() : run_nodes<float>());
@@ -594,6 +599,10 @@ cm_status cm_model_closure_inputs(cm_model* m, const void* Y, double* feat, void
     if (m->desc.closure != CM_CLOSURE_SMAG || !m->desc.richardson) {
         set_error("cm_model_closure_inputs: needs the Smagorinsky closure with the Richardson factor");
         return CM_ERR_STATE;
+    }
+    if (m->kp.ice) {
+        set_error("cm_model_closure_inputs: not built with the ice phase");
+        return CM_ERR_UNSUPPORTED;
     }
     CM_TRY_HIP(hipSetDevice(m->grid->device), "hipSetDevice");
     m->kp.feat_out = feat;

@@ -28,6 +28,9 @@ struct Phys {
     static constexpr double cpl = cvl;
     static constexpr double Iv0 = Lv0 - Rv * T0;
     static constexpr double kappa = Rd / cpd;
+    // ice (Table 1: c_vi, L_f0 = I_i0) and the liquid-fraction ramp
+    static constexpr double cvi = 2100.0, Lf0 = 0.3336e6;
+    static constexpr double T_freeze = 273.15, T_icenuc = 233.0;
 };
 
 // Everything the kernels need, passed by value.
@@ -83,6 +86,7 @@ struct KParams {
     double theta_flux, qt_flux;
     int subsidence;
     double sub_w0, sub_ztop, sub_inv;
+    int ice;  // moist: condensate split between liquid and ice by temperature
     int nf;                     // words per node of the stored diffusive flux
     int64_t nnf;                // stride of one F2 word: n_elem x F2_RUN (padded element runs)
     // learned closure

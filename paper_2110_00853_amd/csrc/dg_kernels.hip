@@ -27,6 +27,7 @@
 #include "cm_impl.hpp"
 #include "fp64_math.hpp"
 #include "mlp_common.hpp"
+#include "thermo.hpp"
 
 namespace cm {
 
@@ -133,160 +134,6 @@ __device__ __forceinline__ int ref_index(const KParams& P, int e, int ez, int k,
 }
 
 // ---------------------------------------------------------------------------
-// thermodynamics (Sects. 2.4-2.6), always FP64
-// ---------------------------------------------------------------------------
-struct Th {
-    double rho, u, v, w, e, qt, T, p, c, h, qv, ql, Rm;
-};
-
-__device__ __forceinline__ double pvsat(double T)
-{
-    // Clausius-Clapeyron integrated with constant heat capacities:
-    // p* = p_tr (T/T0)^((c_pv-c_pl)/R_v) exp((L_v0-(c_pv-c_pl)T0)/R_v (1/T0 - 1/T))
-    constexpr double dc = Phys::cpv - Phys::cpl;
-    return Phys::ptr * exp_fin(dc / Phys::Rv * ln_pos(T * (1.0 / Phys::T0)) +
-                               (Phys::Lv0 - dc * Phys::T0) / Phys::Rv * (1.0 / Phys::T0 - frcp(T)));
-}
-
-// Saturation adjustment: T from (rho, q_t, I) by Newton iteration with the
-// analytic derivative dI*/dT; unsaturated air returns T_u directly.
-__device__ __forceinline__ void saturation_adjust(double rho, double qt, double I, double& T, double& ql)
-{
-    const double Tu = Phys::T0 + (I - qt * Phys::Iv0) * frcp((1.0 - qt) * Phys::cvd + qt * Phys::cvv);
-    const double irv = frcp(rho * Phys::Rv);
-    const double qvs_u = pvsat(Tu) * irv * frcp(Tu);
-    if (qt <= qvs_u) { T = Tu; ql = 0.0; return; }
-    double Tn = Tu;
-    for (int it = 0; it < 20; ++it) {
-        const double iT = frcp(Tn);
-        const double qv = pvsat(Tn) * irv * iT;
-        const double dT = Tn - Phys::T0;
-        const double f = (1.0 - qt) * Phys::cvd * dT + qv * (Phys::cvv * dT + Phys::Iv0) + (qt - qv) * Phys::cvl * dT - I;
-        const double Lv = Phys::Lv0 + (Phys::cpv - Phys::cpl) * dT;
-        const double dqv = qv * (Lv * (1.0 / Phys::Rv) * iT * iT - iT);
-        const double cvm = (1.0 - qt) * Phys::cvd + qv * Phys::cvv + (qt - qv) * Phys::cvl;
-        const double fp = cvm + dqv * (Phys::Iv0 + (Phys::cvv - Phys::cvl) * dT);
-        const double step = f * frcp(fp);
-        Tn -= step;
-        if (fabs(step) <= 1e-13 * Tn) break;
-    }
-    double qv = pvsat(Tn) * irv * frcp(Tn);
-    qv = qv < qt ? qv : qt;
-    T = Tn;
-    ql = qt - qv;
-}
-
-// q_l of a moist state at its adjusted temperature T: the adjustment's own
-// q_v = min(q_t, q_v*(T)), for the unsaturated branch as well
-__device__ __forceinline__ double moist_ql(double rho, double rq, double T)
-{
-    const double qt = rq * frcp(rho);
-    const double irv = frcp(rho * Phys::Rv);
-    double qv = pvsat(T) * irv * frcp(T);
-    qv = qv < qt ? qv : qt;
-    return qt - qv;
-}
-
-// the moist recovery when T and q_l are already known (the saturation
-// adjustment of the same state earlier in the stage or step): the same
-// values thermo() gives, without the Newton iteration or q_v*
-__device__ __forceinline__ void thermo_moist_T(double rho, double mx, double my, double mz, double re, double rq,
-                                               double T, double ql, Th& o)
-{
-    const double ir = frcp(rho);
-    o.rho = rho;
-    o.u = mx * ir; o.v = my * ir; o.w = mz * ir;
-    o.e = re * ir;
-    o.qt = rq * ir;
-    o.T = T;
-    o.ql = ql;
-    o.qv = o.qt - o.ql;  // as thermo() forms it
-    o.Rm = Phys::Rd * (1.0 - o.qt) + Phys::Rv * o.qv;
-    const double cvm = (1.0 - o.qt) * Phys::cvd + o.qv * Phys::cvv + o.ql * Phys::cvl;
-    o.p = rho * o.Rm * o.T;
-    o.c = fsqrt((cvm + o.Rm) * frcp(cvm) * o.Rm * o.T);
-    o.h = o.e + o.p * ir;
-}
-
-// temperature of a moist state by the saturation adjustment, Newton
-// started from Tg when that is above T_u (a nearby solution: the previous
-// stage's temperature of the same node); unsaturated air returns T_u.  ql
-// is the liquid fraction at the returned temperature, as moist_ql gives it
-// (zero for unsaturated air without a second q_v* evaluation: there
-// moist_ql's minimum picks q_t)
-__device__ __forceinline__ double moist_T_guess(double rho, double mx, double my, double mz, double re, double rq,
-                                                double z, double g, double Tg, double& ql)
-{
-    const double ir = frcp(rho);
-    const double u = mx * ir, v = my * ir, w = mz * ir;
-    const double I = re * ir - 0.5 * (u * u + v * v + w * w) - g * z;
-    const double qt = rq * ir;
-    const double Tu = Phys::T0 + (I - qt * Phys::Iv0) * frcp((1.0 - qt) * Phys::cvd + qt * Phys::cvv);
-    const double irv = frcp(rho * Phys::Rv);
-    const double qvs_u = pvsat(Tu) * irv * frcp(Tu);
-    ql = 0.0;
-    if (qt <= qvs_u) return Tu;
-    double Tn = Tg > Tu ? Tg : Tu;
-    for (int it = 0; it < 20; ++it) {
-        const double iT = frcp(Tn);
-        const double qv = pvsat(Tn) * irv * iT;
-        const double dT = Tn - Phys::T0;
-        const double f = (1.0 - qt) * Phys::cvd * dT + qv * (Phys::cvv * dT + Phys::Iv0) + (qt - qv) * Phys::cvl * dT - I;
-        const double Lv = Phys::Lv0 + (Phys::cpv - Phys::cpl) * dT;
-        const double dqv = qv * (Lv * (1.0 / Phys::Rv) * iT * iT - iT);
-        const double cvm = (1.0 - qt) * Phys::cvd + qv * Phys::cvv + (qt - qv) * Phys::cvl;
-        const double fp = cvm + dqv * (Phys::Iv0 + (Phys::cvv - Phys::cvl) * dT);
-        const double step = f * frcp(fp);
-        Tn -= step;
-        if (fabs(step) <= 1e-13 * Tn) break;
-    }
-    ql = moist_ql(rho, rq, Tn);
-    return Tn;
-}
-
-template <bool MOIST>
-__device__ __forceinline__ void thermo(double rho, double mx, double my, double mz, double re, double rq, double z,
-                                       double g, Th& o)
-{
-    const double ir = frcp(rho);
-    o.rho = rho;
-    o.u = mx * ir; o.v = my * ir; o.w = mz * ir;
-    o.e = re * ir;
-    const double I = o.e - 0.5 * (o.u * o.u + o.v * o.v + o.w * o.w) - g * z;
-    if (MOIST) {
-        o.qt = rq * ir;
-        saturation_adjust(rho, o.qt, I, o.T, o.ql);
-        o.qv = o.qt - o.ql;
-        o.Rm = Phys::Rd * (1.0 - o.qt) + Phys::Rv * o.qv;
-        const double cvm = (1.0 - o.qt) * Phys::cvd + o.qv * Phys::cvv + o.ql * Phys::cvl;
-        o.p = rho * o.Rm * o.T;
-        o.c = fsqrt((cvm + o.Rm) * frcp(cvm) * o.Rm * o.T);
-    } else {
-        o.qt = 0.0; o.ql = 0.0; o.qv = 0.0;
-        o.T = Phys::T0 + I * (1.0 / Phys::cvd);
-        o.Rm = Phys::Rd;
-        o.p = rho * Phys::Rd * o.T;
-        o.c = fsqrt(Phys::cpd / Phys::cvd * Phys::Rd * o.T);
-    }
-    o.h = o.e + o.p * ir;
-}
-
-// virtual potential temperature theta_v = T (p0/p)^(R_d/c_pd) R_m/R_d, in the
-// storage precision: FP64, or with FP32-bulk storage in FP32 from the FP64
-// T and p (it only enters the Richardson number; pressure and temperature
-// themselves stay FP64)
-template <typename R> __device__ __forceinline__ R theta_v(const Th& o);
-template <> __device__ __forceinline__ double theta_v<double>(const Th& o)
-{
-    return o.T * exp_fin(Phys::kappa * ln_pos(Phys::p0 * frcp(o.p))) * (o.Rm * (1.0 / Phys::Rd));
-}
-template <> __device__ __forceinline__ float theta_v<float>(const Th& o)
-{
-    const float x = (float)(Phys::p0 / o.p);
-    return (float)o.T * __expf((float)Phys::kappa * __logf(x)) * (float)(o.Rm * (1.0 / Phys::Rd));
-}
-
-// ---------------------------------------------------------------------------
 // reference state: background pushed through the same thermodynamics
 // ---------------------------------------------------------------------------
 template <bool MOIST>
@@ -306,7 +153,7 @@ __global__ void k_reference(KParams P, const double* __restrict__ Yr, int64_t nr
     }
     Th th;
     thermo<MOIST>(Yr[r], Yr[nref + r], Yr[2 * nref + r], Yr[3 * nref + r], Yr[4 * nref + r],
-                  MOIST ? Yr[5 * nref + r] : 0.0, z, P.g, th);
+                  MOIST ? Yr[5 * nref + r] : 0.0, z, P.g, P.ice, th);
     pr[r] = th.p;
     rhor[r] = th.rho;
 }
@@ -542,7 +389,7 @@ template <typename R, bool MOIST>
 struct GradLoad {
     int dir, sd, own, nbl, en, ezn;
     R Yp[MOIST ? 6 : 5];
-    double Tq, qlq;  // moist, T_given: the neighbour node's T and q_l
+    double Tq, qcq;  // moist, T_given: the neighbour node's T and condensate
 };
 
 template <typename R, bool MOIST>
@@ -557,12 +404,12 @@ __device__ __forceinline__ void grad_load(const KParams& P, int task, int e, int
     if (MOIST && P.T_given) {
         const int64_t nt = (int64_t)(f.en >= 0 ? f.en : e) * run_nodes<double>() + f.nbl;
         f.Tq = P.Tn[nt];
-        f.qlq = P.Tn[P.nnT + nt];
+        f.qcq = P.Tn[P.nnT + nt];
     }
 }
 
 // lift * (g* - g^-) of one face task into sL[q][task]
-template <typename R, bool MOIST, bool WARP>
+template <typename R, bool MOIST, bool WARP, bool ICE>
 __device__ __forceinline__ void grad_face(const KParams& P, const GradLoad<R, MOIST>& f, int task, int e,
                                           bool need_thv, bool thv_all_faces, R (*sg)[BLOCK], R (*sL)[NFT])
 {
@@ -573,10 +420,10 @@ __device__ __forceinline__ void grad_face(const KParams& P, const GradLoad<R, MO
         Th tp;
         if (MOIST && P.T_given)
             thermo_moist_T((double)f.Yp[0], (double)f.Yp[1], (double)f.Yp[2], (double)f.Yp[3], (double)f.Yp[4],
-                           (double)f.Yp[MOIST ? 5 : 0], f.Tq, f.qlq, tp);
+                           (double)f.Yp[MOIST ? 5 : 0], f.Tq, f.qcq, ICE, tp);
         else
             thermo<MOIST>((double)f.Yp[0], (double)f.Yp[1], (double)f.Yp[2], (double)f.Yp[3], (double)f.Yp[4],
-                          MOIST ? (double)f.Yp[5] : 0.0, node_z<WARP>(P, f.en, f.ezn, f.nbl / (NQ * NQ), f.nbl), P.g, tp);
+                          MOIST ? (double)f.Yp[5] : 0.0, node_z<WARP>(P, f.en, f.ezn, f.nbl / (NQ * NQ), f.nbl), P.g, ICE, tp);
         R gp[NG];
         gp[0] = (R)tp.u; gp[1] = (R)tp.v; gp[2] = (R)tp.w; gp[3] = (R)tp.h;
         if (MOIST) gp[GQ] = (R)tp.qt;
@@ -604,7 +451,9 @@ __device__ __forceinline__ void grad_face(const KParams& P, const GradLoad<R, MO
 // gradient + closure pass
 // ---------------------------------------------------------------------------
 // FEAT: also export the closure inputs per node (P.feat_out), for training
-template <typename R, bool MOIST, bool WARP, bool MLP, bool FEAT = false>
+// ICE: the moist thermodynamics with the ice phase (a compile-time variant,
+// so that the liquid-only kernels keep their registers)
+template <typename R, bool MOIST, bool WARP, bool MLP, bool FEAT = false, bool ICE = false>
 __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(MLP || MOIST || WARP || FEAT ? 1 : CM_GRAD_WPE))) void k_grad(const KParams P)
 {
     constexpr int NV = MOIST ? 6 : 5;
@@ -646,29 +495,29 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(MLP || MO
         if (MOIST && P.T_given)
             thermo_moist_T(Yv[0], Yv[1], Yv[2], Yv[3], Yv[4], Yv[MOIST ? 5 : 0],
                            P.Tn[(int64_t)e * run_nodes<double>() + tt],
-                           P.Tn[P.nnT + (int64_t)e * run_nodes<double>() + tt], th);
+                           P.Tn[P.nnT + (int64_t)e * run_nodes<double>() + tt], ICE, th);
         else
-            thermo<MOIST>(Yv[0], Yv[1], Yv[2], Yv[3], Yv[4], MOIST ? Yv[5] : 0.0, node_z<WARP>(P, e, ez, k, tt), P.g, th);
+            thermo<MOIST>(Yv[0], Yv[1], Yv[2], Yv[3], Yv[4], MOIST ? Yv[5] : 0.0, node_z<WARP>(P, e, ez, k, tt), P.g, ICE, th);
     }
     sg[0][t] = (R)th.u; sg[1][t] = (R)th.v; sg[2][t] = (R)th.w; sg[3][t] = (R)th.h;
     if (MOIST) sg[GQ][t] = (R)th.qt;
-    // the tendency pass of this stage takes T and q_l from here instead of
+    // the tendency pass of this stage takes T and the condensate from here instead of
     // repeating the saturation adjustment (every lane stores: whole lines)
     if (MOIST && !P.T_given) {
         const int64_t nt = (int64_t)e * run_nodes<double>() + t;
         __builtin_nontemporal_store(act ? th.T : 0.0, &P.Tn[nt]);
-        __builtin_nontemporal_store(act ? th.ql : 0.0, &P.Tn[P.nnT + nt]);
+        __builtin_nontemporal_store(act ? th.qc : 0.0, &P.Tn[P.nnT + nt]);
     }
     sg[GT][t] = need_thv ? theta_v<R>(th) : (R)0;
     __syncthreads();
 
     // phase B: face tasks -> lift * (g* - g^-), centred g* (walls: 0); the
     // first task's neighbour state was loaded at kernel entry
-    grad_face<R, MOIST, WARP>(P, g0, t, e, need_thv, WARP || FEAT, sg, sL);
+    grad_face<R, MOIST, WARP, ICE>(P, g0, t, e, need_thv, WARP || FEAT, sg, sL);
     if (t + BLOCK < 150) {
         GradLoad<R, MOIST> g1;
         grad_load<R, MOIST>(P, t + BLOCK, e, ex, ey, ez, g1);
-        grad_face<R, MOIST, WARP>(P, g1, t + BLOCK, e, need_thv, WARP || FEAT, sg, sL);
+        grad_face<R, MOIST, WARP, ICE>(P, g1, t + BLOCK, e, need_thv, WARP || FEAT, sg, sL);
     }
     __syncthreads();
 
@@ -964,8 +813,8 @@ struct FaceLoad {
     int dir, sd, own, nbl, en, ezn;
     R Yp[NV], wp[VISC ? NWF : 1];
     double prp;
-    double Tq, qlq;  // moist viscous: T and q_l of the neighbour node (of this node on a wall)
-    double To, qlo;  // moist viscous: T and q_l of the own node
+    double Tq, qcq;  // moist viscous: T and condensate of the neighbour node (of this node on a wall)
+    double To, qco;  // moist viscous: T and condensate of the own node
 };
 
 template <typename R, bool MOIST, bool WARP, bool VISC>
@@ -1004,10 +853,10 @@ __device__ __forceinline__ void face_load(const KParams& P, const R* __restrict_
     if (MOIST && VISC) {
         const int64_t nt = (int64_t)eo * run_nodes<double>() + rn;
         f.Tq = P.Tn[nt];
-        f.qlq = P.Tn[P.nnT + nt];
+        f.qcq = P.Tn[P.nnT + nt];
         const int64_t no = (int64_t)e * run_nodes<double>() + f.own;
         f.To = P.Tn[no];
-        f.qlo = P.Tn[P.nnT + no];
+        f.qco = P.Tn[P.nnT + no];
     }
 }
 
@@ -1092,10 +941,14 @@ __device__ __forceinline__ void hllc_dissipation(const Th& a, const Th& b, const
 
 // numerical flux of one face task; writes lift (n.F^- - n.F^*) over the
 // task's own-node entries of sG (the divergence is already done)
-template <typename R, bool MOIST, bool WARP, bool VISC, int FLUX>
+template <typename R, bool MOIST, bool WARP, bool VISC, int VAR>
 __device__ __forceinline__ void face_flux(const KParams& P, const FaceLoad<R, MOIST, WARP, VISC>& f, int e, int ez,
                                           R (*sG)[NP], R (*sP)[BLOCK], R (*sY)[BLOCK])
 {
+    // VAR: the numerical flux of a dry model (0 Rusanov, 1 Roe, 2 HLLC); for
+    // a moist model 1 selects the ice phase
+    constexpr int FLUX = MOIST ? 0 : VAR;
+    constexpr bool ICE = MOIST && VAR == 1;
     constexpr int NV = MOIST ? 6 : 5;
     const int64_t nn = P.nn;
     const int dir = f.dir, sd = f.sd, own = f.own, nbl = f.nbl, en = f.en;
@@ -1123,10 +976,10 @@ __device__ __forceinline__ void face_flux(const KParams& P, const FaceLoad<R, MO
     } else {
         if (MOIST)
             thermo_moist_T((double)Ym[0], (double)Ym[1], (double)Ym[2], (double)Ym[3], (double)Ym[4],
-                           (double)Ym[NV - 1], f.To, f.qlo, to);
+                           (double)Ym[NV - 1], f.To, f.qco, ICE, to);
         else
             thermo<false>((double)Ym[0], (double)Ym[1], (double)Ym[2], (double)Ym[3], (double)Ym[4], 0.0,
-                          node_z<WARP>(P, e, ez, own / (NQ * NQ), own), P.g, to);
+                          node_z<WARP>(P, e, ez, own / (NQ * NQ), own), P.g, ICE, to);
         um[0] = (R)to.u; um[1] = (R)to.v; um[2] = (R)to.w;
         cm = (R)to.c;
     }
@@ -1141,10 +994,10 @@ __device__ __forceinline__ void face_flux(const KParams& P, const FaceLoad<R, MO
         Th tp;
         if (MOIST && VISC)
             thermo_moist_T((double)f.Yp[0], (double)f.Yp[1], (double)f.Yp[2], (double)f.Yp[3], (double)f.Yp[4],
-                           (double)f.Yp[NV - 1], f.Tq, f.qlq, tp);
+                           (double)f.Yp[NV - 1], f.Tq, f.qcq, ICE, tp);
         else
             thermo<MOIST>((double)f.Yp[0], (double)f.Yp[1], (double)f.Yp[2], (double)f.Yp[3], (double)f.Yp[4],
-                          MOIST ? (double)f.Yp[NV - 1] : 0.0, node_z<WARP>(P, en, ezn, kn, nbl), P.g, tp);
+                          MOIST ? (double)f.Yp[NV - 1] : 0.0, node_z<WARP>(P, en, ezn, kn, nbl), P.g, ICE, tp);
         const R up[3] = {(R)tp.u, (R)tp.v, (R)tp.w};
         R fp[NV];
         flux1_normal<R, MOIST>((R)tp.rho, up, (R)(tp.p - f.prp), (R)(tp.rho * tp.e + tp.p), (R)(tp.rho * tp.qt), n,
@@ -1176,17 +1029,17 @@ __device__ __forceinline__ void face_flux(const KParams& P, const FaceLoad<R, MO
         // mirrored: the Rusanov flux of (Y-, ghost) plus the prescribed wall
         // diffusive flux
         // (without KEEP_P, to already holds this node's thermodynamics; on a
-        // wall the neighbour slot's T and q_l are this node's)
+        // wall the neighbour slot's T and condensate are this node's)
         Th tm = to;
         if (KEEP_P && !MOIST)
             thermo<false>((double)Ym[0], (double)Ym[1], (double)Ym[2], (double)Ym[3], (double)Ym[4], 0.0,
-                          node_z<WARP>(P, e, ez, own / (NQ * NQ), own), P.g, tm);
+                          node_z<WARP>(P, e, ez, own / (NQ * NQ), own), P.g, ICE, tm);
         else if (KEEP_P && MOIST && VISC)
             thermo_moist_T((double)Ym[0], (double)Ym[1], (double)Ym[2], (double)Ym[3], (double)Ym[4],
-                           (double)Ym[NV - 1], f.Tq, f.qlq, tm);
+                           (double)Ym[NV - 1], f.Tq, f.qcq, ICE, tm);
         else if (MOIST && !VISC)
             thermo<MOIST>((double)Ym[0], (double)Ym[1], (double)Ym[2], (double)Ym[3], (double)Ym[4],
-                          (double)Ym[NV - 1], node_z<WARP>(P, e, ez, own / (NQ * NQ), own), P.g, tm);
+                          (double)Ym[NV - 1], node_z<WARP>(P, e, ez, own / (NQ * NQ), own), P.g, ICE, tm);
         const R rho = Ym[0];
         const R pp = (R)(tm.p - f.prp), ep = (R)(tm.rho * tm.e + tm.p);
         const R rq = MOIST ? Ym[NV - 1] : (R)0;
@@ -1249,7 +1102,7 @@ struct OwnLoad {
     R w[VISC ? NWS : 1];
     R Jam[WARP ? 10 : 1];  // J a^d (9) and 1/J
     double pr, rr;
-    double T, ql;  // moist viscous: T and q_l from earlier in the stage
+    double T, qc;  // moist viscous: T and condensate from earlier in the stage
 };
 
 template <typename R, bool MOIST, bool WARP, bool VISC, int MODE>
@@ -1274,7 +1127,7 @@ __device__ __forceinline__ void own_load(const KParams& P, int e, int ez, int tt
     o.rr = P.rhor[ri];
     if (MOIST && VISC) {
         o.T = P.Tn[(int64_t)e * run_nodes<double>() + tt];
-        o.ql = P.Tn[P.nnT + (int64_t)e * run_nodes<double>() + tt];
+        o.qc = P.Tn[P.nnT + (int64_t)e * run_nodes<double>() + tt];
     }
     if (WARP) {
         const R* m = (const R*)P.metrics;
@@ -1289,13 +1142,14 @@ __device__ __forceinline__ void own_load(const KParams& P, int e, int ez, int tt
 // (A = 0, dQ not read).  The second face task (t + BLOCK < 150) is loaded
 // just before it is needed: loaded earlier, its registers stay live through
 // the divergence and cost a wave per SIMD (measured slower).
-template <typename R, bool MOIST, bool WARP, bool VISC, int MODE, int FLUX>
+template <typename R, bool MOIST, bool WARP, bool VISC, int MODE, int VAR>
 __device__ __forceinline__ void tend_element(const KParams& P, int e, int t,
                                              const OwnLoad<R, MOIST, WARP, VISC, MODE>& o,
                                              const FaceLoad<R, MOIST, WARP, VISC>& ft0, R dval,
                                              R (*sG)[NP], R (*sP)[BLOCK], R (*sY)[BLOCK], R* sD,
                                              const R* __restrict__ F2, R A, R B, R dt)
 {
+    constexpr bool ICE = MOIST && VAR == 1;
     constexpr int NV = MOIST ? 6 : 5;
     constexpr int NW = MOIST ? 12 : 9;
     const bool act = t < NP;
@@ -1308,10 +1162,10 @@ __device__ __forceinline__ void tend_element(const KParams& P, int e, int t,
         Th th;
         if (MOIST && VISC)
             thermo_moist_T((double)o.Yr[0], (double)o.Yr[1], (double)o.Yr[2], (double)o.Yr[3], (double)o.Yr[4],
-                           (double)o.Yr[NV - 1], o.T, o.ql, th);
+                           (double)o.Yr[NV - 1], o.T, o.qc, ICE, th);
         else
             thermo<MOIST>((double)o.Yr[0], (double)o.Yr[1], (double)o.Yr[2], (double)o.Yr[3], (double)o.Yr[4],
-                          MOIST ? (double)o.Yr[NV - 1] : 0.0, z, P.g, th);
+                          MOIST ? (double)o.Yr[NV - 1] : 0.0, z, P.g, ICE, th);
         rho_d = th.rho;
         mom_d[0] = (double)o.Yr[1]; mom_d[1] = (double)o.Yr[2]; mom_d[2] = (double)o.Yr[3];
         R F[NV][3];
@@ -1372,11 +1226,11 @@ __device__ __forceinline__ void tend_element(const KParams& P, int e, int t,
     // phase C: face tasks.  lift (n.F^- - n.F^*): n.F^- comes from the
     // contravariant flux already in LDS (lift n.F = side G^dir / (J w_N)).
     // The first task's loads were issued at kernel entry (ft0).
-    face_flux<R, MOIST, WARP, VISC, FLUX>(P, ft0, e, ez, sG, sP, sY);
+    face_flux<R, MOIST, WARP, VISC, VAR>(P, ft0, e, ez, sG, sP, sY);
     if (t + BLOCK < NFT) {
         FaceLoad<R, MOIST, WARP, VISC> ft1;
         face_load<R, MOIST, WARP, VISC>(P, F2, t + BLOCK, e, ex, ey, ez, ft1);
-        face_flux<R, MOIST, WARP, VISC, FLUX>(P, ft1, e, ez, sG, sP, sY);
+        face_flux<R, MOIST, WARP, VISC, VAR>(P, ft1, e, ez, sG, sP, sY);
     }
     __syncthreads();
 
@@ -1445,12 +1299,12 @@ __device__ __forceinline__ void tend_element(const KParams& P, int e, int t,
     if (MOIST && VISC && MODE != 0 && P.Tnext != nullptr) {
         // temperature of the output state, from the input state's as the
         // Newton start: the next stage's passes read it instead of solving
-        double qlnew;
+        double qcnew;
         const double Tnew = moist_T_guess((double)Rv[0], (double)Rv[1], (double)Rv[2], (double)Rv[3],
-                                          (double)Rv[4], (double)Rv[NV - 1], z, P.g, o.T, qlnew);
+                                          (double)Rv[4], (double)Rv[NV - 1], z, P.g, o.T, ICE, qcnew);
         const int64_t nt = (int64_t)e * run_nodes<double>() + t;
         __builtin_nontemporal_store(Tnew, &P.Tnext[nt]);
-        __builtin_nontemporal_store(qlnew, &P.Tnext[P.nnT + nt]);
+        __builtin_nontemporal_store(qcnew, &P.Tnext[P.nnT + nt]);
     }
 }
 
@@ -1465,7 +1319,9 @@ __device__ __forceinline__ void tend_element(const KParams& P, int e, int t,
 
 // one element per block: own loads first, then the first face task's, so
 // that their latency overlaps phase A
-template <typename R, bool MOIST, bool WARP, bool VISC, int MODE, int FLUX>
+// VAR: numerical flux of a dry model (0 Rusanov, 1 Roe, 2 HLLC), or for a
+// moist model 1 = thermodynamics with the ice phase
+template <typename R, bool MOIST, bool WARP, bool VISC, int MODE, int VAR>
 __global__ __launch_bounds__(BLOCK) void k_tend(const KParams P, const R* __restrict__ F2, R A, R B, R dt)
 {
     constexpr int NV = MOIST ? 6 : 5;
@@ -1479,7 +1335,7 @@ __global__ __launch_bounds__(BLOCK) void k_tend(const KParams P, const R* __rest
     own_load<R, MOIST, WARP, VISC, MODE>(P, e, ez, tt, o);
     FaceLoad<R, MOIST, WARP, VISC> ft0;
     face_load<R, MOIST, WARP, VISC>(P, F2, t, e, ex, ey, ez, ft0);
-    tend_element<R, MOIST, WARP, VISC, MODE, FLUX>(P, e, t, o, ft0, dval, sG, sP, sY, sD, F2, A, B, dt);
+    tend_element<R, MOIST, WARP, VISC, MODE, VAR>(P, e, t, o, ft0, dval, sG, sP, sY, sD, F2, A, B, dt);
 }
 
 #undef CM_TEND_LDS
@@ -1513,10 +1369,13 @@ static hipError_t launch_typed(cm_model* m, const void* Y, void* out, void* dQ, 
     const dim3 grid(P.n_elem), block(BLOCK);
     const R* F2 = (const R*)m->d_F2;
     const bool visc = m->desc.closure != CM_CLOSURE_NONE;
+    const bool ice = MOIST && P.ice;
     if (visc) {
         cm_model::ProfRec* r = prof_begin(m, 0, s);
         if (m->desc.closure == CM_CLOSURE_MLP)
             hipLaunchKernelGGL((k_grad<R, MOIST, WARP, true>), grid, block, 0, s, P);
+        else if (ice)
+            hipLaunchKernelGGL((k_grad<R, MOIST, WARP, false, false, MOIST>), grid, block, 0, s, P);
         else
             hipLaunchKernelGGL((k_grad<R, MOIST, WARP, false>), grid, block, 0, s, P);
         prof_end(r, s);
@@ -1530,14 +1389,15 @@ static hipError_t launch_typed(cm_model* m, const void* Y, void* out, void* dQ, 
         else if (mode == 1) CM_TEND(V, 1, FL); \
         else CM_TEND(V, 2, FL);           \
     } while (0)
-    // Roe and HLLC are instantiated for dry models only (the model rejects them otherwise)
-    const int flux = MOIST ? 0 : m->desc.flux;
+    // Roe and HLLC are instantiated for dry models only (the model rejects
+    // them otherwise); for moist models the same slot selects the ice phase
+    const int flux = MOIST ? (ice ? 1 : 0) : m->desc.flux;
     if (visc) {
-        if (flux == 1) CM_TEND_MODES(true, MOIST ? 0 : 1);
+        if (flux == 1) CM_TEND_MODES(true, 1);
         else if (flux == 2) CM_TEND_MODES(true, MOIST ? 0 : 2);
         else CM_TEND_MODES(true, 0);
     } else {
-        if (flux == 1) CM_TEND_MODES(false, MOIST ? 0 : 1);
+        if (flux == 1) CM_TEND_MODES(false, 1);
         else if (flux == 2) CM_TEND_MODES(false, MOIST ? 0 : 2);
         else CM_TEND_MODES(false, 0);
     }

@@ -6,6 +6,7 @@
 #include <mutex>
 
 #include "cm_impl.hpp"
+#include "thermo.hpp"
 
 namespace cm {
 
@@ -30,48 +31,15 @@ __device__ __forceinline__ void neu_merge(Neu& a, const Neu& b)
     a.c += b.c;
 }
 
-__device__ __forceinline__ double pvsat_d(double T)
-{
-    constexpr double dc = Phys::cpv - Phys::cpl;
-    return Phys::ptr * exp(dc / Phys::Rv * log(T / Phys::T0) +
-                           (Phys::Lv0 - dc * Phys::T0) / Phys::Rv * (1.0 / Phys::T0 - 1.0 / T));
-}
-
-// temperature and sound speed of one node (same thermodynamics as the RHS)
+// temperature and sound speed of one node (the thermodynamics of the passes)
 template <bool MOIST>
 __device__ void temp_sound(double rho, double mx, double my, double mz, double re, double rq, double z, double g,
-                           double& T, double& c)
+                           bool ice, double& T, double& c)
 {
-    const double ir = 1.0 / rho;
-    const double I = re * ir - 0.5 * (mx * mx + my * my + mz * mz) * ir * ir - g * z;
-    if (!MOIST) {
-        T = Phys::T0 + I / Phys::cvd;
-        c = sqrt(Phys::cpd / Phys::cvd * Phys::Rd * T);
-        return;
-    }
-    const double qt = rq * ir;
-    const double Tu = Phys::T0 + (I - qt * Phys::Iv0) / ((1.0 - qt) * Phys::cvd + qt * Phys::cvv);
-    double Tn = Tu;
-    if (qt > pvsat_d(Tu) / (rho * Phys::Rv * Tu)) {
-        for (int it = 0; it < 20; ++it) {
-            const double qv = pvsat_d(Tn) / (rho * Phys::Rv * Tn);
-            const double dT = Tn - Phys::T0;
-            const double f = (1.0 - qt) * Phys::cvd * dT + qv * (Phys::cvv * dT + Phys::Iv0) + (qt - qv) * Phys::cvl * dT - I;
-            const double Lv = Phys::Lv0 + (Phys::cpv - Phys::cpl) * dT;
-            const double dqv = qv * (Lv / (Phys::Rv * Tn * Tn) - 1.0 / Tn);
-            const double cvm = (1.0 - qt) * Phys::cvd + qv * Phys::cvv + (qt - qv) * Phys::cvl;
-            const double step = f / (cvm + dqv * (Phys::Iv0 + (Phys::cvv - Phys::cvl) * dT));
-            Tn -= step;
-            if (fabs(step) <= 1e-13 * Tn) break;
-        }
-    }
-    double qv = pvsat_d(Tn) / (rho * Phys::Rv * Tn);
-    qv = qv < qt ? qv : qt;
-    const double ql = qt - qv;
-    const double Rm = Phys::Rd * (1.0 - qt) + Phys::Rv * qv;
-    const double cvm = (1.0 - qt) * Phys::cvd + qv * Phys::cvv + ql * Phys::cvl;
-    T = Tn;
-    c = sqrt((cvm + Rm) / cvm * Rm * Tn);
+    Th o;
+    thermo<MOIST>(rho, mx, my, mz, re, rq, z, g, ice, o);
+    T = o.T;
+    c = o.c;
 }
 
 struct DiagArgs {
@@ -84,6 +52,7 @@ struct DiagArgs {
     const double* invJ;      // warped: per-node 1/J (FP64) or null
     const double* zn;        // warped: node heights or null
     double g, dt, dmin;
+    int ice;
 };
 
 template <typename R, bool MOIST>
@@ -117,7 +86,7 @@ __global__ __launch_bounds__(RB) void k_diag1(const DiagArgs A, const R* __restr
         const double aw = fabs(y[3] * ir);
         maxw = aw > maxw ? aw : maxw;
         double T, c;
-        temp_sound<MOIST>(y[0], y[1], y[2], y[3], y[4], MOIST ? y[5] : 0.0, z, A.g, T, c);
+        temp_sound<MOIST>(y[0], y[1], y[2], y[3], y[4], MOIST ? y[5] : 0.0, z, A.g, A.ice != 0, T, c);
         Tmin = T < Tmin ? T : Tmin;
         Tmax = T > Tmax ? T : Tmax;
         if (A.dt > 0.0) {
@@ -217,6 +186,7 @@ static hipError_t diagnostics_ws(const cm_model* m, const void* Y, double dt, cm
     A.invJ = g->d_metrics64 ? g->d_metrics64 + 9 * g->n_nodes : nullptr;
     A.zn = g->d_z;
     A.g = m->desc.g;
+    A.ice = m->desc.ice;
     A.dt = dt;
     A.dmin = g->dmin;
     int nblk = (int)((A.nn + RB - 1) / RB);

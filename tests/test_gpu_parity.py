@@ -313,3 +313,73 @@ def test_moist_model_rejects_roe_and_hllc(dev):
         with pytest.raises(B.CMError) as ei:
             B.Model(g, dict(c["model"], flux=flux))
         assert ei.value.status == B.CM_ERR_UNSUPPORTED
+
+
+def _cold_moist_state(c, seed=12):
+    """A cold moist state for the ice phase: pressure of an isothermal 250 K
+    column, temperature falling from 280 K at the ground to 225 K at 3 km
+    with smooth +-3 K and velocity perturbations, total water about twice
+    the vapour that saturates over liquid, so that condensate forms all
+    liquid, on the liquid-fraction ramp (233-273.15 K) and all ice."""
+    xyz = W.node_coords(c["grid"])
+    z = xyz[2]
+    rng = np.random.default_rng(seed)
+    p, T = W.isothermal(z, 250.0)
+    zero = np.zeros_like(z)
+    Yref = W.state_from_primitives(p, T, zero, zero, zero, z, qt=np.full_like(z, 1.0e-3))
+    noise = lambda: W._smooth_noise(xyz, c["grid"], rng)  # noqa: E731
+    Tp = 280.0 - 55.0 * z / 3000.0 + 3.0 * noise()
+    qs = W.pvsat(Tp) / ((p - W.pvsat(Tp)) / (287.0 * Tp) * 462.0 * Tp)
+    qt = qs * (2.0 + 0.5 * noise())
+    Y = W.state_from_primitives(p, Tp, 5.0 * noise(), 5.0 * noise(), 5.0 * noise(), z, qt=qt)
+    return Y, Yref
+
+
+ICE_CASES = {
+    "ice": _small("moist_64", (4, 3, 4), (400.0, 300.0, 3000.0)),
+    "ice_warped": _small("moist_64", (4, 2, 4), (1500.0, 500.0, 3000.0), topo=1, topo_a=300.0, topo_xc=750.0,
+                         topo_h=200.0),
+    "ice_inviscid": _small("moist_64", (3, 2, 4), (300.0, 200.0, 3000.0)),
+}
+for _c in ICE_CASES.values():
+    _c["model"]["ice"] = True
+ICE_CASES["ice_inviscid"]["model"]["closure"] = "none"
+
+
+@pytest.mark.parametrize("name", list(ICE_CASES))
+def test_ice_phase_rhs_and_steps_match_oracle(dev, name):
+    c = ICE_CASES[name]
+    Y, Yref = _cold_moist_state(c)
+    # the state holds condensate on both sides of the liquid-fraction ramp
+    T, _, qc, _ = oracle.thermo_nodes(Y, W.node_coords(c["grid"])[2], 9.81, ice=True)
+    assert (qc > 0).mean() > 0.3 and T.min() < 233.0 and T.max() > 273.15
+    g = B.Grid(c["grid"])
+    m = B.Model(g, c["model"], Yref)
+    om = oracle.Model(oracle.Grid(c["grid"]), c["model"], Yref)
+    Yd, Rd = m.new_state(Y), m.new_state()
+    m.rhs(Yd, Rd)
+    dev.cuda.synchronize()
+    err = rhs_errors(m.to_numpy(Rd), om.rhs(Y), Y, hmin(c["grid"]))
+    print(name, "ice-phase rhs errors", err)
+    assert np.all(err < RHS_TOL), err
+    dt = W.cfl_dt(c["grid"], 360.0)
+    Ya, Yb, dQ = m.new_state(Y), m.new_state(), m.new_state()
+    for _ in range(3):
+        m.lsrk_step(Ya, Yb, dQ, 0.0, dt)
+        Ya, Yb = Yb, Ya
+    dev.cuda.synchronize()
+    Yo, _ = om.steps(Y, dt, 3)
+    serr = state_errors(m.to_numpy(Ya), Yo)
+    print(name, "ice-phase state errors after 3 steps", serr)
+    assert np.all(serr < 1e-10), serr
+    # without the ice phase the same state evolves differently
+    Rl = oracle.Model(oracle.Grid(c["grid"]), dict(c["model"], ice=False), Yref).rhs(Y)
+    assert np.abs(Rl - om.rhs(Y)).max() > 1e-6 * np.abs(Rl).max()
+
+
+def test_ice_phase_rejects_the_learned_closure(dev):
+    c = ICE_CASES["ice"]
+    g = B.Grid(c["grid"])
+    with pytest.raises(B.CMError) as ei:
+        B.Model(g, dict(c["model"], closure="mlp"))
+    assert ei.value.status == B.CM_ERR_UNSUPPORTED
