@@ -216,6 +216,23 @@ CM_API cm_status cm_lsrk_step(cm_model* model, void* Y, void* Y_alt, void* dQ, d
 CM_API cm_status cm_lsrk144_step(cm_model* model, void* Y, void* Y_alt, void* dQ, double t, double dt,
                                  void* hip_stream);
 
+/* Exponential modal filter (Sect. 5.4, eq. exponential_filter), in place on
+ * the state Y (layout as cm_dg_rhs).  For each variable v with bit v set in
+ * var_mask, each element's deviation from the model's background state
+ * (Yref_host of cm_model_create; zero without one) is expanded in Legendre
+ * modes along each direction, mode n is scaled by sigma(n) = exp(-alpha
+ * ((n - Nc)/(N - Nc))^order) for n > Nc (by 1 for n <= Nc), and the
+ * background is added back.  order is the filter order s (the paper uses
+ * 64 on the velocity), alpha = -ln(machine epsilon) (36 in double
+ * precision).  Mode 0 is never changed, so each element's integral of
+ * every variable over its reference cube is kept; on flat meshes (constant
+ * Jacobian) that is its physical integral.  Elements are filtered independently;
+ * asynchronous on the stream.  Errors: CM_ERR_ARG (null, var_mask 0 or
+ * beyond nvar bits, order < 1, alpha < 0 or not finite, Nc outside
+ * 0 .. N-1). */
+CM_API cm_status cm_exp_filter(cm_model* model, void* Y, int var_mask, int order, double alpha, int Nc,
+                               void* hip_stream);
+
 /* Conservation and health diagnostics (Sect. 6): compensated (Neumaier) FP64
  * integrals in a deterministic two-stage reduction, extrema, CFL and a
  * non-finite count.  Synchronises the stream.  Returns CM_ERR_NONFINITE

@@ -107,6 +107,7 @@ def _declare(L):
     L.cmref_saturation_adjust_phase.argtypes = [C.c_double, C.c_double, C.c_double, C.c_int, C.POINTER(C.c_double),
                                                 C.POINTER(C.c_double), C.POINTER(C.c_double)]
     L.cmref_numflux_point.argtypes = [C.c_int, C.c_int, _P, _P, C.c_double, C.c_double, C.c_double, _P, _P]
+    L.cmref_exp_filter.argtypes = [C.c_void_p, _P, C.c_int, C.c_int, C.c_double, C.c_int]
     L.cmref_rusanov_point.argtypes = [C.c_int, _P, _P, C.c_double, C.c_double, C.c_double,
                                       C.c_double, C.c_double, _P, _P]
     L.cmref_smagorinsky_point.argtypes = [_P, C.c_double, C.c_double, C.c_double, C.c_double,
@@ -296,6 +297,13 @@ class Model:
         fn = {"lsrk54": self._L.cmref_lsrk_steps, "lsrk144": self._L.cmref_lsrk144_steps}[scheme]
         fn(self.h, Y, dQ, float(t), float(dt), int(nsteps))
         return Y, dQ
+
+    def exp_filter(self, Y, mask: int, order: int = 64, alpha: float = 36.0, Nc: int = 0):
+        """A filtered copy of Y (exponential modal filter on the deviation of
+        the variables in mask from the background)."""
+        Y = self._chk(Y).copy()
+        self._L.cmref_exp_filter(self.h, Y, int(mask), int(order), float(alpha), int(Nc))
+        return Y
 
     def integrals(self, Y):
         """Domain integrals of each variable (w J weighted) and kinetic energy."""

@@ -572,6 +572,7 @@ typedef struct {
     cmref_model_desc m;
     double* pr;    /* reference pressure per node */
     double* rhor;  /* reference density per node */
+    double* Yref;  /* the background state itself [nvar][nn] (zeros without one) */
     double Delta;  /* filter width (dx dy dz)^(1/3), dx = h/N */
     /* learned closure parameters (FP64 copy), optional */
     double* mlp;
@@ -591,6 +592,8 @@ void* cmref_model_create(void* grid, const cmref_model_desc* m, const double* Yr
     long nn = M->G->nnodes;
     M->pr = (double*)calloc(nn, sizeof(double));
     M->rhor = (double*)calloc(nn, sizeof(double));
+    M->Yref = (double*)calloc((size_t)m->nvar * nn, sizeof(double));
+    if (Yref) memcpy(M->Yref, Yref, sizeof(double) * (size_t)m->nvar * nn);
     if (Yref) {
         /* reference state: the unperturbed background pushed through the
          * same thermodynamic functions as the prognostic state */
@@ -612,8 +615,79 @@ void cmref_model_destroy(void* h)
 {
     model_t* M = (model_t*)h;
     if (!M) return;
-    free(M->pr); free(M->rhor); free(M->mlp); free(M->mlp_bf16);
+    free(M->pr); free(M->rhor); free(M->Yref); free(M->mlp); free(M->mlp_bf16);
     free(M);
+}
+
+/* Exponential modal filter (Sect. 5.4, eq. exponential_filter), in place:
+ * in every element, the deviation of each variable in mask (bit v) from the
+ * background is expanded in Legendre modes along each direction, mode n
+ * scaled by sigma(n) = exp(-alpha ((n - Nc)/(N - Nc))^order) for n > Nc (1
+ * otherwise), and the background added back.  The 1-D filter is V diag(sigma)
+ * V^-1 with V[i][n] = P_n(xi_i); the 3-D one, their Kronecker product, is
+ * applied as a dense (N+1)^3 x (N+1)^3 matrix. */
+void cmref_exp_filter(void* h, double* Y, int mask, int order, double alpha, int Nc)
+{
+    model_t* M = (model_t*)h;
+    const grid_t* G = M->G;
+    const int N = G->N, Q = N + 1, Np = Q * Q * Q;
+    const long nn = G->nnodes;
+    double V[CMREF_MAXQ][CMREF_MAXQ], A[CMREF_MAXQ][2 * CMREF_MAXQ], F1[CMREF_MAXQ][CMREF_MAXQ];
+    for (int i = 0; i < Q; ++i)
+        for (int n = 0; n < Q; ++n) {
+            double P, dP;
+            legendre(n, G->xi[i], &P, &dP);
+            V[i][n] = P;
+        }
+    /* V^-1 by Gauss-Jordan elimination with partial pivoting on [V | I] */
+    for (int i = 0; i < Q; ++i)
+        for (int j = 0; j < 2 * Q; ++j) A[i][j] = j < Q ? V[i][j] : (j - Q == i ? 1.0 : 0.0);
+    for (int c = 0; c < Q; ++c) {
+        int piv = c;
+        for (int r = c + 1; r < Q; ++r) if (fabs(A[r][c]) > fabs(A[piv][c])) piv = r;
+        for (int j = 0; j < 2 * Q; ++j) { double t = A[c][j]; A[c][j] = A[piv][j]; A[piv][j] = t; }
+        double d = A[c][c];
+        for (int j = 0; j < 2 * Q; ++j) A[c][j] /= d;
+        for (int r = 0; r < Q; ++r) {
+            if (r == c) continue;
+            double f = A[r][c];
+            for (int j = 0; j < 2 * Q; ++j) A[r][j] -= f * A[c][j];
+        }
+    }
+    double sig[CMREF_MAXQ];
+    for (int n = 0; n < Q; ++n)
+        sig[n] = n <= Nc ? 1.0 : exp(-alpha * pow((double)(n - Nc) / (double)(N - Nc), (double)order));
+    for (int i = 0; i < Q; ++i)
+        for (int l = 0; l < Q; ++l) {
+            double acc = 0.0;
+            for (int n = 0; n < Q; ++n) acc += V[i][n] * sig[n] * A[n][Q + l];
+            F1[i][l] = acc;
+        }
+    double* F3 = (double*)malloc(sizeof(double) * Np * Np);
+    for (int a = 0; a < Np; ++a) {
+        int i = a % Q, j = (a / Q) % Q, k = a / (Q * Q);
+        for (int b = 0; b < Np; ++b) {
+            int l = b % Q, m = (b / Q) % Q, o = b / (Q * Q);
+            F3[a * Np + b] = F1[i][l] * F1[j][m] * F1[k][o];
+        }
+    }
+    const long ne = nn / Np;
+    #pragma omp parallel for schedule(static)
+    for (long e = 0; e < ne; ++e) {
+        double d[CMREF_MAXQ * CMREF_MAXQ * CMREF_MAXQ];
+        for (int v = 0; v < M->m.nvar; ++v) {
+            if (!(mask & (1 << v))) continue;
+            double* y = Y + v * nn + e * Np;
+            const double* yr = M->Yref + v * nn + e * Np;
+            for (int b = 0; b < Np; ++b) d[b] = y[b] - yr[b];
+            for (int a = 0; a < Np; ++a) {
+                double acc = 0.0;
+                for (int b = 0; b < Np; ++b) acc += F3[a * Np + b] * d[b];
+                y[a] = yr[a] + acc;
+            }
+        }
+    }
+    free(F3);
 }
 
 void cmref_model_reference(void* h, double* pr, double* rhor)

@@ -23,7 +23,7 @@ FLUXES = {"rusanov": 0, "roe": 1, "hllc": 2}
 EXPORTED = [
     "cm_grid_create", "cm_grid_destroy", "cm_grid_query", "cm_grid_copy_coords", "cm_grid_copy_wJ",
     "cm_grid_copy_metrics", "cm_model_create", "cm_model_destroy", "cm_model_set_mlp",
-    "cm_model_mlp_fallbacks", "cm_dg_rhs", "cm_lsrk_step", "cm_lsrk144_step", "cm_diagnostics",
+    "cm_model_mlp_fallbacks", "cm_dg_rhs", "cm_lsrk_step", "cm_lsrk144_step", "cm_exp_filter", "cm_diagnostics",
     "cm_diagnostics_noalloc",
     "cm_mlp_create",
     "cm_mlp_destroy", "cm_mlp_train_step", "cm_mlp_grads", "cm_mlp_infer", "cm_mlp_get_params",
@@ -100,6 +100,7 @@ def load():
     L.cm_dg_rhs.argtypes = [_VP, _VP, _VP, C.c_double, _VP]
     L.cm_lsrk_step.argtypes = [_VP, _VP, _VP, _VP, C.c_double, C.c_double, _VP]
     L.cm_lsrk144_step.argtypes = [_VP, _VP, _VP, _VP, C.c_double, C.c_double, _VP]
+    L.cm_exp_filter.argtypes = [_VP, _VP, C.c_int, C.c_int, C.c_double, C.c_int, _VP]
     L.cm_diagnostics.argtypes = [_VP, _VP, C.c_double, C.POINTER(Diag), _VP]
     L.cm_diagnostics_noalloc.argtypes = [_VP, _VP, C.c_double, C.POINTER(Diag), _VP]
     L.cm_mlp_create.argtypes = [C.POINTER(MLPDesc), C.c_uint64, C.c_int, C.POINTER(_VP)]
@@ -298,6 +299,13 @@ class Model:
         self._chk(Y, Y_alt, dQ)
         _check(load().cm_lsrk144_step(self.h, Y.data_ptr(), Y_alt.data_ptr(), dQ.data_ptr(), float(t),
                                       float(dt), _stream_ptr(stream)))
+        return Y
+
+    def exp_filter(self, Y, mask: int, order: int = 64, alpha: float = 36.0, Nc: int = 0, stream=None):
+        """Exponential modal filter in place on the variables in mask (bit v)."""
+        self._chk(Y)
+        _check(load().cm_exp_filter(self.h, Y.data_ptr(), int(mask), int(order), float(alpha), int(Nc),
+                                    _stream_ptr(stream)))
         return Y
 
     def diagnostics(self, Y, dt: float = 0.0, stream=None, noalloc: bool = False) -> dict:

@@ -325,6 +325,7 @@ cm_status cm_model_destroy(cm_model* m)
         if (m->d_T[q]) (void)hipFree(m->d_T[q]);
     if (m->d_pr) (void)hipFree(m->d_pr);
     if (m->d_rhor) (void)hipFree(m->d_rhor);
+    if (m->d_Yref) (void)hipFree(m->d_Yref);
     if (m->d_partials) (void)hipFree(m->d_partials);
     if (m->d_mlp_w) (void)hipFree(m->d_mlp_w);
     if (m->d_mlp_norm) (void)hipFree(m->d_mlp_norm);
@@ -472,16 +473,18 @@ cm_status cm_model_create(const cm_grid* g, const cm_model_desc* desc, const dou
     k.Tnext = nullptr;
     k.T_given = 0;
     k.nnT = g->n_elem * run_nodes<double>();
-    if (e == hipSuccess && Yref) {
-        // push the background through the device thermodynamics
-        const int64_t nref = m->ref_per_node ? nn : (int64_t)g->desc.ne[2] * NQ;
-        double* d_Yr = nullptr;
-        e = hipMalloc(&d_Yr, sizeof(double) * Yr.size());
-        if (e == hipSuccess) e = hipMemcpy(d_Yr, Yr.data(), sizeof(double) * Yr.size(), hipMemcpyHostToDevice);
-        if (e == hipSuccess) e = launch_reference(m, d_Yr, nullptr);
+    if (e == hipSuccess) {
+        // the background in conserved variables (kept for the modal filter,
+        // which acts on deviations from it), then pushed through the device
+        // thermodynamics for p_r and rho_r
+        const size_t nref = m->ref_per_node ? (size_t)nn : (size_t)g->desc.ne[2] * NQ;
+        e = hipMalloc(&m->d_Yref, sizeof(double) * desc->nvar * nref);
+        if (e == hipSuccess && Yref)
+            e = hipMemcpy(m->d_Yref, Yr.data(), sizeof(double) * Yr.size(), hipMemcpyHostToDevice);
+        else if (e == hipSuccess)
+            e = hipMemset(m->d_Yref, 0, sizeof(double) * desc->nvar * nref);
+        if (e == hipSuccess && Yref) e = launch_reference(m, m->d_Yref, nullptr);
         if (e == hipSuccess) e = hipDeviceSynchronize();
-        if (d_Yr) (void)hipFree(d_Yr);
-        (void)nref;
     }
     if (e != hipSuccess) {
         cm_status st = hip_fail(e, "cm_model_create");
@@ -621,6 +624,71 @@ cm_status cm_diagnostics(cm_model* m, const void* Y, double dt, cm_diag* out, vo
         set_error("cm_diagnostics: state holds non-finite values");
         return CM_ERR_NONFINITE;
     }
+    return CM_OK;
+}
+
+// 1-D exponential filter matrix V diag(sigma) V^-1 on the GLL nodes, V[i][n]
+// = P_n(xi_i) (Legendre polynomials by their three-term recurrence, the
+// inverse by Gaussian elimination with partial pivoting)
+static void exp_filter_matrix(const double* xi, int order, double alpha, int Nc, double* F)
+{
+    constexpr int Q = NQ, N = NQ - 1;
+    double V[Q][Q];
+    for (int i = 0; i < Q; ++i) {
+        double pm = 1.0, p = xi[i];
+        V[i][0] = 1.0;
+        V[i][1] = xi[i];
+        for (int n = 1; n < N; ++n) {
+            const double pn = ((2 * n + 1) * xi[i] * p - n * pm) / (n + 1);
+            pm = p;
+            p = pn;
+            V[i][n + 1] = p;
+        }
+    }
+    // solve V X = diag(sigma) ... as X = V^-1 column by column: W = V^-1
+    double Aug[Q][2 * Q];
+    for (int i = 0; i < Q; ++i)
+        for (int j = 0; j < 2 * Q; ++j) Aug[i][j] = j < Q ? V[i][j] : (j - Q == i ? 1.0 : 0.0);
+    for (int c = 0; c < Q; ++c) {
+        int piv = c;
+        for (int r = c + 1; r < Q; ++r)
+            if (std::fabs(Aug[r][c]) > std::fabs(Aug[piv][c])) piv = r;
+        for (int j = 0; j < 2 * Q; ++j) std::swap(Aug[c][j], Aug[piv][j]);
+        for (int r = c + 1; r < Q; ++r) {
+            const double f = Aug[r][c] / Aug[c][c];
+            for (int j = c; j < 2 * Q; ++j) Aug[r][j] -= f * Aug[c][j];
+        }
+    }
+    for (int c = Q - 1; c >= 0; --c) {
+        for (int j = Q; j < 2 * Q; ++j) {
+            double v = Aug[c][j];
+            for (int k = c + 1; k < Q; ++k) v -= Aug[c][k] * Aug[k][j];
+            Aug[c][j] = v / Aug[c][c];
+        }
+    }
+    double sig[Q];
+    for (int n = 0; n < Q; ++n)
+        sig[n] = n <= Nc ? 1.0 : std::exp(-alpha * std::pow((double)(n - Nc) / (double)(N - Nc), (double)order));
+    for (int i = 0; i < Q; ++i)
+        for (int l = 0; l < Q; ++l) {
+            double acc = 0.0;
+            for (int n = 0; n < Q; ++n) acc += V[i][n] * sig[n] * Aug[n][Q + l];
+            F[i * Q + l] = acc;
+        }
+}
+
+cm_status cm_exp_filter(cm_model* m, void* Y, int var_mask, int order, double alpha, int Nc, void* stream)
+{
+    if (!m || !Y) { set_error("cm_exp_filter: null argument"); return CM_ERR_ARG; }
+    if (var_mask <= 0 || var_mask >= (1 << m->desc.nvar)) { set_error("cm_exp_filter: bad variable mask"); return CM_ERR_ARG; }
+    if (order < 1 || !(alpha >= 0.0) || !std::isfinite(alpha) || Nc < 0 || Nc >= NQ - 1) {
+        set_error("cm_exp_filter: need order >= 1, finite alpha >= 0 and 0 <= Nc < N");
+        return CM_ERR_ARG;
+    }
+    CM_TRY_HIP(hipSetDevice(m->grid->device), "hipSetDevice");
+    double F[NQ * NQ];
+    exp_filter_matrix(m->grid->xi, order, alpha, Nc, F);
+    CM_TRY_HIP(launch_exp_filter(m, Y, var_mask, F, (hipStream_t)stream), "cm_exp_filter");
     return CM_OK;
 }
 

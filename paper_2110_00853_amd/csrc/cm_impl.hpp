@@ -140,6 +140,7 @@ struct cm_model {
     int tsel = 0;                // which d_T holds the current stage input's T
     double* d_pr = nullptr;
     double* d_rhor = nullptr;
+    double* d_Yref = nullptr;    // the background itself [nvar][nref] (per level or per node; zeros without one)
     int ref_per_node = 0;
     int has_ref = 0;
     double Delta = 0.0;
@@ -177,6 +178,8 @@ cm_model::ProfRec* prof_begin(cm_model* m, int kind, hipStream_t s);
 void prof_end(cm_model::ProfRec* r, hipStream_t s);
 // reductions (reduce.hip)
 hipError_t launch_diagnostics(const cm_model* m, const void* Y, double dt, cm_diag* out, hipStream_t s);
+// exponential modal filter (filter.hip): F1 the 1-D filter matrix [5][5]
+hipError_t launch_exp_filter(const cm_model* m, void* Y, int mask, const double* F1, hipStream_t s);
 // the same reduction over the library's static per-device workspace (no
 // allocation); its partial-record count equals a model's, so both give
 // bit-identical results
