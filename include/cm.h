@@ -38,6 +38,7 @@
 #ifndef CM_H
 #define CM_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #if defined(__GNUC__) || defined(__clang__)
@@ -215,6 +216,33 @@ CM_API cm_status cm_lsrk_step(cm_model* model, void* Y, void* Y_alt, void* dQ, d
  * cm_lsrk_step. */
 CM_API cm_status cm_lsrk144_step(cm_model* model, void* Y, void* Y_alt, void* dQ, double t, double dt,
                                  void* hip_stream);
+
+/* 1-D IMEX ("HEVI", Sect. 3.2): horizontally explicit, vertically implicit
+ * additive Runge-Kutta step for dry models (nvar = 5) on flat meshes with
+ * walls at the bottom and top (CM_ERR_UNSUPPORTED otherwise).  The implicit
+ * part L is the vertical acoustic operator linearised about the model's
+ * background state (Yref_host of cm_model_create): on the deviation d = Y -
+ * Y_ref, the vertical flux (rho w', p', h_r rho w'), with p' = (R_d/c_vd)
+ * (rho e_tot)' + (R_d T_0 - (R_d/c_vd) g z) rho' and h_r = (rho e_r + p_r) /
+ * rho_r, differentiated by the DG operator along xi3, the vertical part of
+ * the Rusanov penalty at the background sound speed on all five variables,
+ * mirrored ghosts at the walls, and the buoyancy -g rho'.  The explicit part
+ * is cm_dg_rhs minus L.  Integrator: ARK2 of Giraldo, Kelly & Constantinescu
+ * (2013), three stages, second order.  Each implicit stage solves (I - tau L)
+ * d = B - Y_ref on every vertical node line (block-tridiagonal elimination
+ * over the element layers, FP64).
+ *
+ * work: caller-owned device memory of cm_hevi_workspace_bytes bytes (seven
+ * state-sized buffers and the line solver's 60 doubles per element layer and
+ * vertical node line), 256-byte aligned; its contents need no
+ * initialisation and are scratch after the call.  cm_hevi_step advances Y
+ * in place by dt.  cm_hevi_operator writes L(Y - Y_ref) to LY (all five
+ * variables).  cm_hevi_solve writes Y_ref + d with (I - tau L) d = B - Y_ref
+ * to Y (B and Y may be the same buffer).  All asynchronous on the stream. */
+CM_API cm_status cm_hevi_workspace_bytes(const cm_model* model, size_t* bytes);
+CM_API cm_status cm_hevi_step(cm_model* model, void* Y, void* work, double t, double dt, void* hip_stream);
+CM_API cm_status cm_hevi_operator(cm_model* model, const void* Y, void* LY, void* hip_stream);
+CM_API cm_status cm_hevi_solve(cm_model* model, double tau, const void* B, void* Y, void* work, void* hip_stream);
 
 /* Exponential modal filter (Sect. 5.4, eq. exponential_filter), in place on
  * the state Y (layout as cm_dg_rhs).  For each variable v with bit v set in

@@ -107,6 +107,11 @@ def _declare(L):
     L.cmref_saturation_adjust_phase.argtypes = [C.c_double, C.c_double, C.c_double, C.c_int, C.POINTER(C.c_double),
                                                 C.POINTER(C.c_double), C.POINTER(C.c_double)]
     L.cmref_numflux_point.argtypes = [C.c_int, C.c_int, _P, _P, C.c_double, C.c_double, C.c_double, _P, _P]
+    L.cmref_ark2_coeffs.argtypes = [_P, _P, _P]
+    L.cmref_hevi_steps.argtypes = [C.c_void_p, _P, C.c_double, C.c_double, C.c_int]
+    L.cmref_hevi_steps.restype = C.c_int
+    L.cmref_hevi_operator.argtypes = [C.c_void_p, _P, _P]
+    L.cmref_hevi_solve.argtypes = [C.c_void_p, C.c_double, _P, _P]
     L.cmref_exp_filter.argtypes = [C.c_void_p, _P, C.c_int, C.c_int, C.c_double, C.c_int]
     L.cmref_rusanov_point.argtypes = [C.c_int, _P, _P, C.c_double, C.c_double, C.c_double,
                                       C.c_double, C.c_double, _P, _P]
@@ -298,6 +303,27 @@ class Model:
         fn(self.h, Y, dQ, float(t), float(dt), int(nsteps))
         return Y, dQ
 
+    def hevi_steps(self, Y, dt: float, nsteps: int, t: float = 0.0):
+        """Advance a copy of Y by nsteps ARK2 HEVI steps (dry, flat mesh)."""
+        Y = self._chk(Y).copy()
+        if self._L.cmref_hevi_steps(self.h, Y, float(t), float(dt), int(nsteps)):
+            raise ValueError("the HEVI step is for dry models")
+        return Y
+
+    def hevi_operator(self, Y):
+        """L (Y - Y_ref): the linear vertical operator (rho, rho w, rho e_tot rows)."""
+        Y = self._chk(Y)
+        out = np.zeros_like(Y)
+        self._L.cmref_hevi_operator(self.h, Y, out)
+        return out
+
+    def hevi_solve(self, tau: float, B):
+        """Y_ref + x with (I - tau L) x = B - Y_ref on every vertical line."""
+        B = self._chk(B)
+        out = np.zeros_like(B)
+        self._L.cmref_hevi_solve(self.h, float(tau), B, out)
+        return out
+
     def exp_filter(self, Y, mask: int, order: int = 64, alpha: float = 36.0, Nc: int = 0):
         """A filtered copy of Y (exponential modal filter on the deviation of
         the variables in mask from the background)."""
@@ -405,6 +431,13 @@ def lsrk54_coeffs():
 
 
 NPARAM = 9282
+
+
+def ark2_coeffs():
+    """Explicit and implicit tableaus [3][3] and weights of the ARK2 IMEX scheme."""
+    AE, AI, b = np.zeros(9), np.zeros(9), np.zeros(3)
+    lib().cmref_ark2_coeffs(AE, AI, b)
+    return AE.reshape(3, 3), AI.reshape(3, 3), b
 
 
 def lsrk144_coeffs():

@@ -1216,6 +1216,263 @@ void cmref_lsrk144_steps(void* h, double* Y, double* dQ, double t, double dt, in
 }
 
 /* ======================================================================== */
+/* 1-D IMEX (HEVI, Sect. 3.2): the vertical acoustic operator of the dry    */
+/* equations linearised about the background, treated implicitly in an     */
+/* additive Runge-Kutta step (ARK2 of Giraldo, Kelly & Constantinescu 2013) */
+/* ======================================================================== */
+
+/* The linear operator on deviations d = Y - Y_ref of the five dry variables
+ * along one vertical node line (fixed element column ex, ey and node i, j):
+ * vertical flux F = (m, 0, 0, p', h m) with m = (rho w)', p' = (R_d/c_vd) E'
+ * + (R_d T_0 - (R_d/c_vd) g z) rho' (the dry pressure linearised at rest) and
+ * h = (E_r + p_r)/rho_r; L d = -(2/h_z) D F + lift (n.F - n.F*) at the
+ * element's vertical faces with n.F* = n (F^- + F^+)/2 + c_r (d^- - d^+)/2
+ * for every variable (c_r the background's sound speed: the vertical part
+ * of the Rusanov penalty, horizontal momenta included), walls by the
+ * mirrored ghost (m^+ = -m^-), and the buoyancy -g rho' in the vertical
+ * momentum row.  Line vectors are ordered [var][element layer][k]. */
+static void hevi_line_apply(const model_t* M, int ex, int ey, int i, int j, const double* dl, double* out)
+{
+    const grid_t* G = M->G;
+    const int Q = G->Q, N = G->N, nz = G->ne[2];
+    const long nn = G->nnodes;
+    const double g = M->m.g, a = RD / CVD, hz = G->h[2];
+    const double* z = G->xyz + 2 * nn;
+    const int L = nz * Q;
+#define IDX(v, ez, k) ((v) * L + (ez) * Q + (k))
+    for (int ez = 0; ez < nz; ++ez) {
+        long e = ex + (long)G->ne[0] * (ey + (long)G->ne[1] * ez);
+        double F[5][CMREF_MAXQ], c[CMREF_MAXQ];
+        for (int k = 0; k < Q; ++k) {
+            long n = e * G->Np + i + Q * (j + Q * k);
+            double rr = M->Yref[n], Er = M->Yref[4 * nn + n], pr = M->pr[n];
+            double b = RD * TREF0 - a * g * z[n];
+            double h = (Er + pr) / rr;
+            double rho = dl[IDX(0, ez, k)], m = dl[IDX(3, ez, k)], E = dl[IDX(4, ez, k)];
+            F[0][k] = m;
+            F[1][k] = 0.0;
+            F[2][k] = 0.0;
+            F[3][k] = a * E + b * rho;
+            F[4][k] = h * m;
+            c[k] = sqrt(CPD / CVD * pr / rr);
+        }
+        for (int k = 0; k < Q; ++k) {
+            for (int v = 0; v < 5; ++v) {
+                double s = 0.0;
+                for (int l = 0; l < Q; ++l) s += G->D[k * Q + l] * F[v][l];
+                out[IDX(v, ez, k)] = -(2.0 / hz) * s;
+            }
+            out[IDX(3, ez, k)] -= g * dl[IDX(0, ez, k)];
+        }
+        /* faces: k = 0 (n = -1) and k = N (n = +1) */
+        const double lift = (2.0 / hz) / G->w[N];
+        for (int side = -1; side <= 1; side += 2) {
+            int k = side < 0 ? 0 : N;
+            double nrm = side;
+            double dm[5], Fm[5], dp[5], Fp[5], lam = c[k];
+            for (int v = 0; v < 5; ++v) { dm[v] = dl[IDX(v, ez, k)]; Fm[v] = F[v][k]; }
+            long en = neighbour(G, ex, ey, ez, 2, side);
+            if (en >= 0) {
+                int ezn = (int)(en / ((long)G->ne[0] * G->ne[1]));
+                int kn = side < 0 ? N : 0;
+                long np = en * G->Np + i + Q * (j + Q * kn);
+                double rr = M->Yref[np], Er = M->Yref[4 * nn + np], pr = M->pr[np];
+                double b = RD * TREF0 - a * g * z[np];
+                double h = (Er + pr) / rr;
+                for (int v = 0; v < 5; ++v) dp[v] = dl[IDX(v, ezn, kn)];
+                Fp[0] = dp[3];
+                Fp[1] = 0.0;
+                Fp[2] = 0.0;
+                Fp[3] = a * dp[4] + b * dp[0];
+                Fp[4] = h * dp[3];
+                double cp = sqrt(CPD / CVD * pr / rr);
+                if (cp > lam) lam = cp;
+            } else {
+                for (int v = 0; v < 5; ++v) { dp[v] = dm[v]; Fp[v] = Fm[v]; }
+                dp[3] = -dm[3];
+                Fp[0] = -Fm[0];
+                Fp[4] = -Fm[4];
+            }
+            for (int v = 0; v < 5; ++v) {
+                double fstar = 0.5 * nrm * (Fm[v] + Fp[v]) + 0.5 * lam * (dm[v] - dp[v]);
+                out[IDX(v, ez, k)] += lift * (nrm * Fm[v] - fstar);
+            }
+        }
+    }
+#undef IDX
+}
+
+static void line_gather(const model_t* M, int ex, int ey, int i, int j, const double* Y, int dev, double* dl)
+{
+    const grid_t* G = M->G;
+    const int Q = G->Q, nz = G->ne[2];
+    const long nn = G->nnodes;
+    for (int v = 0; v < 5; ++v)
+        for (int ez = 0; ez < nz; ++ez)
+            for (int k = 0; k < Q; ++k) {
+                long e = ex + (long)G->ne[0] * (ey + (long)G->ne[1] * ez);
+                long n = e * G->Np + i + Q * (j + Q * k);
+                dl[v * nz * Q + ez * Q + k] = Y[v * nn + n] - (dev ? M->Yref[v * nn + n] : 0.0);
+            }
+}
+
+static void line_scatter(const model_t* M, int ex, int ey, int i, int j, const double* dl, double* Y, int add_ref)
+{
+    const grid_t* G = M->G;
+    const int Q = G->Q, nz = G->ne[2];
+    const long nn = G->nnodes;
+    for (int v = 0; v < 5; ++v)
+        for (int ez = 0; ez < nz; ++ez)
+            for (int k = 0; k < Q; ++k) {
+                long e = ex + (long)G->ne[0] * (ey + (long)G->ne[1] * ez);
+                long n = e * G->Np + i + Q * (j + Q * k);
+                Y[v * nn + n] = dl[v * nz * Q + ez * Q + k] + (add_ref ? M->Yref[v * nn + n] : 0.0);
+            }
+}
+
+/* LY = L (Y - Y_ref) on every node */
+static void hevi_apply(const model_t* M, const double* Y, double* LY)
+{
+    const grid_t* G = M->G;
+    const int Q = G->Q;
+    const long nn = G->nnodes;
+    const int nline = 5 * G->ne[2] * Q;
+    memset(LY, 0, sizeof(double) * (size_t)M->m.nvar * nn);
+    #pragma omp parallel for collapse(2) schedule(static)
+    for (int ey = 0; ey < G->ne[1]; ++ey)
+        for (int ex = 0; ex < G->ne[0]; ++ex) {
+            double* dl = (double*)malloc(sizeof(double) * nline * 2);
+            double* ol = dl + nline;
+            for (int j = 0; j < Q; ++j)
+                for (int i = 0; i < Q; ++i) {
+                    line_gather(M, ex, ey, i, j, Y, 1, dl);
+                    hevi_line_apply(M, ex, ey, i, j, dl, ol);
+                    line_scatter(M, ex, ey, i, j, ol, LY, 0);
+                }
+            free(dl);
+        }
+}
+
+/* Y_out = Y_ref + x with (I - tau L) x = B - Y_ref on every line: the line
+ * matrix assembled column by column from the operator and solved by
+ * Gaussian elimination with partial pivoting */
+static void hevi_solve(const model_t* M, double tau, const double* B, double* Yout)
+{
+    const grid_t* G = M->G;
+    const int Q = G->Q;
+    const int n = 5 * G->ne[2] * Q;
+    #pragma omp parallel for collapse(2) schedule(static)
+    for (int ey = 0; ey < G->ne[1]; ++ey)
+        for (int ex = 0; ex < G->ne[0]; ++ex) {
+            double* A = (double*)malloc(sizeof(double) * (size_t)n * (n + 1));
+            double* u = (double*)malloc(sizeof(double) * 2 * n);
+            double* Lu = u + n;
+            for (int j = 0; j < Q; ++j)
+                for (int i = 0; i < Q; ++i) {
+                    for (int col = 0; col < n; ++col) {
+                        for (int r = 0; r < n; ++r) u[r] = r == col ? 1.0 : 0.0;
+                        hevi_line_apply(M, ex, ey, i, j, u, Lu);
+                        for (int r = 0; r < n; ++r) A[(size_t)r * (n + 1) + col] = u[r] - tau * Lu[r];
+                    }
+                    line_gather(M, ex, ey, i, j, B, 1, u);
+                    for (int r = 0; r < n; ++r) A[(size_t)r * (n + 1) + n] = u[r];
+                    for (int c = 0; c < n; ++c) {
+                        int piv = c;
+                        for (int r = c + 1; r < n; ++r)
+                            if (fabs(A[(size_t)r * (n + 1) + c]) > fabs(A[(size_t)piv * (n + 1) + c])) piv = r;
+                        if (piv != c)
+                            for (int k = 0; k <= n; ++k) {
+                                double t = A[(size_t)c * (n + 1) + k];
+                                A[(size_t)c * (n + 1) + k] = A[(size_t)piv * (n + 1) + k];
+                                A[(size_t)piv * (n + 1) + k] = t;
+                            }
+                        for (int r = c + 1; r < n; ++r) {
+                            double f = A[(size_t)r * (n + 1) + c] / A[(size_t)c * (n + 1) + c];
+                            if (f == 0.0) continue;
+                            for (int k = c; k <= n; ++k) A[(size_t)r * (n + 1) + k] -= f * A[(size_t)c * (n + 1) + k];
+                        }
+                    }
+                    for (int r = n - 1; r >= 0; --r) {
+                        double v = A[(size_t)r * (n + 1) + n];
+                        for (int k = r + 1; k < n; ++k) v -= A[(size_t)r * (n + 1) + k] * u[k];
+                        u[r] = v / A[(size_t)r * (n + 1) + r];
+                    }
+                    line_scatter(M, ex, ey, i, j, u, Yout, 1);
+                }
+            free(A);
+            free(u);
+        }
+}
+
+/* ARK2 (Giraldo, Kelly & Constantinescu 2013): gamma = 1 - 1/sqrt2, delta =
+ * 1/(2 sqrt2), a32 = (3 + 2 sqrt2)/6; explicit rows (0), (2 gamma), (1 - a32,
+ * a32); implicit rows (0), (gamma, gamma), (delta, delta, gamma); weights
+ * (delta, delta, gamma), shared by both. */
+void cmref_ark2_coeffs(double* AE, double* AI, double* b)
+{
+    const double gam = 1.0 - 1.0 / sqrt(2.0), del = 1.0 / (2.0 * sqrt(2.0)), a32 = (3.0 + 2.0 * sqrt(2.0)) / 6.0;
+    double ae[9] = {0, 0, 0, 2 * gam, 0, 0, 1 - a32, a32, 0};
+    double ai[9] = {0, 0, 0, gam, gam, 0, del, del, gam};
+    for (int q = 0; q < 9; ++q) { AE[q] = ae[q]; AI[q] = ai[q]; }
+    b[0] = del; b[1] = del; b[2] = gam;
+}
+
+/* nsteps HEVI steps in place: stages Y_s solve Y_s - dt a_ss L(Y_s - Y_ref) =
+ * Y_n + dt sum_{r<s} (aE_sr E_r + aI_sr L_r), E = R(Y) - L(Y - Y_ref);
+ * Y_{n+1} = Y_n + dt sum_s b_s (E_s + L_s).  Dry models on flat meshes. */
+int cmref_hevi_steps(void* h, double* Y, double t, double dt, int nsteps)
+{
+    model_t* M = (model_t*)h;
+    (void)t;
+    if (M->m.nvar != 5) return 1;
+    const long nn = M->G->nnodes, n = (long)M->m.nvar * nn;
+    double AE[9], AI[9], b[3];
+    cmref_ark2_coeffs(AE, AI, b);
+    double* Ys = (double*)malloc(sizeof(double) * n);
+    double* Bs = (double*)malloc(sizeof(double) * n);
+    double* E = (double*)malloc(sizeof(double) * 3 * n);
+    double* Lt = (double*)malloc(sizeof(double) * 3 * n);
+    work_t W; work_alloc(M, &W, slots(&M->m));
+    for (int step = 0; step < nsteps; ++step) {
+        for (int s = 0; s < 3; ++s) {
+            for (long q = 0; q < n; ++q) {
+                double acc = Y[q];
+                for (int r = 0; r < s; ++r) acc += dt * (AE[3 * s + r] * E[r * n + q] + AI[3 * s + r] * Lt[r * n + q]);
+                Bs[q] = acc;
+            }
+            if (AI[3 * s + s] != 0.0) {
+                memcpy(Ys, Bs, sizeof(double) * n);   /* variables outside the operator */
+                hevi_solve(M, dt * AI[3 * s + s], Bs, Ys);
+            } else {
+                memcpy(Ys, Bs, sizeof(double) * n);
+            }
+            rhs_eval(M, Ys, E + s * n, &W);
+            hevi_apply(M, Ys, Lt + s * n);
+            for (long q = 0; q < n; ++q) E[s * n + q] -= Lt[s * n + q];
+        }
+        for (long q = 0; q < n; ++q)
+            Y[q] += dt * (b[0] * (E[q] + Lt[q]) + b[1] * (E[n + q] + Lt[n + q]) + b[2] * (E[2 * n + q] + Lt[2 * n + q]));
+    }
+    work_free(&W);
+    free(Ys); free(Bs); free(E); free(Lt);
+    return 0;
+}
+
+/* L (Y - Y_ref), for the operator's tests */
+void cmref_hevi_operator(void* h, const double* Y, double* LY)
+{
+    hevi_apply((const model_t*)h, Y, LY);
+}
+
+/* solve (I - tau L) x = B - Y_ref on every vertical line; returns Y_ref + x */
+void cmref_hevi_solve(void* h, double tau, const double* B, double* Y)
+{
+    const model_t* M = (const model_t*)h;
+    memcpy(Y, B, sizeof(double) * (size_t)M->m.nvar * M->G->nnodes);
+    hevi_solve(M, tau, B, Y);
+}
+
+/* ======================================================================== */
 /* Integrals (Sect. 6): sum of w_i w_j w_k |J| Y_v, Neumaier-compensated in  */
 /* long double.  out[v] for v < nvar, then kinetic energy.                   */
 /* ======================================================================== */

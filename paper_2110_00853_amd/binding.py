@@ -24,6 +24,7 @@ EXPORTED = [
     "cm_grid_create", "cm_grid_destroy", "cm_grid_query", "cm_grid_copy_coords", "cm_grid_copy_wJ",
     "cm_grid_copy_metrics", "cm_model_create", "cm_model_destroy", "cm_model_set_mlp",
     "cm_model_mlp_fallbacks", "cm_dg_rhs", "cm_lsrk_step", "cm_lsrk144_step", "cm_exp_filter", "cm_diagnostics",
+    "cm_hevi_workspace_bytes", "cm_hevi_step", "cm_hevi_operator", "cm_hevi_solve",
     "cm_diagnostics_noalloc",
     "cm_mlp_create",
     "cm_mlp_destroy", "cm_mlp_train_step", "cm_mlp_grads", "cm_mlp_infer", "cm_mlp_get_params",
@@ -101,6 +102,10 @@ def load():
     L.cm_lsrk_step.argtypes = [_VP, _VP, _VP, _VP, C.c_double, C.c_double, _VP]
     L.cm_lsrk144_step.argtypes = [_VP, _VP, _VP, _VP, C.c_double, C.c_double, _VP]
     L.cm_exp_filter.argtypes = [_VP, _VP, C.c_int, C.c_int, C.c_double, C.c_int, _VP]
+    L.cm_hevi_workspace_bytes.argtypes = [_VP, C.POINTER(C.c_size_t)]
+    L.cm_hevi_step.argtypes = [_VP, _VP, _VP, C.c_double, C.c_double, _VP]
+    L.cm_hevi_operator.argtypes = [_VP, _VP, _VP, _VP]
+    L.cm_hevi_solve.argtypes = [_VP, C.c_double, _VP, _VP, _VP, _VP]
     L.cm_diagnostics.argtypes = [_VP, _VP, C.c_double, C.POINTER(Diag), _VP]
     L.cm_diagnostics_noalloc.argtypes = [_VP, _VP, C.c_double, C.POINTER(Diag), _VP]
     L.cm_mlp_create.argtypes = [C.POINTER(MLPDesc), C.c_uint64, C.c_int, C.POINTER(_VP)]
@@ -299,6 +304,31 @@ class Model:
         self._chk(Y, Y_alt, dQ)
         _check(load().cm_lsrk144_step(self.h, Y.data_ptr(), Y_alt.data_ptr(), dQ.data_ptr(), float(t),
                                       float(dt), _stream_ptr(stream)))
+        return Y
+
+    def hevi_workspace(self):
+        """A device workspace for the 1-D IMEX calls (uint8 tensor)."""
+        import torch
+
+        n = C.c_size_t()
+        _check(load().cm_hevi_workspace_bytes(self.h, C.byref(n)))
+        return torch.empty(int(n.value), dtype=torch.uint8, device="cuda:%d" % self.grid.device)
+
+    def hevi_step(self, Y, work, t: float, dt: float, stream=None):
+        """One 1-D IMEX (HEVI, ARK2) step; Y is advanced in place."""
+        self._chk(Y)
+        _check(load().cm_hevi_step(self.h, Y.data_ptr(), work.data_ptr(), float(t), float(dt), _stream_ptr(stream)))
+        return Y
+
+    def hevi_operator(self, Y, out, stream=None):
+        self._chk(Y, out)
+        _check(load().cm_hevi_operator(self.h, Y.data_ptr(), out.data_ptr(), _stream_ptr(stream)))
+        return out
+
+    def hevi_solve(self, tau: float, B, Y, work, stream=None):
+        self._chk(B, Y)
+        _check(load().cm_hevi_solve(self.h, float(tau), B.data_ptr(), Y.data_ptr(), work.data_ptr(),
+                                    _stream_ptr(stream)))
         return Y
 
     def exp_filter(self, Y, mask: int, order: int = 64, alpha: float = 36.0, Nc: int = 0, stream=None):

@@ -692,6 +692,108 @@ cm_status cm_exp_filter(cm_model* m, void* Y, int var_mask, int order, double al
     return CM_OK;
 }
 
+// ---- 1-D IMEX (HEVI) -----------------------------------------------------
+static cm_status hevi_check(const cm_model* m, const char* name)
+{
+    if (!m) { set_error(std::string(name) + ": null model"); return CM_ERR_ARG; }
+    const cm_grid* g = m->grid;
+    if (m->desc.nvar != 5 || g->desc.topo != 0 || g->desc.periodic[2]) {
+        set_error(std::string(name) + ": the 1-D IMEX step is for dry models on flat meshes with walls at "
+                                      "the bottom and top");
+        return CM_ERR_UNSUPPORTED;
+    }
+    return CM_OK;
+}
+
+static size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+// workspace: seven state buffers (the stage state, three explicit and three
+// implicit tendencies), then the line solver's 60 doubles per element layer
+// and vertical node line
+static size_t hevi_state_bytes(const cm_model* m)
+{
+    const size_t s = m->desc.precision == CM_FP64 ? 8 : 4;
+    return align256(s * m->desc.nvar * m->grid->n_elem * SRUN);
+}
+
+cm_status cm_hevi_workspace_bytes(const cm_model* m, size_t* bytes)
+{
+    cm_status st = hevi_check(m, "cm_hevi_workspace_bytes");
+    if (st != CM_OK) return st;
+    if (!bytes) { set_error("cm_hevi_workspace_bytes: null argument"); return CM_ERR_ARG; }
+    *bytes = 7 * hevi_state_bytes(m) +
+             align256(sizeof(double) * 60 * (size_t)m->grid->desc.ne[2] * (size_t)hevi_lines(m));
+    return CM_OK;
+}
+
+cm_status cm_hevi_step(cm_model* m, void* Y, void* work, double t, double dt, void* stream)
+{
+    (void)t;
+    cm_status st = hevi_check(m, "cm_hevi_step");
+    if (st != CM_OK) return st;
+    st = check_model(m, "cm_hevi_step");
+    if (st != CM_OK) return st;
+    if (!Y || !work) { set_error("cm_hevi_step: null pointer"); return CM_ERR_ARG; }
+    if (!(dt > 0.0) || !std::isfinite(dt)) { set_error("cm_hevi_step: dt must be positive and finite"); return CM_ERR_ARG; }
+    CM_TRY_HIP(hipSetDevice(m->grid->device), "hipSetDevice");
+    hipStream_t s = (hipStream_t)stream;
+    const size_t sb = hevi_state_bytes(m);
+    char* w = (char*)work;
+    void* Ys = w;
+    void* E[3] = {w + sb, w + 2 * sb, w + 3 * sb};
+    void* L[3] = {w + 4 * sb, w + 5 * sb, w + 6 * sb};
+    double* scratch = (double*)(w + 7 * sb);
+    // ARK2 of Giraldo, Kelly & Constantinescu (2013)
+    const double gam = 1.0 - 1.0 / std::sqrt(2.0), del = 1.0 / (2.0 * std::sqrt(2.0));
+    const double a32 = (3.0 + 2.0 * std::sqrt(2.0)) / 6.0;
+    const double AE[3][3] = {{0, 0, 0}, {2 * gam, 0, 0}, {1 - a32, a32, 0}};
+    const double AI[3][3] = {{0, 0, 0}, {gam, gam, 0}, {del, del, gam}};
+    const double bw[3] = {del, del, gam};
+    for (int stg = 0; stg < 3; ++stg) {
+        double c[6];
+        const void* X[6];
+        int n = 0;
+        for (int r = 0; r < stg; ++r) {
+            c[n] = dt * AE[stg][r]; X[n++] = E[r];
+            c[n] = dt * AI[stg][r]; X[n++] = L[r];
+        }
+        CM_TRY_HIP(launch_combine(m, Y, Ys, n, c, X, s), "cm_hevi_step combine");
+        if (AI[stg][stg] != 0.0)
+            CM_TRY_HIP(launch_hevi_solve(m, dt * AI[stg][stg], Ys, Ys, scratch, s), "cm_hevi_step solve");
+        CM_TRY_HIP(launch_rhs(m, Ys, E[stg], nullptr, 0, 0.0, 0.0, 0.0, s), "cm_hevi_step rhs");
+        CM_TRY_HIP(launch_hevi_operator(m, Ys, L[stg], E[stg], s), "cm_hevi_step operator");
+    }
+    double c[6];
+    const void* X[6];
+    for (int r = 0; r < 3; ++r) {
+        c[2 * r] = dt * bw[r]; X[2 * r] = E[r];
+        c[2 * r + 1] = dt * bw[r]; X[2 * r + 1] = L[r];
+    }
+    CM_TRY_HIP(launch_combine(m, Y, Y, 6, c, X, s), "cm_hevi_step update");
+    return CM_OK;
+}
+
+cm_status cm_hevi_operator(cm_model* m, const void* Y, void* LY, void* stream)
+{
+    cm_status st = hevi_check(m, "cm_hevi_operator");
+    if (st != CM_OK) return st;
+    if (!Y || !LY || Y == LY) { set_error("cm_hevi_operator: bad state pointers"); return CM_ERR_ARG; }
+    CM_TRY_HIP(hipSetDevice(m->grid->device), "hipSetDevice");
+    CM_TRY_HIP(launch_hevi_operator(m, Y, LY, nullptr, (hipStream_t)stream), "cm_hevi_operator");
+    return CM_OK;
+}
+
+cm_status cm_hevi_solve(cm_model* m, double tau, const void* B, void* Y, void* work, void* stream)
+{
+    cm_status st = hevi_check(m, "cm_hevi_solve");
+    if (st != CM_OK) return st;
+    if (!B || !Y || !work || !(tau >= 0.0) || !std::isfinite(tau)) { set_error("cm_hevi_solve: bad argument"); return CM_ERR_ARG; }
+    CM_TRY_HIP(hipSetDevice(m->grid->device), "hipSetDevice");
+    double* scratch = (double*)((char*)work + 7 * hevi_state_bytes(m));
+    CM_TRY_HIP(launch_hevi_solve(m, tau, B, Y, scratch, (hipStream_t)stream), "cm_hevi_solve");
+    return CM_OK;
+}
+
 cm_status cm_diagnostics_noalloc(cm_model* m, const void* Y, double dt, cm_diag* out, void* stream)
 {
     if (!m || !Y || !out) { set_error("cm_diagnostics_noalloc: null argument"); return CM_ERR_ARG; }

@@ -178,6 +178,13 @@ cm_model::ProfRec* prof_begin(cm_model* m, int kind, hipStream_t s);
 void prof_end(cm_model::ProfRec* r, hipStream_t s);
 // reductions (reduce.hip)
 hipError_t launch_diagnostics(const cm_model* m, const void* Y, double dt, cm_diag* out, hipStream_t s);
+// 1-D IMEX (hevi.hip): the linear vertical operator (Lout = L(Y - Y_ref),
+// Eout -= Lout when given), the line solves, and out = base + sum c_q X_q
+hipError_t launch_hevi_operator(const cm_model* m, const void* Y, void* Lout, void* Eout, hipStream_t s);
+hipError_t launch_hevi_solve(const cm_model* m, double tau, const void* B, void* Yout, double* scratch, hipStream_t s);
+hipError_t launch_combine(const cm_model* m, const void* base, void* out, int n, const double* c, const void* const* X,
+                          hipStream_t s);
+int64_t hevi_lines(const cm_model* m);
 // exponential modal filter (filter.hip): F1 the 1-D filter matrix [5][5]
 hipError_t launch_exp_filter(const cm_model* m, void* Y, int mask, const double* F1, hipStream_t s);
 // the same reduction over the library's static per-device workspace (no

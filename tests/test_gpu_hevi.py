@@ -1,0 +1,122 @@
+"""The 1-D IMEX step (HEVI, Sect. 3.2) on the GPU through the C ABI against
+the oracle: the linear vertical operator, the line solves, and whole ARK2
+steps (FP64 and FP32-bulk, inviscid and Smagorinsky), plus stability at a
+step far beyond the explicit vertical acoustic limit on a strongly
+anisotropic mesh, and the configurations it rejects."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2110_00853_amd import binding as B
+from paper_2110_00853_amd import workloads as W
+from parity import state_errors
+
+pytestmark = pytest.mark.gpu
+
+
+def _case(ne, hi, closure="smag"):
+    c = W.case("bubble_32", ne=ne, hi=hi)
+    c["model"]["closure"] = closure
+    return c
+
+
+CASES = {
+    "smag": _case((3, 2, 4), (900.0, 600.0, 800.0)),
+    "inviscid_ragged": _case((2, 3, 5), (600.0, 900.0, 500.0), closure="none"),
+    # 10 m-tall, 400 m-wide elements; a small constant viscosity (the
+    # implicit part covers the vertical acoustics, not vertical diffusion:
+    # Smagorinsky's eddy viscosity on 10 m layers limits the step itself)
+    "anisotropic": _case((3, 2, 6), (1200.0, 800.0, 60.0), closure="const"),
+}
+CASES["anisotropic"]["model"]["nu"] = 1.0
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_operator_and_solve_match_oracle(name):
+    import torch
+
+    c = CASES[name]
+    Y, Yref, _ = W.perturbed_state(c, seed=21, amp_u=5.0, amp_T=2.0)
+    g = B.Grid(c["grid"])
+    m = B.Model(g, c["model"], Yref)
+    om = oracle.Model(oracle.Grid(c["grid"]), c["model"], Yref)
+    print("hevi operator and solve:", name, flush=True)
+    Yd, Ld = m.new_state(Y), m.new_state()
+    m.hevi_operator(Yd, Ld)
+    work = m.hevi_workspace()
+    tau = 0.05
+    Xd = m.new_state()
+    m.hevi_solve(tau, Yd, Xd, work)
+    torch.cuda.synchronize()
+    Lo = om.hevi_operator(Y)
+    Lg = m.to_numpy(Ld)
+    for v in range(5):
+        sc = max(np.abs(Lo[v]).max(), 1e-300)
+        assert np.abs(Lg[v] - Lo[v]).max() <= 1e-12 * sc, (v, np.abs(Lg[v] - Lo[v]).max() / sc)
+    Xo = om.hevi_solve(tau, Y)
+    Xg = m.to_numpy(Xd)
+    for v in range(5):
+        sc = max(np.abs(Xo[v] - Yref[v]).max(), 1e-300)
+        err = np.abs(Xg[v] - Xo[v]).max() / sc
+        print(name, "solve var", v, "error relative to the deviation", err)
+        assert err <= 1e-11, (v, err)
+
+
+@pytest.mark.parametrize("name", ["smag", "inviscid_ragged"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_hevi_steps_match_oracle(name, precision):
+    import torch
+
+    c = CASES[name]
+    Y, Yref, speed = W.perturbed_state(c, seed=22, amp_u=5.0, amp_T=2.0)
+    dt = 0.5 * W.cfl_dt(c["grid"], speed)
+    g = B.Grid(c["grid"])
+    m = B.Model(g, c["model"], Yref, precision=precision)
+    Yd = m.new_state(Y)
+    work = m.hevi_workspace()
+    for _ in range(3):
+        m.hevi_step(Yd, work, 0.0, dt)
+    torch.cuda.synchronize()
+    Yo = oracle.Model(oracle.Grid(c["grid"]), c["model"], Yref).hevi_steps(Y, dt, 3)
+    err = state_errors(m.to_numpy(Yd).astype(np.float64), Yo)
+    print(name, precision, "HEVI state errors after 3 steps", err)
+    assert np.all(err < (1e-10 if precision == "fp64" else 1e-2)), err
+
+
+def test_hevi_stable_far_beyond_the_vertical_acoustic_limit():
+    """10 m-tall, 400 m-wide elements: twelve times the explicit vertical
+    step, 200 steps, bounded; the oracle agrees after 5 of them."""
+    import torch
+
+    c = CASES["anisotropic"]
+    Y, Yref, speed = W.perturbed_state(c, seed=23, amp_u=2.0, amp_T=0.5)
+    dt = 12.0 * W.cfl_dt(c["grid"], speed)
+    g = B.Grid(c["grid"])
+    m = B.Model(g, c["model"], Yref)
+    Yd = m.new_state(Y)
+    work = m.hevi_workspace()
+    for _ in range(5):
+        m.hevi_step(Yd, work, 0.0, dt)
+    torch.cuda.synchronize()
+    Yo = oracle.Model(oracle.Grid(c["grid"]), c["model"], Yref).hevi_steps(Y, dt, 5)
+    err = state_errors(m.to_numpy(Yd), Yo)
+    print("anisotropic HEVI, 5 steps at 12x the explicit vertical limit: state errors", err)
+    assert np.all(err < 1e-9), err
+    for _ in range(195):
+        m.hevi_step(Yd, work, 0.0, dt)
+    d = m.diagnostics(Yd, dt)
+    print("after 200 steps:", d)
+    assert d["n_nonfinite"] == 0 and d["max_abs_w"] < 10.0
+
+
+def test_hevi_rejects_moist_warped_and_vertically_periodic_models():
+    for name, grid_kw, model_kw in [("moist_64", {}, {}), ("agnesi_96", {}, {}),
+                                   ("bubble_32", {"periodic": [1, 1, 1]}, {"g": 0.0})]:
+        c = W.case(name, ne=(2, 2, 2), hi=(400.0, 400.0, 400.0))
+        c["grid"].update(grid_kw)
+        c["model"].update(model_kw)
+        g = B.Grid(c["grid"])
+        m = B.Model(g, c["model"], None)
+        with pytest.raises(B.CMError) as ei:
+            m.hevi_workspace()
+        assert ei.value.status == B.CM_ERR_UNSUPPORTED
