@@ -129,6 +129,8 @@ def _declare(L):
     L.cmref_mlp_forward_bf16.argtypes = [_P, _P, C.c_int, _P]
     L.cmref_mlp_grad.argtypes = [_P, _P, _P, C.c_int, _P]
     L.cmref_mlp_grad.restype = C.c_double
+    L.cmref_mlp_grad_bf16.argtypes = [_P, _P, _P, C.c_int, _P, _P]
+    L.cmref_mlp_grad_bf16.restype = C.c_double
     L.cmref_adam_step.argtypes = [_P, _P, _P, _P, C.c_int, C.c_double, C.c_double, C.c_double, C.c_double]
     L.cmref_bf16.argtypes = [C.c_double]
     L.cmref_bf16.restype = C.c_double
@@ -465,6 +467,19 @@ def mlp_grad(params, X, T):
     g = np.zeros(NPARAM)
     loss = lib().cmref_mlp_grad(p, X.ravel(), T.ravel(), X.shape[0], g)
     return loss, g
+
+
+def mlp_grad_bf16(params, X, T):
+    """(loss, gradient, magnitude) with the GPU's rounding points: bfloat16
+    matrix operands, FP32 sums, FP32 bias / SiLU / derivative arithmetic;
+    magnitude[q] = sum of |terms| of gradient q."""
+    p = np.ascontiguousarray(params, dtype=np.float64)
+    X = np.ascontiguousarray(X, dtype=np.float64)
+    T = np.ascontiguousarray(T, dtype=np.float64)
+    g = np.zeros(p.size)
+    mag = np.zeros(p.size)
+    loss = lib().cmref_mlp_grad_bf16(p, X.ravel(), T.ravel(), X.shape[0], g, mag)
+    return loss, g, mag
 
 
 def adam_step(params, grad, m, v, step, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):

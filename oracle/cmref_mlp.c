@@ -184,6 +184,93 @@ double cmref_mlp_grad(const double* p, const double* x, const double* t, int n, 
     return loss / n;
 }
 
+static float silu_f(float z) { return z / (1.0f + expf(-z)); }
+static float dsilu_f(float z)
+{
+    float sg = 1.0f / (1.0f + expf(-z));
+    return sg * (1.0f + z * (1.0f - sg));
+}
+static float bfr(double v) { return bf16_round((float)v); }
+
+/* The loss gradient as the GPU's training kernels form it, for an
+ * element-wise comparison: every operand of a matrix product (inputs,
+ * weights, activations, output and hidden gradients) rounded to bfloat16,
+ * the products summed exactly (FP64, where the GPU sums in FP32), sums of
+ * products rounded to FP32, then FP32 arithmetic for the bias, SiLU and its
+ * derivative, and the output residual 2 (o - t)/n.  mag[q] receives the
+ * sum of the magnitudes of the terms that make up g[q] (the scale an FP32
+ * summation error is relative to).  Returns the loss. */
+double cmref_mlp_grad_bf16(const double* p, const double* x, const double* t, int n, double* g, double* mag)
+{
+    const int offW[4] = {OFF_W1, OFF_W2, OFF_W3, OFF_W4};
+    const int offB[4] = {OFF_B1, OFF_B2, OFF_B3, OFF_B4};
+    const int nin[4] = {NI, NH, NH, NH}, nout[4] = {NH, NH, NH, NO};
+    float* Wb = (float*)malloc(sizeof(float) * NPARAM);
+    for (int q = 0; q < NPARAM; ++q) Wb[q] = bfr(p[q]);
+    /* per layer: the bf16 input of the product and the FP32 pre-activation */
+    float* in[4];
+    float* Z[4];
+    for (int l = 0; l < 4; ++l) {
+        in[l] = (float*)malloc(sizeof(float) * (size_t)n * nin[l]);
+        Z[l] = (float*)malloc(sizeof(float) * (size_t)n * nout[l]);
+    }
+    for (int s = 0; s < n; ++s)
+        for (int i = 0; i < NI; ++i) in[0][s * NI + i] = bfr(x[s * NI + i]);
+    for (int l = 0; l < 4; ++l)
+        for (int s = 0; s < n; ++s)
+            for (int k = 0; k < nout[l]; ++k) {
+                double acc = 0.0;
+                for (int i = 0; i < nin[l]; ++i) acc += (double)in[l][s * nin[l] + i] * Wb[offW[l] + k * nin[l] + i];
+                float z = (float)acc + (float)p[offB[l] + k];
+                Z[l][s * nout[l] + k] = z;
+                if (l < 3) in[l + 1][s * NH + k] = bf16_round(silu_f(z));
+            }
+    memset(g, 0, sizeof(double) * NPARAM);
+    memset(mag, 0, sizeof(double) * NPARAM);
+    /* output residual */
+    float* d = (float*)malloc(sizeof(float) * (size_t)n * NH);
+    float* dn = (float*)malloc(sizeof(float) * (size_t)n * NH);
+    double loss = 0.0;
+    for (int s = 0; s < n; ++s)
+        for (int k = 0; k < NO; ++k) {
+            float r = Z[3][s * NO + k] - (float)t[s * NO + k];
+            loss += (double)r * r;
+            d[s * NO + k] = 2.0f * r / (float)n;
+        }
+    for (int l = 3; l >= 0; --l) {
+        const int no = nout[l], ni = nin[l];
+        /* weight gradient sum_s bf16(d) bf16(in), bias gradient sum_s d */
+        for (int k = 0; k < no; ++k) {
+            for (int i = 0; i < ni; ++i) {
+                double acc = 0.0, am = 0.0;
+                for (int s = 0; s < n; ++s) {
+                    double term = (double)bf16_round(d[s * no + k]) * in[l][s * ni + i];
+                    acc += term;
+                    am += fabs(term);
+                }
+                g[offW[l] + k * ni + i] = (double)(float)acc;
+                mag[offW[l] + k * ni + i] = am;
+            }
+            double acc = 0.0, am = 0.0;
+            for (int s = 0; s < n; ++s) { acc += d[s * no + k]; am += fabs(d[s * no + k]); }
+            g[offB[l] + k] = (double)(float)acc;
+            mag[offB[l] + k] = am;
+        }
+        if (l == 0) break;
+        /* gradient of the layer below's pre-activation */
+        for (int s = 0; s < n; ++s)
+            for (int i = 0; i < ni; ++i) {
+                double acc = 0.0;
+                for (int k = 0; k < no; ++k) acc += (double)bf16_round(d[s * no + k]) * Wb[offW[l] + k * ni + i];
+                dn[s * ni + i] = (float)acc * dsilu_f(Z[l - 1][s * NH + i]);
+            }
+        float* tmp = d; d = dn; dn = tmp;
+    }
+    for (int l = 0; l < 4; ++l) { free(in[l]); free(Z[l]); }
+    free(d); free(dn); free(Wb);
+    return loss / n;
+}
+
 /* One Adam step (Kingma & Ba) with bias correction; step counts from 1. */
 void cmref_adam_step(double* p, const double* g, double* m, double* v, int step, double lr, double b1,
                      double b2, double eps)

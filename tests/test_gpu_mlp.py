@@ -1,7 +1,7 @@
-"""GPU checks of the learned closure: BF16-MFMA inference against the oracle
-network with bfloat16 operands, hand-written backward against the FP64
-oracle gradient, training lowers the loss, and the fused closure inside the
-gradient kernel against the oracle right-hand side."""
+"""GPU checks of the learned closure: BF16-MFMA inference and the hand-written
+backward against the oracle network with the same bfloat16 rounding points,
+element by element; training lowers the loss; and the fused closure inside
+the gradient kernel against the oracle right-hand side."""
 import numpy as np
 import pytest
 
@@ -34,6 +34,9 @@ def torch():
 
 
 def test_mfma_inference_matches_bf16_oracle(torch):
+    """Element by element: the oracle network with the same bfloat16
+    operands differs from the MFMA one only by FP32 summation order and the
+    odd hidden activation that rounds to the other bfloat16 neighbour."""
     p = _params(1)
     rng = np.random.default_rng(2)
     X = rng.normal(size=(3000, 12)).astype(np.float32)
@@ -47,11 +50,21 @@ def test_mfma_inference_matches_bf16_oracle(torch):
     e64 = np.abs(out - ref64).max() / scale
     print("vs bf16 oracle: median %.2e  99%% %.2e  max %.2e; vs fp64 max %.2e" % (
         np.median(e16), np.quantile(e16, 0.99), e16.max(), e64))
-    assert np.median(e16) < 1e-5 and np.quantile(e16, 0.99) < 1e-3
+    assert e16.max() < INFER_MAX, e16.max()
+    assert np.median(e16) < 1e-5
     assert e64 < 5e-2
 
 
-def test_backward_matches_fp64_gradient(torch):
+# measured maxima (6.6e-4 and 7.3e-6) times about four
+INFER_MAX = 3e-3
+GRAD_MAX = 3e-5
+
+
+def test_backward_matches_bf16_oracle_elementwise(torch):
+    """Every one of the 9282 gradient entries against the oracle gradient
+    with the same rounding points (bfloat16 operands, FP32 sums and
+    activations), relative to the sum of the magnitudes of its terms; the
+    FP64 gradient as a looser check on the whole."""
     p = _params(3)
     rng = np.random.default_rng(4)
     X = rng.normal(size=(2048, 12)).astype(np.float32)
@@ -59,19 +72,20 @@ def test_backward_matches_fp64_gradient(torch):
     net = B.MLP(seed=0)
     net.set_params(p)
     g = net.grads(torch.from_numpy(X).cuda(), torch.from_numpy(T).cuda()).astype(np.float64)
+    _, g16, mag = oracle.mlp_grad_bf16(p, X.astype(np.float64), T.astype(np.float64))
+    ratio = np.abs(g - g16) / mag
+    off = 0
+    for name, n in (("W1", 768), ("b1", 64), ("W2", 4096), ("b2", 64), ("W3", 4096), ("b3", 64),
+                    ("W4", 128), ("b4", 2)):
+        r = ratio[off:off + n]
+        print("%s: max %.2e  median %.2e" % (name, r.max(), np.median(r)))
+        off += n
+    assert ratio.max() < GRAD_MAX, (int(ratio.argmax()), ratio.max())
     _, gref = oracle.mlp_grad(p, X.astype(np.float64), T.astype(np.float64))
     rel = np.linalg.norm(g - gref) / np.linalg.norm(gref)
     cos = g @ gref / (np.linalg.norm(g) * np.linalg.norm(gref))
-    print("grad rel L2 %.3e cosine %.6f" % (rel, cos))
+    print("vs fp64: grad rel L2 %.3e cosine %.6f" % (rel, cos))
     assert rel < 3e-2 and cos > 0.999
-    # each layer separately
-    off = 0
-    for nout, nin in ((64, 12), (64, 64), (64, 64), (2, 64)):
-        for n in (nout * nin, nout):
-            seg = slice(off, off + n)
-            r = np.linalg.norm(g[seg] - gref[seg]) / np.linalg.norm(gref[seg])
-            assert r < 5e-2, (off, r)
-            off += n
 
 
 def test_training_reduces_loss(torch):

@@ -174,3 +174,28 @@ def test_closure_constant_training_input_passes_at_its_value(oracle_lib):
     gu = np.zeros((3, 3))
     assert not oracle_lib.mlp_closure(p, mean, std, lo, hi, gu, 0.0, Delta, 0.0)[0]
     assert oracle_lib.mlp_closure(p, mean, std, lo, hi, gu, 0.0, Delta * 1.001, 0.0)[0]
+
+
+def test_bf16_emulated_gradient_against_fp64(oracle_lib):
+    """The gradient with the GPU's rounding points (bfloat16 products, FP32
+    sums and activations) stays within the bfloat16 rounding of the FP64
+    back-propagated gradient (pinned above by finite differences), term by
+    term: |g16 - g64| <= 0.03 sum|terms|, with 2^-8 the bfloat16 unit
+    roundoff compounded over four layers. A dropped term, a transposed
+    operand or a derivative at the wrong layer is an O(1) change of that
+    ratio. Its loss is the mean squared error of the bfloat16 forward pass."""
+    rng = np.random.default_rng(6)
+    p = _random_params(7).astype(np.float32).astype(np.float64)
+    X = rng.normal(size=(300, NI)).astype(np.float32).astype(np.float64)
+    T = rng.normal(size=(300, NO)).astype(np.float32).astype(np.float64)
+    l64, g64 = oracle_lib.mlp_grad(p, X, T)
+    l16, g16, mag = oracle_lib.mlp_grad_bf16(p, X, T)
+    assert np.all(mag > 0)
+    ratio = np.abs(g16 - g64) / mag
+    assert ratio.max() < 0.03, ratio.max()
+    assert np.linalg.norm(g16 - g64) < 1e-2 * np.linalg.norm(g64)
+    # and it is not the FP64 gradient: the rounding shows
+    assert ratio.max() > 1e-5
+    o16 = oracle_lib.mlp_forward(p, X, bf16=True)
+    assert l16 == pytest.approx(np.sum((o16 - T) ** 2) / 300, rel=1e-6)
+    assert l16 == pytest.approx(l64, rel=1e-2)
