@@ -398,7 +398,7 @@ def initial_state(c: dict, xyz=None):
     z = xyz[2]
     zero = np.zeros_like(z)
     if ic["kind"] == "bubble":
-        Y, Yref, cmax = bubble_state(grid, ic["center"], g=g, xyz=xyz)
+        Y, Yref, cmax = bubble_state(grid, ic["center"], dtheta=ic.get("dtheta", 1.0), g=g, xyz=xyz)
         return Y, Yref, cfl_dt(grid, cmax)
     if ic["kind"] == "density_current":
         Y, Yref, cmax = density_current_state(grid, ic["theta0"], ic["theta_c"], ic["center"], ic["radii"],

@@ -160,3 +160,35 @@ def test_fused_closure_rhs_matches_oracle(torch):
     print("fused mlp closure rhs errors", err, "fallbacks", nfb, nfb_ref)
     assert abs(nfb - nfb_ref) <= max(2, 0.01 * nfb_ref)
     assert np.all(err < 1e-4), err
+
+
+def test_no_fallback_inside_training_range_with_a_non_float_filter_width(torch):
+    """Filter width 1000/12 m (3 elements over 1 km), which float32 cannot
+    hold: with the training range spanning every node's inputs, no node falls
+    back, on the GPU or in the oracle, and the right-hand sides agree."""
+    c = W.case("learned_32", ne=(3, 3, 3), hi=(1000.0, 1000.0, 1000.0))
+    Y, Yref, _ = W.perturbed_state(c, seed=12, amp_u=6.0, amp_T=2.0)
+    raw = _features(c, Y, Yref)
+    Delta = raw[0, 10]
+    assert np.float32(Delta) != Delta
+    mean = raw.mean(axis=0)
+    std = raw.std(axis=0)
+    std[std == 0] = 1.0
+    Xs = (raw - mean) / std
+    norm = np.concatenate([mean, std, Xs.min(axis=0), Xs.max(axis=0)]).astype(np.float32)
+    mean, std, lo, hi = (norm[12 * q:12 * (q + 1)].astype(np.float64) for q in range(4))
+    p = _params(13)
+    p[-2:] = [-1.0, 0.2]
+    om = oracle.Model(oracle.Grid(c["grid"]), c["model"], Yref)
+    om.set_mlp(p, mean, std, lo, hi, use_fallback=True, bf16=True)
+    Rref = om.rhs(Y)
+    g = B.Grid(c["grid"])
+    m = B.Model(g, c["model"], Yref)
+    m.set_mlp(p.astype(np.float32), norm)
+    Yd, Rd = m.new_state(Y), m.new_state()
+    m.rhs(Yd, Rd)
+    nfb, nfb_ref = m.mlp_fallbacks(), om.mlp_fallbacks()
+    err = rhs_errors(m.to_numpy(Rd), Rref, Y, hmin(c["grid"]))
+    print("non-float filter width: fallbacks", nfb, nfb_ref, "rhs errors", err)
+    assert nfb == 0 and nfb_ref == 0
+    assert np.all(err < 1e-4), err

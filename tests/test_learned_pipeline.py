@@ -53,3 +53,41 @@ def test_no_sgs_stress_without_subfilter_content():
     m = Yc[1:4]
     for q, (a, b) in enumerate(((0, 0), (1, 1), (2, 2), (0, 1), (0, 2), (1, 2))):
         assert np.allclose(ruu[q] - m[a] * m[b] / Yc[0], 0.0, atol=1e-10 * np.abs(ruu[q]).max())
+
+
+def test_heldout_box_interior_reproduces_full_grid_inputs(oracle_lib, tmp_path):
+    """Closure inputs and targets recomputed on a stored box's interior
+    elements equal those of the whole coarse grid at the same nodes (BR1
+    gradients reach face neighbours only), up to the box's float32 storage."""
+    import sys
+    import os
+
+    sys.path.insert(0, os.path.dirname(__file__))
+    from test_learned_gain import box_samples
+
+    cf = W.case("bubble_32", ne=(16, 16, 16))
+    cc = W.case("bubble_32", ne=(8, 8, 8))
+    Yf, _, _ = W.perturbed_state(cf, seed=31, amp_u=4.0, amp_T=1.0)
+    zf = W.node_coords(cf["grid"])[2]
+    snap = Lp.filtered(Yf, zf, cf["grid"]["ne"])
+    Yc = snap[0]
+    Gd = oracle_lib.Grid(cc["grid"])
+    grad, _ = oracle_lib.Model(Gd, dict(cc["model"], closure="smag")).gradients(Yc)
+    gu, gth = grad[:3], grad[-1]
+    h = 6400.0 / 8
+    Delta = float(np.cbrt((h / 4) ** 3))
+    tau, q = Lp.sgs_fluxes(*snap)
+    T_full, mask = Lp.targets_from_fluxes(Yc[0], tau, q, gu, gth, Delta)
+    assert mask.sum() > 1000
+    box = Lp.heldout_box(snap, mask, cc["grid"])
+    path = str(tmp_path / "box.npz")
+    np.savez(path, Delta=np.float64(Delta), **{"box_%s" % k: v for k, v in box.items()})
+    X, T, _ = box_samples(np.load(path), cc["model"]["Cs"], cc["model"]["Prt"])
+    # the same nodes on the full grid
+    st = box["start"]
+    ez, ey, ex = np.meshgrid(*[np.arange(st[d] + 1, st[d] + 5) for d in (2, 1, 0)], indexing="ij")
+    nodes = ((((ez * 8 + ey) * 8 + ex).ravel())[:, None] * 125 + np.arange(125)[None]).ravel()
+    m = mask[nodes]
+    assert np.allclose(T, T_full[nodes][m], rtol=0, atol=2e-3 * np.abs(T_full[nodes][m]).max())
+    gu_full = gu[:, :, nodes][:, :, m].reshape(9, -1).T
+    assert np.allclose(X[:, :9], gu_full, rtol=0, atol=1e-5 * np.abs(gu_full).max())
