@@ -92,7 +92,7 @@ struct KParams {
     // learned closure
     const uint16_t* mlp_frag;   // bf16 B fragments of the four layers
     const float* mlp_bias;      // biases: 64, 64, 64, 2 (padded to 16)
-    const double* mlp_norm;     // mean[12], std[12], range centre[12], allowed distance from it[12]
+    const double* mlp_norm;     // mean[12], std[12], range centre[12], allowed distance from it[12], 1/std[12]
     int mlp_fallback_on;
     unsigned long long* mlp_fallbacks;
     double* feat_out;           // when set, the gradient pass also writes the closure inputs [nn][16]

@@ -305,11 +305,12 @@ __device__ __forceinline__ float silu_fast(float z)
     return z * __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(-1.4426950408889634f * z));
 }
 
-// bias + SiLU of one accumulator tile, rounded to bf16 (nearest even)
-__device__ __forceinline__ bf16x4 act_bf16(const f32x4& d, const float4& b)
+// SiLU of one accumulator tile (bias included: the accumulation starts from
+// it), rounded to bf16 (nearest even)
+__device__ __forceinline__ bf16x4 act_bf16(const f32x4& d)
 {
-    const f32x2 lo = {silu_fast(d[0] + b.x), silu_fast(d[1] + b.y)};
-    const f32x2 hi = {silu_fast(d[2] + b.z), silu_fast(d[3] + b.w)};
+    const f32x2 lo = {silu_fast(d[0]), silu_fast(d[1])};
+    const f32x2 hi = {silu_fast(d[2]), silu_fast(d[3])};
     const u32x2 u = {__builtin_bit_cast(unsigned, __builtin_convertvector(lo, bf16x2v)),
                      __builtin_bit_cast(unsigned, __builtin_convertvector(hi, bf16x2v))};
     return __builtin_bit_cast(bf16x4, u);
@@ -331,43 +332,44 @@ __device__ __forceinline__ void mlp_forward_wave(const KParams& P, const uint16_
 #pragma unroll
     for (int ht = 0; ht < 4; ++ht) {
         const bf16x4 a = frag[ht * 64 + lane];
-        const float4 b = *(const float4*)&bias[16 * ht + kq];
+        const f32x4 b = *(const f32x4*)&bias[16 * ht + kq];
 #pragma unroll
-        for (int nt = 0; nt < 4; ++nt)
-            h[ht][nt] = act_bf16(mfma16(a, xin[nt], f32x4{0.0f, 0.0f, 0.0f, 0.0f}), b);
+        for (int nt = 0; nt < 4; ++nt) h[ht][nt] = act_bf16(mfma16(a, xin[nt], b));
     }
-    // layers 2 and 3: K = 64
+    // layers 2 and 3: K = 64 as two 32-wide chunks; chunk c of a node tile
+    // is the activation tiles 2c and 2c + 1 side by side
+    const bf16x8s* frag8 = (const bf16x8s*)P.mlp_frag;   // in units of 64 lanes x 8
 #pragma unroll
     for (int layer = 0; layer < 2; ++layer) {
         f32x4 acc[4][4];
 #pragma unroll
+        for (int ht = 0; ht < 4; ++ht) {
+            const f32x4 b = *(const f32x4*)&bias[64 * (layer + 1) + 16 * ht + kq];
+#pragma unroll
+            for (int nt = 0; nt < 4; ++nt) acc[ht][nt] = b;
+        }
+#pragma unroll
         for (int ht = 0; ht < 4; ++ht)
 #pragma unroll
-            for (int nt = 0; nt < 4; ++nt) acc[ht][nt] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+            for (int c = 0; c < 2; ++c) {
+                const bf16x8s a = frag8[((FRAG_L1 + layer * FRAG_L2) / 2 + 2 * ht + c) * 64 + lane];
 #pragma unroll
-        for (int ht = 0; ht < 4; ++ht)
-#pragma unroll
-            for (int ks = 0; ks < 4; ++ks) {
-                const bf16x4 a = frag[(FRAG_L1 + layer * FRAG_L2 + 4 * ht + ks) * 64 + lane];
-#pragma unroll
-                for (int nt = 0; nt < 4; ++nt) acc[ht][nt] = mfma16(a, h[ks][nt], acc[ht][nt]);
+                for (int nt = 0; nt < 4; ++nt) acc[ht][nt] = mfma32(a, h[2 * c][nt], h[2 * c + 1][nt], acc[ht][nt]);
             }
 #pragma unroll
-        for (int ht = 0; ht < 4; ++ht) {
-            const float4 b = *(const float4*)&bias[64 * (layer + 1) + 16 * ht + kq];
+        for (int ht = 0; ht < 4; ++ht)
 #pragma unroll
-            for (int nt = 0; nt < 4; ++nt) h[ht][nt] = act_bf16(acc[ht][nt], b);
-        }
+            for (int nt = 0; nt < 4; ++nt) h[ht][nt] = act_bf16(acc[ht][nt]);
     }
     // layer 4: one 16-row output tile (rows 0 and 1 real)
     f32x4 out[4];
 #pragma unroll
     for (int nt = 0; nt < 4; ++nt) out[nt] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
-    for (int ks = 0; ks < 4; ++ks) {
-        const bf16x4 a = frag[(FRAG_L1 + FRAG_L2 + FRAG_L3 + ks) * 64 + lane];
+    for (int c = 0; c < 2; ++c) {
+        const bf16x8s a = frag8[((FRAG_L1 + FRAG_L2 + FRAG_L3) / 2 + c) * 64 + lane];
 #pragma unroll
-        for (int nt = 0; nt < 4; ++nt) out[nt] = mfma16(a, h[ks][nt], out[nt]);
+        for (int nt = 0; nt < 4; ++nt) out[nt] = mfma32(a, h[2 * c][nt], h[2 * c + 1][nt], out[nt]);
     }
     // lane r < 16 holds rows 0..3 of node 16 nt + r: move outputs 0 and 1 to
     // the lane that owns the node (16 nt + r)
@@ -382,7 +384,14 @@ __device__ __forceinline__ void mlp_forward_wave(const KParams& P, const uint16_
     o1 = v1 + bias[193];
 }
 
-__device__ __forceinline__ double softplus_d(double x) { return x > 30.0 ? x : log1p(exp(x)); }
+// softplus log(1 + e^x) = max(x, 0) + log(1 + e^-|x|) in FP32 from the
+// hardware exp2 / log2 estimates (log(1 + u) by its series for u < 2^-10)
+__device__ __forceinline__ float softplus_f(float x)
+{
+    const float u = __builtin_amdgcn_exp2f(-1.4426950408889634f * fabsf(x));
+    const float l = u < 0x1p-10f ? u * (1.0f - 0.5f * u) : 0.6931471805599453f * __builtin_amdgcn_logf(1.0f + u);
+    return fmaxf(x, 0.0f) + l;
+}
 
 // neighbour state of one gradient face task
 template <typename R, bool MOIST>
@@ -649,7 +658,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(MLP || MO
             bool out_of_range = false;
 #pragma unroll
             for (int q = 0; q < 12; ++q) {
-                const double x = (raw[q] - P.mlp_norm[q]) / P.mlp_norm[12 + q];
+                const double x = (raw[q] - P.mlp_norm[q]) * P.mlp_norm[48 + q];
                 if (fabs(x - P.mlp_norm[24 + q]) > P.mlp_norm[36 + q]) out_of_range = true;
                 sX[t][q] = f2bf((float)x);
             }
@@ -663,8 +672,8 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(MLP || MO
             for (int a = 0; a < 3; ++a)
 #pragma unroll
                 for (int b = 0; b < 3; ++b) SSd += 2.0 * (double)S[a][b] * (double)S[a][b];
-            const double nu_m = P.Delta * P.Delta * sqrt(SSd) * softplus_d((double)o0);
-            const double pr_m = 0.1 + softplus_d((double)o1);
+            const double nu_m = P.Delta * P.Delta * sqrt(SSd) * (double)softplus_f(o0);
+            const double pr_m = 0.1 + (double)softplus_f(o1);
             const bool fb = P.mlp_fallback_on && (out_of_range || !isfinite(nu_m) || !isfinite(pr_m));
             if (!fb) {
                 nu = (R)nu_m;

@@ -413,24 +413,32 @@ cm_status cm_model_set_mlp(cm_model* m, const float* params, const float* norm)
             return CM_ERR_ARG;
         }
     CM_TRY_HIP(hipSetDevice(m->grid->device), "hipSetDevice");
-    // A-operand tiles of W [out][in] for the transposed forward: fragment
-    // (layer, output tile ht, k step ks), lane l, element q holds
-    // W[16 ht + l % 16][16 ks + 4 (l / 16) + q] (zero outside the matrix)
+    // A-operand tiles of W [out][in] for the transposed forward (zero
+    // outside the matrix).  Layer 1, 16x16x16 tile ht: lane l, element q holds
+    // W[16 ht + l % 16][4 (l / 16) + q].  Layers 2-4, 16x16x32 tile (ht, chunk
+    // c): lane l, slot s holds W[16 ht + l % 16][32 c + k32_unit(l / 16, s)].
     std::vector<uint16_t> frag((size_t)FRAG_TOTAL * 64 * 4, 0);
-    struct L { int off, nin, nout, ht, ks; } layers[4] = {
-        {OFF_W1, MLP_NI, MLP_NH, 4, 1}, {OFF_W2, MLP_NH, MLP_NH, 4, 4},
-        {OFF_W3, MLP_NH, MLP_NH, 4, 4}, {OFF_W4, MLP_NH, MLP_NO, 1, 4}};
-    int f = 0;
-    for (const L& l : layers)
+    struct L { int off, nin, nout, ht, base; } layers[4] = {
+        {OFF_W1, MLP_NI, MLP_NH, 4, 0}, {OFF_W2, MLP_NH, MLP_NH, 4, FRAG_L1},
+        {OFF_W3, MLP_NH, MLP_NH, 4, FRAG_L1 + FRAG_L2}, {OFF_W4, MLP_NH, MLP_NO, 1, FRAG_L1 + FRAG_L2 + FRAG_L3}};
+    auto wbf = [&](const L& l, int j, int k) {
+        return f2bf((j < l.nout && k < l.nin) ? params[l.off + j * l.nin + k] : 0.0f);
+    };
+    for (int ht = 0; ht < 4; ++ht)
+        for (int lane = 0; lane < 64; ++lane)
+            for (int q = 0; q < 4; ++q)
+                frag[((size_t)ht * 64 + lane) * 4 + q] = wbf(layers[0], ht * 16 + (lane & 15), 4 * (lane >> 4) + q);
+    for (int li = 1; li < 4; ++li) {
+        const L& l = layers[li];
         for (int ht = 0; ht < l.ht; ++ht)
-            for (int ks = 0; ks < l.ks; ++ks, ++f)
+            for (int c = 0; c < 2; ++c)
                 for (int lane = 0; lane < 64; ++lane)
-                    for (int q = 0; q < 4; ++q) {
-                        const int j = ht * 16 + (lane & 15);
-                        const int k = ks * 16 + 4 * (lane >> 4) + q;
-                        const float w = (j < l.nout && k < l.nin) ? params[l.off + j * l.nin + k] : 0.0f;
-                        frag[((size_t)f * 64 + lane) * 4 + q] = f2bf(w);
+                    for (int s = 0; s < 8; ++s) {
+                        const size_t unit = (size_t)l.base + 2 * (2 * ht + c);
+                        frag[unit * 64 * 4 + (size_t)lane * 8 + s] =
+                            wbf(l, ht * 16 + (lane & 15), 32 * c + k32_unit(lane >> 4, s));
                     }
+    }
     std::vector<float> bias(3 * MLP_NH + 16, 0.0f);
     for (int q = 0; q < MLP_NH; ++q) {
         bias[q] = params[OFF_B1 + q];
@@ -442,25 +450,27 @@ cm_status cm_model_set_mlp(cm_model* m, const float* params, const float* norm)
     // device copy: mean[12], std[12], centre of the standardised training
     // range[12], allowed distance from the centre[12] = 1.1 x half-width plus
     // 2^-20 (1 + |mean/std|) (the float rounding of the normalisation, so an
-    // input that was constant in training passes at its training value)
-    std::vector<double> nrm(48);
+    // input that was constant in training passes at its training value),
+    // 1 / std[12]
+    std::vector<double> nrm(60);
     for (int q = 0; q < 12; ++q) {
         const double mean = norm[q], sd = norm[12 + q], lo = norm[24 + q], hi = norm[36 + q];
         nrm[q] = mean;
         nrm[12 + q] = sd;
         nrm[24 + q] = 0.5 * (lo + hi);
         nrm[36 + q] = 1.1 * (0.5 * (hi - lo)) + std::ldexp(1.0 + std::fabs(mean / sd), -20);
+        nrm[48 + q] = 1.0 / sd;
     }
     if (!m->d_mlp_w) {
         const size_t bytes = frag.size() * sizeof(uint16_t) + bias.size() * sizeof(float);
         CM_TRY_HIP(hipMalloc(&m->d_mlp_w, bytes), "cm_model_set_mlp");
-        CM_TRY_HIP(hipMalloc(&m->d_mlp_norm, sizeof(double) * 48), "cm_model_set_mlp");
+        CM_TRY_HIP(hipMalloc(&m->d_mlp_norm, sizeof(double) * 60), "cm_model_set_mlp");
     }
     uint16_t* dfrag = (uint16_t*)m->d_mlp_w;
     float* dbias = (float*)(dfrag + frag.size());
     CM_TRY_HIP(hipMemcpy(dfrag, frag.data(), frag.size() * sizeof(uint16_t), hipMemcpyHostToDevice), "copy");
     CM_TRY_HIP(hipMemcpy(dbias, bias.data(), bias.size() * sizeof(float), hipMemcpyHostToDevice), "copy");
-    CM_TRY_HIP(hipMemcpy(m->d_mlp_norm, nrm.data(), sizeof(double) * 48, hipMemcpyHostToDevice), "copy");
+    CM_TRY_HIP(hipMemcpy(m->d_mlp_norm, nrm.data(), sizeof(double) * 60, hipMemcpyHostToDevice), "copy");
     m->kp.mlp_frag = dfrag;
     m->kp.mlp_bias = dbias;
     m->kp.mlp_norm = m->d_mlp_norm;

@@ -269,21 +269,37 @@ def no_fallback(norm):
     return n
 
 
-def posteriori(cc, Yref_c, Yc0, ref_snap, t_eval, nets, log, on_result=None):
+def _errors(Y, zc, th_bg, snap):
+    """theta and w errors of a coarse state against a filtered snapshot:
+    relative L2 (theta of its deviation from the background) and RMS."""
+    Yr = snap[0]
+    th_ref = snap[2] / Yr[0]
+    w_ref = Yr[3] / Yr[0]
+    th = _theta(Y, zc)
+    w = Y[3] / Y[0]
+    n = float(th.size)
+    return {"theta_rel_l2": float(np.linalg.norm(th - th_ref) / np.linalg.norm(th_ref - th_bg)),
+            "w_rel_l2": float(np.linalg.norm(w - w_ref) / np.linalg.norm(w_ref)),
+            "theta_rms_K": float(np.linalg.norm(th - th_ref) / np.sqrt(n)),
+            "theta_dev_rms_K": float(np.linalg.norm(th_ref - th_bg) / np.sqrt(n)),
+            "w_rms": float(np.linalg.norm(w - w_ref) / np.sqrt(n)),
+            "w_ref_rms": float(np.linalg.norm(w_ref) / np.sqrt(n))}
+
+
+def posteriori(cc, Yref_c, Yc0, snaps, t_eval, nets, log, on_result=None):
     """Coarse runs from the filtered initial state to t_eval, one per
-    (name, closure, params, norm), against the filtered resolved run:
-    relative L2 errors of theta (of its deviation from the background) and w."""
+    (name, closure, params, norm), against the filtered resolved run at
+    t_eval (and, as a history, at every other snapshot time after 0): theta
+    (its deviation from the background) and w errors."""
     import torch
 
     gc = B.Grid(cc["grid"])
     zc = W.node_coords(cc["grid"])[2]
-    Yr = ref_snap[0]
-    th_ref = ref_snap[2] / Yr[0]
-    w_ref = Yr[3] / Yr[0]
     th_bg = _theta(Yref_c, zc)
     dt_c = W.cfl_dt(cc["grid"], 360.0)
     n_c = int(round(t_eval / dt_c))
     dt_c = t_eval / n_c
+    checks = {int(round(tc / dt_c)): tc for tc in snaps if 0.0 < tc < t_eval}
     out = {"dt_coarse": dt_c, "steps": n_c}
     for name, closure, params, norm in nets:
         m = B.Model(gc, dict(cc["model"], closure=closure), Yref_c)
@@ -291,23 +307,28 @@ def posteriori(cc, Yref_c, Yc0, ref_snap, t_eval, nets, log, on_result=None):
             m.set_mlp(params, norm)
         Ya, Yb, dQ = m.new_state(Yc0), m.new_state(), m.new_state()
         tt = 0.0
+        hist = {}
+        el = 0.0
         t0 = time.time()
-        for _ in range(n_c):
+        for s in range(1, n_c + 1):
             m.lsrk_step(Ya, Yb, dQ, tt, dt_c)
             Ya, Yb = Yb, Ya
             tt += dt_c
+            if s in checks:
+                torch.cuda.synchronize()
+                el += time.time() - t0
+                e = _errors(m.to_numpy(Ya), zc, th_bg, snaps[checks[s]])
+                hist["%g" % checks[s]] = [e["theta_rel_l2"], e["w_rel_l2"]]
+                t0 = time.time()
         torch.cuda.synchronize()
-        el = time.time() - t0
-        Y = m.to_numpy(Ya)
-        th = _theta(Y, zc)
-        w = Y[3] / Y[0]
-        r = {"theta_rel_l2": float(np.linalg.norm(th - th_ref) / np.linalg.norm(th_ref - th_bg)),
-             "w_rel_l2": float(np.linalg.norm(w - w_ref) / np.linalg.norm(w_ref)), "seconds": el,
-             "dof_updates_per_s": gc.n_nodes * 5 * 5 * n_c / el}
+        el += time.time() - t0
+        r = _errors(m.to_numpy(Ya), zc, th_bg, snaps[t_eval])
+        r.update({"seconds": el, "dof_updates_per_s": gc.n_nodes * 5 * 5 * n_c / el, "history": hist})
         if closure == "mlp":
             r["fallback_fraction"] = m.mlp_fallbacks() / float(gc.n_nodes * 5 * n_c)
         out[name] = r
-        log("%s: theta err %.4f  w err %.4f  (%.1f s)" % (name, r["theta_rel_l2"], r["w_rel_l2"], el))
+        log("%s: theta err %.4f  w err %.4f  (%.1f s)  history %s"
+            % (name, r["theta_rel_l2"], r["w_rel_l2"], el, hist))
         if on_result is not None:
             on_result(out)
         del Ya, Yb, dQ, m
@@ -392,7 +413,7 @@ def run_pipeline(fine_ne=64, t_train=C5_TRAIN, t_eval=C5_EVAL, t_holdout=C5_HOLD
         np.savez_compressed(out_npz, params=params, norm=norm, Delta=np.float64(Delta),
                             Prt=np.float64(cc["model"]["Prt"]), Cs=np.float64(cc["model"]["Cs"]),
                             t_box=np.float64(t_holdout or 0.0), **extra)
-    save(posteriori(cc, Yref_c, snaps[0.0][0], snaps[t_eval], t_eval, nets, log, on_result=save))
+    save(posteriori(cc, Yref_c, snaps[0.0][0], snaps, t_eval, nets, log, on_result=save))
     return results
 
 
@@ -408,7 +429,7 @@ def run_heldout(weights_npz, fine_ne=64, dtheta=HELDOUT_DTHETA, t_eval=HELDOUT_T
     cf = W.case("bubble_32", ne=(fine_ne,) * 3)
     cc = W.case("bubble_32", ne=(coarse_ne,) * 3)
     cf["ic"]["dtheta"] = cc["ic"]["dtheta"] = dtheta
-    snaps, Yref_f, dt_f = resolved_run(cf, [0.0, t_eval], log, t_start)
+    snaps, Yref_f, dt_f = resolved_run(cf, [0.0] + [t_eval * k / 5.0 for k in range(1, 6)], log, t_start)
     gc = B.Grid(cc["grid"])
     Yref_c = coarse_grain_state(Yref_f, cf["grid"]["ne"])
     Delta = float(np.cbrt(np.prod((np.array(cc["grid"]["hi"]) / np.array(cc["grid"]["ne"])) / 4.0)))
@@ -430,7 +451,7 @@ def run_heldout(weights_npz, fine_ne=64, dtheta=HELDOUT_DTHETA, t_eval=HELDOUT_T
             with open(out_json, "w") as f:
                 json.dump(results, f)
 
-    save(posteriori(cc, Yref_c, snaps[0.0][0], snaps[t_eval], t_eval, nets, log, on_result=save))
+    save(posteriori(cc, Yref_c, snaps[0.0][0], snaps, t_eval, nets, log, on_result=save))
     return results
 
 
