@@ -217,6 +217,7 @@ def copy_bandwidth(nbytes: int = 1 << 30, reps: int = 5):
 def other_setup(name: str, steps: int, warmup: int):
     """FP64 and FP32-bulk throughput of another named setup (same step, same
     timing as the main line, fewer steps)."""
+    import numpy as np
     import torch
 
     from paper_2110_00853_amd import binding as B
@@ -235,10 +236,14 @@ def other_setup(name: str, steps: int, warmup: int):
     # passes
     nf_words = {5: 9, 6: 12}[nvar]
     metric_words = 2 * (10 + 4.8) if c["grid"].get("topo") == 1 else 0
+    R0 = {}
     for prec in ("fp64", "fp32"):
         m = B.Model(grid, c["model"], Yref, precision=prec)
         Ya, Yb, dQ = m.new_state(Y0), m.new_state(), m.new_state()
         stream = torch.cuda.current_stream()
+        # right-hand side at t = 0, for the FP32-bulk error against FP64
+        m.rhs(Ya, dQ, 0.0, stream)
+        R0[prec] = m.tendency_to_numpy(dQ).astype(np.float64)
         t = 0.0
         for _ in range(warmup):
             m.lsrk_step(Ya, Yb, dQ, t, dt, stream)
@@ -267,6 +272,9 @@ def other_setup(name: str, steps: int, warmup: int):
                      "grad_avg_us": prof["grad"][0] * 1e3 / max(prof["grad"][1], 1),
                      "n_nonfinite": d["n_nonfinite"]}
         del m, Ya, Yb, dQ
+    a, b = R0["fp64"], R0["fp32"]
+    res["fp32"]["rhs_rel_err_vs_fp64_t0"] = [float(np.abs(b[v] - a[v]).max() / np.abs(a[v]).max())
+                                             for v in range(nvar)]
     return res
 
 

@@ -24,6 +24,12 @@
  *    stream whole lines.  Element type double (CM_FP64) or float
  *    (CM_FP32_BULK), at least 16-byte aligned (256-byte for whole lines).
  *    The library never frees or retains them beyond a call.
+ *  - What a state buffer holds: CM_FP64 models store full values;
+ *    CM_FP32_BULK models store float(Y - Y_bg), each value's deviation from
+ *    the model's background (cm_model_create), so that the FP32 rounding
+ *    scales with the deviation and not with the hydrostatic background.
+ *    cm_state_import / cm_state_export convert from and to full FP64
+ *    values.  Tendencies (dQ, dYdt) are full values in both.
  *  - Grid and model objects own their device arrays (metrics, element
  *    traversal table, reference state, diffusive-flux scratch, the node
  *    temperatures moist viscous models carry between the passes and stages
@@ -161,11 +167,15 @@ CM_API cm_status cm_grid_copy_metrics(const cm_grid* grid, double* Ja_host, doub
  * the hydrostatic background; the library pushes it through its own
  * thermodynamics to obtain the reference pressure p_r and density rho_r
  * factored out of the momentum flux and the buoyancy (Sect. 2.4).  NULL
- * means p_r = rho_r = 0.  In CM_FP32_BULK the background is first rounded
- * to float, so a state equal to it is exactly at rest.
+ * means p_r = rho_r = 0.  In CM_FP32_BULK the kernels evolve the stored
+ * deviation about the background rounded to float (p_r and rho_r are
+ * computed from that rounding), so that an imported state equal to Yref is
+ * stored as exact zeros and is exactly at rest.
  * Errors: CM_ERR_ARG, CM_ERR_UNSUPPORTED (nvar not 5/6), CM_ERR_HIP/ALLOC. */
 CM_API cm_status cm_model_create(const cm_grid* grid, const cm_model_desc* desc, const double* Yref_host,
                           cm_model** out);
+/* Frees the model's device arrays.  Does not read the grid, so the grid may
+ * be destroyed first (garbage collectors finalise in any order). */
 CM_API cm_status cm_model_destroy(cm_model* model);
 
 /* Learned closure weights for CM_CLOSURE_MLP (host, float32).  params: the
@@ -258,6 +268,17 @@ CM_API cm_status cm_hevi_solve(cm_model* model, double tau, const void* B, void*
  * asynchronous on the stream.  Errors: CM_ERR_ARG (null, var_mask 0 or
  * beyond nvar bits, order < 1, alpha < 0 or not finite, Nc outside
  * 0 .. N-1). */
+/* Stored state <-> full FP64 state.  cm_state_import writes the model's
+ * storage of the full state Y_full into `state`; cm_state_export writes the
+ * full values of `state` into Y_full.  Both buffers: caller-owned device
+ * memory in the state layout above (Y_full double, `state` the model's
+ * element type); padding slots of the output are written as zeros, those
+ * of the input are not read.  For CM_FP64 the two are the same values
+ * (the call copies; the buffers may coincide).  Asynchronous on the stream.
+ * Errors: CM_ERR_ARG (null pointer). */
+CM_API cm_status cm_state_import(cm_model* model, const double* Y_full, void* state, void* hip_stream);
+CM_API cm_status cm_state_export(cm_model* model, const void* state, double* Y_full, void* hip_stream);
+
 CM_API cm_status cm_exp_filter(cm_model* model, void* Y, int var_mask, int order, double alpha, int Nc,
                                void* hip_stream);
 

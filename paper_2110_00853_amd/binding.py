@@ -25,7 +25,7 @@ EXPORTED = [
     "cm_grid_copy_metrics", "cm_model_create", "cm_model_destroy", "cm_model_set_mlp",
     "cm_model_mlp_fallbacks", "cm_dg_rhs", "cm_lsrk_step", "cm_lsrk144_step", "cm_exp_filter", "cm_diagnostics",
     "cm_hevi_workspace_bytes", "cm_hevi_step", "cm_hevi_operator", "cm_hevi_solve",
-    "cm_diagnostics_noalloc",
+    "cm_diagnostics_noalloc", "cm_state_import", "cm_state_export",
     "cm_mlp_create",
     "cm_mlp_destroy", "cm_mlp_train_step", "cm_mlp_grads", "cm_mlp_infer", "cm_mlp_get_params",
     "cm_mlp_set_params", "cm_model_profile", "cm_model_profile_read", "cm_model_closure_inputs",
@@ -102,6 +102,8 @@ def load():
     L.cm_lsrk_step.argtypes = [_VP, _VP, _VP, _VP, C.c_double, C.c_double, _VP]
     L.cm_lsrk144_step.argtypes = [_VP, _VP, _VP, _VP, C.c_double, C.c_double, _VP]
     L.cm_exp_filter.argtypes = [_VP, _VP, C.c_int, C.c_int, C.c_double, C.c_int, _VP]
+    L.cm_state_import.argtypes = [_VP, _VP, _VP, _VP]
+    L.cm_state_export.argtypes = [_VP, _VP, _VP, _VP]
     L.cm_hevi_workspace_bytes.argtypes = [_VP, C.POINTER(C.c_size_t)]
     L.cm_hevi_step.argtypes = [_VP, _VP, _VP, C.c_double, C.c_double, _VP]
     L.cm_hevi_operator.argtypes = [_VP, _VP, _VP, _VP]
@@ -264,24 +266,44 @@ class Model:
                                  % (self.dtype, self.nvar, self.grid.state_stride))
 
     def new_state(self, Y: np.ndarray | None = None):
-        """A device state buffer [nvar, state_stride]; from a node-ordered
-        array Y [nvar, n_nodes] if given (padding slots zero)."""
+        """A device state buffer [nvar, state_stride] in the model's storage
+        (FP32-bulk: deviations from the background); the model's storage of
+        the node-ordered full state Y [nvar, n_nodes] if given (through
+        cm_state_import), else zeros."""
         import torch
 
         g = self.grid
         dev = "cuda:%d" % g.device
+        S = torch.zeros((self.nvar, g.state_stride), dtype=self.dtype, device=dev)
         if Y is None:
-            return torch.zeros((self.nvar, g.state_stride), dtype=self.dtype, device=dev)
+            return S
         Y = np.asarray(Y)
         if Y.shape != (self.nvar, g.n_nodes):
             raise ValueError("state must have shape [nvar, n_nodes] = (%d, %d)" % (self.nvar, g.n_nodes))
         P = np.zeros((self.nvar, g.n_elem, g.srun), dtype=np.float64)
         P[:, :, :125] = Y.reshape(self.nvar, g.n_elem, 125)
-        return torch.from_numpy(P.reshape(self.nvar, g.state_stride)).to(device=dev, dtype=self.dtype)
+        Yd = torch.from_numpy(P.reshape(self.nvar, g.state_stride)).to(device=dev)
+        _check(load().cm_state_import(self.h, Yd.data_ptr(), S.data_ptr(), _stream_ptr(None)))
+        torch.cuda.current_stream().synchronize()
+        return S
 
     def to_numpy(self, T) -> np.ndarray:
-        """Node-ordered host copy [nvar, n_nodes] of a device state buffer
-        (padding slots dropped), in the buffer's precision."""
+        """Node-ordered host copy [nvar, n_nodes] of the full state a device
+        state buffer holds (through cm_state_export; padding slots dropped),
+        in float64."""
+        import torch
+
+        g = self.grid
+        self._chk(T)
+        Yd = torch.empty((self.nvar, g.state_stride), dtype=torch.float64, device=T.device)
+        _check(load().cm_state_export(self.h, T.data_ptr(), Yd.data_ptr(), _stream_ptr(None)))
+        A = Yd.cpu().numpy().reshape(self.nvar, g.n_elem, g.srun)[:, :, :125]
+        A = np.ascontiguousarray(A).reshape(self.nvar, g.n_nodes)
+        return A
+
+    def tendency_to_numpy(self, T) -> np.ndarray:
+        """Node-ordered host copy [nvar, n_nodes] of a tendency buffer (dQ,
+        dY/dt: full values in both precisions), in the buffer's precision."""
         g = self.grid
         self._chk(T)
         A = T.cpu().numpy().reshape(self.nvar, g.n_elem, g.srun)[:, :, :125]

@@ -9,7 +9,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libcm.so")
-SOURCES = ["api.cpp", "dg_kernels.hip", "reduce.hip", "mlp.hip", "filter.hip", "hevi.hip"]
+SOURCES = ["api.cpp", "dg_kernels.hip", "reduce.hip", "mlp.hip", "filter.hip", "hevi.hip", "state.hip"]
 CHECK_LIB = os.path.join(HERE, "libcm_fp64check.so")
 CHECK_SOURCES = ["fp64_check.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -319,13 +319,15 @@ cm_status cm_grid_copy_metrics(const cm_grid* g, double* Ja, double* J)
 cm_status cm_model_destroy(cm_model* m)
 {
     if (!m) return CM_OK;
-    (void)hipSetDevice(m->grid->device);
+    (void)hipSetDevice(m->device);
     if (m->d_F2) (void)hipFree(m->d_F2);
     for (int q = 0; q < 2; ++q)
         if (m->d_T[q]) (void)hipFree(m->d_T[q]);
     if (m->d_pr) (void)hipFree(m->d_pr);
     if (m->d_rhor) (void)hipFree(m->d_rhor);
     if (m->d_Yref) (void)hipFree(m->d_Yref);
+    if (m->d_bg32) (void)hipFree(m->d_bg32);
+    if (m->d_bg64) (void)hipFree(m->d_bg64);
     if (m->d_partials) (void)hipFree(m->d_partials);
     if (m->d_mlp_w) (void)hipFree(m->d_mlp_w);
     if (m->d_mlp_norm) (void)hipFree(m->d_mlp_norm);
@@ -361,6 +363,7 @@ cm_status cm_model_create(const cm_grid* g, const cm_model_desc* desc, const dou
     cm_model* m = new (std::nothrow) cm_model();
     if (!m) { set_error("cm_model_create: out of host memory"); return CM_ERR_ALLOC; }
     m->grid = g;
+    m->device = g->device;
     m->desc = *desc;
     const int64_t nn = g->n_nodes;
     const int moist = desc->nvar == 6;
@@ -478,12 +481,39 @@ cm_status cm_model_create(const cm_grid* g, const cm_model_desc* desc, const dou
         // which acts on deviations from it), then pushed through the device
         // thermodynamics for p_r and rho_r
         const size_t nref = m->ref_per_node ? (size_t)nn : (size_t)g->desc.ne[2] * NQ;
+        m->nref = (int64_t)nref;
         e = hipMalloc(&m->d_Yref, sizeof(double) * desc->nvar * nref);
         if (e == hipSuccess && Yref)
             e = hipMemcpy(m->d_Yref, Yr.data(), sizeof(double) * Yr.size(), hipMemcpyHostToDevice);
         else if (e == hipSuccess)
             e = hipMemset(m->d_Yref, 0, sizeof(double) * desc->nvar * nref);
         if (e == hipSuccess && Yref) e = launch_reference(m, m->d_Yref, nullptr);
+        // FP32-bulk states are stored as deviations from the background (its
+        // values were rounded to float above, so this copy is exact)
+        if (e == hipSuccess && desc->precision == CM_FP32_BULK) {
+            std::vector<float> b((size_t)desc->nvar * nref, 0.0f);
+            if (Yref)
+                for (size_t q = 0; q < b.size(); ++q) b[q] = (float)Yr[q];
+            e = hipMalloc(&m->d_bg32, sizeof(float) * b.size());
+            if (e == hipSuccess) e = hipMemcpy(m->d_bg32, b.data(), sizeof(float) * b.size(), hipMemcpyHostToDevice);
+            if (e == hipSuccess && Yref) {
+                // the background as given, in the same table layout
+                std::vector<double> b64((size_t)desc->nvar * nref);
+                for (int64_t r = 0; r < (int64_t)nref; ++r) {
+                    int64_t src = r;
+                    if (!m->ref_per_node) {
+                        const int64_t ez = r / NQ, k = r % NQ;
+                        src = ez * (int64_t)g->desc.ne[0] * g->desc.ne[1] * NP + k * NQ * NQ;
+                    }
+                    for (int v = 0; v < desc->nvar; ++v) b64[(size_t)v * nref + r] = Yref[(int64_t)v * nn + src];
+                }
+                e = hipMalloc(&m->d_bg64, sizeof(double) * b64.size());
+                if (e == hipSuccess)
+                    e = hipMemcpy(m->d_bg64, b64.data(), sizeof(double) * b64.size(), hipMemcpyHostToDevice);
+            }
+        }
+        m->kp.bg32 = m->d_bg32;
+        m->kp.nref = m->nref;
         if (e == hipSuccess) e = hipDeviceSynchronize();
     }
     if (e != hipSuccess) {
@@ -675,6 +705,22 @@ static void exp_filter_matrix(const double* xi, int order, double alpha, int Nc,
             for (int n = 0; n < Q; ++n) acc += V[i][n] * sig[n] * Aug[n][Q + l];
             F[i * Q + l] = acc;
         }
+}
+
+cm_status cm_state_import(cm_model* m, const double* Y_full, void* state, void* stream)
+{
+    if (!m || !Y_full || !state) { set_error("cm_state_import: null argument"); return CM_ERR_ARG; }
+    CM_TRY_HIP(hipSetDevice(m->grid->device), "hipSetDevice");
+    CM_TRY_HIP(launch_state_convert(m, Y_full, state, true, (hipStream_t)stream), "cm_state_import");
+    return CM_OK;
+}
+
+cm_status cm_state_export(cm_model* m, const void* state, double* Y_full, void* stream)
+{
+    if (!m || !Y_full || !state) { set_error("cm_state_export: null argument"); return CM_ERR_ARG; }
+    CM_TRY_HIP(hipSetDevice(m->grid->device), "hipSetDevice");
+    CM_TRY_HIP(launch_state_convert(m, state, Y_full, false, (hipStream_t)stream), "cm_state_export");
+    return CM_OK;
 }
 
 cm_status cm_exp_filter(cm_model* m, void* Y, int var_mask, int order, double alpha, int Nc, void* stream)

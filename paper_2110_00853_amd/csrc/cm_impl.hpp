@@ -74,6 +74,11 @@ struct KParams {
     const double* rhor;         // reference density
     int ref_per_node;
     int has_ref;
+    // FP32-bulk storage holds each state as its deviation from the
+    // background: the background [nvar][nref] (float, indexed like pr), null
+    // for FP64 models, whose states hold full values
+    const float* bg32;
+    int64_t nref;
     // physics
     double g;
     int closure;
@@ -133,6 +138,7 @@ struct cm_grid {
 
 struct cm_model {
     const cm_grid* grid = nullptr;
+    int device = 0;              // the grid's device, kept so that destroy never reads the grid
     cm_model_desc desc{};
     int nf = 0;
     void* d_F2 = nullptr;        // [nf][nn] storage type
@@ -141,6 +147,9 @@ struct cm_model {
     double* d_pr = nullptr;
     double* d_rhor = nullptr;
     double* d_Yref = nullptr;    // the background itself [nvar][nref] (per level or per node; zeros without one)
+    float* d_bg32 = nullptr;     // FP32-bulk models: the same background in float (its values are floats)
+    double* d_bg64 = nullptr;    // FP32-bulk models with a background: the background as given (state import/export)
+    int64_t nref = 0;            // entries per variable of the background tables
     int ref_per_node = 0;
     int has_ref = 0;
     double Delta = 0.0;
@@ -187,6 +196,7 @@ hipError_t launch_combine(const cm_model* m, const void* base, void* out, int n,
 int64_t hevi_lines(const cm_model* m);
 // exponential modal filter (filter.hip): F1 the 1-D filter matrix [5][5]
 hipError_t launch_exp_filter(const cm_model* m, void* Y, int mask, const double* F1, hipStream_t s);
+hipError_t launch_state_convert(const cm_model* m, const void* src, void* dst, bool to_storage, hipStream_t s);
 // the same reduction over the library's static per-device workspace (no
 // allocation); its partial-record count equals a model's, so both give
 // bit-identical results

@@ -133,6 +133,16 @@ __device__ __forceinline__ int ref_index(const KParams& P, int e, int ez, int k,
     return P.ref_per_node ? e * NP + t : ez * NQ + k;
 }
 
+// the full FP64 value of a stored value x of variable v at reference index
+// ri: FP32-bulk storage holds the deviation from the background (so that
+// its rounding error scales with the deviation), FP64 storage the value
+template <typename R>
+__device__ __forceinline__ double full_of(const KParams& P, R x, int v, int ri)
+{
+    if constexpr (sizeof(R) == 8) return x;
+    else return (double)x + (double)P.bg32[(int64_t)v * P.nref + ri];
+}
+
 // ---------------------------------------------------------------------------
 // reference state: background pushed through the same thermodynamics
 // ---------------------------------------------------------------------------
@@ -243,6 +253,9 @@ constexpr int NFT = 150;  // face-node tasks per element: 6 faces x 25 nodes
 
 // waves per SIMD the dry flat gradient pass is compiled for (80 VGPRs, no
 // spills)
+#ifndef CM_MLP_WPE
+#define CM_MLP_WPE 1
+#endif
 #ifndef CM_GRAD_WPE
 #define CM_GRAD_WPE 6
 #endif
@@ -316,69 +329,79 @@ __device__ __forceinline__ bf16x4 act_bf16(const f32x4& d)
     return __builtin_bit_cast(bf16x4, u);
 }
 
-// raw outputs (o0, o1) of the node of this lane; row0 = first row of the wave
+// raw outputs (o0, o1) of the node of this lane; row0 = first row of the
+// wave.  The wave's four 16-node tiles go through the network CM_MLP_NT at a
+// time (fewer live activation and accumulator registers for smaller groups,
+// the weight tiles read once per group).
+#ifndef CM_MLP_NT
+#define CM_MLP_NT 2
+#endif
 __device__ __forceinline__ void mlp_forward_wave(const KParams& P, const uint16_t (*sX)[MLP_XS], int row0, float& o0,
                                                  float& o1)
 {
+    constexpr int NTP = CM_MLP_NT;
     const int lane = threadIdx.x & 63;
     const int r = lane & 15, kq = (lane >> 4) * 4;
     const bf16x4* frag = (const bf16x4*)P.mlp_frag;
-    const float* bias = P.mlp_bias;
-    bf16x4 h[4][4];  // activations [hidden tile][node tile]
-    // layer 1: K = 16 (12 inputs, zero padded)
-    bf16x4 xin[4];
-#pragma unroll
-    for (int nt = 0; nt < 4; ++nt) xin[nt] = *(const bf16x4*)&sX[row0 + 16 * nt + r][kq];
-#pragma unroll
-    for (int ht = 0; ht < 4; ++ht) {
-        const bf16x4 a = frag[ht * 64 + lane];
-        const f32x4 b = *(const f32x4*)&bias[16 * ht + kq];
-#pragma unroll
-        for (int nt = 0; nt < 4; ++nt) h[ht][nt] = act_bf16(mfma16(a, xin[nt], b));
-    }
-    // layers 2 and 3: K = 64 as two 32-wide chunks; chunk c of a node tile
-    // is the activation tiles 2c and 2c + 1 side by side
     const bf16x8s* frag8 = (const bf16x8s*)P.mlp_frag;   // in units of 64 lanes x 8
-#pragma unroll
-    for (int layer = 0; layer < 2; ++layer) {
-        f32x4 acc[4][4];
-#pragma unroll
-        for (int ht = 0; ht < 4; ++ht) {
-            const f32x4 b = *(const f32x4*)&bias[64 * (layer + 1) + 16 * ht + kq];
-#pragma unroll
-            for (int nt = 0; nt < 4; ++nt) acc[ht][nt] = b;
-        }
-#pragma unroll
-        for (int ht = 0; ht < 4; ++ht)
-#pragma unroll
-            for (int c = 0; c < 2; ++c) {
-                const bf16x8s a = frag8[((FRAG_L1 + layer * FRAG_L2) / 2 + 2 * ht + c) * 64 + lane];
-#pragma unroll
-                for (int nt = 0; nt < 4; ++nt) acc[ht][nt] = mfma32(a, h[2 * c][nt], h[2 * c + 1][nt], acc[ht][nt]);
-            }
-#pragma unroll
-        for (int ht = 0; ht < 4; ++ht)
-#pragma unroll
-            for (int nt = 0; nt < 4; ++nt) h[ht][nt] = act_bf16(acc[ht][nt]);
-    }
-    // layer 4: one 16-row output tile (rows 0 and 1 real)
-    f32x4 out[4];
-#pragma unroll
-    for (int nt = 0; nt < 4; ++nt) out[nt] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
-#pragma unroll
-    for (int c = 0; c < 2; ++c) {
-        const bf16x8s a = frag8[((FRAG_L1 + FRAG_L2 + FRAG_L3) / 2 + c) * 64 + lane];
-#pragma unroll
-        for (int nt = 0; nt < 4; ++nt) out[nt] = mfma32(a, h[2 * c][nt], h[2 * c + 1][nt], out[nt]);
-    }
-    // lane r < 16 holds rows 0..3 of node 16 nt + r: move outputs 0 and 1 to
-    // the lane that owns the node (16 nt + r)
+    const float* bias = P.mlp_bias;
     float v0 = 0.0f, v1 = 0.0f;
 #pragma unroll
-    for (int nt = 0; nt < 4; ++nt) {
-        const float s0 = __shfl(out[nt][0], r);
-        const float s1 = __shfl(out[nt][1], r);
-        if ((lane >> 4) == nt) { v0 = s0; v1 = s1; }
+    for (int g = 0; g < 4; g += NTP) {
+        bf16x4 h[4][NTP];  // activations [hidden tile][node tile of the group]
+        // layer 1: K = 16 (12 inputs, zero padded)
+        bf16x4 xin[NTP];
+#pragma unroll
+        for (int n = 0; n < NTP; ++n) xin[n] = *(const bf16x4*)&sX[row0 + 16 * (g + n) + r][kq];
+#pragma unroll
+        for (int ht = 0; ht < 4; ++ht) {
+            const bf16x4 a = frag[ht * 64 + lane];
+            const f32x4 b = *(const f32x4*)&bias[16 * ht + kq];
+#pragma unroll
+            for (int n = 0; n < NTP; ++n) h[ht][n] = act_bf16(mfma16(a, xin[n], b));
+        }
+        // layers 2 and 3: K = 64 as two 32-wide chunks; chunk c of a node
+        // tile is the activation tiles 2c and 2c + 1 side by side
+#pragma unroll
+        for (int layer = 0; layer < 2; ++layer) {
+            f32x4 acc[4][NTP];
+#pragma unroll
+            for (int ht = 0; ht < 4; ++ht) {
+                const f32x4 b = *(const f32x4*)&bias[64 * (layer + 1) + 16 * ht + kq];
+#pragma unroll
+                for (int n = 0; n < NTP; ++n) acc[ht][n] = b;
+            }
+#pragma unroll
+            for (int ht = 0; ht < 4; ++ht)
+#pragma unroll
+                for (int c = 0; c < 2; ++c) {
+                    const bf16x8s a = frag8[((FRAG_L1 + layer * FRAG_L2) / 2 + 2 * ht + c) * 64 + lane];
+#pragma unroll
+                    for (int n = 0; n < NTP; ++n) acc[ht][n] = mfma32(a, h[2 * c][n], h[2 * c + 1][n], acc[ht][n]);
+                }
+#pragma unroll
+            for (int ht = 0; ht < 4; ++ht)
+#pragma unroll
+                for (int n = 0; n < NTP; ++n) h[ht][n] = act_bf16(acc[ht][n]);
+        }
+        // layer 4: one 16-row output tile (rows 0 and 1 real)
+        f32x4 out[NTP];
+#pragma unroll
+        for (int n = 0; n < NTP; ++n) out[n] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            const bf16x8s a = frag8[((FRAG_L1 + FRAG_L2 + FRAG_L3) / 2 + c) * 64 + lane];
+#pragma unroll
+            for (int n = 0; n < NTP; ++n) out[n] = mfma32(a, h[2 * c][n], h[2 * c + 1][n], out[n]);
+        }
+        // lane r < 16 holds rows 0..3 of node 16 nt + r: move outputs 0 and
+        // 1 to the lane that owns the node (16 nt + r)
+#pragma unroll
+        for (int n = 0; n < NTP; ++n) {
+            const float s0 = __shfl(out[n][0], r);
+            const float s1 = __shfl(out[n][1], r);
+            if ((lane >> 4) == g + n) { v0 = s0; v1 = s1; }
+        }
     }
     o0 = v0 + bias[192];
     o1 = v1 + bias[193];
@@ -427,12 +450,15 @@ __device__ __forceinline__ void grad_face(const KParams& P, const GradLoad<R, MO
     R jump[NG];
     if (f.en >= 0) {
         Th tp;
+        double yp[MOIST ? 6 : 5];
+        const int rip = ref_index(P, f.en, f.ezn, f.nbl / (NQ * NQ), f.nbl);
+#pragma unroll
+        for (int v = 0; v < (MOIST ? 6 : 5); ++v) yp[v] = full_of<R>(P, f.Yp[v], v, rip);
         if (MOIST && P.T_given)
-            thermo_moist_T((double)f.Yp[0], (double)f.Yp[1], (double)f.Yp[2], (double)f.Yp[3], (double)f.Yp[4],
-                           (double)f.Yp[MOIST ? 5 : 0], f.Tq, f.qcq, ICE, tp);
+            thermo_moist_T(yp[0], yp[1], yp[2], yp[3], yp[4], yp[MOIST ? 5 : 0], f.Tq, f.qcq, ICE, tp);
         else
-            thermo<MOIST>((double)f.Yp[0], (double)f.Yp[1], (double)f.Yp[2], (double)f.Yp[3], (double)f.Yp[4],
-                          MOIST ? (double)f.Yp[5] : 0.0, node_z<WARP>(P, f.en, f.ezn, f.nbl / (NQ * NQ), f.nbl), P.g, ICE, tp);
+            thermo<MOIST>(yp[0], yp[1], yp[2], yp[3], yp[4], MOIST ? yp[MOIST ? 5 : 0] : 0.0,
+                          node_z<WARP>(P, f.en, f.ezn, f.nbl / (NQ * NQ), f.nbl), P.g, ICE, tp);
         R gp[NG];
         gp[0] = (R)tp.u; gp[1] = (R)tp.v; gp[2] = (R)tp.w; gp[3] = (R)tp.h;
         if (MOIST) gp[GQ] = (R)tp.qt;
@@ -463,7 +489,7 @@ __device__ __forceinline__ void grad_face(const KParams& P, const GradLoad<R, MO
 // ICE: the moist thermodynamics with the ice phase (a compile-time variant,
 // so that the liquid-only kernels keep their registers)
 template <typename R, bool MOIST, bool WARP, bool MLP, bool FEAT = false, bool ICE = false>
-__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(MLP || MOIST || WARP || FEAT ? 1 : CM_GRAD_WPE))) void k_grad(const KParams P)
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(MLP ? CM_MLP_WPE : (MOIST || WARP || FEAT ? 1 : CM_GRAD_WPE)))) void k_grad(const KParams P)
 {
     constexpr int NV = MOIST ? 6 : 5;
     constexpr int NG = MOIST ? 6 : 5;  // u v w h [qt] thv
@@ -499,8 +525,9 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(MLP || MO
     {
         double Yv[NV];
         const uint32_t soff = (uint32_t)(e * SRUN + tt) * (uint32_t)sizeof(R);
+        const int ri = ref_index(P, e, ez, k, tt);
 #pragma unroll
-        for (int v = 0; v < NV; ++v) Yv[v] = (double)*gptr<const R>(P.Ys[v], soff);
+        for (int v = 0; v < NV; ++v) Yv[v] = full_of<R>(P, *gptr<const R>(P.Ys[v], soff), v, ri);
         if (MOIST && P.T_given)
             thermo_moist_T(Yv[0], Yv[1], Yv[2], Yv[3], Yv[4], Yv[MOIST ? 5 : 0],
                            P.Tn[(int64_t)e * run_nodes<double>() + tt],
@@ -821,6 +848,7 @@ struct FaceLoad {
     static constexpr int NWF = WARP ? NW : (MOIST ? 5 : 4);
     int dir, sd, own, nbl, en, ezn;
     R Yp[NV], wp[VISC ? NWF : 1];
+    float bgp[sizeof(R) == 4 ? NV : 1];  // FP32 storage: the neighbour node's background
     double prp;
     double Tq, qcq;  // moist viscous: T and condensate of the neighbour node (of this node on a wall)
     double To, qco;  // moist viscous: T and condensate of the own node
@@ -858,7 +886,12 @@ __device__ __forceinline__ void face_load(const KParams& P, const R* __restrict_
     // reference pressure of the neighbour node; on a wall the neighbour slot
     // holds this element's mirrored node, and the flux needs this node's
     const int rn = f.en >= 0 ? f.nbl : f.own;
-    f.prp = P.pr[ref_index(P, eo, ezo, rn / (NQ * NQ), rn)];
+    const int rin = ref_index(P, eo, ezo, rn / (NQ * NQ), rn);
+    f.prp = P.pr[rin];
+    if constexpr (sizeof(R) == 4) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) f.bgp[v] = P.bg32[(int64_t)v * P.nref + rin];
+    }
     if (MOIST && VISC) {
         const int64_t nt = (int64_t)eo * run_nodes<double>() + rn;
         f.Tq = P.Tn[nt];
@@ -969,6 +1002,18 @@ __device__ __forceinline__ void face_flux(const KParams& P, const FaceLoad<R, MO
     R Ym[NV];
 #pragma unroll
     for (int v = 0; v < NV; ++v) Ym[v] = sY[v][own];
+    // full own and neighbour states in FP64 (FP32-bulk stores deviations
+    // from the background; on a wall the neighbour slot is this node)
+    const int rio = ref_index(P, e, ez, own / (NQ * NQ), own);
+    double ym[NV], yp[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        ym[v] = full_of<R>(P, Ym[v], v, rio);
+        // the neighbour's background was loaded with its state (on a wall
+        // the neighbour slot is this node, and so is the background read)
+        if constexpr (sizeof(R) == 8) yp[v] = f.Yp[v];
+        else yp[v] = (double)f.Yp[v] + (double)f.bgp[v];
+    }
     // own node's velocity and sound speed: from LDS in the moist inviscid
     // case (the saturation adjustment is too costly to repeat) and with FP32
     // storage (LDS is not the limit there); recomputed from the own state in
@@ -984,11 +1029,10 @@ __device__ __forceinline__ void face_flux(const KParams& P, const FaceLoad<R, MO
         cm = sP[3][own];
     } else {
         if (MOIST)
-            thermo_moist_T((double)Ym[0], (double)Ym[1], (double)Ym[2], (double)Ym[3], (double)Ym[4],
-                           (double)Ym[NV - 1], f.To, f.qco, ICE, to);
+            thermo_moist_T(ym[0], ym[1], ym[2], ym[3], ym[4], ym[NV - 1], f.To, f.qco, ICE, to);
         else
-            thermo<false>((double)Ym[0], (double)Ym[1], (double)Ym[2], (double)Ym[3], (double)Ym[4], 0.0,
-                          node_z<WARP>(P, e, ez, own / (NQ * NQ), own), P.g, ICE, to);
+            thermo<false>(ym[0], ym[1], ym[2], ym[3], ym[4], 0.0, node_z<WARP>(P, e, ez, own / (NQ * NQ), own), P.g,
+                          ICE, to);
         um[0] = (R)to.u; um[1] = (R)to.v; um[2] = (R)to.w;
         cm = (R)to.c;
     }
@@ -1002,11 +1046,10 @@ __device__ __forceinline__ void face_flux(const KParams& P, const FaceLoad<R, MO
         const int kn = nbl / (NQ * NQ);
         Th tp;
         if (MOIST && VISC)
-            thermo_moist_T((double)f.Yp[0], (double)f.Yp[1], (double)f.Yp[2], (double)f.Yp[3], (double)f.Yp[4],
-                           (double)f.Yp[NV - 1], f.Tq, f.qcq, ICE, tp);
+            thermo_moist_T(yp[0], yp[1], yp[2], yp[3], yp[4], yp[NV - 1], f.Tq, f.qcq, ICE, tp);
         else
-            thermo<MOIST>((double)f.Yp[0], (double)f.Yp[1], (double)f.Yp[2], (double)f.Yp[3], (double)f.Yp[4],
-                          MOIST ? (double)f.Yp[NV - 1] : 0.0, node_z<WARP>(P, en, ezn, kn, nbl), P.g, ICE, tp);
+            thermo<MOIST>(yp[0], yp[1], yp[2], yp[3], yp[4], MOIST ? yp[NV - 1] : 0.0,
+                          node_z<WARP>(P, en, ezn, kn, nbl), P.g, ICE, tp);
         const R up[3] = {(R)tp.u, (R)tp.v, (R)tp.w};
         R fp[NV];
         flux1_normal<R, MOIST>((R)tp.rho, up, (R)(tp.p - f.prp), (R)(tp.rho * tp.e + tp.p), (R)(tp.rho * tp.qt), n,
@@ -1024,7 +1067,8 @@ __device__ __forceinline__ void face_flux(const KParams& P, const FaceLoad<R, MO
             const R lam = lm > lp ? lm : lp;
 #pragma unroll
             for (int v = 0; v < NV; ++v)
-                contrib[v] = (R)0.5 * (liftFm[v] - lift * fp[v]) - (R)0.5 * lift * lam * (Ym[v] - f.Yp[v]);
+                contrib[v] = (R)0.5 * (liftFm[v] - lift * fp[v]) -
+                             (R)0.5 * lift * lam * (sizeof(R) == 8 ? Ym[v] - f.Yp[v] : (R)(ym[v] - yp[v]));
         } else {
             const double nd[3] = {(double)n[0], (double)n[1], (double)n[2]};
             double D[5];
@@ -1041,17 +1085,16 @@ __device__ __forceinline__ void face_flux(const KParams& P, const FaceLoad<R, MO
         // wall the neighbour slot's T and condensate are this node's)
         Th tm = to;
         if (KEEP_P && !MOIST)
-            thermo<false>((double)Ym[0], (double)Ym[1], (double)Ym[2], (double)Ym[3], (double)Ym[4], 0.0,
-                          node_z<WARP>(P, e, ez, own / (NQ * NQ), own), P.g, ICE, tm);
+            thermo<false>(ym[0], ym[1], ym[2], ym[3], ym[4], 0.0, node_z<WARP>(P, e, ez, own / (NQ * NQ), own), P.g,
+                          ICE, tm);
         else if (KEEP_P && MOIST && VISC)
-            thermo_moist_T((double)Ym[0], (double)Ym[1], (double)Ym[2], (double)Ym[3], (double)Ym[4],
-                           (double)Ym[NV - 1], f.Tq, f.qcq, ICE, tm);
+            thermo_moist_T(ym[0], ym[1], ym[2], ym[3], ym[4], ym[NV - 1], f.Tq, f.qcq, ICE, tm);
         else if (MOIST && !VISC)
-            thermo<MOIST>((double)Ym[0], (double)Ym[1], (double)Ym[2], (double)Ym[3], (double)Ym[4],
-                          (double)Ym[NV - 1], node_z<WARP>(P, e, ez, own / (NQ * NQ), own), P.g, ICE, tm);
-        const R rho = Ym[0];
+            thermo<MOIST>(ym[0], ym[1], ym[2], ym[3], ym[4], ym[NV - 1], node_z<WARP>(P, e, ez, own / (NQ * NQ), own),
+                          P.g, ICE, tm);
+        const R rho = sizeof(R) == 8 ? Ym[0] : (R)ym[0];
         const R pp = (R)(tm.p - f.prp), ep = (R)(tm.rho * tm.e + tm.p);
-        const R rq = MOIST ? Ym[NV - 1] : (R)0;
+        const R rq = MOIST ? (sizeof(R) == 8 ? Ym[NV - 1] : (R)ym[NV - 1]) : (R)0;
         const R ug[3] = {um[0] - (R)2 * unm * n[0], um[1] - (R)2 * unm * n[1], um[2] - (R)2 * unm * n[2]};
         R f1m[NV], f1g[NV];
         flux1_normal<R, MOIST>(rho, um, pp, ep, rq, n, f1m);
@@ -1060,7 +1103,8 @@ __device__ __forceinline__ void face_flux(const KParams& P, const FaceLoad<R, MO
         R jumpY[NV];
 #pragma unroll
         for (int v = 0; v < NV; ++v) jumpY[v] = (R)0;
-        const R mn = Ym[1] * n[0] + Ym[2] * n[1] + Ym[3] * n[2];
+        const R mn = sizeof(R) == 8 ? Ym[1] * n[0] + Ym[2] * n[1] + Ym[3] * n[2]
+                                    : (R)ym[1] * n[0] + (R)ym[2] * n[1] + (R)ym[3] * n[2];
         jumpY[1] = (R)2 * mn * n[0];
         jumpY[2] = (R)2 * mn * n[1];
         jumpY[3] = (R)2 * mn * n[2];
@@ -1108,6 +1152,7 @@ struct OwnLoad {
     static constexpr int NW = MOIST ? 12 : 9;
     static constexpr int NWS = NW + (MOIST ? 2 : 1);  // with the subsidence words
     R Yr[NV];
+    float bg[sizeof(R) == 4 ? NV : 1];  // FP32 storage: the node's background
     R w[VISC ? NWS : 1];
     R Jam[WARP ? 10 : 1];  // J a^d (9) and 1/J
     double pr, rr;
@@ -1134,6 +1179,10 @@ __device__ __forceinline__ void own_load(const KParams& P, int e, int ez, int tt
     const int ri = ref_index(P, e, ez, tt / (NQ * NQ), tt);
     o.pr = P.pr[ri];
     o.rr = P.rhor[ri];
+    if constexpr (sizeof(R) == 4) {
+#pragma unroll
+        for (int v = 0; v < O::NV; ++v) o.bg[v] = P.bg32[(int64_t)v * P.nref + ri];
+    }
     if (MOIST && VISC) {
         o.T = P.Tn[(int64_t)e * run_nodes<double>() + tt];
         o.qc = P.Tn[P.nnT + (int64_t)e * run_nodes<double>() + tt];
@@ -1169,14 +1218,18 @@ __device__ __forceinline__ void tend_element(const KParams& P, int e, int t,
     double rho_d, mom_d[3];
     {
         Th th;
+        double y[NV];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            if constexpr (sizeof(R) == 8) y[v] = o.Yr[v];
+            else y[v] = (double)o.Yr[v] + (double)o.bg[v];
+        }
         if (MOIST && VISC)
-            thermo_moist_T((double)o.Yr[0], (double)o.Yr[1], (double)o.Yr[2], (double)o.Yr[3], (double)o.Yr[4],
-                           (double)o.Yr[NV - 1], o.T, o.qc, ICE, th);
+            thermo_moist_T(y[0], y[1], y[2], y[3], y[4], y[NV - 1], o.T, o.qc, ICE, th);
         else
-            thermo<MOIST>((double)o.Yr[0], (double)o.Yr[1], (double)o.Yr[2], (double)o.Yr[3], (double)o.Yr[4],
-                          MOIST ? (double)o.Yr[NV - 1] : 0.0, z, P.g, ICE, th);
+            thermo<MOIST>(y[0], y[1], y[2], y[3], y[4], MOIST ? y[NV - 1] : 0.0, z, P.g, ICE, th);
         rho_d = th.rho;
-        mom_d[0] = (double)o.Yr[1]; mom_d[1] = (double)o.Yr[2]; mom_d[2] = (double)o.Yr[3];
+        mom_d[0] = y[1]; mom_d[1] = y[2]; mom_d[2] = y[3];
         R F[NV][3];
         flux1<R, MOIST>(th, o.pr, F);
         const R um[3] = {(R)th.u, (R)th.v, (R)th.w};
@@ -1309,8 +1362,13 @@ __device__ __forceinline__ void tend_element(const KParams& P, int e, int t,
         // temperature of the output state, from the input state's as the
         // Newton start: the next stage's passes read it instead of solving
         double qcnew;
-        const double Tnew = moist_T_guess((double)Rv[0], (double)Rv[1], (double)Rv[2], (double)Rv[3],
-                                          (double)Rv[4], (double)Rv[NV - 1], z, P.g, o.T, ICE, qcnew);
+        double yn[NV];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            if constexpr (sizeof(R) == 8) yn[v] = Rv[v];
+            else yn[v] = (double)Rv[v] + (double)o.bg[v];
+        }
+        const double Tnew = moist_T_guess(yn[0], yn[1], yn[2], yn[3], yn[4], yn[NV - 1], z, P.g, o.T, ICE, qcnew);
         const int64_t nt = (int64_t)e * run_nodes<double>() + t;
         __builtin_nontemporal_store(Tnew, &P.Tnext[nt]);
         __builtin_nontemporal_store(qcnew, &P.Tnext[P.nnT + nt]);

@@ -28,7 +28,8 @@ __global__ __launch_bounds__(BLOCK) void k_filter(const FilterArgs A, R* __restr
     for (int v = 0; v < A.nvar; ++v) {
         if (!((A.mask >> v) & 1)) continue;
         R* y = Y + v * A.nnS + (int64_t)e * SRUN + tt;
-        const double ref = A.Yref[v * A.nref + ri];
+        // FP32-bulk states already hold the deviation from the background
+        const double ref = sizeof(R) == 8 ? A.Yref[v * A.nref + ri] : 0.0;
         const double yv = act ? (double)*y : 0.0;
         a[t] = act ? yv - ref : 0.0;
         __syncthreads();

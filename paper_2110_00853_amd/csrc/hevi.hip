@@ -39,6 +39,15 @@ __device__ __forceinline__ int64_t href(const HeviArgs& A, int e, int ez, int k,
     return A.ref_per_node ? (int64_t)e * NP + t : (int64_t)ez * NQ + k;
 }
 
+// what a stored state value is relative to: FP64 states hold full values,
+// FP32-bulk states their deviation from the background
+template <typename R>
+__device__ __forceinline__ double sref(const HeviArgs& A, int v, int64_t ri)
+{
+    if constexpr (sizeof(R) == 8) return A.Yref[v * A.nref + ri];
+    else return 0.0;
+}
+
 // background quantities at one node: rho_r, p_r, h_r = (E_r + p_r)/rho_r,
 // b = R_d T0 - (R_d/c_vd) g z (the coefficient of rho' in p'), c_r
 struct HRef {
@@ -75,7 +84,7 @@ __global__ __launch_bounds__(BLOCK) void k_vlin(const HeviArgs A, const R* __res
     const HRef r = href_at(A, ri, ez, k);
     double d[5];
 #pragma unroll
-    for (int v = 0; v < 5; ++v) d[v] = (double)Y[v * A.nnS + soff] - A.Yref[v * A.nref + ri];
+    for (int v = 0; v < 5; ++v) d[v] = (double)Y[v * A.nnS + soff] - sref<R>(A, v, ri);
     const double Fm[5] = {d[3], 0.0, 0.0, a * d[4] + r.b * d[0], r.h * d[3]};
     sF[0][t] = Fm[0];
     sF[1][t] = Fm[3];
@@ -105,7 +114,7 @@ __global__ __launch_bounds__(BLOCK) void k_vlin(const HeviArgs A, const R* __res
             double dp[5];
 #pragma unroll
             for (int v = 0; v < 5; ++v)
-                dp[v] = (double)Y[v * A.nnS + (int64_t)en * SRUN + tn] - A.Yref[v * A.nref + rin];
+                dp[v] = (double)Y[v * A.nnS + (int64_t)en * SRUN + tn] - sref<R>(A, v, rin);
             const double Fp[5] = {dp[3], 0.0, 0.0, a * dp[4] + rn.b * dp[0], rn.h * dp[3]};
             const double lam = r.c > rn.c ? r.c : rn.c;
 #pragma unroll
@@ -272,7 +281,7 @@ __global__ __launch_bounds__(VS_THREADS) void k_vsolve(const HeviArgs A, const R
             const int var = v3 == 0 ? 0 : (v3 == 1 ? 3 : 4);
             const int tnode = i + NQ * (j + NQ * k);
             const int64_t ri = href(A, e, ez, k, tnode);
-            double rhs = (double)B[var * A.nnS + (int64_t)e * SRUN + tnode] - A.Yref[var * A.nref + ri];
+            double rhs = (double)B[var * A.nnS + (int64_t)e * SRUN + tnode] - sref<R>(A, var, ri);
             if (k == 0 && ez > 0) {
                 double s = 0.0;
                 for (int q = 0; q < 3; ++q) s += Cb[v3][q] * yprev[q];
@@ -316,7 +325,7 @@ __global__ __launch_bounds__(VS_THREADS) void k_vsolve(const HeviArgs A, const R
             const int var = v3 == 0 ? 0 : (v3 == 1 ? 3 : 4);
             const int tnode = i + NQ * (j + NQ * k);
             const int64_t ri = href(A, e, ez, k, tnode);
-            Yo[var * A.nnS + (int64_t)e * SRUN + tnode] = (R)(A.Yref[var * A.nref + ri] + x[r]);
+            Yo[var * A.nnS + (int64_t)e * SRUN + tnode] = (R)(sref<R>(A, var, ri) + x[r]);
         }
         for (int v = 0; v < 3; ++v) xb[v] = x[vb(v, 0)];
     }
@@ -336,10 +345,10 @@ __global__ __launch_bounds__(VS_THREADS) void k_vsolve(const HeviArgs A, const R
                 const double lam = ra.c > rb.c ? ra.c : rb.c;
                 const double s = 0.5 * tau * lift * lam, al = 1.0 + s, det = al * al - s * s;
                 for (int v = 1; v <= 2; ++v) {
-                    const double xa = (double)B[v * A.nnS + (int64_t)e * SRUN + tnode] - A.Yref[v * A.nref + ri];
-                    const double xbv = (double)B[v * A.nnS + (int64_t)en * SRUN + tn] - A.Yref[v * A.nref + rin];
-                    Yo[v * A.nnS + (int64_t)e * SRUN + tnode] = (R)(A.Yref[v * A.nref + ri] + (al * xa + s * xbv) / det);
-                    Yo[v * A.nnS + (int64_t)en * SRUN + tn] = (R)(A.Yref[v * A.nref + rin] + (s * xa + al * xbv) / det);
+                    const double xa = (double)B[v * A.nnS + (int64_t)e * SRUN + tnode] - sref<R>(A, v, ri);
+                    const double xbv = (double)B[v * A.nnS + (int64_t)en * SRUN + tn] - sref<R>(A, v, rin);
+                    Yo[v * A.nnS + (int64_t)e * SRUN + tnode] = (R)(sref<R>(A, v, ri) + (al * xa + s * xbv) / det);
+                    Yo[v * A.nnS + (int64_t)en * SRUN + tn] = (R)(sref<R>(A, v, rin) + (s * xa + al * xbv) / det);
                 }
             } else if (!(k == 0 && ez > 0)) {
                 for (int v = 1; v <= 2; ++v) Yo[v * A.nnS + (int64_t)e * SRUN + tnode] = B[v * A.nnS + (int64_t)e * SRUN + tnode];

@@ -53,6 +53,10 @@ struct DiagArgs {
     const double* zn;        // warped: node heights or null
     double g, dt, dmin;
     int ice;
+    // FP32-bulk states hold deviations from this background (null: full values)
+    const float* bg32;
+    int64_t nref;
+    int ref_per_node;
 };
 
 template <typename R, bool MOIST>
@@ -68,13 +72,14 @@ __global__ __launch_bounds__(RB) void k_diag1(const DiagArgs A, const R* __restr
         const int64_t slot = e * SRUN + t;  // the node's slot in the state buffer
         double y[NV];
         bool fin = true;
+        const int i = t % NQ, j = (t / NQ) % NQ, k = t / (NQ * NQ);
+        const int64_t ri = A.ref_per_node ? n : (e / ((int64_t)A.ne0 * A.ne1)) * NQ + k;
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
-            y[v] = (double)Y[v * A.nnS + slot];
+            y[v] = (double)Y[v * A.nnS + slot] + (A.bg32 ? (double)A.bg32[v * A.nref + ri] : 0.0);
             if (!isfinite(y[v])) { nonfin += 1.0; fin = false; }
         }
         if (!fin) continue;
-        const int i = t % NQ, j = (t / NQ) % NQ, k = t / (NQ * NQ);
         const double J = A.invJ ? 1.0 / A.invJ[n] : A.Jc;
         const double wJ = A.w[i] * A.w[j] * A.w[k] * J;
         const double z = A.zn ? A.zn[n] : A.lo2 + ((double)(e / ((int64_t)A.ne0 * A.ne1)) + A.zg[k]) * A.h2;
@@ -189,6 +194,9 @@ static hipError_t diagnostics_ws(const cm_model* m, const void* Y, double dt, cm
     A.ice = m->desc.ice;
     A.dt = dt;
     A.dmin = g->dmin;
+    A.bg32 = m->d_bg32;
+    A.nref = m->nref;
+    A.ref_per_node = m->ref_per_node;
     int nblk = (int)((A.nn + RB - 1) / RB);
     if (nblk > n_records - 1) nblk = n_records - 1;
     double* part = ws;

@@ -47,7 +47,7 @@ def test_full_size_rhs_matches_oracle(name):
         Rd = m.new_state()
         m.rhs(Yd, Rd)
         torch.cuda.synchronize()
-        Rg = m.to_numpy(Rd).astype(np.float64)
+        Rg = m.tendency_to_numpy(Rd).astype(np.float64)
         out[prec] = rhs_errors(Rg, Rref, Y, hmin(c["grid"]))
         lit[prec] = literal_rhs_errors(Rg, Rref)
         del m, Yd, Rd
@@ -55,7 +55,7 @@ def test_full_size_rhs_matches_oracle(name):
           "oracle 1-ulp floor", floor, "oracle vs FMA-contracted oracle", cfloor, "fp32-bulk", out["fp32"])
     assert np.all(out["fp64"] < tol), (out["fp64"], tol)
     assert np.all(out["fp64"] <= np.maximum(1e-11, 1.5 * cfloor)), (out["fp64"], cfloor)
-    assert np.all(np.isfinite(out["fp32"])) and np.all(out["fp32"] < 5e-2), out["fp32"]
+    assert np.all(np.isfinite(out["fp32"])) and np.all(out["fp32"] < 2e-3), out["fp32"]
 
 
 def test_full_size_two_lsrk_steps_match_oracle():

@@ -49,7 +49,7 @@ def test_operator_and_solve_match_oracle(name):
     m.hevi_solve(tau, Yd, Xd, work)
     torch.cuda.synchronize()
     Lo = om.hevi_operator(Y)
-    Lg = m.to_numpy(Ld)
+    Lg = m.tendency_to_numpy(Ld)
     for v in range(5):
         sc = max(np.abs(Lo[v]).max(), 1e-300)
         assert np.abs(Lg[v] - Lo[v]).max() <= 1e-12 * sc, (v, np.abs(Lg[v] - Lo[v]).max() / sc)
@@ -80,7 +80,7 @@ def test_hevi_steps_match_oracle(name, precision):
     Yo = oracle.Model(oracle.Grid(c["grid"]), c["model"], Yref).hevi_steps(Y, dt, 3)
     err = state_errors(m.to_numpy(Yd).astype(np.float64), Yo)
     print(name, precision, "HEVI state errors after 3 steps", err)
-    assert np.all(err < (1e-10 if precision == "fp64" else 1e-2)), err
+    assert np.all(err < (1e-10 if precision == "fp64" else 1e-5)), err
 
 
 def test_hevi_stable_far_beyond_the_vertical_acoustic_limit():

@@ -40,7 +40,7 @@ def _rhs(torch, grid, model, Y, Yref=None, precision="fp64"):
     Rd = m.new_state()
     m.rhs(Yd, Rd)
     torch.cuda.synchronize()
-    return m.to_numpy(Rd).astype(np.float64)
+    return m.tendency_to_numpy(Rd).astype(np.float64)
 
 
 CASES = [(g, c, n) for g in ("cartesian", "warped") for c in ("none", "const", "smag") for n in (5, 6)]

@@ -155,7 +155,7 @@ def test_fused_closure_rhs_matches_oracle(torch):
     Rd = m.new_state()
     m.rhs(Yd, Rd)
     nfb = m.mlp_fallbacks()
-    Rg = m.to_numpy(Rd)
+    Rg = m.tendency_to_numpy(Rd)
     err = rhs_errors(Rg, Rref, Y, hmin(c["grid"]))
     print("fused mlp closure rhs errors", err, "fallbacks", nfb, nfb_ref)
     assert abs(nfb - nfb_ref) <= max(2, 0.01 * nfb_ref)
@@ -188,7 +188,7 @@ def test_no_fallback_inside_training_range_with_a_non_float_filter_width(torch):
     Yd, Rd = m.new_state(Y), m.new_state()
     m.rhs(Yd, Rd)
     nfb, nfb_ref = m.mlp_fallbacks(), om.mlp_fallbacks()
-    err = rhs_errors(m.to_numpy(Rd), Rref, Y, hmin(c["grid"]))
+    err = rhs_errors(m.tendency_to_numpy(Rd), Rref, Y, hmin(c["grid"]))
     print("non-float filter width: fallbacks", nfb, nfb_ref, "rhs errors", err)
     assert nfb == 0 and nfb_ref == 0
     assert np.all(err < 1e-4), err

@@ -110,7 +110,7 @@ def test_rhs_fp64_matches_oracle(dev, name):
     Rd = m.new_state()
     m.rhs(Yd, Rd)
     dev.cuda.synchronize()
-    Rg = m.to_numpy(Rd)
+    Rg = m.tendency_to_numpy(Rd)
     Rref = oracle.Model(oracle.Grid(c["grid"]), c["model"], Yref).rhs(Y)
     err = rhs_errors(Rg, Rref, Y, hmin(c["grid"]))
     print(name, "rhs errors per variable", err)
@@ -144,8 +144,9 @@ def test_lsrk_step_matches_oracle(dev, name):
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 def test_lsrk144_step_matches_oracle(dev, name, precision):
     """LSRK144 (fourteen fused stages, new state back in the input buffer)
-    against the oracle's: FP64 at 1e-10 after 3 steps; FP32-bulk bounded at 1e-2
-    (its momenta carry the FP32 rounding of the hydrostatic balance)."""
+    against the oracle's: FP64 at 1e-10 after 3 steps; FP32-bulk at 2e-3
+    (measured at most 2.5e-4: FP32 flux arithmetic on deviations stored in
+    FP32 from the background)."""
     c = SMALL_CASES[name]
     Y, Yref = _state(c)
     _, _, speed = W.perturbed_state(c, seed=11, amp_u=6.0, amp_T=2.0, amp_q=1.5e-3)
@@ -161,7 +162,7 @@ def test_lsrk144_step_matches_oracle(dev, name, precision):
     Yo, _ = oracle.Model(oracle.Grid(c["grid"]), c["model"], Yref).steps(Y, dt, nsteps, scheme="lsrk144")
     err = state_errors(Yg, Yo)
     print(name, precision, "LSRK144 state errors after", nsteps, "steps", err)
-    assert np.all(err < (1e-10 if precision == "fp64" else 1e-2)), err
+    assert np.all(err < (1e-10 if precision == "fp64" else 2e-3)), err
 
 
 def test_bubble_4_hundred_steps(dev):
@@ -258,7 +259,8 @@ def test_conservation_on_gpu_closed_box(dev):
 
 
 def test_fp32_bulk_rhs_error_is_stated(dev):
-    """FP32-bulk tendency against the FP64 oracle: error stated, bounded."""
+    """FP32-bulk tendency against the FP64 oracle: error stated, bounded at
+    1e-3 (measured at most 1.2e-4, moist)."""
     for name in ("smag_ragged", "moist", "warped", "moist_warped"):
         c = SMALL_CASES[name]
         Y, Yref = _state(c)
@@ -268,11 +270,32 @@ def test_fp32_bulk_rhs_error_is_stated(dev):
         Rd = m.new_state()
         m.rhs(Yd, Rd)
         dev.cuda.synchronize()
-        Rg = m.to_numpy(Rd).astype(np.float64)
+        Rg = m.tendency_to_numpy(Rd).astype(np.float64)
         Rref = oracle.Model(oracle.Grid(c["grid"]), c["model"], Yref).rhs(Y)
         err = rhs_errors(Rg, Rref, Y, hmin(c["grid"]))
         print(name, "fp32-bulk rhs errors per variable", err)
-        assert np.all(np.isfinite(Rg)) and np.all(err < 5e-2), err
+        assert np.all(np.isfinite(Rg)) and np.all(err < 1e-3), err
+
+
+@pytest.mark.parametrize("name", ["smag_ragged", "moist", "warped"])
+def test_fp32_state_storage_round_trip(dev, name):
+    """FP32-bulk storage holds float(Y - Y_bg): importing the background
+    gives exact zeros, and a state comes back within float rounding of its
+    deviation from the background (not of its full value); FP64 storage
+    round-trips exactly."""
+    c = SMALL_CASES[name]
+    Y, Yref = _state(c)
+    assert Yref is not None
+    g = B.Grid(c["grid"])
+    m32 = B.Model(g, c["model"], Yref, precision="fp32")
+    assert bool((m32.new_state(Yref) == 0).all())
+    back = m32.to_numpy(m32.new_state(Y))
+    # float rounding of the deviation, plus the FP64 subtraction and addition
+    bound = 2.0 ** -24 * np.abs(Y - Yref) + 2.0 ** -51 * np.abs(Y)
+    assert np.all(np.abs(back - Y) <= bound)
+    assert np.abs(Y - Yref).max() > 1e-3      # a real deviation was stored
+    m64 = B.Model(g, c["model"], Yref)
+    assert np.array_equal(m64.to_numpy(m64.new_state(Y)), Y)
 
 
 def test_state_padding_contract(dev):
@@ -359,7 +382,7 @@ def test_ice_phase_rhs_and_steps_match_oracle(dev, name):
     Yd, Rd = m.new_state(Y), m.new_state()
     m.rhs(Yd, Rd)
     dev.cuda.synchronize()
-    err = rhs_errors(m.to_numpy(Rd), om.rhs(Y), Y, hmin(c["grid"]))
+    err = rhs_errors(m.tendency_to_numpy(Rd), om.rhs(Y), Y, hmin(c["grid"]))
     print(name, "ice-phase rhs errors", err)
     assert np.all(err < RHS_TOL), err
     dt = W.cfl_dt(c["grid"], 360.0)
