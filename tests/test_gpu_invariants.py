@@ -75,3 +75,25 @@ def test_hydrostatic_rest_stays_at_rest(torch, closure, size):
     assert np.abs(R[0]).max() == 0.0
     assert np.abs(R[1:4]).max() <= 1e-12 * rho_g
     assert np.abs(R[4]).max() <= 1e-12 * rho_g * 300.0
+
+
+@pytest.mark.parametrize("size", ["small", "full_32"])
+def test_fp32_bulk_rest_state_stays_at_rest(torch, size):
+    """FP32-bulk stores deviations from the background: the neutral rest
+    state imported as its own background is stored as zeros, so the mass
+    tendency vanishes exactly and the momentum tendencies to the FP64 model's
+    bound (the FP64 thermodynamics of the float-rounded background against
+    the reference computed from it); the energy tendency keeps only the FP32
+    rounding of the diffusive flux of h_tot."""
+    if size == "small":
+        g = dict(CART, periodic=[1, 1, 0], hi=[600.0, 400.0, 1500.0])
+    else:
+        g = dict(FULL, periodic=[1, 1, 0])
+    Y = W.neutral_rest_state(g)
+    model = {"nvar": 5, "closure": "const", "nu": 75.0, "g": 9.81, "richardson": True}
+    R = _rhs(torch, g, model, Y, Y, precision="fp32")
+    rho_g = Y[0].max() * 9.81
+    print(size, "fp32 rest-state tendency maxima", np.abs(R).max(axis=1))
+    assert np.abs(R[0]).max() == 0.0
+    assert np.abs(R[1:4]).max() <= 1e-12 * rho_g
+    assert np.abs(R[4]).max() <= 1e-4 * rho_g * 300.0
