@@ -1,5 +1,6 @@
 /*
- * FP64 CPU oracle for the nodal DG right-hand side, the LSRK54 step and the
+ * FP64 CPU oracle for the nodal DG right-hand side, the LSRK54 and LSRK144
+ * steps, the 1-D IMEX (HEVI) step, the exponential filter and the
  * conservation integrals.
  *
  * TEST INFRASTRUCTURE ONLY (see cmref.h).  Written as plain loops in the
@@ -12,8 +13,15 @@
  *   Sect. 3.1 (nodal GLL expansion, tensor-product derivatives, mapping,
  *              weak/strong DG form, Rusanov flux, BR1 auxiliary gradient,
  *              semi-discrete matrix problem)
- *   Sect. 3.2 (low-storage explicit Runge-Kutta, Carpenter-Kennedy family)
- *   Sect. 4   (SGS stress, diffusivity, Smagorinsky-Lilly, Richardson corr.)
+ *   Sect. 2.5, 2.7 and Table 1 (ice phase: liquid fraction, saturation
+ *              over the mix)
+ *   Sect. 3.1 (Roe and HLLC numerical fluxes for dry air)
+ *   Sect. 3.2 (low-storage explicit Runge-Kutta, Carpenter-Kennedy family and
+ *              the 14-stage method of Niegemann, Diehl and Busch; additive
+ *              Runge-Kutta IMEX with the vertical acoustics implicit)
+ *   Sect. 4   (SGS stress, diffusivity, Smagorinsky-Lilly, Richardson corr.,
+ *              Vreman eq. vreman-sgs)
+ *   Sect. 5.4 (exponential modal filter, eq. exponential_filter)
  *   Sect. 6   (normalised mass / energy integrals)
  *   App. A    (wall ghost states, prescribed wall fluxes, Rayleigh sponge)
  */
