@@ -89,7 +89,10 @@ def run(args):
             Ya, Yb = Yb, Ya
             t += dt
         torch.cuda.synchronize()
-        m.profile(True)
+        # the timed K steps (the throughput), then K more with an event pair
+        # around every kernel launch (the per-kernel averages of the roofline;
+        # the events add a few microseconds between launches, so they stay out
+        # of the throughput run)
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         torch.cuda.synchronize()
         w0 = time.perf_counter()
@@ -102,6 +105,12 @@ def run(args):
         torch.cuda.synchronize()
         wall = time.perf_counter() - w0
         ms = e0.elapsed_time(e1)
+        m.profile(True)
+        for _ in range(steps):
+            m.lsrk_step(Ya, Yb, dQ, t, dt, stream)
+            Ya, Yb = Yb, Ya
+            t += dt
+        torch.cuda.synchronize()
         prof = m.profile_read()
         m.profile(False)
         diag = m.diagnostics(Ya, dt)
@@ -167,7 +176,8 @@ def run(args):
             "value": v32, "ms_per_step": ms32 / args.steps, "speedup_vs_fp64": v32 / value,
             "tend_achieved_GBs": nn * (tf32 + 4 * to32) / 5.0 / (t32_ms * 1e-3 / t32_n) / 1e9,
             "state_rel_err_vs_fp64_after_steps": err,
-            "note": "warmup+steps LSRK54 steps from the same initial state; max-norm error per variable",
+            "note": "warmup + 2 x steps LSRK54 steps from the same initial state (the timed steps, then the "
+                    "profiled ones); max-norm error per variable",
         }
         del m32, Y32
     if not args.no_learned and c["model"].get("closure") == "smag":
@@ -175,7 +185,7 @@ def run(args):
         mdl = dict(c["model"], closure="mlp")
         mL, YL, msL, _, profL, _ = timed("fp64", args.steps, args.warmup, model=mdl, mlp=(params, norm))
         vL = nn * nvar * 5 * args.steps / (msL * 1e-3)
-        fb = mL.mlp_fallbacks() / float(nn * 5 * (args.steps + args.warmup))
+        fb = mL.mlp_fallbacks() / float(nn * 5 * (2 * args.steps + args.warmup))
         gL_ms, gL_n = profL["grad"]
         out["learned_closure"] = {
             "value": vL, "ms_per_step": msL / args.steps, "speedup_vs_fp64_smagorinsky": vL / value,
@@ -249,7 +259,6 @@ def other_setup(name: str, steps: int, warmup: int):
             m.lsrk_step(Ya, Yb, dQ, t, dt, stream)
             Ya, Yb = Yb, Ya
             t += dt
-        m.profile(True)
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         torch.cuda.synchronize()
         e0.record(stream)
@@ -260,6 +269,12 @@ def other_setup(name: str, steps: int, warmup: int):
         e1.record(stream)
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1)
+        m.profile(True)           # per-kernel averages from a second, profiled run
+        for _ in range(steps):
+            m.lsrk_step(Ya, Yb, dQ, t, dt, stream)
+            Ya, Yb = Yb, Ya
+            t += dt
+        torch.cuda.synchronize()
         prof = m.profile_read()
         m.profile(False)
         d = m.diagnostics(Ya, dt)
