@@ -199,6 +199,8 @@ def run(args):
     out["roofline"]["achieved_vs_copy"] = achieved / out["hbm_copy_GBs"]
     if not args.no_setups:
         out["other_setups"] = {name: other_setup(name, args.setup_steps, 2) for name in ("moist_64", "agnesi_96")}
+    if not args.no_next:
+        out["next_rows"] = next_rows(max(args.setup_steps, 10), 2)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(c, Y0, Yref, nn, nvar, dt)
     return out
@@ -298,6 +300,138 @@ def other_setup(name: str, steps: int, warmup: int):
     return res
 
 
+def lsrk_throughput(B, grid, c, Y0, Yref, dt, steps, warmup, scheme="lsrk54", precision="fp64"):
+    """Throughput of one model with LSRK54 or LSRK144 (timed steps without
+    per-kernel events, then as many profiled ones for the kernel averages)
+    and the tendency pass's fraction of the HBM roofline on the algorithmic
+    bytes of the headline formula."""
+    import torch
+
+    m = B.Model(grid, c["model"], Yref, precision=precision)
+    Ya, Yb, dQ = m.new_state(Y0), m.new_state(), m.new_state()
+    stream = torch.cuda.current_stream()
+    nst = 5 if scheme == "lsrk54" else 14
+    state = {"Ya": Ya, "Yb": Yb, "t": 0.0}
+
+    def advance():
+        if scheme == "lsrk54":
+            m.lsrk_step(state["Ya"], state["Yb"], dQ, state["t"], dt, stream)
+            state["Ya"], state["Yb"] = state["Yb"], state["Ya"]
+        else:
+            m.lsrk144_step(state["Ya"], state["Yb"], dQ, state["t"], dt, stream)
+        state["t"] += dt
+
+    for _ in range(warmup):
+        advance()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(steps):
+        advance()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    m.profile(True)
+    for _ in range(steps):
+        advance()
+    torch.cuda.synchronize()
+    prof = m.profile_read()
+    m.profile(False)
+    d = m.diagnostics(state["Ya"], dt)
+    nn, nvar = grid.n_nodes, c["model"]["nvar"]
+    nf = 0
+    if c["model"].get("closure", "none") != "none":
+        nf = {5: 9, 6: 12}[nvar] + ((1 if nvar == 5 else 2) if c["model"].get("subsidence") else 0)
+    sb = 8 if precision == "fp64" else 4
+    _, tf_b, to_b = alg_bytes(nvar, nf, sb)
+    tend_avg = prof["tend"][0] * 1e-3 / prof["tend"][1]
+    tend_bytes = nn * (tf_b + (nst - 1) * to_b) / nst
+    return {"value": nn * nvar * nst * steps / (ms * 1e-3), "ms_per_step": ms / steps, "stages": nst,
+            "tend_avg_us": tend_avg * 1e6, "grad_avg_us": prof["grad"][0] * 1e3 / max(prof["grad"][1], 1),
+            "tend_roofline_frac": tend_bytes / tend_avg / 1e9 / HBM_PEAK_GBS, "n_nonfinite": d["n_nonfinite"]}
+
+
+def next_rows(steps: int, warmup: int):
+    """The widened rows on their own workloads, FP64: LSRK144, the Vreman
+    closure and the Roe and HLLC fluxes on the 32^3 bubble; the ice phase on
+    the moist set-up; the density current; the exponential filter (one
+    in-place pass over all five variables of the 32^3 bubble) and the 1-D
+    IMEX step on a strongly anisotropic mesh, against LSRK54 at its own
+    stable step there."""
+    import torch
+
+    from paper_2110_00853_amd import binding as B
+    from paper_2110_00853_amd import workloads as W
+
+    res = {}
+    c = W.case("bubble_32")
+    Y0, Yref, dt = W.initial_state(c)
+    grid = B.Grid(c["grid"], device=0)
+    res["lsrk144_bubble_32"] = lsrk_throughput(B, grid, c, Y0, Yref, dt, steps, warmup, scheme="lsrk144")
+    for name, over in (("vreman_bubble_32", {"closure": "vreman"}), ("roe_bubble_32", {"flux": "roe"}),
+                       ("hllc_bubble_32", {"flux": "hllc"})):
+        cv = dict(c, model=dict(c["model"], **over))
+        res[name] = lsrk_throughput(B, grid, cv, Y0, Yref, dt, steps, warmup)
+    # exponential filter: read and write of every variable, in place
+    m = B.Model(grid, c["model"], Yref)
+    Yd = m.new_state(Y0)
+    stream = torch.cuda.current_stream()
+    for _ in range(3):
+        m.exp_filter(Yd, 0b11111, 64, 36.0, 0, stream)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    nrep = 50
+    for _ in range(nrep):
+        m.exp_filter(Yd, 0b11111, 64, 36.0, 0, stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    us = e0.elapsed_time(e1) * 1e3 / nrep
+    fbytes = 2.0 * 5 * 8 * grid.n_nodes
+    res["exp_filter_bubble_32"] = {"us_per_call": us, "alg_bytes": fbytes, "achieved_GBs": fbytes / us / 1e3,
+                                   "roofline_frac": fbytes / us / 1e3 / HBM_PEAK_GBS}
+    del m, Yd, grid
+    cd = W.case("density_current")
+    Yc, Yrc, dtc = W.initial_state(cd)
+    res["density_current"] = lsrk_throughput(B, B.Grid(cd["grid"], device=0), cd, Yc, Yrc, dtc, steps, warmup)
+    cm = W.case("moist_64")
+    cm["model"]["ice"] = 1
+    Ym, Yrm, dtm = W.initial_state(cm)
+    res["ice_moist_64"] = lsrk_throughput(B, B.Grid(cm["grid"], device=0), cm, Ym, Yrm, dtm, max(steps // 10, 5), 2)
+    # 1-D IMEX on 5 m-tall, 200 m-wide elements (32 x 32 x 32), constant
+    # nu = 1: twelve times the explicit vertical limit (a horizontal Courant
+    # number of 0.12), against LSRK54 at that limit
+    ch = W.case("bubble_32", hi=(6400.0, 6400.0, 160.0))
+    ch["model"] = dict(ch["model"], closure="const", nu=1.0)
+    ch["ic"] = dict(ch["ic"], center=(3200.0, 3200.0, 80.0))
+    Yh, Yrh, dth = W.initial_state(ch)
+    gh = B.Grid(ch["grid"], device=0)
+    mh = B.Model(gh, ch["model"], Yrh)
+    Ya = mh.new_state(Yh)
+    work = mh.hevi_workspace()
+    dt_hevi = 12.0 * dth
+    nh = max(steps // 10, 10)
+    for _ in range(3):
+        mh.hevi_step(Ya, work, 0.0, dt_hevi, stream)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(nh):
+        mh.hevi_step(Ya, work, 0.0, dt_hevi, stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms_h = e0.elapsed_time(e1) / nh
+    dh = mh.diagnostics(Ya, dt_hevi)
+    del mh, Ya, work
+    ex = lsrk_throughput(B, gh, ch, Yh, Yrh, dth, nh, 3)
+    res["hevi_anisotropic_32"] = {
+        "ms_per_step": ms_h, "dt": dt_hevi, "lsrk54_ms_per_step": ex["ms_per_step"], "lsrk54_dt": dth,
+        "simulated_time_speedup_vs_lsrk54": (dt_hevi / ms_h) / (dth / ex["ms_per_step"]),
+        "n_nonfinite": dh["n_nonfinite"],
+        "note": "ARK2 (explicit horizontal, implicit vertical acoustics), 32x32x32 elements of 200 x 200 x 5 m, "
+                "const nu = 1, dt = 12 x the explicit vertical limit; LSRK54 at that limit on the same mesh"}
+    return res
+
+
 def mlp_weights(B, grid, c, Yref, Y0):
     """Trained weights of the learned closure if the package holds them,
     else a seeded random initialisation standardised on this state's inputs
@@ -382,6 +516,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--no-setups", action="store_true", help="skip the moist and mountain setups")
+    ap.add_argument("--no-next", action="store_true",
+                    help="skip LSRK144, Vreman, Roe, HLLC, ice, density current, filter and 1-D IMEX")
     ap.add_argument("--setup-steps", type=int, default=100)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 1 GiB device copy (for scaling HBM byte counters)")
