@@ -1,7 +1,8 @@
 // Exponential modal filter (Sect. 5.4, eq. exponential_filter): one element
-// per 128-thread block; for each selected variable the deviation from the
-// background goes through the 1-D filter matrix along xi1, xi2 and xi3 in
-// LDS (three passes of five-term sums) and the background is added back.
+// per 128-thread block; the deviations from the background of all selected
+// variables go together through the 1-D filter matrix along xi1, xi2 and
+// xi3 in LDS (three passes of five-term sums, four barriers per element) and
+// the background is added back.
 // Elements are independent, so the state is filtered in place.
 #include "cm_impl.hpp"
 
@@ -18,37 +19,58 @@ struct FilterArgs {
 template <typename R>
 __global__ __launch_bounds__(BLOCK) void k_filter(const FilterArgs A, R* __restrict__ Y)
 {
-    __shared__ double a[BLOCK], b[BLOCK];
+    constexpr int MV = 6;  // at most six variables, filtered together
+    __shared__ double a[MV][BLOCK], b[MV][BLOCK];
+    __shared__ double sF[NQ * NQ];  // the 1-D matrix (a lane-indexed read of the launch arguments would be a
+                                    // vector load at every use)
     const int e = blockIdx.x;
     const int t = threadIdx.x;
+    if (t < NQ * NQ) sF[t] = A.F[t];
     const bool act = t < NP;
     const int tt = act ? t : NP - 1;
     const int i = tt % NQ, j = (tt / NQ) % NQ, k = tt / (NQ * NQ);
     const int64_t ri = A.ref_per_node ? (int64_t)e * NP + tt : (int64_t)(e / A.ne01) * NQ + k;
-    for (int v = 0; v < A.nvar; ++v) {
-        if (!((A.mask >> v) & 1)) continue;
-        R* y = Y + v * A.nnS + (int64_t)e * SRUN + tt;
+    // every selected variable's loads first, so that their latencies overlap
+    double ref[MV];
+#pragma unroll
+    for (int v = 0; v < MV; ++v) {
+        if (v >= A.nvar || !((A.mask >> v) & 1)) continue;
         // FP32-bulk states already hold the deviation from the background
-        const double ref = sizeof(R) == 8 ? A.Yref[v * A.nref + ri] : 0.0;
-        const double yv = act ? (double)*y : 0.0;
-        a[t] = act ? yv - ref : 0.0;
-        __syncthreads();
+        ref[v] = sizeof(R) == 8 ? A.Yref[v * A.nref + ri] : 0.0;
+        const double yv = act ? (double)Y[v * A.nnS + (int64_t)e * SRUN + tt] : 0.0;
+        a[v][t] = act ? yv - ref[v] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int v = 0; v < MV; ++v) {
+        if (v >= A.nvar || !((A.mask >> v) & 1)) continue;
         double s = 0.0;
 #pragma unroll
-        for (int l = 0; l < NQ; ++l) s += A.F[i * NQ + l] * a[l + NQ * (j + NQ * k)];
-        b[t] = s;
-        __syncthreads();
-        s = 0.0;
+        for (int l = 0; l < NQ; ++l) s += sF[i * NQ + l] * a[v][l + NQ * (j + NQ * k)];
+        b[v][t] = s;
+    }
+    __syncthreads();
+    double s2[MV];
 #pragma unroll
-        for (int l = 0; l < NQ; ++l) s += A.F[j * NQ + l] * b[i + NQ * (l + NQ * k)];
-        __syncthreads();
-        a[t] = s;
-        __syncthreads();
-        s = 0.0;
+    for (int v = 0; v < MV; ++v) {
+        if (v >= A.nvar || !((A.mask >> v) & 1)) continue;
+        double s = 0.0;
 #pragma unroll
-        for (int l = 0; l < NQ; ++l) s += A.F[k * NQ + l] * a[i + NQ * (j + NQ * l)];
-        if (act) *y = (R)(ref + s);
-        __syncthreads();
+        for (int l = 0; l < NQ; ++l) s += sF[j * NQ + l] * b[v][i + NQ * (l + NQ * k)];
+        s2[v] = s;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int v = 0; v < MV; ++v)
+        if (v < A.nvar && ((A.mask >> v) & 1)) a[v][t] = s2[v];
+    __syncthreads();
+#pragma unroll
+    for (int v = 0; v < MV; ++v) {
+        if (v >= A.nvar || !((A.mask >> v) & 1)) continue;
+        double s = 0.0;
+#pragma unroll
+        for (int l = 0; l < NQ; ++l) s += sF[k * NQ + l] * a[v][i + NQ * (j + NQ * l)];
+        if (act) Y[v * A.nnS + (int64_t)e * SRUN + tt] = (R)(ref[v] + s);
     }
 }
 

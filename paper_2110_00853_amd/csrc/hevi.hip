@@ -8,10 +8,10 @@
 //   k_vlin   : L (Y - Y_ref) per node, one element per block (fluxes of a
 //              vertical node line through LDS, face terms with the element
 //              above or below), optionally subtracted from a right-hand side
-//   k_vsolve : (I - tau L) x = B - Y_ref on every vertical node line, one
-//              line per thread: block-tridiagonal elimination over the
+//   k_vsolve : (I - tau L) x = B - Y_ref on every vertical node line, 16
+//              lanes per line: block-tridiagonal elimination over the
 //              element layers with 15 x 15 blocks for (rho, rho w, rho e_tot)
-//              (LU with partial pivoting in thread-private LDS), 2 x 2 face
+//              (rows across lanes, partial pivoting through LDS), 2 x 2 face
 //              systems for the horizontal momenta (only the face penalty
 //              couples them)
 //   k_combine: out = base + sum_i c_i X_i over the node slots
@@ -31,7 +31,7 @@ struct HeviArgs {
     const double* pr;          // background pressure [nref]
     double lo2, h2, g, tau;
     double zg[NQ], D[NQ * NQ];
-    double* scratch;           // solver workspace [nz][60][n_lines]
+    double* scratch;           // solver workspace [n_lines][nz][60]
 };
 
 __device__ __forceinline__ int64_t href(const HeviArgs& A, int e, int ez, int k, int t)
@@ -135,52 +135,32 @@ __global__ __launch_bounds__(BLOCK) void k_vlin(const HeviArgs A, const R* __res
     }
 }
 
-constexpr int VS_THREADS = 32;  // lines per block of the line solver
-constexpr int VS_N = 15;        // unknowns per element block: (rho, rho w, rho e_tot) x 5 nodes
-
-// LU with partial pivoting of the thread's 15 x 15 block (thread-private
-// LDS, the thread index fastest), then solves for nr right-hand sides
-__device__ __forceinline__ void lu_solve(double (*M)[VS_N][VS_THREADS], double (*Bm)[4][VS_THREADS], int nr, int t)
-{
-    for (int c = 0; c < VS_N; ++c) {
-        int piv = c;
-        double best = fabs(M[c][c][t]);
-        for (int r = c + 1; r < VS_N; ++r) {
-            const double v = fabs(M[r][c][t]);
-            if (v > best) { best = v; piv = r; }
-        }
-        if (piv != c) {
-            for (int q = 0; q < VS_N; ++q) {
-                const double tmp = M[c][q][t];
-                M[c][q][t] = M[piv][q][t];
-                M[piv][q][t] = tmp;
-            }
-            for (int q = 0; q < nr; ++q) {
-                const double tmp = Bm[c][q][t];
-                Bm[c][q][t] = Bm[piv][q][t];
-                Bm[piv][q][t] = tmp;
-            }
-        }
-        const double inv = 1.0 / M[c][c][t];
-        for (int r = c + 1; r < VS_N; ++r) {
-            const double f = M[r][c][t] * inv;
-            if (f == 0.0) continue;
-            for (int q = c + 1; q < VS_N; ++q) M[r][q][t] -= f * M[c][q][t];
-            for (int q = 0; q < nr; ++q) Bm[r][q][t] -= f * Bm[c][q][t];
-        }
-    }
-    for (int r = VS_N - 1; r >= 0; --r) {
-        const double inv = 1.0 / M[r][r][t];
-        for (int q = 0; q < nr; ++q) {
-            double v = Bm[r][q][t];
-            for (int c = r + 1; c < VS_N; ++c) v -= M[r][c][t] * Bm[c][q][t];
-            Bm[r][q][t] = v * inv;
-        }
-    }
-}
+constexpr int VS_N = 15;         // unknowns per element block: (rho, rho w, rho e_tot) x 5 nodes
+constexpr int VS_LANES = 16;     // lanes per vertical line: lane r < 15 holds row r of the block
+constexpr int VS_BLOCK = 64;     // one wave: four lines
 
 // index of (variable 0 rho, 1 rho w, 2 rho e_tot; node k) in an element block
 __device__ __forceinline__ int vb(int v3, int k) { return v3 * NQ + k; }
+
+// one step of an arg-max over the 16 lanes of a DPP row: the value and lane
+// index of the partner lane given by the DPP control (0xB1: quad_perm
+// [1,0,3,2]; 0x4E: quad_perm [2,3,0,1]; 0x141: row_half_mirror; 0x140:
+// row_mirror; the four in this order pair every lane with every other of its
+// row), larger value first, the lower index on ties
+template <int CTRL>
+__device__ __forceinline__ void row_argmax_step(double& best, int& who)
+{
+    const unsigned long long bits = __builtin_bit_cast(unsigned long long, best);
+    const int lo = __builtin_amdgcn_update_dpp((int)(unsigned)bits, (int)(unsigned)bits, CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp((int)(unsigned)(bits >> 32), (int)(unsigned)(bits >> 32), CTRL, 0xF,
+                                               0xF, false);
+    const double ob = __builtin_bit_cast(double, ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
+    const int ow = __builtin_amdgcn_update_dpp(who, who, CTRL, 0xF, 0xF, false);
+    if (ob > best || (ob == best && ow < who)) {
+        best = ob;
+        who = ow;
+    }
+}
 
 // Jacobian of the vertical flux (rho w, p', h rho w') w.r.t. (rho', m, E')
 __device__ __forceinline__ void flux_jac(const HRef& r, double J[3][3])
@@ -191,149 +171,235 @@ __device__ __forceinline__ void flux_jac(const HRef& r, double J[3][3])
 }
 
 // Y_out = Y_ref + x with (I - tau L) x = B - Y_ref on every vertical line
-// (B and Y_out may be the same buffer: each thread reads its line before it
-// writes it)
+// (B and Y_out may be the same buffer: a line is read before it is written,
+// and lines do not share nodes).
+//
+// Sixteen lanes per line, four lines per wave.  Over the element layers from
+// the bottom, lane r assembles row r of the layer's 15 x 15 block I - tau L_e
+// in registers, with the Schur update of its bottom-node rows by the layer
+// below (the layers couple through one node pair, a rank-3 coupling); the
+// block is solved by Gaussian elimination with partial pivoting across the
+// lanes (the pivot row broadcast through LDS; the lane that supplied the
+// pivot for column c then owns unknown c) for the deviation and the three
+// unit vectors at the top nodes.  Each layer leaves y_e and Z_e = W_e Btil_e
+// in the workspace ([line][layer][60]); the back substitution
+// x_e = y_e - Z_e x_{e+1}(bottom nodes) runs from the top.  The horizontal
+// momenta are coupled only by the face penalty: 2 x 2 systems per interior
+// vertical face, solved by lanes 0-9.
 template <typename R>
-__global__ __launch_bounds__(VS_THREADS) void k_vsolve(const HeviArgs A, const R* __restrict__ B, R* __restrict__ Yo,
-                                                       int64_t n_lines)
+__global__ __launch_bounds__(VS_BLOCK) void k_vsolve(const HeviArgs A, const R* __restrict__ B, R* __restrict__ Yo,
+                                                     int64_t n_lines)
 {
-    __shared__ double sM[VS_N][VS_N][VS_THREADS];
-    __shared__ double sB[VS_N][4][VS_THREADS];
-    const int t = threadIdx.x;
-    const int64_t line = (int64_t)blockIdx.x * VS_THREADS + t;
-    if (line >= n_lines) return;  // no barriers below: the threads work alone
+    constexpr int NG = VS_BLOCK / VS_LANES;
+    __shared__ double sP[NG][VS_N + 4];   // pivot row (15 entries and 4 right-hand sides)
+    __shared__ double sQ[NG][24];         // per-layer broadcasts
+    const int lane = threadIdx.x;
+    const int gq = lane / VS_LANES, r = lane % VS_LANES;
+    const int64_t line_id = (int64_t)blockIdx.x * NG + gq;
+    const bool live = line_id < n_lines;                 // groups past the end compute, never write
+    const int64_t line = live ? line_id : n_lines - 1;
+    const bool rowl = r < VS_N;
+    const int v3 = rowl ? r / NQ : 0, kr = rowl ? r % NQ : 0;
     const int node = (int)(line % (NQ * NQ));
     const int64_t col = line / (NQ * NQ);
     const int i = node % NQ, j = node / NQ;
     const int ex = (int)(col % A.ne0), ey = (int)(col / A.ne0);
     const double tau = A.tau, r2h = 2.0 / A.h2, lift = r2h * 10.0;
     const int nz = A.ne2;
-    double* scr = A.scratch;
-    // scratch layout [ez][q][line]: q < 45 the columns of Z_e (15 x 3),
-    // 45 .. 59 the forward solution y_e
-    auto S = [&](int ez, int q) -> double& { return scr[((int64_t)ez * 60 + q) * n_lines + line]; };
+    double* scr = A.scratch + line * (int64_t)nz * 60;   // [layer][60]: Z rows (45), then y (15)
+    const int var = v3 == 0 ? 0 : (v3 == 1 ? 3 : 4);
     double G[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};  // S_{e-1} Btil_{e-1}
     double yprev[3] = {0, 0, 0};                          // y_{e-1} at its top nodes
-    double Cb[3][3];                                      // coupling of this element's bottom to the one below
+    double Dr[NQ];                                        // row kr of the differentiation matrix
+#pragma unroll
+    for (int l = 0; l < NQ; ++l) Dr[l] = A.D[kr * NQ + l];
     for (int ez = 0; ez < nz; ++ez) {
         const int e = ex + A.ne0 * (ey + A.ne1 * ez);
         HRef rk[NQ];
 #pragma unroll
         for (int k = 0; k < NQ; ++k) rk[k] = href_at(A, href(A, e, ez, k, i + NQ * (j + NQ * k)), ez, k);
-        // assemble I - tau L_e
-        for (int r = 0; r < VS_N; ++r)
-            for (int c = 0; c < VS_N; ++c) sM[r][c][t] = r == c ? 1.0 : 0.0;
-        for (int k = 0; k < NQ; ++k) {
-            for (int l = 0; l < NQ; ++l) {
-                const double cf = tau * r2h * A.D[k * NQ + l];
-                double J[3][3];
-                flux_jac(rk[l], J);
-                for (int v = 0; v < 3; ++v)
-                    for (int w = 0; w < 3; ++w)
-                        if (J[v][w] != 0.0) sM[vb(v, k)][vb(w, l)][t] += cf * J[v][w];
-            }
-            sM[vb(1, k)][vb(0, k)][t] += tau * A.g;
+        const HRef ro = href_at(A, href(A, e, ez, kr, i + NQ * (j + NQ * kr)), ez, kr);  // this row's node
+        // row r of I - tau L_e, its coupling row to the layer below (bottom
+        // rows) or above (top rows), and its right-hand sides
+        double M[VS_N];
+#pragma unroll
+        for (int c = 0; c < VS_N; ++c) M[c] = c == r ? 1.0 : 0.0;
+#pragma unroll
+        for (int l = 0; l < NQ; ++l) {
+            const double cf = tau * r2h * Dr[l];
+            double J[3][3];
+            flux_jac(rk[l], J);
+#pragma unroll
+            for (int w = 0; w < 3; ++w) M[vb(w, l)] += cf * J[v3][w];
         }
-        double Bt[3][3];  // coupling of this element's top to the one above
-        for (int side = 0; side < 2; ++side) {
-            const int k = side == 0 ? 0 : NQ - 1;
+        if (v3 == 1) M[vb(0, kr)] += tau * A.g;
+        double cpl[3] = {0.0, 0.0, 0.0};
+        if (kr == 0 || kr == NQ - 1) {
+            const int side = kr == 0 ? 0 : 1;
             const double nrm = side == 0 ? -1.0 : 1.0;
             const int ezn = ez + (side == 0 ? -1 : 1);
             if (ezn >= 0 && ezn < nz) {
-                const int kn = NQ - 1 - k;
+                const int kn = NQ - 1 - kr;
                 const int en = e + (side == 0 ? -A.ne01 : A.ne01);
                 const HRef rn = href_at(A, href(A, en, ezn, kn, i + NQ * (j + NQ * kn)), ezn, kn);
-                const double lam = rk[k].c > rn.c ? rk[k].c : rn.c;
+                const double lam = ro.c > rn.c ? ro.c : rn.c;
                 double Jm[3][3], Jp[3][3];
-                flux_jac(rk[k], Jm);
+                flux_jac(ro, Jm);
                 flux_jac(rn, Jp);
-                for (int v = 0; v < 3; ++v)
-                    for (int w = 0; w < 3; ++w) {
-                        // own node: L += lift (n/2 J^- - lam/2 I); neighbour: L += lift (-n/2 J^+ + lam/2 I)
-                        sM[vb(v, k)][vb(w, k)][t] -= tau * lift * (0.5 * nrm * Jm[v][w] - (v == w ? 0.5 * lam : 0.0));
-                        const double off = -tau * lift * (-0.5 * nrm * Jp[v][w] + (v == w ? 0.5 * lam : 0.0));
-                        if (side == 0) Cb[v][w] = off;
-                        else Bt[v][w] = off;
-                    }
+#pragma unroll
+                for (int w = 0; w < 3; ++w) {
+                    M[vb(w, kr)] -= tau * lift * (0.5 * nrm * Jm[v3][w] - (v3 == w ? 0.5 * lam : 0.0));
+                    cpl[w] = -tau * lift * (-0.5 * nrm * Jp[v3][w] + (v3 == w ? 0.5 * lam : 0.0));
+                }
             } else {
                 // wall: L_rho += lift n m, L_m -= lift c m, L_E += lift n h m
-                sM[vb(0, k)][vb(1, k)][t] -= tau * lift * nrm;
-                sM[vb(1, k)][vb(1, k)][t] += tau * lift * rk[k].c;
-                sM[vb(2, k)][vb(1, k)][t] -= tau * lift * nrm * rk[k].h;
-                for (int v = 0; v < 3; ++v)
-                    for (int w = 0; w < 3; ++w) {
-                        if (side == 0) Cb[v][w] = 0.0;
-                        else Bt[v][w] = 0.0;
-                    }
+                if (v3 == 0) M[vb(1, kr)] -= tau * lift * nrm;
+                if (v3 == 1) M[vb(1, kr)] += tau * lift * ro.c;
+                if (v3 == 2) M[vb(1, kr)] -= tau * lift * nrm * ro.h;
             }
         }
-        // Schur update of the bottom nodes by the elements below
-        if (ez > 0)
-            for (int v = 0; v < 3; ++v)
-                for (int w = 0; w < 3; ++w) {
-                    double s = 0.0;
-                    for (int q = 0; q < 3; ++q) s += Cb[v][q] * G[q][w];
-                    sM[vb(v, 0)][vb(w, 0)][t] -= s;
+        const int tnode = i + NQ * (j + NQ * kr);
+        const int64_t ri = href(A, e, ez, kr, tnode);
+        double b[4];
+        b[0] = (double)B[var * A.nnS + (int64_t)e * SRUN + tnode] - sref<R>(A, var, ri);
+        if (kr == 0 && ez > 0) {
+            // Schur update of the bottom-node rows by the layers below
+#pragma unroll
+            for (int w = 0; w < 3; ++w) {
+                double sg = 0.0;
+#pragma unroll
+                for (int q = 0; q < 3; ++q) sg += cpl[q] * G[q][w];
+                M[vb(w, 0)] -= sg;
+            }
+            double sy = 0.0;
+#pragma unroll
+            for (int q = 0; q < 3; ++q) sy += cpl[q] * yprev[q];
+            b[0] -= sy;
+        }
+#pragma unroll
+        for (int q = 0; q < 3; ++q) b[1 + q] = r == vb(q, NQ - 1) ? 1.0 : 0.0;
+
+        // elimination with partial pivoting across the lanes of the line
+        bool used = !rowl;
+        int mycol = -1;
+#pragma unroll
+        for (int c = 0; c < VS_N; ++c) {
+            // pivot: the largest |M[c]| among the rows not yet used, the
+            // lowest row on ties
+            double best = used ? -1.0 : fabs(M[c]);
+            int who = r;
+            row_argmax_step<0xB1>(best, who);
+            row_argmax_step<0x4E>(best, who);
+            row_argmax_step<0x141>(best, who);
+            row_argmax_step<0x140>(best, who);
+            if (r == who) {
+#pragma unroll
+                for (int q = 0; q < VS_N; ++q) sP[gq][q] = M[q];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) sP[gq][VS_N + q] = b[q];
+                used = true;
+                mycol = c;
+            }
+            __syncthreads();
+            if (!used) {
+                const double f = M[c] * (1.0 / sP[gq][c]);
+                if (f != 0.0) {
+#pragma unroll
+                    for (int q = c + 1; q < VS_N; ++q) M[q] -= f * sP[gq][q];
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) b[q] -= f * sP[gq][VS_N + q];
                 }
-        // right-hand sides: unit vectors at the top nodes, and the deviation
-        for (int r = 0; r < VS_N; ++r) {
-            const int v3 = r / NQ, k = r % NQ;
-            const int var = v3 == 0 ? 0 : (v3 == 1 ? 3 : 4);
-            const int tnode = i + NQ * (j + NQ * k);
-            const int64_t ri = href(A, e, ez, k, tnode);
-            double rhs = (double)B[var * A.nnS + (int64_t)e * SRUN + tnode] - sref<R>(A, var, ri);
-            if (k == 0 && ez > 0) {
-                double s = 0.0;
-                for (int q = 0; q < 3; ++q) s += Cb[v3][q] * yprev[q];
-                rhs -= s;
             }
-            sB[r][0][t] = rhs;
-            for (int q = 0; q < 3; ++q) sB[r][1 + q][t] = r == vb(q, NQ - 1) ? 1.0 : 0.0;
+            __syncthreads();
         }
-        lu_solve(sM, sB, 4, t);
-        // S_e (3 x 3) = W_e at the top nodes; G = S_e Btil_e; Z_e = W_e Btil_e
+        // back substitution, column by column from the last: the owner of
+        // unknown c finishes it and broadcasts it, the others subtract
+        double x[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int c = VS_N - 1; c >= 0; --c) {
+            if (mycol == c) {
+                const double inv = 1.0 / M[c];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    x[q] = b[q] * inv;
+                    sP[gq][q] = x[q];
+                }
+            }
+            __syncthreads();
+            if (mycol >= 0 && mycol < c) {
+#pragma unroll
+                for (int q = 0; q < 4; ++q) b[q] -= M[c] * sP[gq][q];
+            }
+            __syncthreads();
+        }
+        // broadcasts: S_e (W at the top-node unknowns), y there, and Btil_e
+        // (the coupling rows of the top nodes)
+        if (mycol >= 0 && mycol % NQ == NQ - 1) {
+            const int v = mycol / NQ;
+#pragma unroll
+            for (int q = 0; q < 3; ++q) sQ[gq][3 * v + q] = x[1 + q];
+            sQ[gq][9 + v] = x[0];
+        }
+        if (rowl && kr == NQ - 1) {
+#pragma unroll
+            for (int w = 0; w < 3; ++w) sQ[gq][12 + 3 * v3 + w] = cpl[w];
+        }
+        __syncthreads();
+        double Bt[3][3];
+#pragma unroll
+        for (int q = 0; q < 3; ++q)
+#pragma unroll
+            for (int w = 0; w < 3; ++w) Bt[q][w] = sQ[gq][12 + 3 * q + w];
+#pragma unroll
         for (int v = 0; v < 3; ++v) {
+#pragma unroll
             for (int w = 0; w < 3; ++w) {
-                double s = 0.0;
-                for (int q = 0; q < 3; ++q) s += sB[vb(v, NQ - 1)][1 + q][t] * Bt[q][w];
-                G[v][w] = s;
+                double sg = 0.0;
+#pragma unroll
+                for (int q = 0; q < 3; ++q) sg += sQ[gq][3 * v + q] * Bt[q][w];
+                G[v][w] = sg;
             }
-            yprev[v] = sB[vb(v, NQ - 1)][0][t];
+            yprev[v] = sQ[gq][9 + v];
         }
-        for (int r = 0; r < VS_N; ++r) {
+        if (mycol >= 0 && live) {
+#pragma unroll
             for (int w = 0; w < 3; ++w) {
-                double s = 0.0;
-                for (int q = 0; q < 3; ++q) s += sB[r][1 + q][t] * Bt[q][w];
-                S(ez, r * 3 + w) = s;
+                double sz = 0.0;
+#pragma unroll
+                for (int q = 0; q < 3; ++q) sz += x[1 + q] * Bt[q][w];
+                scr[ez * 60 + mycol * 3 + w] = sz;
             }
-            S(ez, 45 + r) = sB[r][0][t];
+            scr[ez * 60 + 45 + mycol] = x[0];
         }
+        __syncthreads();
     }
-    // back substitution: x_e = y_e - Z_e x_{e+1}(bottom nodes)
-    double xb[3] = {0, 0, 0};
+    // back substitution over the layers from the top: lane r takes unknown r
+    double xb[3] = {0.0, 0.0, 0.0};
     for (int ez = nz - 1; ez >= 0; --ez) {
         const int e = ex + A.ne0 * (ey + A.ne1 * ez);
-        double x[VS_N];
-        for (int r = 0; r < VS_N; ++r) {
-            double v = S(ez, 45 + r);
+        double xr = 0.0;
+        if (rowl) {
+            xr = scr[ez * 60 + 45 + r];
             if (ez < nz - 1)
-                for (int w = 0; w < 3; ++w) v -= S(ez, r * 3 + w) * xb[w];
-            x[r] = v;
+#pragma unroll
+                for (int w = 0; w < 3; ++w) xr -= scr[ez * 60 + r * 3 + w] * xb[w];
+            const int tnode = i + NQ * (j + NQ * kr);
+            const int64_t ri = href(A, e, ez, kr, tnode);
+            if (live) Yo[var * A.nnS + (int64_t)e * SRUN + tnode] = (R)(sref<R>(A, var, ri) + xr);
+            if (kr == 0) sQ[gq][v3] = xr;
         }
-        for (int r = 0; r < VS_N; ++r) {
-            const int v3 = r / NQ, k = r % NQ;
-            const int var = v3 == 0 ? 0 : (v3 == 1 ? 3 : 4);
-            const int tnode = i + NQ * (j + NQ * k);
-            const int64_t ri = href(A, e, ez, k, tnode);
-            Yo[var * A.nnS + (int64_t)e * SRUN + tnode] = (R)(sref<R>(A, var, ri) + x[r]);
-        }
-        for (int v = 0; v < 3; ++v) xb[v] = x[vb(v, 0)];
+        __syncthreads();
+#pragma unroll
+        for (int w = 0; w < 3; ++w) xb[w] = sQ[gq][w];
+        __syncthreads();
     }
     // horizontal momenta: identity except the 2 x 2 systems of the interior
-    // vertical faces, [1 + s, -s; -s, 1 + s] with s = tau lift lam / 2
-    for (int ez = 0; ez < nz; ++ez) {
-        const int e = ex + A.ne0 * (ey + A.ne1 * ez);
-        for (int k = 0; k < NQ; ++k) {
+    // vertical faces, [1 + s, -s; -s, 1 + s] with s = tau lift lam / 2; lane
+    // r < 10 takes variable 1 + r / 5 at node r % 5 of every layer
+    if (r < 2 * NQ && live) {
+        const int v = 1 + r / NQ, k = r % NQ;
+        for (int ez = 0; ez < nz; ++ez) {
+            const int e = ex + A.ne0 * (ey + A.ne1 * ez);
             const int tnode = i + NQ * (j + NQ * k);
             const int64_t ri = href(A, e, ez, k, tnode);
             if (k == NQ - 1 && ez < nz - 1) {
@@ -343,15 +409,13 @@ __global__ __launch_bounds__(VS_THREADS) void k_vsolve(const HeviArgs A, const R
                 const int64_t rin = href(A, en, ez + 1, 0, tn);
                 const HRef ra = href_at(A, ri, ez, k), rb = href_at(A, rin, ez + 1, 0);
                 const double lam = ra.c > rb.c ? ra.c : rb.c;
-                const double s = 0.5 * tau * lift * lam, al = 1.0 + s, det = al * al - s * s;
-                for (int v = 1; v <= 2; ++v) {
-                    const double xa = (double)B[v * A.nnS + (int64_t)e * SRUN + tnode] - sref<R>(A, v, ri);
-                    const double xbv = (double)B[v * A.nnS + (int64_t)en * SRUN + tn] - sref<R>(A, v, rin);
-                    Yo[v * A.nnS + (int64_t)e * SRUN + tnode] = (R)(sref<R>(A, v, ri) + (al * xa + s * xbv) / det);
-                    Yo[v * A.nnS + (int64_t)en * SRUN + tn] = (R)(sref<R>(A, v, rin) + (s * xa + al * xbv) / det);
-                }
+                const double sv = 0.5 * tau * lift * lam, al = 1.0 + sv, det = al * al - sv * sv;
+                const double xa = (double)B[v * A.nnS + (int64_t)e * SRUN + tnode] - sref<R>(A, v, ri);
+                const double xbv = (double)B[v * A.nnS + (int64_t)en * SRUN + tn] - sref<R>(A, v, rin);
+                Yo[v * A.nnS + (int64_t)e * SRUN + tnode] = (R)(sref<R>(A, v, ri) + (al * xa + sv * xbv) / det);
+                Yo[v * A.nnS + (int64_t)en * SRUN + tn] = (R)(sref<R>(A, v, rin) + (sv * xa + al * xbv) / det);
             } else if (!(k == 0 && ez > 0)) {
-                for (int v = 1; v <= 2; ++v) Yo[v * A.nnS + (int64_t)e * SRUN + tnode] = B[v * A.nnS + (int64_t)e * SRUN + tnode];
+                Yo[v * A.nnS + (int64_t)e * SRUN + tnode] = B[v * A.nnS + (int64_t)e * SRUN + tnode];
             }
         }
     }
@@ -416,7 +480,7 @@ hipError_t launch_hevi_solve(const cm_model* m, double tau, const void* B, void*
 {
     const HeviArgs A = hevi_args(m, tau, scratch);
     const int64_t nl = hevi_lines(m);
-    const dim3 grid((unsigned)((nl + VS_THREADS - 1) / VS_THREADS)), block(VS_THREADS);
+    const dim3 grid((unsigned)((nl + VS_BLOCK / VS_LANES - 1) / (VS_BLOCK / VS_LANES))), block(VS_BLOCK);
     if (m->desc.precision == CM_FP64)
         hipLaunchKernelGGL(k_vsolve<double>, grid, block, 0, s, A, (const double*)B, (double*)Yout, nl);
     else
