@@ -179,8 +179,8 @@ __device__ __forceinline__ void flux_jac(const HRef& r, double J[3][3])
 // in registers, with the Schur update of its bottom-node rows by the layer
 // below (the layers couple through one node pair, a rank-3 coupling); the
 // block is solved by Gaussian elimination with partial pivoting across the
-// lanes (the pivot row broadcast through LDS; the lane that supplied the
-// pivot for column c then owns unknown c) for the deviation and the three
+// lanes (the pivot row goes to the row's lanes by lane permutes; the lane
+// that supplied the pivot for column c then owns unknown c) for the deviation and the three
 // unit vectors at the top nodes.  Each layer leaves y_e and Z_e = W_e Btil_e
 // in the workspace ([line][layer][60]); the back substitution
 // x_e = y_e - Z_e x_{e+1}(bottom nodes) runs from the top.  The horizontal
@@ -191,7 +191,6 @@ __global__ __launch_bounds__(VS_BLOCK) void k_vsolve(const HeviArgs A, const R* 
                                                      int64_t n_lines)
 {
     constexpr int NG = VS_BLOCK / VS_LANES;
-    __shared__ double sP[NG][VS_N + 4];   // pivot row (15 entries and 4 right-hand sides)
     __shared__ double sQ[NG][24];         // per-layer broadcasts
     const int lane = threadIdx.x;
     const int gq = lane / VS_LANES, r = lane % VS_LANES;
@@ -279,9 +278,12 @@ __global__ __launch_bounds__(VS_BLOCK) void k_vsolve(const HeviArgs A, const R* 
 #pragma unroll
         for (int q = 0; q < 3; ++q) b[1 + q] = r == vb(q, NQ - 1) ? 1.0 : 0.0;
 
-        // elimination with partial pivoting across the lanes of the line
+        // elimination with partial pivoting across the lanes of the line;
+        // the pivot row goes to the other lanes of the row by lane permutes
         bool used = !rowl;
         int mycol = -1;
+        int owner[VS_N];
+        const int base = lane - r;  // first lane of this line's row
 #pragma unroll
         for (int c = 0; c < VS_N; ++c) {
             // pivot: the largest |M[c]| among the rows not yet used, the
@@ -292,45 +294,44 @@ __global__ __launch_bounds__(VS_BLOCK) void k_vsolve(const HeviArgs A, const R* 
             row_argmax_step<0x4E>(best, who);
             row_argmax_step<0x141>(best, who);
             row_argmax_step<0x140>(best, who);
-            if (r == who) {
+            owner[c] = who;
+            const bool piv = r == who;
+            double pr[VS_N], pb[4];
 #pragma unroll
-                for (int q = 0; q < VS_N; ++q) sP[gq][q] = M[q];
+            for (int q = c; q < VS_N; ++q) pr[q] = __shfl(M[q], base + who);
 #pragma unroll
-                for (int q = 0; q < 4; ++q) sP[gq][VS_N + q] = b[q];
+            for (int q = 0; q < 4; ++q) pb[q] = __shfl(b[q], base + who);
+            if (piv) {
                 used = true;
                 mycol = c;
-            }
-            __syncthreads();
-            if (!used) {
-                const double f = M[c] * (1.0 / sP[gq][c]);
+            } else if (!used) {
+                const double f = M[c] * (1.0 / pr[c]);
                 if (f != 0.0) {
 #pragma unroll
-                    for (int q = c + 1; q < VS_N; ++q) M[q] -= f * sP[gq][q];
+                    for (int q = c + 1; q < VS_N; ++q) M[q] -= f * pr[q];
 #pragma unroll
-                    for (int q = 0; q < 4; ++q) b[q] -= f * sP[gq][VS_N + q];
+                    for (int q = 0; q < 4; ++q) b[q] -= f * pb[q];
                 }
             }
-            __syncthreads();
         }
         // back substitution, column by column from the last: the owner of
-        // unknown c finishes it and broadcasts it, the others subtract
+        // unknown c finishes it, the others take it by a lane permute and
+        // subtract
         double x[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
         for (int c = VS_N - 1; c >= 0; --c) {
+            double xc[4];
             if (mycol == c) {
                 const double inv = 1.0 / M[c];
 #pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    x[q] = b[q] * inv;
-                    sP[gq][q] = x[q];
-                }
+                for (int q = 0; q < 4; ++q) x[q] = b[q] * inv;
             }
-            __syncthreads();
+#pragma unroll
+            for (int q = 0; q < 4; ++q) xc[q] = __shfl(x[q], base + owner[c]);
             if (mycol >= 0 && mycol < c) {
 #pragma unroll
-                for (int q = 0; q < 4; ++q) b[q] -= M[c] * sP[gq][q];
+                for (int q = 0; q < 4; ++q) b[q] -= M[c] * xc[q];
             }
-            __syncthreads();
         }
         // broadcasts: S_e (W at the top-node unknowns), y there, and Btil_e
         // (the coupling rows of the top nodes)
