@@ -82,3 +82,59 @@ def test_full_size_two_lsrk_steps_match_oracle():
     rel_change = np.array([np.abs(Yg[v] - Yo[v]).max() for v in range(Y.shape[0])]) / np.maximum(moved, 1e-300)
     print("2-step state errors", err, "relative to the change over the 2 steps", rel_change)
     assert np.all(err < STEP_TOL), err
+
+
+@pytest.mark.parametrize("name,over", [("bubble_32", {"closure": "vreman"}), ("bubble_32", {"flux": "roe"}),
+                                       ("bubble_32", {"flux": "hllc"}), ("moist_64", {"ice": 1})],
+                         ids=["vreman", "roe", "hllc", "ice"])
+def test_full_size_variant_rhs_matches_oracle(name, over):
+    """The closure, flux and ice-phase variants at the sizes bench.py times
+    them (Vreman, Roe, HLLC on the 32^3 bubble; the ice phase on the moist
+    64x64x30 set-up): the FP64 tendency of every node against the oracle at
+    1e-11, or at four times the oracle's own 1-ulp floor where that floor
+    exceeds it.  HLLC is such a case on the bubble at rest: its contact speed
+    divides the pressure jump, which one-ulp input changes make of order
+    ulp(p), by rho (S - u), so the oracle's energy tendency moves 5.7e-11
+    under them (the GPU lands 1.2e-11 from it).  The distance to the
+    FMA-contracted oracle is printed; on these dry states it is below 1e-16
+    and bounds nothing."""
+    import torch
+
+    c = W.case(name)
+    c["model"] = dict(c["model"], **over)
+    Y, Yref, dt = W.initial_state(c)
+    print("full-size rhs:", name, over, flush=True)
+    h = hmin(c["grid"])
+    Rref, floor = rounding_floor(oracle.Model(oracle.Grid(c["grid"]), c["model"], Yref).rhs, Y, h)
+    cfloor = contraction_floor(c["grid"], c["model"], Yref, Y, Rref, h)
+    g = B.Grid(c["grid"])
+    m = B.Model(g, c["model"], Yref)
+    Yd = m.new_state(Y)
+    Rd = m.new_state()
+    m.rhs(Yd, Rd)
+    torch.cuda.synchronize()
+    Rg = m.tendency_to_numpy(Rd).astype(np.float64)
+    err = rhs_errors(Rg, Rref, Y, h)
+    print(name, over, "full-size rhs errors", err, "plain relative", literal_rhs_errors(Rg, Rref),
+          "oracle 1-ulp floor", floor, "oracle vs FMA-contracted oracle", cfloor)
+    assert np.all(err < np.maximum(1e-11, 4.0 * floor)), (err, floor)
+
+
+def test_full_size_lsrk144_step_matches_oracle():
+    """One LSRK144 step (fourteen fused stages) of the 32^3 bubble in the
+    launch configuration bench.py times, against the oracle's."""
+    import torch
+
+    c = W.case("bubble_32")
+    Y, Yref, dt = W.initial_state(c)
+    dt4 = 4.0 * dt  # the step the fourteen-stage scheme runs at in the density-current test
+    print("full-size LSRK144 step: bubble_32", flush=True)
+    Yo, _ = oracle.Model(oracle.Grid(c["grid"]), c["model"], Yref).steps(Y, dt4, 1, scheme="lsrk144")
+    g = B.Grid(c["grid"])
+    m = B.Model(g, c["model"], Yref)
+    Ya, Yb, dQ = m.new_state(Y), m.new_state(), m.new_state()
+    m.lsrk144_step(Ya, Yb, dQ, 0.0, dt4)
+    torch.cuda.synchronize()
+    err = state_errors(m.to_numpy(Ya), Yo)
+    print("LSRK144 full-size state errors", err)
+    assert np.all(err < STEP_TOL), err

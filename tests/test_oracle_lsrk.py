@@ -124,3 +124,29 @@ def test_lsrk144_empirical_temporal_order(oracle_lib):
         errs.append(np.abs(Y[1] - ref[1]).max())
     orders = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
     assert np.all(orders > 3.7), (errs, orders)
+
+
+def test_lsrk144_amplifies_stage_rounding(oracle_lib):
+    """The fourteen-stage coefficients are large (A down to -7.1, B up to
+    5.5), so the partial stage sums cancel and each stage's rounding is
+    amplified: three steps of the 4^3 bubble, started once from the state and
+    once from the state with every word moved by at most one ulp, separate
+    about a hundred times further under LSRK144 (at twice the step) than
+    under LSRK54.  This is why the GPU's LSRK144 parity is a few 1e-11 in
+    momentum where its LSRK54 parity is 1e-13; both stay under the 1e-10
+    step bar."""
+    from parity import state_errors
+
+    c = W.case("bubble_4")
+    Y, Yref, speed = W.perturbed_state(c, seed=11, amp_u=6.0, amp_T=2.0, amp_q=1.5e-3)
+    dt = W.cfl_dt(c["grid"], speed)
+    Yp = Y * (1.0 + 2.2e-16 * np.random.default_rng(1).choice([-1.0, 0.0, 1.0], size=Y.shape))
+    M = oracle_lib.Model(oracle_lib.Grid(c["grid"]), c["model"], Yref)
+    sep = {}
+    for scheme, f in (("lsrk54", 1.0), ("lsrk144", 2.0)):
+        Ya, _ = M.steps(Y, f * dt, 3, scheme=scheme)
+        Yb, _ = M.steps(Yp, f * dt, 3, scheme=scheme)
+        sep[scheme] = state_errors(Yb, Ya)
+    ratio = sep["lsrk144"][1:4].max() / sep["lsrk54"][1:4].max()
+    assert ratio > 20.0, sep
+    assert sep["lsrk144"].max() < 1e-10, sep
