@@ -142,24 +142,15 @@ constexpr int VS_BLOCK = 64;     // one wave: four lines
 // index of (variable 0 rho, 1 rho w, 2 rho e_tot; node k) in an element block
 __device__ __forceinline__ int vb(int v3, int k) { return v3 * NQ + k; }
 
-// one step of an arg-max over the 16 lanes of a DPP row: the value and lane
-// index of the partner lane given by the DPP control (0xB1: quad_perm
-// [1,0,3,2]; 0x4E: quad_perm [2,3,0,1]; 0x141: row_half_mirror; 0x140:
-// row_mirror; the four in this order pair every lane with every other of its
-// row), larger value first, the lower index on ties
+// one step of a maximum over the 16 lanes of a DPP row: the key of the
+// partner lane given by the DPP control (0xB1: quad_perm [1,0,3,2]; 0x4E:
+// quad_perm [2,3,0,1]; 0x141: row_half_mirror; 0x140: row_mirror; the four
+// in this order pair every lane with every other of its row)
 template <int CTRL>
-__device__ __forceinline__ void row_argmax_step(double& best, int& who)
+__device__ __forceinline__ unsigned row_max_step(unsigned key)
 {
-    const unsigned long long bits = __builtin_bit_cast(unsigned long long, best);
-    const int lo = __builtin_amdgcn_update_dpp((int)(unsigned)bits, (int)(unsigned)bits, CTRL, 0xF, 0xF, false);
-    const int hi = __builtin_amdgcn_update_dpp((int)(unsigned)(bits >> 32), (int)(unsigned)(bits >> 32), CTRL, 0xF,
-                                               0xF, false);
-    const double ob = __builtin_bit_cast(double, ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
-    const int ow = __builtin_amdgcn_update_dpp(who, who, CTRL, 0xF, 0xF, false);
-    if (ob > best || (ob == best && ow < who)) {
-        best = ob;
-        who = ow;
-    }
+    const unsigned o = (unsigned)__builtin_amdgcn_update_dpp((int)key, (int)key, CTRL, 0xF, 0xF, false);
+    return o > key ? o : key;
 }
 
 // Jacobian of the vertical flux (rho w, p', h rho w') w.r.t. (rho', m, E')
@@ -179,8 +170,9 @@ __device__ __forceinline__ void flux_jac(const HRef& r, double J[3][3])
 // in registers, with the Schur update of its bottom-node rows by the layer
 // below (the layers couple through one node pair, a rank-3 coupling); the
 // block is solved by Gaussian elimination with partial pivoting across the
-// lanes (the pivot row goes to the row's lanes by lane permutes; the lane
-// that supplied the pivot for column c then owns unknown c) for the deviation and the three
+// lanes (the pivot by a DPP maximum over the row, the pivot row to the row's
+// lanes by lane permutes; the lane that supplied the pivot for column c then
+// owns unknown c) for the deviation and the three
 // unit vectors at the top nodes.  Each layer leaves y_e and Z_e = W_e Btil_e
 // in the workspace ([line][layer][60]); the back substitution
 // x_e = y_e - Z_e x_{e+1}(bottom nodes) runs from the top.  The horizontal
@@ -219,19 +211,15 @@ __global__ __launch_bounds__(VS_BLOCK) void k_vsolve(const HeviArgs A, const R* 
         for (int k = 0; k < NQ; ++k) rk[k] = href_at(A, href(A, e, ez, k, i + NQ * (j + NQ * k)), ez, k);
         const HRef ro = href_at(A, href(A, e, ez, kr, i + NQ * (j + NQ * kr)), ez, kr);  // this row's node
         // row r of I - tau L_e, its coupling row to the layer below (bottom
-        // rows) or above (top rows), and its right-hand sides
-        double M[VS_N];
+        // rows) or above (top rows), and its right-hand sides.  The terms in
+        // this row's own node columns (w, kr) (the identity, buoyancy, the
+        // face penalty or the wall) are summed first and enter with a
+        // compare on the column's node, so that no entry is addressed by a
+        // lane-dependent index.
+        double own[3];
 #pragma unroll
-        for (int c = 0; c < VS_N; ++c) M[c] = c == r ? 1.0 : 0.0;
-#pragma unroll
-        for (int l = 0; l < NQ; ++l) {
-            const double cf = tau * r2h * Dr[l];
-            double J[3][3];
-            flux_jac(rk[l], J);
-#pragma unroll
-            for (int w = 0; w < 3; ++w) M[vb(w, l)] += cf * J[v3][w];
-        }
-        if (v3 == 1) M[vb(0, kr)] += tau * A.g;
+        for (int w = 0; w < 3; ++w) own[w] = w == v3 ? 1.0 : 0.0;
+        if (v3 == 1) own[0] += tau * A.g;
         double cpl[3] = {0.0, 0.0, 0.0};
         if (kr == 0 || kr == NQ - 1) {
             const int side = kr == 0 ? 0 : 1;
@@ -247,15 +235,24 @@ __global__ __launch_bounds__(VS_BLOCK) void k_vsolve(const HeviArgs A, const R* 
                 flux_jac(rn, Jp);
 #pragma unroll
                 for (int w = 0; w < 3; ++w) {
-                    M[vb(w, kr)] -= tau * lift * (0.5 * nrm * Jm[v3][w] - (v3 == w ? 0.5 * lam : 0.0));
+                    own[w] -= tau * lift * (0.5 * nrm * Jm[v3][w] - (v3 == w ? 0.5 * lam : 0.0));
                     cpl[w] = -tau * lift * (-0.5 * nrm * Jp[v3][w] + (v3 == w ? 0.5 * lam : 0.0));
                 }
             } else {
                 // wall: L_rho += lift n m, L_m -= lift c m, L_E += lift n h m
-                if (v3 == 0) M[vb(1, kr)] -= tau * lift * nrm;
-                if (v3 == 1) M[vb(1, kr)] += tau * lift * ro.c;
-                if (v3 == 2) M[vb(1, kr)] -= tau * lift * nrm * ro.h;
+                if (v3 == 0) own[1] -= tau * lift * nrm;
+                if (v3 == 1) own[1] += tau * lift * ro.c;
+                if (v3 == 2) own[1] -= tau * lift * nrm * ro.h;
             }
+        }
+        double M[VS_N];
+#pragma unroll
+        for (int l = 0; l < NQ; ++l) {
+            const double cf = tau * r2h * Dr[l];
+            double J[3][3];
+            flux_jac(rk[l], J);
+#pragma unroll
+            for (int w = 0; w < 3; ++w) M[vb(w, l)] = cf * J[v3][w] + (l == kr ? own[w] : 0.0);
         }
         const int tnode = i + NQ * (j + NQ * kr);
         const int64_t ri = href(A, e, ez, kr, tnode);
@@ -286,33 +283,33 @@ __global__ __launch_bounds__(VS_BLOCK) void k_vsolve(const HeviArgs A, const R* 
         const int base = lane - r;  // first lane of this line's row
 #pragma unroll
         for (int c = 0; c < VS_N; ++c) {
-            // pivot: the largest |M[c]| among the rows not yet used, the
-            // lowest row on ties
-            double best = used ? -1.0 : fabs(M[c]);
-            int who = r;
-            row_argmax_step<0xB1>(best, who);
-            row_argmax_step<0x4E>(best, who);
-            row_argmax_step<0x141>(best, who);
-            row_argmax_step<0x140>(best, who);
+            // pivot: the largest |M[c]| among the rows not yet used, as one
+            // 32-bit key per lane: the bits of |M[c]| in FP32 (their order is
+            // the order of the magnitudes) with the low four replaced by
+            // 15 - r, so the row maximum names its lane (the largest
+            // magnitude to 2^-19, the lowest row among those); used rows 0
+            unsigned key = used ? 0u : ((__float_as_uint((float)fabs(M[c])) & ~0xFu) | (unsigned)(15 - r));
+            key = row_max_step<0xB1>(key);
+            key = row_max_step<0x4E>(key);
+            key = row_max_step<0x141>(key);
+            key = row_max_step<0x140>(key);
+            const int who = 15 - (int)(key & 0xFu);
             owner[c] = who;
-            const bool piv = r == who;
-            double pr[VS_N], pb[4];
-#pragma unroll
-            for (int q = c; q < VS_N; ++q) pr[q] = __shfl(M[q], base + who);
-#pragma unroll
-            for (int q = 0; q < 4; ++q) pb[q] = __shfl(b[q], base + who);
-            if (piv) {
+            // the pivot row's entries right of c and its right-hand sides go
+            // to the row's lanes one at a time; the rows not yet used subtract
+            // their multiple of it (the multiplier is zero on the pivot row
+            // and on used rows, which a finite pivot row leaves unchanged)
+            const int src = base + who;
+            const double pc = __shfl(M[c], src);
+            const double f = (!used && r != who) ? M[c] * (1.0 / pc) : 0.0;
+            if (r == who) {
                 used = true;
                 mycol = c;
-            } else if (!used) {
-                const double f = M[c] * (1.0 / pr[c]);
-                if (f != 0.0) {
-#pragma unroll
-                    for (int q = c + 1; q < VS_N; ++q) M[q] -= f * pr[q];
-#pragma unroll
-                    for (int q = 0; q < 4; ++q) b[q] -= f * pb[q];
-                }
             }
+#pragma unroll
+            for (int q = c + 1; q < VS_N; ++q) M[q] = fma(-f, __shfl(M[q], src), M[q]);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) b[q] = fma(-f, __shfl(b[q], src), b[q]);
         }
         // back substitution, column by column from the last: the owner of
         // unknown c finishes it, the others take it by a lane permute and
@@ -328,10 +325,9 @@ __global__ __launch_bounds__(VS_BLOCK) void k_vsolve(const HeviArgs A, const R* 
             }
 #pragma unroll
             for (int q = 0; q < 4; ++q) xc[q] = __shfl(x[q], base + owner[c]);
-            if (mycol >= 0 && mycol < c) {
+            const double u = (mycol >= 0 && mycol < c) ? M[c] : 0.0;
 #pragma unroll
-                for (int q = 0; q < 4; ++q) b[q] -= M[c] * xc[q];
-            }
+            for (int q = 0; q < 4; ++q) b[q] = fma(-u, xc[q], b[q]);
         }
         // broadcasts: S_e (W at the top-node unknowns), y there, and Btil_e
         // (the coupling rows of the top nodes)
