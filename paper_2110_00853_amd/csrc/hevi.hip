@@ -153,12 +153,16 @@ __device__ __forceinline__ unsigned row_max_step(unsigned key)
     return o > key ? o : key;
 }
 
-// Jacobian of the vertical flux (rho w, p', h rho w') w.r.t. (rho', m, E')
-__device__ __forceinline__ void flux_jac(const HRef& r, double J[3][3])
+// entry (row v, column w) of the Jacobian of the vertical flux
+// (rho w, p', h rho w') w.r.t. (rho', m, E'):
+//   [0 1 0; b 0 R_d/c_vd; 0 h 0]
+// (w a compile-time column, v the lane's row: written out so that it is a
+// select, not an indexed read of a register array)
+__device__ __forceinline__ double jac_entry(const HRef& r, int v, int w)
 {
-    J[0][0] = 0.0; J[0][1] = 1.0; J[0][2] = 0.0;
-    J[1][0] = r.b; J[1][1] = 0.0; J[1][2] = Phys::Rd / Phys::cvd;
-    J[2][0] = 0.0; J[2][1] = r.h; J[2][2] = 0.0;
+    if (w == 0) return v == 1 ? r.b : 0.0;
+    if (w == 1) return v == 0 ? 1.0 : (v == 2 ? r.h : 0.0);
+    return v == 1 ? Phys::Rd / Phys::cvd : 0.0;
 }
 
 // Y_out = Y_ref + x with (I - tau L) x = B - Y_ref on every vertical line
@@ -230,13 +234,10 @@ __global__ __launch_bounds__(VS_BLOCK) void k_vsolve(const HeviArgs A, const R* 
                 const int en = e + (side == 0 ? -A.ne01 : A.ne01);
                 const HRef rn = href_at(A, href(A, en, ezn, kn, i + NQ * (j + NQ * kn)), ezn, kn);
                 const double lam = ro.c > rn.c ? ro.c : rn.c;
-                double Jm[3][3], Jp[3][3];
-                flux_jac(ro, Jm);
-                flux_jac(rn, Jp);
 #pragma unroll
                 for (int w = 0; w < 3; ++w) {
-                    own[w] -= tau * lift * (0.5 * nrm * Jm[v3][w] - (v3 == w ? 0.5 * lam : 0.0));
-                    cpl[w] = -tau * lift * (-0.5 * nrm * Jp[v3][w] + (v3 == w ? 0.5 * lam : 0.0));
+                    own[w] -= tau * lift * (0.5 * nrm * jac_entry(ro, v3, w) - (v3 == w ? 0.5 * lam : 0.0));
+                    cpl[w] = -tau * lift * (-0.5 * nrm * jac_entry(rn, v3, w) + (v3 == w ? 0.5 * lam : 0.0));
                 }
             } else {
                 // wall: L_rho += lift n m, L_m -= lift c m, L_E += lift n h m
@@ -249,10 +250,8 @@ __global__ __launch_bounds__(VS_BLOCK) void k_vsolve(const HeviArgs A, const R* 
 #pragma unroll
         for (int l = 0; l < NQ; ++l) {
             const double cf = tau * r2h * Dr[l];
-            double J[3][3];
-            flux_jac(rk[l], J);
 #pragma unroll
-            for (int w = 0; w < 3; ++w) M[vb(w, l)] = cf * J[v3][w] + (l == kr ? own[w] : 0.0);
+            for (int w = 0; w < 3; ++w) M[vb(w, l)] = cf * jac_entry(rk[l], v3, w) + (l == kr ? own[w] : 0.0);
         }
         const int tnode = i + NQ * (j + NQ * kr);
         const int64_t ri = href(A, e, ez, kr, tnode);
