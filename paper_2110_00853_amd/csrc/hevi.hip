@@ -278,6 +278,7 @@ __global__ __launch_bounds__(VS_BLOCK) void k_vsolve(const HeviArgs A, const R* 
         // the pivot row goes to the other lanes of the row by lane permutes
         bool used = !rowl;
         int mycol = -1;
+        double myrp = 0.0;
         int owner[VS_N];
         const int base = lane - r;  // first lane of this line's row
 #pragma unroll
@@ -299,11 +300,16 @@ __global__ __launch_bounds__(VS_BLOCK) void k_vsolve(const HeviArgs A, const R* 
             // their multiple of it (the multiplier is zero on the pivot row
             // and on used rows, which a finite pivot row leaves unchanged)
             const int src = base + who;
-            const double pc = __shfl(M[c], src);
-            const double f = (!used && r != who) ? M[c] * (1.0 / pc) : 0.0;
+            // the pivot's reciprocal (Newton-refined hardware estimate; the
+            // pivot of a nonsingular block is finite and nonzero) serves the
+            // multipliers here and, kept by the pivot lane, its unknown in the
+            // back substitution
+            const double rp = frcp(__shfl(M[c], src));
+            const double f = (!used && r != who) ? M[c] * rp : 0.0;
             if (r == who) {
                 used = true;
                 mycol = c;
+                myrp = rp;
             }
 #pragma unroll
             for (int q = c + 1; q < VS_N; ++q) M[q] = fma(-f, __shfl(M[q], src), M[q]);
@@ -317,11 +323,9 @@ __global__ __launch_bounds__(VS_BLOCK) void k_vsolve(const HeviArgs A, const R* 
 #pragma unroll
         for (int c = VS_N - 1; c >= 0; --c) {
             double xc[4];
-            if (mycol == c) {
-                const double inv = 1.0 / M[c];
+            const bool mine = mycol == c;
 #pragma unroll
-                for (int q = 0; q < 4; ++q) x[q] = b[q] * inv;
-            }
+            for (int q = 0; q < 4; ++q) x[q] = mine ? b[q] * myrp : x[q];
 #pragma unroll
             for (int q = 0; q < 4; ++q) xc[q] = __shfl(x[q], base + owner[c]);
             const double u = (mycol >= 0 && mycol < c) ? M[c] : 0.0;
