@@ -188,6 +188,7 @@ __global__ __launch_bounds__(VS_BLOCK) void k_vsolve(const HeviArgs A, const R* 
 {
     constexpr int NG = VS_BLOCK / VS_LANES;
     __shared__ double sQ[NG][24];         // per-layer broadcasts
+    __shared__ double sG[NG][12];         // S_{e-1} Btil_{e-1} (9) and y_{e-1} at its top nodes (3)
     const int lane = threadIdx.x;
     const int gq = lane / VS_LANES, r = lane % VS_LANES;
     const int64_t line_id = (int64_t)blockIdx.x * NG + gq;
@@ -203,11 +204,9 @@ __global__ __launch_bounds__(VS_BLOCK) void k_vsolve(const HeviArgs A, const R* 
     const int nz = A.ne2;
     double* scr = A.scratch + line * (int64_t)nz * 60;   // [layer][60]: Z rows (45), then y (15)
     const int var = v3 == 0 ? 0 : (v3 == 1 ? 3 : 4);
-    double G[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};  // S_{e-1} Btil_{e-1}
-    double yprev[3] = {0, 0, 0};                          // y_{e-1} at its top nodes
-    double Dr[NQ];                                        // row kr of the differentiation matrix
-#pragma unroll
-    for (int l = 0; l < NQ; ++l) Dr[l] = A.D[kr * NQ + l];
+    __shared__ double sD[NQ * NQ];  // the differentiation matrix (its row kr read per layer)
+    if (lane < NQ * NQ) sD[lane] = A.D[lane];
+    __syncthreads();
     for (int ez = 0; ez < nz; ++ez) {
         const int e = ex + A.ne0 * (ey + A.ne1 * ez);
         HRef rk[NQ];
@@ -249,7 +248,7 @@ __global__ __launch_bounds__(VS_BLOCK) void k_vsolve(const HeviArgs A, const R* 
         double M[VS_N];
 #pragma unroll
         for (int l = 0; l < NQ; ++l) {
-            const double cf = tau * r2h * Dr[l];
+            const double cf = tau * r2h * sD[kr * NQ + l];
 #pragma unroll
             for (int w = 0; w < 3; ++w) M[vb(w, l)] = cf * jac_entry(rk[l], v3, w) + (l == kr ? own[w] : 0.0);
         }
@@ -263,12 +262,12 @@ __global__ __launch_bounds__(VS_BLOCK) void k_vsolve(const HeviArgs A, const R* 
             for (int w = 0; w < 3; ++w) {
                 double sg = 0.0;
 #pragma unroll
-                for (int q = 0; q < 3; ++q) sg += cpl[q] * G[q][w];
+                for (int q = 0; q < 3; ++q) sg += cpl[q] * sG[gq][3 * q + w];
                 M[vb(w, 0)] -= sg;
             }
             double sy = 0.0;
 #pragma unroll
-            for (int q = 0; q < 3; ++q) sy += cpl[q] * yprev[q];
+            for (int q = 0; q < 3; ++q) sy += cpl[q] * sG[gq][9 + q];
             b[0] -= sy;
         }
 #pragma unroll
@@ -279,7 +278,6 @@ __global__ __launch_bounds__(VS_BLOCK) void k_vsolve(const HeviArgs A, const R* 
         bool used = !rowl;
         int mycol = -1;
         double myrp = 0.0;
-        int owner[VS_N];
         const int base = lane - r;  // first lane of this line's row
 #pragma unroll
         for (int c = 0; c < VS_N; ++c) {
@@ -294,7 +292,6 @@ __global__ __launch_bounds__(VS_BLOCK) void k_vsolve(const HeviArgs A, const R* 
             key = row_max_step<0x141>(key);
             key = row_max_step<0x140>(key);
             const int who = 15 - (int)(key & 0xFu);
-            owner[c] = who;
             // the pivot row's entries right of c and its right-hand sides go
             // to the row's lanes one at a time; the rows not yet used subtract
             // their multiple of it (the multiplier is zero on the pivot row
@@ -326,8 +323,10 @@ __global__ __launch_bounds__(VS_BLOCK) void k_vsolve(const HeviArgs A, const R* 
             const bool mine = mycol == c;
 #pragma unroll
             for (int q = 0; q < 4; ++q) x[q] = mine ? b[q] * myrp : x[q];
+            // the lane of this row that owns unknown c
+            const int own = __builtin_ctzll(__ballot(mycol == c) >> base);
 #pragma unroll
-            for (int q = 0; q < 4; ++q) xc[q] = __shfl(x[q], base + owner[c]);
+            for (int q = 0; q < 4; ++q) xc[q] = __shfl(x[q], base + own);
             const double u = (mycol >= 0 && mycol < c) ? M[c] : 0.0;
 #pragma unroll
             for (int q = 0; q < 4; ++q) b[q] = fma(-u, xc[q], b[q]);
@@ -350,16 +349,16 @@ __global__ __launch_bounds__(VS_BLOCK) void k_vsolve(const HeviArgs A, const R* 
         for (int q = 0; q < 3; ++q)
 #pragma unroll
             for (int w = 0; w < 3; ++w) Bt[q][w] = sQ[gq][12 + 3 * q + w];
+        // for the next layer's bottom rows (per line, in LDS): lane r < 9
+        // forms entry r of S_e Btil_e, lanes 9-11 copy y_e
+        if (r < 9) {
+            const int v = r / 3, w = r % 3;
+            double sg = 0.0;
 #pragma unroll
-        for (int v = 0; v < 3; ++v) {
-#pragma unroll
-            for (int w = 0; w < 3; ++w) {
-                double sg = 0.0;
-#pragma unroll
-                for (int q = 0; q < 3; ++q) sg += sQ[gq][3 * v + q] * Bt[q][w];
-                G[v][w] = sg;
-            }
-            yprev[v] = sQ[gq][9 + v];
+            for (int q = 0; q < 3; ++q) sg += sQ[gq][3 * v + q] * sQ[gq][12 + 3 * q + w];
+            sG[gq][r] = sg;
+        } else if (r < 12) {
+            sG[gq][r] = sQ[gq][r];
         }
         if (mycol >= 0 && live) {
 #pragma unroll
