@@ -242,7 +242,7 @@ CM_API cm_status cm_lsrk144_step(cm_model* model, void* Y, void* Y_alt, void* dQ
  * d = B - Y_ref on every vertical node line (block-tridiagonal elimination
  * over the element layers, FP64).
  *
- * work: caller-owned device memory of cm_hevi_workspace_bytes bytes (seven
+ * work: caller-owned device memory of cm_hevi_workspace_bytes bytes (six
  * state-sized buffers and the line solver's 60 doubles per element layer and
  * vertical node line), 256-byte aligned; its contents need no
  * initialisation and are scratch after the call.  cm_hevi_step advances Y

@@ -753,9 +753,10 @@ static cm_status hevi_check(const cm_model* m, const char* name)
 
 static size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 
-// workspace: seven state buffers (the stage state, three explicit and three
-// implicit tendencies), then the line solver's 60 doubles per element layer
-// and vertical node line
+// workspace: six state buffers (the stage state, the right-hand sides of the
+// three stages and the vertical operator of the first two), then the line
+// solver's 60 doubles per element layer and vertical node line
+constexpr int HEVI_STATE_BUFFERS = 6;
 static size_t hevi_state_bytes(const cm_model* m)
 {
     const size_t s = m->desc.precision == CM_FP64 ? 8 : 4;
@@ -767,7 +768,7 @@ cm_status cm_hevi_workspace_bytes(const cm_model* m, size_t* bytes)
     cm_status st = hevi_check(m, "cm_hevi_workspace_bytes");
     if (st != CM_OK) return st;
     if (!bytes) { set_error("cm_hevi_workspace_bytes: null argument"); return CM_ERR_ARG; }
-    *bytes = 7 * hevi_state_bytes(m) +
+    *bytes = HEVI_STATE_BUFFERS * hevi_state_bytes(m) +
              align256(sizeof(double) * 60 * (size_t)m->grid->desc.ne[2] * (size_t)hevi_lines(m));
     return CM_OK;
 }
@@ -786,36 +787,42 @@ cm_status cm_hevi_step(cm_model* m, void* Y, void* work, double t, double dt, vo
     const size_t sb = hevi_state_bytes(m);
     char* w = (char*)work;
     void* Ys = w;
-    void* E[3] = {w + sb, w + 2 * sb, w + 3 * sb};
-    void* L[3] = {w + 4 * sb, w + 5 * sb, w + 6 * sb};
-    double* scratch = (double*)(w + 7 * sb);
-    // ARK2 of Giraldo, Kelly & Constantinescu (2013)
+    void* Rs[3] = {w + sb, w + 2 * sb, w + 3 * sb};  // R(Y_s), the full right-hand side of each stage
+    void* L[2] = {w + 4 * sb, w + 5 * sb};  // L(Y_s), its linear vertical part (the last stage's is not needed)
+    double* scratch = (double*)(w + HEVI_STATE_BUFFERS * sb);
+    // ARK2 of Giraldo, Kelly & Constantinescu (2013), explicit part R - L,
+    // implicit part L: a stage combines a_sr (R_r - L_r) + ahat_sr L_r =
+    // a_sr R_r + (ahat_sr - a_sr) L_r, and the weights of the two parts are
+    // equal, so the update needs only the R_r
     const double gam = 1.0 - 1.0 / std::sqrt(2.0), del = 1.0 / (2.0 * std::sqrt(2.0));
     const double a32 = (3.0 + 2.0 * std::sqrt(2.0)) / 6.0;
     const double AE[3][3] = {{0, 0, 0}, {2 * gam, 0, 0}, {1 - a32, a32, 0}};
     const double AI[3][3] = {{0, 0, 0}, {gam, gam, 0}, {del, del, gam}};
     const double bw[3] = {del, del, gam};
     for (int stg = 0; stg < 3; ++stg) {
-        double c[6];
-        const void* X[6];
-        int n = 0;
-        for (int r = 0; r < stg; ++r) {
-            c[n] = dt * AE[stg][r]; X[n++] = E[r];
-            c[n] = dt * AI[stg][r]; X[n++] = L[r];
-        }
-        CM_TRY_HIP(launch_combine(m, Y, Ys, n, c, X, s), "cm_hevi_step combine");
-        if (AI[stg][stg] != 0.0)
+        // the first stage is the state itself
+        const void* Yst = stg == 0 ? Y : Ys;
+        if (stg > 0) {
+            double c[6];
+            const void* X[6];
+            int n = 0;
+            for (int r = 0; r < stg; ++r) {
+                c[n] = dt * AE[stg][r]; X[n++] = Rs[r];
+                c[n] = dt * (AI[stg][r] - AE[stg][r]); X[n++] = L[r];
+            }
+            CM_TRY_HIP(launch_combine(m, Y, Ys, n, c, X, s), "cm_hevi_step combine");
             CM_TRY_HIP(launch_hevi_solve(m, dt * AI[stg][stg], Ys, Ys, scratch, s), "cm_hevi_step solve");
-        CM_TRY_HIP(launch_rhs(m, Ys, E[stg], nullptr, 0, 0.0, 0.0, 0.0, s), "cm_hevi_step rhs");
-        CM_TRY_HIP(launch_hevi_operator(m, Ys, L[stg], E[stg], s), "cm_hevi_step operator");
+        }
+        CM_TRY_HIP(launch_rhs(m, Yst, Rs[stg], nullptr, 0, 0.0, 0.0, 0.0, s), "cm_hevi_step rhs");
+        if (stg < 2) CM_TRY_HIP(launch_hevi_operator(m, Yst, L[stg], nullptr, s), "cm_hevi_step operator");
     }
-    double c[6];
-    const void* X[6];
+    double c[3];
+    const void* X[3];
     for (int r = 0; r < 3; ++r) {
-        c[2 * r] = dt * bw[r]; X[2 * r] = E[r];
-        c[2 * r + 1] = dt * bw[r]; X[2 * r + 1] = L[r];
+        c[r] = dt * bw[r];
+        X[r] = Rs[r];
     }
-    CM_TRY_HIP(launch_combine(m, Y, Y, 6, c, X, s), "cm_hevi_step update");
+    CM_TRY_HIP(launch_combine(m, Y, Y, 3, c, X, s), "cm_hevi_step update");
     return CM_OK;
 }
 
@@ -835,7 +842,7 @@ cm_status cm_hevi_solve(cm_model* m, double tau, const void* B, void* Y, void* w
     if (st != CM_OK) return st;
     if (!B || !Y || !work || !(tau >= 0.0) || !std::isfinite(tau)) { set_error("cm_hevi_solve: bad argument"); return CM_ERR_ARG; }
     CM_TRY_HIP(hipSetDevice(m->grid->device), "hipSetDevice");
-    double* scratch = (double*)((char*)work + 7 * hevi_state_bytes(m));
+    double* scratch = (double*)((char*)work + HEVI_STATE_BUFFERS * hevi_state_bytes(m));
     CM_TRY_HIP(launch_hevi_solve(m, tau, B, Y, scratch, (hipStream_t)stream), "cm_hevi_solve");
     return CM_OK;
 }
