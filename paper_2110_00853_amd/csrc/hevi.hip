@@ -176,10 +176,11 @@ __device__ __forceinline__ double jac_entry(const HRef& r, int v, int w)
 // block is solved by Gaussian elimination with partial pivoting across the
 // lanes (the pivot by a DPP maximum over the row, the pivot row to the row's
 // lanes by lane permutes; the lane that supplied the pivot for column c then
-// owns unknown c) for the deviation and the three
-// unit vectors at the top nodes.  Each layer leaves y_e and Z_e = W_e Btil_e
-// in the workspace ([line][layer][60]); the back substitution
-// x_e = y_e - Z_e x_{e+1}(bottom nodes) runs from the top.  The horizontal
+// owns unknown c) for the deviation and the three unit vectors at the top
+// nodes.  Each layer leaves y_e and Z_e = W_e Btil_e in the workspace
+// ([line][layer][60]) and its coupling to the next layer (S_e Btil_e, y_e at
+// the top nodes) in LDS; the back substitution x_e = y_e - Z_e
+// x_{e+1}(bottom nodes) runs from the top.  The horizontal
 // momenta are coupled only by the face penalty: 2 x 2 systems per interior
 // vertical face, solved by lanes 0-9.
 template <typename R>
