@@ -29,6 +29,11 @@ CASES = {
     "anisotropic": _case((3, 2, 6), (1200.0, 800.0, 60.0), closure="const"),
 }
 CASES["anisotropic"]["model"]["nu"] = 1.0
+# the degenerate line: one element layer between the walls (no coupling
+# between layers), in a single element column (25 lines: the last wave holds
+# one line and three groups past the end)
+CASES["one_layer"] = _case((1, 1, 1), (400.0, 400.0, 300.0), closure="const")
+CASES["one_layer"]["model"]["nu"] = 1.0
 
 
 @pytest.mark.parametrize("name", list(CASES))
@@ -62,7 +67,7 @@ def test_operator_and_solve_match_oracle(name):
         assert err <= 1e-11, (v, err)
 
 
-@pytest.mark.parametrize("name", ["smag", "inviscid_ragged"])
+@pytest.mark.parametrize("name", ["smag", "inviscid_ragged", "one_layer"])
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 def test_hevi_steps_match_oracle(name, precision):
     import torch
