@@ -243,9 +243,10 @@ CM_API cm_status cm_lsrk144_step(cm_model* model, void* Y, void* Y_alt, void* dQ
  * over the element layers, FP64).
  *
  * work: caller-owned device memory of cm_hevi_workspace_bytes bytes (six
- * state-sized buffers and the line solver's 60 doubles per element layer and
- * vertical node line), 256-byte aligned; its contents need no
- * initialisation and are scratch after the call.  cm_hevi_step advances Y
+ * state-sized buffers, the line solver's 60 doubles per element layer and
+ * vertical node line, and two doubles per background entry), 256-byte
+ * aligned; its contents need no initialisation and are scratch after the
+ * call.  cm_hevi_step advances Y
  * in place by dt.  cm_hevi_operator writes L(Y - Y_ref) to LY (all five
  * variables).  cm_hevi_solve writes Y_ref + d with (I - tau L) d = B - Y_ref
  * to Y (B and Y may be the same buffer).  All asynchronous on the stream. */

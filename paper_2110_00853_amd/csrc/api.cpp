@@ -755,7 +755,8 @@ static size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 
 // workspace: six state buffers (the stage state, the right-hand sides of the
 // three stages and the vertical operator of the first two), then the line
-// solver's 60 doubles per element layer and vertical node line
+// solver's 60 doubles per element layer and vertical node line, then its
+// background table (h_r and c_r per background entry)
 constexpr int HEVI_STATE_BUFFERS = 6;
 static size_t hevi_state_bytes(const cm_model* m)
 {
@@ -768,8 +769,10 @@ cm_status cm_hevi_workspace_bytes(const cm_model* m, size_t* bytes)
     cm_status st = hevi_check(m, "cm_hevi_workspace_bytes");
     if (st != CM_OK) return st;
     if (!bytes) { set_error("cm_hevi_workspace_bytes: null argument"); return CM_ERR_ARG; }
+    const size_t nref = m->ref_per_node ? (size_t)m->grid->n_nodes : (size_t)m->grid->desc.ne[2] * NQ;
     *bytes = HEVI_STATE_BUFFERS * hevi_state_bytes(m) +
-             align256(sizeof(double) * 60 * (size_t)m->grid->desc.ne[2] * (size_t)hevi_lines(m));
+             sizeof(double) * 60 * (size_t)m->grid->desc.ne[2] * (size_t)hevi_lines(m) +
+             align256(sizeof(double) * 2 * nref);
     return CM_OK;
 }
 

@@ -32,6 +32,7 @@ struct HeviArgs {
     double lo2, h2, g, tau;
     double zg[NQ], D[NQ * NQ];
     double* scratch;           // solver workspace [n_lines][nz][60]
+    double* hc;                // solver: h_r and c_r of every background entry [nref][2] (in the workspace)
 };
 
 __device__ __forceinline__ int64_t href(const HeviArgs& A, int e, int ez, int k, int t)
@@ -63,6 +64,31 @@ __device__ __forceinline__ HRef href_at(const HeviArgs& A, int64_t ri, int ez, i
     const double z = A.lo2 + ((double)ez + A.zg[k]) * A.h2;
     r.b = Phys::Rd * Phys::T0 - (Phys::Rd / Phys::cvd) * A.g * z;
     r.c = fsqrt(Phys::cpd / Phys::cvd * pr * frcp(r.rr));
+    return r;
+}
+
+// the solver's per-entry background table: h_r and c_r, each formed once
+// per solve instead of at every node of every layer of every line
+__global__ __launch_bounds__(256) void k_href_table(const HeviArgs A)
+{
+    const int64_t ri = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (ri >= A.nref) return;
+    // the level of the entry only enters b, which the table does not hold
+    const HRef r = href_at(A, ri, 0, 0);
+    A.hc[2 * ri] = r.h;
+    A.hc[2 * ri + 1] = r.c;
+}
+
+// background quantities of one node for the solver: h_r and c_r from the
+// table, b from the node height (rho_r is not needed there)
+__device__ __forceinline__ HRef href_tab(const HeviArgs& A, int64_t ri, int ez, int k)
+{
+    HRef r;
+    r.rr = 0.0;
+    r.h = A.hc[2 * ri];
+    r.c = A.hc[2 * ri + 1];
+    const double z = A.lo2 + ((double)ez + A.zg[k]) * A.h2;
+    r.b = Phys::Rd * Phys::T0 - (Phys::Rd / Phys::cvd) * A.g * z;
     return r;
 }
 
@@ -212,8 +238,8 @@ __global__ __launch_bounds__(VS_BLOCK) void k_vsolve(const HeviArgs A, const R* 
         const int e = ex + A.ne0 * (ey + A.ne1 * ez);
         HRef rk[NQ];
 #pragma unroll
-        for (int k = 0; k < NQ; ++k) rk[k] = href_at(A, href(A, e, ez, k, i + NQ * (j + NQ * k)), ez, k);
-        const HRef ro = href_at(A, href(A, e, ez, kr, i + NQ * (j + NQ * kr)), ez, kr);  // this row's node
+        for (int k = 0; k < NQ; ++k) rk[k] = href_tab(A, href(A, e, ez, k, i + NQ * (j + NQ * k)), ez, k);
+        const HRef ro = href_tab(A, href(A, e, ez, kr, i + NQ * (j + NQ * kr)), ez, kr);  // this row's node
         // row r of I - tau L_e, its coupling row to the layer below (bottom
         // rows) or above (top rows), and its right-hand sides.  The terms in
         // this row's own node columns (w, kr) (the identity, buoyancy, the
@@ -232,7 +258,7 @@ __global__ __launch_bounds__(VS_BLOCK) void k_vsolve(const HeviArgs A, const R* 
             if (ezn >= 0 && ezn < nz) {
                 const int kn = NQ - 1 - kr;
                 const int en = e + (side == 0 ? -A.ne01 : A.ne01);
-                const HRef rn = href_at(A, href(A, en, ezn, kn, i + NQ * (j + NQ * kn)), ezn, kn);
+                const HRef rn = href_tab(A, href(A, en, ezn, kn, i + NQ * (j + NQ * kn)), ezn, kn);
                 const double lam = ro.c > rn.c ? ro.c : rn.c;
 #pragma unroll
                 for (int w = 0; w < 3; ++w) {
@@ -407,7 +433,7 @@ __global__ __launch_bounds__(VS_BLOCK) void k_vsolve(const HeviArgs A, const R* 
                 const int en = e + A.ne01;
                 const int tn = i + NQ * j;
                 const int64_t rin = href(A, en, ez + 1, 0, tn);
-                const HRef ra = href_at(A, ri, ez, k), rb = href_at(A, rin, ez + 1, 0);
+                const HRef ra = href_tab(A, ri, ez, k), rb = href_tab(A, rin, ez + 1, 0);
                 const double lam = ra.c > rb.c ? ra.c : rb.c;
                 const double sv = 0.5 * tau * lift * lam, al = 1.0 + sv, det = al * al - sv * sv;
                 const double xa = (double)B[v * A.nnS + (int64_t)e * SRUN + tnode] - sref<R>(A, v, ri);
@@ -460,6 +486,7 @@ static HeviArgs hevi_args(const cm_model* m, double tau, double* scratch)
     for (int q = 0; q < NQ; ++q) A.zg[q] = 0.5 * (1.0 + g->xi[q]);
     for (int q = 0; q < NQ * NQ; ++q) A.D[q] = g->D[q];
     A.scratch = scratch;
+    A.hc = scratch ? scratch + 60 * (int64_t)A.ne2 * hevi_lines(m) : nullptr;
     return A;
 }
 
@@ -480,6 +507,7 @@ hipError_t launch_hevi_solve(const cm_model* m, double tau, const void* B, void*
 {
     const HeviArgs A = hevi_args(m, tau, scratch);
     const int64_t nl = hevi_lines(m);
+    hipLaunchKernelGGL(k_href_table, dim3((unsigned)((A.nref + 255) / 256)), dim3(256), 0, s, A);
     const dim3 grid((unsigned)((nl + VS_BLOCK / VS_LANES - 1) / (VS_BLOCK / VS_LANES))), block(VS_BLOCK);
     if (m->desc.precision == CM_FP64)
         hipLaunchKernelGGL(k_vsolve<double>, grid, block, 0, s, A, (const double*)B, (double*)Yout, nl);
