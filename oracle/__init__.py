@@ -112,6 +112,8 @@ def _declare(L):
     L.cmref_hevi_steps.restype = C.c_int
     L.cmref_hevi_operator.argtypes = [C.c_void_p, _P, _P]
     L.cmref_hevi_solve.argtypes = [C.c_void_p, C.c_double, _P, _P]
+    L.cmref_hevi_solve_lines.argtypes = [C.c_void_p, C.c_double, _P, _P,
+                                         np.ctypeslib.ndpointer(np.int64, flags="C_CONTIGUOUS"), C.c_int]
     L.cmref_exp_filter.argtypes = [C.c_void_p, _P, C.c_int, C.c_int, C.c_double, C.c_int]
     L.cmref_rusanov_point.argtypes = [C.c_int, _P, _P, C.c_double, C.c_double, C.c_double,
                                       C.c_double, C.c_double, _P, _P]
@@ -324,6 +326,17 @@ class Model:
         B = self._chk(B)
         out = np.zeros_like(B)
         self._L.cmref_hevi_solve(self.h, float(tau), B, out)
+        return out
+
+    def hevi_solve_lines(self, tau: float, B, lines):
+        """hevi_solve on the listed vertical lines only (line = (ex + ne0 ey)
+        25 + i + 5 j); the other lines of the result hold B."""
+        B = self._chk(B)
+        out = B.copy()
+        ln = np.ascontiguousarray(np.asarray(lines, dtype=np.int64))
+        n_lines = self.grid._d.ne[0] * self.grid._d.ne[1] * 25
+        assert len(np.unique(ln)) == len(ln) and np.all((ln >= 0) & (ln < n_lines)), "bad line list"
+        self._L.cmref_hevi_solve_lines(self.h, float(tau), B, out, ln, int(len(ln)))
         return out
 
     def exp_filter(self, Y, mask: int, order: int = 64, alpha: float = 36.0, Nc: int = 0):

@@ -1361,9 +1361,47 @@ static void hevi_apply(const model_t* M, const double* Y, double* LY)
         }
 }
 
-/* Y_out = Y_ref + x with (I - tau L) x = B - Y_ref on every line: the line
- * matrix assembled column by column from the operator and solved by
- * Gaussian elimination with partial pivoting */
+/* Y_out = Y_ref + x with (I - tau L) x = B - Y_ref on the vertical line
+ * (ex, ey, i, j): the line matrix assembled column by column from the
+ * operator and solved by Gaussian elimination with partial pivoting.  A
+ * holds n (n + 1) doubles and u 2 n, n = 5 nz Q. */
+static void hevi_solve_line(const model_t* M, double tau, int ex, int ey, int i, int j, const double* B,
+                            double* Yout, double* A, double* u)
+{
+    const int n = 5 * M->G->ne[2] * M->G->Q;
+    double* Lu = u + n;
+    for (int col = 0; col < n; ++col) {
+        for (int r = 0; r < n; ++r) u[r] = r == col ? 1.0 : 0.0;
+        hevi_line_apply(M, ex, ey, i, j, u, Lu);
+        for (int r = 0; r < n; ++r) A[(size_t)r * (n + 1) + col] = u[r] - tau * Lu[r];
+    }
+    line_gather(M, ex, ey, i, j, B, 1, u);
+    for (int r = 0; r < n; ++r) A[(size_t)r * (n + 1) + n] = u[r];
+    for (int c = 0; c < n; ++c) {
+        int piv = c;
+        for (int r = c + 1; r < n; ++r)
+            if (fabs(A[(size_t)r * (n + 1) + c]) > fabs(A[(size_t)piv * (n + 1) + c])) piv = r;
+        if (piv != c)
+            for (int k = 0; k <= n; ++k) {
+                double t = A[(size_t)c * (n + 1) + k];
+                A[(size_t)c * (n + 1) + k] = A[(size_t)piv * (n + 1) + k];
+                A[(size_t)piv * (n + 1) + k] = t;
+            }
+        for (int r = c + 1; r < n; ++r) {
+            double f = A[(size_t)r * (n + 1) + c] / A[(size_t)c * (n + 1) + c];
+            if (f == 0.0) continue;
+            for (int k = c; k <= n; ++k) A[(size_t)r * (n + 1) + k] -= f * A[(size_t)c * (n + 1) + k];
+        }
+    }
+    for (int r = n - 1; r >= 0; --r) {
+        double v = A[(size_t)r * (n + 1) + n];
+        for (int k = r + 1; k < n; ++k) v -= A[(size_t)r * (n + 1) + k] * u[k];
+        u[r] = v / A[(size_t)r * (n + 1) + r];
+    }
+    line_scatter(M, ex, ey, i, j, u, Yout, 1);
+}
+
+/* the same on every line */
 static void hevi_solve(const model_t* M, double tau, const double* B, double* Yout)
 {
     const grid_t* G = M->G;
@@ -1374,39 +1412,8 @@ static void hevi_solve(const model_t* M, double tau, const double* B, double* Yo
         for (int ex = 0; ex < G->ne[0]; ++ex) {
             double* A = (double*)malloc(sizeof(double) * (size_t)n * (n + 1));
             double* u = (double*)malloc(sizeof(double) * 2 * n);
-            double* Lu = u + n;
             for (int j = 0; j < Q; ++j)
-                for (int i = 0; i < Q; ++i) {
-                    for (int col = 0; col < n; ++col) {
-                        for (int r = 0; r < n; ++r) u[r] = r == col ? 1.0 : 0.0;
-                        hevi_line_apply(M, ex, ey, i, j, u, Lu);
-                        for (int r = 0; r < n; ++r) A[(size_t)r * (n + 1) + col] = u[r] - tau * Lu[r];
-                    }
-                    line_gather(M, ex, ey, i, j, B, 1, u);
-                    for (int r = 0; r < n; ++r) A[(size_t)r * (n + 1) + n] = u[r];
-                    for (int c = 0; c < n; ++c) {
-                        int piv = c;
-                        for (int r = c + 1; r < n; ++r)
-                            if (fabs(A[(size_t)r * (n + 1) + c]) > fabs(A[(size_t)piv * (n + 1) + c])) piv = r;
-                        if (piv != c)
-                            for (int k = 0; k <= n; ++k) {
-                                double t = A[(size_t)c * (n + 1) + k];
-                                A[(size_t)c * (n + 1) + k] = A[(size_t)piv * (n + 1) + k];
-                                A[(size_t)piv * (n + 1) + k] = t;
-                            }
-                        for (int r = c + 1; r < n; ++r) {
-                            double f = A[(size_t)r * (n + 1) + c] / A[(size_t)c * (n + 1) + c];
-                            if (f == 0.0) continue;
-                            for (int k = c; k <= n; ++k) A[(size_t)r * (n + 1) + k] -= f * A[(size_t)c * (n + 1) + k];
-                        }
-                    }
-                    for (int r = n - 1; r >= 0; --r) {
-                        double v = A[(size_t)r * (n + 1) + n];
-                        for (int k = r + 1; k < n; ++k) v -= A[(size_t)r * (n + 1) + k] * u[k];
-                        u[r] = v / A[(size_t)r * (n + 1) + r];
-                    }
-                    line_scatter(M, ex, ey, i, j, u, Yout, 1);
-                }
+                for (int i = 0; i < Q; ++i) hevi_solve_line(M, tau, ex, ey, i, j, B, Yout, A, u);
             free(A);
             free(u);
         }
@@ -1470,6 +1477,28 @@ int cmref_hevi_steps(void* h, double* Y, double t, double dt, int nsteps)
 void cmref_hevi_operator(void* h, const double* Y, double* LY)
 {
     hevi_apply((const model_t*)h, Y, LY);
+}
+
+/* the line solve on the listed lines only (line = (ex + ne0 ey) Q^2 + i +
+ * Q j, each listed once), for checks at sizes where solving every line
+ * would take minutes; Y must hold B beforehand, and the other lines keep it */
+void cmref_hevi_solve_lines(void* h, double tau, const double* B, double* Y, const long* lines, int nl)
+{
+    const model_t* M = (const model_t*)h;
+    const grid_t* G = M->G;
+    const int Q = G->Q;
+    const int n = 5 * G->ne[2] * Q;
+    #pragma omp parallel for schedule(dynamic)
+    for (int q = 0; q < nl; ++q) {
+        const long line = lines[q];
+        const long col = line / (Q * Q);
+        const int node = (int)(line % (Q * Q));
+        double* A = (double*)malloc(sizeof(double) * (size_t)n * (n + 1));
+        double* u = (double*)malloc(sizeof(double) * 2 * n);
+        hevi_solve_line(M, tau, (int)(col % G->ne[0]), (int)(col / G->ne[0]), node % Q, node / Q, B, Y, A, u);
+        free(A);
+        free(u);
+    }
 }
 
 /* solve (I - tau L) x = B - Y_ref on every vertical line; returns Y_ref + x */

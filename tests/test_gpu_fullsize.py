@@ -138,3 +138,52 @@ def test_full_size_lsrk144_step_matches_oracle():
     err = state_errors(m.to_numpy(Ya), Yo)
     print("LSRK144 full-size state errors", err)
     assert np.all(err < STEP_TOL), err
+
+
+def test_full_size_vertical_operator_and_sampled_line_solves():
+    """The 1-D IMEX pieces at the size bench.py times them (32x32x32 elements
+    of 200 x 200 x 5 m, 25,600 vertical lines of 32 layers): the vertical
+    operator on every node, and the line solve at the first ARK2 stage's tau
+    for a step twelve times the explicit vertical limit, the GPU solving
+    every line and the oracle 48 of them (the four corner columns, both ends
+    of the line range and 38 random lines; solving all of them densely would
+    take the oracle minutes)."""
+    import torch
+
+    c = W.case("bubble_32", hi=(6400.0, 6400.0, 160.0))
+    c["model"] = dict(c["model"], closure="const", nu=1.0)
+    c["ic"] = dict(c["ic"], center=(3200.0, 3200.0, 80.0))
+    _, _, dt = W.initial_state(c)
+    Bst, Yref, _ = W.perturbed_state(c, seed=23, amp_u=5.0, amp_T=2.0)
+    tau = 12.0 * dt * (1.0 - 1.0 / np.sqrt(2.0))
+    ne0, ne1, ne2 = c["grid"]["ne"]
+    n_lines = ne0 * ne1 * 25
+    rng = np.random.default_rng(3)
+    corners = [(ex + ne0 * ey) * 25 + node for ex in (0, ne0 - 1) for ey in (0, ne1 - 1) for node in (0, 24)]
+    lines = np.unique(np.concatenate([corners, [1, n_lines - 2], rng.choice(n_lines, 38, replace=False)]))
+    print("full-size vertical operator and", len(lines), "sampled line solves", flush=True)
+    g = B.Grid(c["grid"])
+    m = B.Model(g, c["model"], Yref)
+    om = oracle.Model(oracle.Grid(c["grid"]), c["model"], Yref)
+    Bd, Ld, Xd = m.new_state(Bst), m.new_state(), m.new_state()
+    work = m.hevi_workspace()
+    m.hevi_operator(Bd, Ld)
+    m.hevi_solve(tau, Bd, Xd, work)
+    torch.cuda.synchronize()
+    Lo = om.hevi_operator(Bst)
+    Lg = m.tendency_to_numpy(Ld)
+    lerr = np.array([np.abs(Lg[v] - Lo[v]).max() / max(np.abs(Lo[v]).max(), 1e-300) for v in range(5)])
+    Xo = om.hevi_solve_lines(tau, Bst, lines)
+    Xg = m.to_numpy(Xd)
+    on = np.zeros(Bst.shape[1], bool)
+    for ln in lines:
+        col, node = divmod(int(ln), 25)
+        ex, ey, i, j = col % ne0, col // ne0, node % 5, node // 5
+        for ez in range(ne2):
+            e = ex + ne0 * (ey + ne1 * ez)
+            on[e * 125 + i + 5 * (j + 5 * np.arange(5))] = True
+    serr = np.array([np.abs(Xg[v, on] - Xo[v, on]).max() / max(np.abs(Xo[v, on] - Yref[v, on]).max(), 1e-300)
+                     for v in range(5)])
+    print("operator errors", lerr, "sampled solve errors relative to the deviation", serr)
+    assert np.all(lerr <= 1e-12), lerr
+    assert np.all(serr <= 1e-11), serr

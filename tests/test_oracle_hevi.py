@@ -138,3 +138,28 @@ def test_hevi_is_stable_beyond_the_vertical_acoustic_limit(oracle_lib):
     with np.errstate(all="ignore"):
         Ye, _ = M.steps(Y0, dt, 20)
     assert not np.all(np.isfinite(Ye)) or np.abs(Ye[3]).max() > 1e3 * max(np.abs(Y0[3]).max(), 1.0)
+
+
+def test_solve_on_listed_lines_is_the_full_solve_there(oracle_lib):
+    """The sampled line solve (used where solving every line would take
+    minutes) gives the full solve's values on the listed lines, bit for bit,
+    and leaves the others at B."""
+    c = W.case("bubble_32", ne=(3, 2, 3), hi=(900.0, 600.0, 300.0))
+    c["model"]["closure"] = "const"
+    B, Yref, _ = W.perturbed_state(c, seed=5, amp_u=4.0, amp_T=1.5)
+    M = oracle_lib.Model(oracle_lib.Grid(c["grid"]), c["model"], Yref)
+    full = M.hevi_solve(0.05, B)
+    lines = np.array([0, 7, 26, 49, 77, 149])
+    part = M.hevi_solve_lines(0.05, B, lines)
+    ne0, ne1, ne2 = 3, 2, 3
+    on = np.zeros(B.shape[1], bool)
+    for ln in lines:
+        col, node = divmod(int(ln), 25)
+        ex, ey, i, j = col % ne0, col // ne0, node % 5, node // 5
+        for ez in range(ne2):
+            e = ex + ne0 * (ey + ne1 * ez)
+            for k in range(5):
+                on[e * 125 + i + 5 * (j + 5 * k)] = True
+    assert np.array_equal(part[:, on], full[:, on])
+    assert np.array_equal(part[:, ~on], B[:, ~on])
+    assert not np.array_equal(full[:, ~on], B[:, ~on])
