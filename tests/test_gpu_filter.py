@@ -73,3 +73,24 @@ def test_filter_keeps_the_background_and_element_integrals():
         assert np.abs(after - before).max() <= 1e-13 * np.abs(Y[v]).max() * np.abs(wJ).sum() / ne, v
     with pytest.raises(B.CMError):
         m.exp_filter(Yd, 1 << 5, 8, 36.0, 0)
+
+
+def test_full_size_filter_matches_oracle():
+    """The filter in the configuration bench.py times (all five variables of
+    the 32^3 bubble, order 64, alpha 36, in place) against the oracle on
+    every node, on a perturbed state."""
+    import torch
+
+    c = W.case("bubble_32")
+    Y, Yref, _ = W.perturbed_state(c, seed=12, amp_u=4.0, amp_T=1.5)
+    print("full-size filter: bubble_32", flush=True)
+    g = B.Grid(c["grid"])
+    m = B.Model(g, c["model"], Yref)
+    Yd = m.new_state(Y)
+    m.exp_filter(Yd, 0b11111, 64, 36.0, 0)
+    torch.cuda.synchronize()
+    Yg = m.to_numpy(Yd)
+    Yo = oracle.Model(oracle.Grid(c["grid"]), c["model"], Yref).exp_filter(Y, 0b11111, 64, 36.0, 0)
+    err = np.array([np.abs(Yg[v] - Yo[v]).max() / max(np.abs(Yo[v] - Yref[v]).max(), 1e-300) for v in range(5)])
+    print("full-size filter errors relative to the deviation", err)
+    assert np.all(err <= 1e-13), err
