@@ -187,3 +187,31 @@ def test_full_size_vertical_operator_and_sampled_line_solves():
     print("operator errors", lerr, "sampled solve errors relative to the deviation", serr)
     assert np.all(lerr <= 1e-12), lerr
     assert np.all(serr <= 1e-11), serr
+
+
+def test_largest_accepted_grid_rhs_matches_oracle():
+    """The largest mesh the library accepts with 32-bit kernel indexing
+    (128 x 128 x 65 elements, 133M nodes: nodes x 16 words just under 2^31;
+    one more layer is refused, as is the larger mesh of tests/test_abi.py): the FP64 tendency on
+    every node against the oracle, so that no offset in any kernel overflows
+    at the top of the range."""
+    import torch
+
+    c = W.case("bubble_32", ne=(128, 128, 65), hi=(25600.0, 25600.0, 13000.0))
+    assert 128 * 128 * 65 * 125 * 16 < 2**31 <= 128 * 128 * 66 * 125 * 16
+    print("largest grid: initial state", flush=True)
+    Y, Yref, _ = W.initial_state(c)
+    print("largest grid: GPU tendency", flush=True)
+    g = B.Grid(c["grid"])
+    m = B.Model(g, c["model"], Yref)
+    Yd, Rd = m.new_state(Y), m.new_state()
+    m.rhs(Yd, Rd)
+    torch.cuda.synchronize()
+    Rg = m.tendency_to_numpy(Rd)
+    del m, Yd, Rd, g
+    torch.cuda.empty_cache()
+    print("largest grid: oracle tendency", flush=True)
+    Ro = oracle.Model(oracle.Grid(c["grid"]), c["model"], Yref).rhs(Y)
+    err = rhs_errors(Rg, Ro, Y, hmin(c["grid"]))
+    print("largest grid rhs errors", err)
+    assert np.all(err < 1e-11), err
