@@ -332,6 +332,7 @@ cm_status cm_model_destroy(cm_model* m)
     if (m->d_mlp_w) (void)hipFree(m->d_mlp_w);
     if (m->d_mlp_norm) (void)hipFree(m->d_mlp_norm);
     if (m->d_fallbacks) (void)hipFree(m->d_fallbacks);
+    if (m->d_hevi_fac) (void)hipFree(m->d_hevi_fac);
     for (auto& r : m->prof) {
         (void)hipEventDestroy(r.a);
         (void)hipEventDestroy(r.b);
@@ -514,6 +515,11 @@ cm_status cm_model_create(const cm_grid* g, const cm_model_desc* desc, const dou
         }
         m->kp.bg32 = m->d_bg32;
         m->kp.nref = m->nref;
+        // the 1-D IMEX line factor, for models whose vertical lines all share
+        // one matrix (dry, flat mesh, walls at the bottom and top, background
+        // per level)
+        if (e == hipSuccess && desc->nvar == 5 && g->desc.topo == 0 && !g->desc.periodic[2] && !m->ref_per_node)
+            e = hipMalloc(&m->d_hevi_fac, sizeof(double) * hevi_factor_doubles(g->desc.ne[2]));
         if (e == hipSuccess) e = hipDeviceSynchronize();
     }
     if (e != hipSuccess) {

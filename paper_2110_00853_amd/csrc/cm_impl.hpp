@@ -161,6 +161,10 @@ struct cm_model {
     double* d_mlp_norm = nullptr;
     unsigned long long* d_fallbacks = nullptr;
     int mlp_ready = 0;
+    // 1-D IMEX: the line factor shared by every vertical line (models with a
+    // per-level background on flat meshes) and the tau it was formed for
+    double* d_hevi_fac = nullptr;
+    double hevi_fac_tau = -1.0;
     cm::KParams kp{};
     // optional per-launch event timing
     struct ProfRec {
@@ -190,7 +194,8 @@ hipError_t launch_diagnostics(const cm_model* m, const void* Y, double dt, cm_di
 // 1-D IMEX (hevi.hip): the linear vertical operator (Lout = L(Y - Y_ref),
 // Eout -= Lout when given), the line solves, and out = base + sum c_q X_q
 hipError_t launch_hevi_operator(const cm_model* m, const void* Y, void* Lout, void* Eout, hipStream_t s);
-hipError_t launch_hevi_solve(const cm_model* m, double tau, const void* B, void* Yout, double* scratch, hipStream_t s);
+hipError_t launch_hevi_solve(cm_model* m, double tau, const void* B, void* Yout, double* scratch, hipStream_t s);
+size_t hevi_factor_doubles(int nz);
 hipError_t launch_combine(const cm_model* m, const void* base, void* out, int n, const double* c, const void* const* X,
                           hipStream_t s);
 int64_t hevi_lines(const cm_model* m);

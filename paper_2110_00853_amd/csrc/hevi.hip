@@ -191,6 +191,58 @@ __device__ __forceinline__ double jac_entry(const HRef& r, int v, int w)
     return v == 1 ? Phys::Rd / Phys::cvd : 0.0;
 }
 
+// row r = (v3, kr) of the layer block I - tau L_e on the vertical line of
+// node (i, j) of element e (layer ez), and the row's coupling cpl to the
+// nearest node of the neighbouring layer (bottom rows: the layer below, top
+// rows: the layer above; zero at the walls).  Background from the table hc.
+__device__ __forceinline__ void assemble_row(const HeviArgs& A, const double* sD, int e, int ez, int i, int j,
+                                             int v3, int kr, double M[VS_N], double cpl[3])
+{
+    const double tau = A.tau, r2h = 2.0 / A.h2, lift = r2h * 10.0;
+    const int nz = A.ne2;
+    HRef rk[NQ];
+#pragma unroll
+    for (int k = 0; k < NQ; ++k) rk[k] = href_tab(A, href(A, e, ez, k, i + NQ * (j + NQ * k)), ez, k);
+    const HRef ro = href_tab(A, href(A, e, ez, kr, i + NQ * (j + NQ * kr)), ez, kr);  // this row's node
+    // the terms in this row's own node columns (w, kr) (the identity,
+    // buoyancy, the face penalty or the wall) are summed first and enter
+    // with a compare on the column's node, so that no entry is addressed by
+    // a lane-dependent index
+    double own[3];
+#pragma unroll
+    for (int w = 0; w < 3; ++w) own[w] = w == v3 ? 1.0 : 0.0;
+    if (v3 == 1) own[0] += tau * A.g;
+#pragma unroll
+    for (int w = 0; w < 3; ++w) cpl[w] = 0.0;
+    if (kr == 0 || kr == NQ - 1) {
+        const int side = kr == 0 ? 0 : 1;
+        const double nrm = side == 0 ? -1.0 : 1.0;
+        const int ezn = ez + (side == 0 ? -1 : 1);
+        if (ezn >= 0 && ezn < nz) {
+            const int kn = NQ - 1 - kr;
+            const int en = e + (side == 0 ? -A.ne01 : A.ne01);
+            const HRef rn = href_tab(A, href(A, en, ezn, kn, i + NQ * (j + NQ * kn)), ezn, kn);
+            const double lam = ro.c > rn.c ? ro.c : rn.c;
+#pragma unroll
+            for (int w = 0; w < 3; ++w) {
+                own[w] -= tau * lift * (0.5 * nrm * jac_entry(ro, v3, w) - (v3 == w ? 0.5 * lam : 0.0));
+                cpl[w] = -tau * lift * (-0.5 * nrm * jac_entry(rn, v3, w) + (v3 == w ? 0.5 * lam : 0.0));
+            }
+        } else {
+            // wall: L_rho += lift n m, L_m -= lift c m, L_E += lift n h m
+            if (v3 == 0) own[1] -= tau * lift * nrm;
+            if (v3 == 1) own[1] += tau * lift * ro.c;
+            if (v3 == 2) own[1] -= tau * lift * nrm * ro.h;
+        }
+    }
+#pragma unroll
+    for (int l = 0; l < NQ; ++l) {
+        const double cf = tau * r2h * sD[kr * NQ + l];
+#pragma unroll
+        for (int w = 0; w < 3; ++w) M[vb(w, l)] = cf * jac_entry(rk[l], v3, w) + (l == kr ? own[w] : 0.0);
+    }
+}
+
 // Y_out = Y_ref + x with (I - tau L) x = B - Y_ref on every vertical line
 // (B and Y_out may be the same buffer: a line is read before it is written,
 // and lines do not share nodes).
@@ -236,49 +288,8 @@ __global__ __launch_bounds__(VS_BLOCK) void k_vsolve(const HeviArgs A, const R* 
     __syncthreads();
     for (int ez = 0; ez < nz; ++ez) {
         const int e = ex + A.ne0 * (ey + A.ne1 * ez);
-        HRef rk[NQ];
-#pragma unroll
-        for (int k = 0; k < NQ; ++k) rk[k] = href_tab(A, href(A, e, ez, k, i + NQ * (j + NQ * k)), ez, k);
-        const HRef ro = href_tab(A, href(A, e, ez, kr, i + NQ * (j + NQ * kr)), ez, kr);  // this row's node
-        // row r of I - tau L_e, its coupling row to the layer below (bottom
-        // rows) or above (top rows), and its right-hand sides.  The terms in
-        // this row's own node columns (w, kr) (the identity, buoyancy, the
-        // face penalty or the wall) are summed first and enter with a
-        // compare on the column's node, so that no entry is addressed by a
-        // lane-dependent index.
-        double own[3];
-#pragma unroll
-        for (int w = 0; w < 3; ++w) own[w] = w == v3 ? 1.0 : 0.0;
-        if (v3 == 1) own[0] += tau * A.g;
-        double cpl[3] = {0.0, 0.0, 0.0};
-        if (kr == 0 || kr == NQ - 1) {
-            const int side = kr == 0 ? 0 : 1;
-            const double nrm = side == 0 ? -1.0 : 1.0;
-            const int ezn = ez + (side == 0 ? -1 : 1);
-            if (ezn >= 0 && ezn < nz) {
-                const int kn = NQ - 1 - kr;
-                const int en = e + (side == 0 ? -A.ne01 : A.ne01);
-                const HRef rn = href_tab(A, href(A, en, ezn, kn, i + NQ * (j + NQ * kn)), ezn, kn);
-                const double lam = ro.c > rn.c ? ro.c : rn.c;
-#pragma unroll
-                for (int w = 0; w < 3; ++w) {
-                    own[w] -= tau * lift * (0.5 * nrm * jac_entry(ro, v3, w) - (v3 == w ? 0.5 * lam : 0.0));
-                    cpl[w] = -tau * lift * (-0.5 * nrm * jac_entry(rn, v3, w) + (v3 == w ? 0.5 * lam : 0.0));
-                }
-            } else {
-                // wall: L_rho += lift n m, L_m -= lift c m, L_E += lift n h m
-                if (v3 == 0) own[1] -= tau * lift * nrm;
-                if (v3 == 1) own[1] += tau * lift * ro.c;
-                if (v3 == 2) own[1] -= tau * lift * nrm * ro.h;
-            }
-        }
-        double M[VS_N];
-#pragma unroll
-        for (int l = 0; l < NQ; ++l) {
-            const double cf = tau * r2h * sD[kr * NQ + l];
-#pragma unroll
-            for (int w = 0; w < 3; ++w) M[vb(w, l)] = cf * jac_entry(rk[l], v3, w) + (l == kr ? own[w] : 0.0);
-        }
+        double M[VS_N], cpl[3];
+        assemble_row(A, sD, e, ez, i, j, v3, kr, M, cpl);
         const int tnode = i + NQ * (j + NQ * kr);
         const int64_t ri = href(A, e, ez, kr, tnode);
         double b[4];
@@ -466,6 +477,197 @@ __global__ __launch_bounds__(256) void k_combine(const CombineArgs C, const R* _
     out[q] = (R)v;
 }
 
+// ---- lines with a common matrix ------------------------------------------
+// With the background given per level (horizontally uniform) on a flat mesh,
+// every vertical line has the same matrix I - tau L: only the right-hand
+// sides differ.  The block elimination over the layers is then done once per
+// tau (k_vfactor), and each line only applies it (k_vapply).  Per layer e the
+// factor holds Minv_e, the inverse of the layer block after the Schur update
+// of its bottom-node rows by the layers below; Z_e = W_e Btil_e (W_e: the
+// columns of Minv_e at the top-node rows, Btil_e: the coupling rows of the
+// top nodes to the layer above); and Cb_e, the coupling rows of the bottom
+// nodes to the layer below: HEVI_FAC doubles per layer.
+constexpr int HEVI_FAC = VS_N * VS_N + 3 * VS_N + 9;
+
+// one block of 64 threads: the line of node (0, 0) of element column (0, 0);
+// each layer's block inverted by Gauss-Jordan elimination with partial
+// pivoting in LDS (the largest magnitude, the lowest row on ties)
+__global__ __launch_bounds__(64) void k_vfactor(const HeviArgs A, double* __restrict__ F)
+{
+    __shared__ double T[VS_N][2 * VS_N];  // [block | identity] -> [I | Minv]
+    __shared__ double sD[NQ * NQ];
+    __shared__ double Gs[9];              // S_{e-1} Btil_{e-1}
+    __shared__ double Ct[9], Cb[9];       // coupling rows of the top / bottom nodes
+    __shared__ double prow[2 * VS_N], fcol[VS_N];
+    __shared__ int piv;
+    const int t = threadIdx.x;
+    const int nz = A.ne2;
+    if (t < NQ * NQ) sD[t] = A.D[t];
+    if (t < 9) Gs[t] = 0.0;
+    __syncthreads();
+    for (int ez = 0; ez < nz; ++ez) {
+        const int e = A.ne01 * ez;
+        if (t < VS_N) {
+            const int v3 = t / NQ, kr = t % NQ;
+            double M[VS_N], cpl[3];
+            assemble_row(A, sD, e, ez, 0, 0, v3, kr, M, cpl);
+            if (kr == 0 && ez > 0) {
+                for (int w = 0; w < 3; ++w) {
+                    double sg = 0.0;
+                    for (int q = 0; q < 3; ++q) sg += cpl[q] * Gs[3 * q + w];
+                    M[vb(w, 0)] -= sg;
+                }
+            }
+            for (int c = 0; c < VS_N; ++c) {
+                T[t][c] = M[c];
+                T[t][VS_N + c] = c == t ? 1.0 : 0.0;
+            }
+            if (kr == 0)
+                for (int q = 0; q < 3; ++q) Cb[3 * v3 + q] = cpl[q];
+            if (kr == NQ - 1)
+                for (int q = 0; q < 3; ++q) Ct[3 * v3 + q] = cpl[q];
+        }
+        __syncthreads();
+        for (int c = 0; c < VS_N; ++c) {
+            if (t == 0) {
+                int p = c;
+                for (int r = c + 1; r < VS_N; ++r)
+                    if (fabs(T[r][c]) > fabs(T[p][c])) p = r;
+                piv = p;
+            }
+            __syncthreads();
+            const int p = piv;
+            if (p != c && t < 2 * VS_N) {
+                const double a = T[c][t];
+                T[c][t] = T[p][t];
+                T[p][t] = a;
+            }
+            __syncthreads();
+            if (t < 2 * VS_N) prow[t] = T[c][t] / T[c][c];
+            if (t < VS_N) fcol[t] = T[t][c];
+            __syncthreads();
+            for (int q = t; q < VS_N * 2 * VS_N; q += 64) {
+                const int r = q / (2 * VS_N), k = q % (2 * VS_N);
+                T[r][k] = r == c ? prow[k] : T[r][k] - fcol[r] * prow[k];
+            }
+            __syncthreads();
+        }
+        // Minv, Z = W Btil with W = Minv(:, top rows), the coupling rows of
+        // the bottom nodes, and G = S Btil for the next layer (S = W at the
+        // top rows)
+        double* Fe = F + (int64_t)ez * HEVI_FAC;
+        for (int q = t; q < VS_N * VS_N; q += 64) Fe[q] = T[q / VS_N][VS_N + q % VS_N];
+        if (t < 3 * VS_N) {
+            const int r = t / 3, w = t % 3;
+            double z = 0.0;
+            for (int q = 0; q < 3; ++q) z += T[r][VS_N + vb(q, NQ - 1)] * Ct[3 * q + w];
+            Fe[VS_N * VS_N + t] = z;
+        }
+        if (t < 9) Fe[VS_N * VS_N + 3 * VS_N + t] = Cb[t];
+        __syncthreads();
+        if (t < 9) {
+            const int v = t / 3, w = t % 3;
+            double g = 0.0;
+            for (int q = 0; q < 3; ++q) g += T[vb(v, NQ - 1)][VS_N + vb(q, NQ - 1)] * Ct[3 * q + w];
+            Gs[t] = g;
+        }
+        __syncthreads();
+    }
+}
+
+// one thread per vertical line: forward over the layers y_e = Minv_e (b_e -
+// Cb_e y_{e-1}(top nodes)), y_e kept in the workspace ([layer][row][line]),
+// back substitution x_e = y_e - Z_e x_{e+1}(bottom nodes); the horizontal
+// momenta as in k_vsolve.  The factor's entries are the same for every
+// thread (scalar loads).  B and Y may be the same buffer (a line is read
+// before it is written, and lines do not share nodes).
+template <typename R>
+__global__ __launch_bounds__(256) void k_vapply(const HeviArgs A, const double* __restrict__ F, const R* B, R* Y,
+                                                int64_t n_lines)
+{
+    const int64_t line = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (line >= n_lines) return;
+    const int node = (int)(line % (NQ * NQ));
+    const int64_t col = line / (NQ * NQ);
+    const int i = node % NQ, j = node / NQ;
+    const int ex = (int)(col % A.ne0), ey = (int)(col / A.ne0);
+    const int nz = A.ne2;
+    double* ys = A.scratch;
+    double yprev[3] = {0.0, 0.0, 0.0};
+    for (int ez = 0; ez < nz; ++ez) {
+        const int e = ex + A.ne0 * (ey + A.ne1 * ez);
+        const double* Fe = F + (int64_t)ez * HEVI_FAC;
+        double b[VS_N];
+#pragma unroll
+        for (int r = 0; r < VS_N; ++r) {
+            const int v3 = r / NQ, kr = r % NQ, var = v3 == 0 ? 0 : (v3 == 1 ? 3 : 4);
+            const int tnode = i + NQ * (j + NQ * kr);
+            b[r] = (double)B[var * A.nnS + (int64_t)e * SRUN + tnode] - sref<R>(A, var, href(A, e, ez, kr, tnode));
+        }
+        if (ez > 0) {
+#pragma unroll
+            for (int w = 0; w < 3; ++w)
+#pragma unroll
+                for (int q = 0; q < 3; ++q) b[vb(w, 0)] -= Fe[VS_N * VS_N + 3 * VS_N + 3 * w + q] * yprev[q];
+        }
+#pragma unroll
+        for (int r = 0; r < VS_N; ++r) {
+            double y = 0.0;
+#pragma unroll
+            for (int c = 0; c < VS_N; ++c) y += Fe[r * VS_N + c] * b[c];
+            ys[((int64_t)ez * VS_N + r) * n_lines + line] = y;
+            if (r % NQ == NQ - 1) yprev[r / NQ] = y;
+        }
+    }
+    double xb[3] = {0.0, 0.0, 0.0};
+    for (int ez = nz - 1; ez >= 0; --ez) {
+        const int e = ex + A.ne0 * (ey + A.ne1 * ez);
+        const double* Fe = F + (int64_t)ez * HEVI_FAC;
+        double x[VS_N];
+#pragma unroll
+        for (int r = 0; r < VS_N; ++r) {
+            double xr = ys[((int64_t)ez * VS_N + r) * n_lines + line];
+#pragma unroll
+            for (int w = 0; w < 3; ++w) xr -= Fe[VS_N * VS_N + 3 * r + w] * xb[w];
+            x[r] = xr;
+        }
+#pragma unroll
+        for (int r = 0; r < VS_N; ++r) {
+            const int v3 = r / NQ, kr = r % NQ, var = v3 == 0 ? 0 : (v3 == 1 ? 3 : 4);
+            const int tnode = i + NQ * (j + NQ * kr);
+            Y[var * A.nnS + (int64_t)e * SRUN + tnode] = (R)(sref<R>(A, var, href(A, e, ez, kr, tnode)) + x[r]);
+        }
+#pragma unroll
+        for (int w = 0; w < 3; ++w) xb[w] = x[vb(w, 0)];
+    }
+    // horizontal momenta: identity except the 2 x 2 systems of the interior
+    // vertical faces, [1 + s, -s; -s, 1 + s] with s = tau lift lam / 2
+    const double lift = 2.0 / A.h2 * 10.0;
+    for (int v = 1; v <= 2; ++v)
+        for (int ez = 0; ez < nz; ++ez) {
+            const int e = ex + A.ne0 * (ey + A.ne1 * ez);
+#pragma unroll
+            for (int k = 0; k < NQ; ++k) {
+                const int tnode = i + NQ * (j + NQ * k);
+                const int64_t ri = href(A, e, ez, k, tnode);
+                if (k == NQ - 1 && ez < nz - 1) {
+                    const int en = e + A.ne01;
+                    const int tn = i + NQ * j;
+                    const int64_t rin = href(A, en, ez + 1, 0, tn);
+                    const HRef ra = href_tab(A, ri, ez, k), rb = href_tab(A, rin, ez + 1, 0);
+                    const double lam = ra.c > rb.c ? ra.c : rb.c;
+                    const double sv = 0.5 * A.tau * lift * lam, al = 1.0 + sv, det = al * al - sv * sv;
+                    const double xa = (double)B[v * A.nnS + (int64_t)e * SRUN + tnode] - sref<R>(A, v, ri);
+                    const double xbv = (double)B[v * A.nnS + (int64_t)en * SRUN + tn] - sref<R>(A, v, rin);
+                    Y[v * A.nnS + (int64_t)e * SRUN + tnode] = (R)(sref<R>(A, v, ri) + (al * xa + sv * xbv) / det);
+                    Y[v * A.nnS + (int64_t)en * SRUN + tn] = (R)(sref<R>(A, v, rin) + (sv * xa + al * xbv) / det);
+                } else if (!(k == 0 && ez > 0)) {
+                    Y[v * A.nnS + (int64_t)e * SRUN + tnode] = B[v * A.nnS + (int64_t)e * SRUN + tnode];
+                }
+            }
+        }
+}
+
 static HeviArgs hevi_args(const cm_model* m, double tau, double* scratch)
 {
     const cm_grid* g = m->grid;
@@ -503,11 +705,32 @@ hipError_t launch_hevi_operator(const cm_model* m, const void* Y, void* Lout, vo
 
 int64_t hevi_lines(const cm_model* m) { return (int64_t)m->grid->desc.ne[0] * m->grid->desc.ne[1] * NQ * NQ; }
 
-hipError_t launch_hevi_solve(const cm_model* m, double tau, const void* B, void* Yout, double* scratch, hipStream_t s)
+size_t hevi_factor_doubles(int nz) { return (size_t)nz * HEVI_FAC; }
+
+hipError_t launch_hevi_solve(cm_model* m, double tau, const void* B, void* Yout, double* scratch, hipStream_t s)
 {
     const HeviArgs A = hevi_args(m, tau, scratch);
     const int64_t nl = hevi_lines(m);
     hipLaunchKernelGGL(k_href_table, dim3((unsigned)((A.nref + 255) / 256)), dim3(256), 0, s, A);
+    if (m->d_hevi_fac) {
+        // every line has the same matrix: factor once per tau (the stream
+        // orders it before this and later solves), then apply per line
+        if (m->hevi_fac_tau != tau) {
+            m->hevi_fac_tau = -1.0;
+            hipLaunchKernelGGL(k_vfactor, dim3(1), dim3(64), 0, s, A, m->d_hevi_fac);
+            const hipError_t e = hipGetLastError();
+            if (e != hipSuccess) return e;
+            m->hevi_fac_tau = tau;
+        }
+        const dim3 ga((unsigned)((nl + 255) / 256)), ba(256);
+        if (m->desc.precision == CM_FP64)
+            hipLaunchKernelGGL(k_vapply<double>, ga, ba, 0, s, A, (const double*)m->d_hevi_fac, (const double*)B,
+                               (double*)Yout, nl);
+        else
+            hipLaunchKernelGGL(k_vapply<float>, ga, ba, 0, s, A, (const double*)m->d_hevi_fac, (const float*)B,
+                               (float*)Yout, nl);
+        return hipGetLastError();
+    }
     const dim3 grid((unsigned)((nl + VS_BLOCK / VS_LANES - 1) / (VS_BLOCK / VS_LANES))), block(VS_BLOCK);
     if (m->desc.precision == CM_FP64)
         hipLaunchKernelGGL(k_vsolve<double>, grid, block, 0, s, A, (const double*)B, (double*)Yout, nl);

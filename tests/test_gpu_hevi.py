@@ -36,12 +36,30 @@ CASES["one_layer"] = _case((1, 1, 1), (400.0, 400.0, 300.0), closure="const")
 CASES["one_layer"]["model"]["nu"] = 1.0
 
 
+# a background that varies horizontally (density and energy modulated by
+# 0.1 % along x): the lines no longer share one matrix, so the solver takes
+# its general path (every line eliminated on its own)
+CASES["per_node_background"] = _case((3, 2, 4), (900.0, 600.0, 800.0), closure="const")
+CASES["per_node_background"]["model"]["nu"] = 1.0
+
+
+def _state(name, seed, amp_u, amp_T):
+    c = CASES[name]
+    Y, Yref, speed = W.perturbed_state(c, seed=seed, amp_u=amp_u, amp_T=amp_T)
+    if name == "per_node_background":
+        x = W.node_coords(c["grid"])[0]
+        f = 1.0 + 1e-3 * np.sin(2.0 * np.pi * x / c["grid"]["hi"][0])
+        Yref = Yref.copy()
+        Yref[0] *= f
+        Yref[4] *= f
+    return c, Y, Yref, speed
+
+
 @pytest.mark.parametrize("name", list(CASES))
 def test_operator_and_solve_match_oracle(name):
     import torch
 
-    c = CASES[name]
-    Y, Yref, _ = W.perturbed_state(c, seed=21, amp_u=5.0, amp_T=2.0)
+    c, Y, Yref, _ = _state(name, 21, 5.0, 2.0)
     g = B.Grid(c["grid"])
     m = B.Model(g, c["model"], Yref)
     om = oracle.Model(oracle.Grid(c["grid"]), c["model"], Yref)
@@ -67,13 +85,12 @@ def test_operator_and_solve_match_oracle(name):
         assert err <= 1e-11, (v, err)
 
 
-@pytest.mark.parametrize("name", ["smag", "inviscid_ragged", "one_layer"])
+@pytest.mark.parametrize("name", ["smag", "inviscid_ragged", "one_layer", "per_node_background"])
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 def test_hevi_steps_match_oracle(name, precision):
     import torch
 
-    c = CASES[name]
-    Y, Yref, speed = W.perturbed_state(c, seed=22, amp_u=5.0, amp_T=2.0)
+    c, Y, Yref, speed = _state(name, 22, 5.0, 2.0)
     dt = 0.5 * W.cfl_dt(c["grid"], speed)
     g = B.Grid(c["grid"])
     m = B.Model(g, c["model"], Yref, precision=precision)
@@ -125,3 +142,25 @@ def test_hevi_rejects_moist_warped_and_vertically_periodic_models():
         with pytest.raises(B.CMError) as ei:
             m.hevi_workspace()
         assert ei.value.status == B.CM_ERR_UNSUPPORTED
+
+
+def test_line_factor_follows_tau():
+    """The shared line factor is formed once per tau and reused: solves at
+    tau1, tau2, tau1 again and tau2 again on one model each match the
+    oracle's solve at that tau."""
+    import torch
+
+    c, Y, Yref, _ = _state("smag", 24, 5.0, 2.0)
+    g = B.Grid(c["grid"])
+    m = B.Model(g, c["model"], Yref)
+    om = oracle.Model(oracle.Grid(c["grid"]), c["model"], Yref)
+    Yd, Xd = m.new_state(Y), m.new_state()
+    work = m.hevi_workspace()
+    for tau in (0.05, 0.2, 0.05, 0.2):
+        m.hevi_solve(tau, Yd, Xd, work)
+        torch.cuda.synchronize()
+        Xo = om.hevi_solve(tau, Y)
+        Xg = m.to_numpy(Xd)
+        err = max(np.abs(Xg[v] - Xo[v]).max() / max(np.abs(Xo[v] - Yref[v]).max(), 1e-300) for v in range(5))
+        print("tau", tau, "solve error relative to the deviation", err)
+        assert err <= 1e-11, (tau, err)
