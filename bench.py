@@ -411,7 +411,15 @@ def next_rows(steps: int, warmup: int):
     work = mh.hevi_workspace()
     dt_hevi = 12.0 * dth
     nh = max(steps // 10, 10)
-    for _ in range(3):
+    # the first step also forms the line factor (once per step size: every
+    # line shares one matrix on this mesh); timed on its own
+    torch.cuda.synchronize()
+    e0.record(stream)
+    mh.hevi_step(Ya, work, 0.0, dt_hevi, stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms_first = e0.elapsed_time(e1)
+    for _ in range(2):
         mh.hevi_step(Ya, work, 0.0, dt_hevi, stream)
     torch.cuda.synchronize()
     e0.record(stream)
@@ -424,11 +432,13 @@ def next_rows(steps: int, warmup: int):
     del mh, Ya, work
     ex = lsrk_throughput(B, gh, ch, Yh, Yrh, dth, nh, 3)
     res["hevi_anisotropic_32"] = {
-        "ms_per_step": ms_h, "dt": dt_hevi, "lsrk54_ms_per_step": ex["ms_per_step"], "lsrk54_dt": dth,
+        "ms_per_step": ms_h, "first_step_ms_with_line_factor": ms_first, "dt": dt_hevi,
+        "lsrk54_ms_per_step": ex["ms_per_step"], "lsrk54_dt": dth,
         "simulated_time_speedup_vs_lsrk54": (dt_hevi / ms_h) / (dth / ex["ms_per_step"]),
         "n_nonfinite": dh["n_nonfinite"],
         "note": "ARK2 (explicit horizontal, implicit vertical acoustics), 32x32x32 elements of 200 x 200 x 5 m, "
-                "const nu = 1, dt = 12 x the explicit vertical limit; LSRK54 at that limit on the same mesh"}
+                "const nu = 1, dt = 12 x the explicit vertical limit; LSRK54 at that limit on the same mesh; "
+                "the timed steps reuse the line factor the first step formed (same dt)"}
     return res
 
 

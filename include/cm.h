@@ -240,7 +240,12 @@ CM_API cm_status cm_lsrk144_step(cm_model* model, void* Y, void* Y_alt, void* dQ
  * is cm_dg_rhs minus L.  Integrator: ARK2 of Giraldo, Kelly & Constantinescu
  * (2013), three stages, second order.  Each implicit stage solves (I - tau L)
  * d = B - Y_ref on every vertical node line (block-tridiagonal elimination
- * over the element layers, FP64).
+ * over the element layers, FP64).  When the background is horizontally
+ * uniform (given per level), every line has the same matrix: the model then
+ * keeps one factor of it, formed on the stream of the first solve with a
+ * given tau and reused while tau stays the same (calls on one model must be
+ * ordered, as for every model call); otherwise each line is eliminated on
+ * its own.
  *
  * work: caller-owned device memory of cm_hevi_workspace_bytes bytes (six
  * state-sized buffers, the line solver's 60 doubles per element layer and
