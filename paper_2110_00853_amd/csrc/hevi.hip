@@ -575,97 +575,143 @@ __global__ __launch_bounds__(64) void k_vfactor(const HeviArgs A, double* __rest
     }
 }
 
-// one thread per vertical line: forward over the layers y_e = Minv_e (b_e -
-// Cb_e y_{e-1}(top nodes)), y_e kept in the workspace ([layer][row][line]),
-// back substitution x_e = y_e - Z_e x_{e+1}(bottom nodes); the horizontal
-// momenta as in k_vsolve.  The factor's entries are the same for every
-// thread (scalar loads).  B and Y may be the same buffer (a line is read
-// before it is written, and lines do not share nodes).
+// the line's 15 unknowns of layer ez (variables rho, rho w, rho e_tot at its
+// five nodes) as deviations from the background
 template <typename R>
-__global__ __launch_bounds__(256) void k_vapply(const HeviArgs A, const double* __restrict__ F, const R* B, R* Y,
-                                                int64_t n_lines)
+__device__ __forceinline__ void load_layer(const HeviArgs& A, const R* B, int e, int ez, int i, int j, double b[VS_N])
 {
-    const int64_t line = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (line >= n_lines) return;
+#pragma unroll
+    for (int r = 0; r < VS_N; ++r) {
+        const int v3 = r / NQ, kr = r % NQ, var = v3 == 0 ? 0 : (v3 == 1 ? 3 : 4);
+        const int tnode = i + NQ * (j + NQ * kr);
+        b[r] = (double)B[var * A.nnS + (int64_t)e * SRUN + tnode] - sref<R>(A, var, href(A, e, ez, kr, tnode));
+    }
+}
+
+// one thread per vertical line, 64 lines per block (one wave); each layer's
+// factor is staged in LDS (two buffers: the next layer's copy is issued
+// before the current layer's arithmetic) and read by every thread at the
+// same address.  Forward over the layers y_e = Minv_e (b_e - Cb_e
+// y_{e-1}(top nodes)), y_e kept in the workspace ([layer][row][line]); back
+// substitution x_e = y_e - Z_e x_{e+1}(bottom nodes).  The next layer's
+// state loads are also issued before the current layer's arithmetic.
+// Threads past the last line compute on the last line and write nothing, so
+// that every thread reaches the barriers.  B and Y may be the same buffer (a
+// line is read before it is written, and lines do not share nodes).
+template <typename R>
+__global__ __launch_bounds__(64) void k_vapply(const HeviArgs A, const double* __restrict__ F, const R* B, R* Y,
+                                               int64_t n_lines)
+{
+    __shared__ double sF[2][HEVI_FAC];
+    const int nz = A.ne2;
+    const int t = threadIdx.x;
+    const int64_t line_id = (int64_t)blockIdx.x * 64 + t;
+    const bool live = line_id < n_lines;
+    const int64_t line = live ? line_id : n_lines - 1;
     const int node = (int)(line % (NQ * NQ));
     const int64_t col = line / (NQ * NQ);
     const int i = node % NQ, j = node / NQ;
     const int ex = (int)(col % A.ne0), ey = (int)(col / A.ne0);
-    const int nz = A.ne2;
     double* ys = A.scratch;
+    for (int q = t; q < HEVI_FAC; q += 64) sF[0][q] = F[q];
     double yprev[3] = {0.0, 0.0, 0.0};
+    double bn[VS_N];
+    load_layer<R>(A, B, ex + A.ne0 * ey, 0, i, j, bn);
+    __syncthreads();
     for (int ez = 0; ez < nz; ++ez) {
-        const int e = ex + A.ne0 * (ey + A.ne1 * ez);
-        const double* Fe = F + (int64_t)ez * HEVI_FAC;
+        const double* Fe = sF[ez & 1];
+        if (ez + 1 < nz)
+            for (int q = t; q < HEVI_FAC; q += 64) sF[(ez + 1) & 1][q] = F[(int64_t)(ez + 1) * HEVI_FAC + q];
         double b[VS_N];
 #pragma unroll
-        for (int r = 0; r < VS_N; ++r) {
-            const int v3 = r / NQ, kr = r % NQ, var = v3 == 0 ? 0 : (v3 == 1 ? 3 : 4);
-            const int tnode = i + NQ * (j + NQ * kr);
-            b[r] = (double)B[var * A.nnS + (int64_t)e * SRUN + tnode] - sref<R>(A, var, href(A, e, ez, kr, tnode));
-        }
-        if (ez > 0) {
+        for (int r = 0; r < VS_N; ++r) b[r] = bn[r];
+        if (ez + 1 < nz) load_layer<R>(A, B, ex + A.ne0 * (ey + A.ne1 * (ez + 1)), ez + 1, i, j, bn);
 #pragma unroll
-            for (int w = 0; w < 3; ++w)
+        for (int w = 0; w < 3; ++w)
 #pragma unroll
-                for (int q = 0; q < 3; ++q) b[vb(w, 0)] -= Fe[VS_N * VS_N + 3 * VS_N + 3 * w + q] * yprev[q];
-        }
+            for (int q = 0; q < 3; ++q) b[vb(w, 0)] -= Fe[VS_N * VS_N + 3 * VS_N + 3 * w + q] * yprev[q];
 #pragma unroll
         for (int r = 0; r < VS_N; ++r) {
             double y = 0.0;
 #pragma unroll
             for (int c = 0; c < VS_N; ++c) y += Fe[r * VS_N + c] * b[c];
-            ys[((int64_t)ez * VS_N + r) * n_lines + line] = y;
+            if (live) ys[((int64_t)ez * VS_N + r) * n_lines + line] = y;
             if (r % NQ == NQ - 1) yprev[r / NQ] = y;
         }
+        __syncthreads();
     }
+    // the last layer's factor is still in its buffer
     double xb[3] = {0.0, 0.0, 0.0};
+    double yn[VS_N];
+#pragma unroll
+    for (int r = 0; r < VS_N; ++r) yn[r] = ys[((int64_t)(nz - 1) * VS_N + r) * n_lines + line];
     for (int ez = nz - 1; ez >= 0; --ez) {
         const int e = ex + A.ne0 * (ey + A.ne1 * ez);
-        const double* Fe = F + (int64_t)ez * HEVI_FAC;
+        const double* Fe = sF[ez & 1];
+        if (ez > 0)
+            for (int q = t; q < HEVI_FAC; q += 64) sF[(ez - 1) & 1][q] = F[(int64_t)(ez - 1) * HEVI_FAC + q];
         double x[VS_N];
 #pragma unroll
-        for (int r = 0; r < VS_N; ++r) {
-            double xr = ys[((int64_t)ez * VS_N + r) * n_lines + line];
+        for (int r = 0; r < VS_N; ++r) x[r] = yn[r];
+        if (ez > 0)
 #pragma unroll
-            for (int w = 0; w < 3; ++w) xr -= Fe[VS_N * VS_N + 3 * r + w] * xb[w];
-            x[r] = xr;
-        }
+            for (int r = 0; r < VS_N; ++r) yn[r] = ys[((int64_t)(ez - 1) * VS_N + r) * n_lines + line];
 #pragma unroll
-        for (int r = 0; r < VS_N; ++r) {
-            const int v3 = r / NQ, kr = r % NQ, var = v3 == 0 ? 0 : (v3 == 1 ? 3 : 4);
-            const int tnode = i + NQ * (j + NQ * kr);
-            Y[var * A.nnS + (int64_t)e * SRUN + tnode] = (R)(sref<R>(A, var, href(A, e, ez, kr, tnode)) + x[r]);
+        for (int r = 0; r < VS_N; ++r)
+#pragma unroll
+            for (int w = 0; w < 3; ++w) x[r] -= Fe[VS_N * VS_N + 3 * r + w] * xb[w];
+        if (live) {
+#pragma unroll
+            for (int r = 0; r < VS_N; ++r) {
+                const int v3 = r / NQ, kr = r % NQ, var = v3 == 0 ? 0 : (v3 == 1 ? 3 : 4);
+                const int tnode = i + NQ * (j + NQ * kr);
+                Y[var * A.nnS + (int64_t)e * SRUN + tnode] = (R)(sref<R>(A, var, href(A, e, ez, kr, tnode)) + x[r]);
+            }
         }
 #pragma unroll
         for (int w = 0; w < 3; ++w) xb[w] = x[vb(w, 0)];
+        __syncthreads();
     }
-    // horizontal momenta: identity except the 2 x 2 systems of the interior
-    // vertical faces, [1 + s, -s; -s, 1 + s] with s = tau lift lam / 2
+}
+
+// the horizontal momenta of the lines with a common matrix: identity
+// except the 2 x 2 systems of the interior vertical faces, [1 + s, -s; -s,
+// 1 + s] with s = tau lift lam / 2; one thread per (line, variable)
+template <typename R>
+__global__ __launch_bounds__(256) void k_vmom(const HeviArgs A, const R* B, R* Y, int64_t n_lines)
+{
+    const int64_t id = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (id >= 2 * n_lines) return;
+    const int v = 1 + (int)(id / n_lines);
+    const int64_t line = id % n_lines;
+    const int node = (int)(line % (NQ * NQ));
+    const int64_t col = line / (NQ * NQ);
+    const int i = node % NQ, j = node / NQ;
+    const int ex = (int)(col % A.ne0), ey = (int)(col / A.ne0);
+    const int nz = A.ne2;
     const double lift = 2.0 / A.h2 * 10.0;
-    for (int v = 1; v <= 2; ++v)
-        for (int ez = 0; ez < nz; ++ez) {
-            const int e = ex + A.ne0 * (ey + A.ne1 * ez);
+    for (int ez = 0; ez < nz; ++ez) {
+        const int e = ex + A.ne0 * (ey + A.ne1 * ez);
 #pragma unroll
-            for (int k = 0; k < NQ; ++k) {
-                const int tnode = i + NQ * (j + NQ * k);
-                const int64_t ri = href(A, e, ez, k, tnode);
-                if (k == NQ - 1 && ez < nz - 1) {
-                    const int en = e + A.ne01;
-                    const int tn = i + NQ * j;
-                    const int64_t rin = href(A, en, ez + 1, 0, tn);
-                    const HRef ra = href_tab(A, ri, ez, k), rb = href_tab(A, rin, ez + 1, 0);
-                    const double lam = ra.c > rb.c ? ra.c : rb.c;
-                    const double sv = 0.5 * A.tau * lift * lam, al = 1.0 + sv, det = al * al - sv * sv;
-                    const double xa = (double)B[v * A.nnS + (int64_t)e * SRUN + tnode] - sref<R>(A, v, ri);
-                    const double xbv = (double)B[v * A.nnS + (int64_t)en * SRUN + tn] - sref<R>(A, v, rin);
-                    Y[v * A.nnS + (int64_t)e * SRUN + tnode] = (R)(sref<R>(A, v, ri) + (al * xa + sv * xbv) / det);
-                    Y[v * A.nnS + (int64_t)en * SRUN + tn] = (R)(sref<R>(A, v, rin) + (sv * xa + al * xbv) / det);
-                } else if (!(k == 0 && ez > 0)) {
-                    Y[v * A.nnS + (int64_t)e * SRUN + tnode] = B[v * A.nnS + (int64_t)e * SRUN + tnode];
-                }
+        for (int k = 0; k < NQ; ++k) {
+            const int tnode = i + NQ * (j + NQ * k);
+            const int64_t ri = href(A, e, ez, k, tnode);
+            if (k == NQ - 1 && ez < nz - 1) {
+                const int en = e + A.ne01;
+                const int tn = i + NQ * j;
+                const int64_t rin = href(A, en, ez + 1, 0, tn);
+                const HRef ra = href_tab(A, ri, ez, k), rb = href_tab(A, rin, ez + 1, 0);
+                const double lam = ra.c > rb.c ? ra.c : rb.c;
+                const double sv = 0.5 * A.tau * lift * lam, al = 1.0 + sv, det = al * al - sv * sv;
+                const double xa = (double)B[v * A.nnS + (int64_t)e * SRUN + tnode] - sref<R>(A, v, ri);
+                const double xbv = (double)B[v * A.nnS + (int64_t)en * SRUN + tn] - sref<R>(A, v, rin);
+                Y[v * A.nnS + (int64_t)e * SRUN + tnode] = (R)(sref<R>(A, v, ri) + (al * xa + sv * xbv) / det);
+                Y[v * A.nnS + (int64_t)en * SRUN + tn] = (R)(sref<R>(A, v, rin) + (sv * xa + al * xbv) / det);
+            } else if (!(k == 0 && ez > 0)) {
+                Y[v * A.nnS + (int64_t)e * SRUN + tnode] = B[v * A.nnS + (int64_t)e * SRUN + tnode];
             }
         }
+    }
 }
 
 static HeviArgs hevi_args(const cm_model* m, double tau, double* scratch)
@@ -722,13 +768,17 @@ hipError_t launch_hevi_solve(cm_model* m, double tau, const void* B, void* Yout,
             if (e != hipSuccess) return e;
             m->hevi_fac_tau = tau;
         }
-        const dim3 ga((unsigned)((nl + 255) / 256)), ba(256);
-        if (m->desc.precision == CM_FP64)
+        const dim3 ga((unsigned)((nl + 63) / 64)), ba(64);
+        const dim3 gm((unsigned)((2 * nl + 255) / 256)), bm(256);
+        if (m->desc.precision == CM_FP64) {
             hipLaunchKernelGGL(k_vapply<double>, ga, ba, 0, s, A, (const double*)m->d_hevi_fac, (const double*)B,
                                (double*)Yout, nl);
-        else
+            hipLaunchKernelGGL(k_vmom<double>, gm, bm, 0, s, A, (const double*)B, (double*)Yout, nl);
+        } else {
             hipLaunchKernelGGL(k_vapply<float>, ga, ba, 0, s, A, (const double*)m->d_hevi_fac, (const float*)B,
                                (float*)Yout, nl);
+            hipLaunchKernelGGL(k_vmom<float>, gm, bm, 0, s, A, (const float*)B, (float*)Yout, nl);
+        }
         return hipGetLastError();
     }
     const dim3 grid((unsigned)((nl + VS_BLOCK / VS_LANES - 1) / (VS_BLOCK / VS_LANES))), block(VS_BLOCK);
