@@ -598,11 +598,14 @@ __device__ __forceinline__ void load_layer(const HeviArgs& A, const R* B, int e,
 // Threads past the last line compute on the last line and write nothing, so
 // that every thread reaches the barriers.  B and Y may be the same buffer (a
 // line is read before it is written, and lines do not share nodes).
-template <typename R>
+template <typename R, bool WHOLE>
 __global__ __launch_bounds__(64) void k_vapply(const HeviArgs A, const double* __restrict__ F, const R* B, R* Y,
                                                int64_t n_lines)
 {
-    __shared__ double sF[2][HEVI_FAC];
+    // WHOLE: the factor of every layer in LDS at once, copied at entry (no
+    // barrier per layer); else two layer buffers
+    extern __shared__ double sFw[];
+    __shared__ double sF[WHOLE ? 1 : 2][WHOLE ? 1 : HEVI_FAC];
     const int nz = A.ne2;
     const int t = threadIdx.x;
     const int64_t line_id = (int64_t)blockIdx.x * 64 + t;
@@ -613,14 +616,17 @@ __global__ __launch_bounds__(64) void k_vapply(const HeviArgs A, const double* _
     const int i = node % NQ, j = node / NQ;
     const int ex = (int)(col % A.ne0), ey = (int)(col / A.ne0);
     double* ys = A.scratch;
-    for (int q = t; q < HEVI_FAC; q += 64) sF[0][q] = F[q];
+    if (WHOLE)
+        for (int q = t; q < nz * HEVI_FAC; q += 64) sFw[q] = F[q];
+    else
+        for (int q = t; q < HEVI_FAC; q += 64) sF[0][q] = F[q];
     double yprev[3] = {0.0, 0.0, 0.0};
     double bn[VS_N];
     load_layer<R>(A, B, ex + A.ne0 * ey, 0, i, j, bn);
     __syncthreads();
     for (int ez = 0; ez < nz; ++ez) {
-        const double* Fe = sF[ez & 1];
-        if (ez + 1 < nz)
+        const double* Fe = WHOLE ? sFw + ez * HEVI_FAC : sF[ez & 1];
+        if (!WHOLE && ez + 1 < nz)
             for (int q = t; q < HEVI_FAC; q += 64) sF[(ez + 1) & 1][q] = F[(int64_t)(ez + 1) * HEVI_FAC + q];
         double b[VS_N];
 #pragma unroll
@@ -638,7 +644,7 @@ __global__ __launch_bounds__(64) void k_vapply(const HeviArgs A, const double* _
             if (live) ys[((int64_t)ez * VS_N + r) * n_lines + line] = y;
             if (r % NQ == NQ - 1) yprev[r / NQ] = y;
         }
-        __syncthreads();
+        if (!WHOLE) __syncthreads();
     }
     // the last layer's factor is still in its buffer
     double xb[3] = {0.0, 0.0, 0.0};
@@ -647,8 +653,8 @@ __global__ __launch_bounds__(64) void k_vapply(const HeviArgs A, const double* _
     for (int r = 0; r < VS_N; ++r) yn[r] = ys[((int64_t)(nz - 1) * VS_N + r) * n_lines + line];
     for (int ez = nz - 1; ez >= 0; --ez) {
         const int e = ex + A.ne0 * (ey + A.ne1 * ez);
-        const double* Fe = sF[ez & 1];
-        if (ez > 0)
+        const double* Fe = WHOLE ? sFw + ez * HEVI_FAC : sF[ez & 1];
+        if (!WHOLE && ez > 0)
             for (int q = t; q < HEVI_FAC; q += 64) sF[(ez - 1) & 1][q] = F[(int64_t)(ez - 1) * HEVI_FAC + q];
         double x[VS_N];
 #pragma unroll
@@ -670,7 +676,7 @@ __global__ __launch_bounds__(64) void k_vapply(const HeviArgs A, const double* _
         }
 #pragma unroll
         for (int w = 0; w < 3; ++w) xb[w] = x[vb(w, 0)];
-        __syncthreads();
+        if (!WHOLE) __syncthreads();
     }
 }
 
@@ -770,13 +776,19 @@ hipError_t launch_hevi_solve(cm_model* m, double tau, const void* B, void* Yout,
         }
         const dim3 ga((unsigned)((nl + 63) / 64)), ba(64);
         const dim3 gm((unsigned)((2 * nl + 255) / 256)), bm(256);
+        // the whole factor in LDS when it fits a block's share
+        int lds_max = 0;
+        (void)hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, m->device);
+        const size_t whole = sizeof(double) * (size_t)A.ne2 * HEVI_FAC;
+        const bool w = whole + 64 <= (size_t)lds_max;
+        const double* Fd = m->d_hevi_fac;
         if (m->desc.precision == CM_FP64) {
-            hipLaunchKernelGGL(k_vapply<double>, ga, ba, 0, s, A, (const double*)m->d_hevi_fac, (const double*)B,
-                               (double*)Yout, nl);
+            if (w) hipLaunchKernelGGL((k_vapply<double, true>), ga, ba, whole, s, A, Fd, (const double*)B, (double*)Yout, nl);
+            else hipLaunchKernelGGL((k_vapply<double, false>), ga, ba, 0, s, A, Fd, (const double*)B, (double*)Yout, nl);
             hipLaunchKernelGGL(k_vmom<double>, gm, bm, 0, s, A, (const double*)B, (double*)Yout, nl);
         } else {
-            hipLaunchKernelGGL(k_vapply<float>, ga, ba, 0, s, A, (const double*)m->d_hevi_fac, (const float*)B,
-                               (float*)Yout, nl);
+            if (w) hipLaunchKernelGGL((k_vapply<float, true>), ga, ba, whole, s, A, Fd, (const float*)B, (float*)Yout, nl);
+            else hipLaunchKernelGGL((k_vapply<float, false>), ga, ba, 0, s, A, Fd, (const float*)B, (float*)Yout, nl);
             hipLaunchKernelGGL(k_vmom<float>, gm, bm, 0, s, A, (const float*)B, (float*)Yout, nl);
         }
         return hipGetLastError();
