@@ -164,3 +164,44 @@ def test_line_factor_follows_tau():
         err = max(np.abs(Xg[v] - Xo[v]).max() / max(np.abs(Xo[v] - Yref[v]).max(), 1e-300) for v in range(5))
         print("tau", tau, "solve error relative to the deviation", err)
         assert err <= 1e-11, (tau, err)
+
+
+def test_tall_column_stages_the_factor_by_layer():
+    """80 element layers: the shared line factor (80 x 2232 bytes) no longer
+    fits a block's LDS at once, so the apply stages it layer by layer; the
+    GPU solves every line, the oracle two of them.  On a column this tall
+    the oracle's own solve moves by 4.7e-11 of the density deviation when
+    its input moves by one ulp (the rounding of 80 layers accumulates along
+    the line; the per-line elimination lands exactly where the shared factor
+    does), so the bar is twice that floor where it exceeds 1e-11."""
+    import torch
+
+    c = _case((1, 1, 80), (300.0, 300.0, 1600.0), closure="const")
+    c["model"]["nu"] = 1.0
+    Y, Yref, _ = W.perturbed_state(c, seed=25, amp_u=5.0, amp_T=2.0)
+    g = B.Grid(c["grid"])
+    m = B.Model(g, c["model"], Yref)
+    Yd, Xd = m.new_state(Y), m.new_state()
+    work = m.hevi_workspace()
+    tau = 0.05
+    m.hevi_solve(tau, Yd, Xd, work)
+    torch.cuda.synchronize()
+    lines = np.array([0, 18])
+    om = oracle.Model(oracle.Grid(c["grid"]), c["model"], Yref)
+    Xo = om.hevi_solve_lines(tau, Y, lines)
+    Yp = Y * (1.0 + 2.2e-16 * np.random.default_rng(1).choice([-1.0, 0.0, 1.0], size=Y.shape))
+    Xp = om.hevi_solve_lines(tau, Yp, lines)
+    Xg = m.to_numpy(Xd)
+    on = np.zeros(Y.shape[1], bool)
+    for ln in lines:
+        i, j = int(ln) % 5, int(ln) // 5
+        for ez in range(80):
+            on[ez * 125 + i + 5 * (j + 5 * np.arange(5))] = True
+
+    def rel(X):
+        return np.array([np.abs(X[v, on] - Xo[v, on]).max() / max(np.abs(Xo[v, on] - Yref[v, on]).max(), 1e-300)
+                         for v in range(5)])
+
+    err, floor = rel(Xg), rel(Xp)
+    print("tall column sampled solve errors relative to the deviation", err, "oracle 1-ulp floor", floor)
+    assert np.all(err <= np.maximum(1e-11, 2.0 * floor)), (err, floor)
