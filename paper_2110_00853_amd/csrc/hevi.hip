@@ -682,7 +682,12 @@ __global__ __launch_bounds__(64) void k_vapply(const HeviArgs A, const double* _
 
 // the horizontal momenta of the lines with a common matrix: identity
 // except the 2 x 2 systems of the interior vertical faces, [1 + s, -s; -s,
-// 1 + s] with s = tau lift lam / 2; one thread per (line, variable)
+// 1 + s] with s = tau lift lam / 2; one thread per (line, variable).  Each
+// layer's values are loaded, together with the bottom node of the layer
+// above, before anything of the layer is stored, and the next layer's loads
+// go out before this layer's stores (the nodes a layer stores are never
+// loaded later: the bottom node of a layer above the first belongs to the
+// pair below it).
 template <typename R>
 __global__ __launch_bounds__(256) void k_vmom(const HeviArgs A, const R* B, R* Y, int64_t n_lines)
 {
@@ -696,27 +701,43 @@ __global__ __launch_bounds__(256) void k_vmom(const HeviArgs A, const R* B, R* Y
     const int ex = (int)(col % A.ne0), ey = (int)(col / A.ne0);
     const int nz = A.ne2;
     const double lift = 2.0 / A.h2 * 10.0;
+    const R* Bv = B + v * A.nnS;
+    R* Yv = Y + v * A.nnS;
+    // the line's nodes of layer ez (k = 0..4, k = 0 only in the first
+    // layer) and the bottom node of layer ez + 1
+    R cur[NQ + 1], nxt[NQ + 1];
+    auto load = [&](int ez, R* x) {
+        const int64_t eo = (int64_t)(ex + A.ne0 * (ey + A.ne1 * ez)) * SRUN;
+#pragma unroll
+        for (int k = 0; k < NQ; ++k)
+            x[k] = (k > 0 || ez == 0) ? Bv[eo + i + NQ * (j + NQ * k)] : (R)0;
+        x[NQ] = ez + 1 < nz ? Bv[eo + (int64_t)A.ne01 * SRUN + i + NQ * j] : (R)0;
+    };
+    load(0, cur);
     for (int ez = 0; ez < nz; ++ez) {
+        if (ez + 1 < nz) load(ez + 1, nxt);
         const int e = ex + A.ne0 * (ey + A.ne1 * ez);
+        const int64_t eo = (int64_t)e * SRUN;
 #pragma unroll
         for (int k = 0; k < NQ; ++k) {
             const int tnode = i + NQ * (j + NQ * k);
-            const int64_t ri = href(A, e, ez, k, tnode);
             if (k == NQ - 1 && ez < nz - 1) {
                 const int en = e + A.ne01;
                 const int tn = i + NQ * j;
-                const int64_t rin = href(A, en, ez + 1, 0, tn);
+                const int64_t ri = href(A, e, ez, k, tnode), rin = href(A, en, ez + 1, 0, tn);
                 const HRef ra = href_tab(A, ri, ez, k), rb = href_tab(A, rin, ez + 1, 0);
                 const double lam = ra.c > rb.c ? ra.c : rb.c;
                 const double sv = 0.5 * A.tau * lift * lam, al = 1.0 + sv, det = al * al - sv * sv;
-                const double xa = (double)B[v * A.nnS + (int64_t)e * SRUN + tnode] - sref<R>(A, v, ri);
-                const double xbv = (double)B[v * A.nnS + (int64_t)en * SRUN + tn] - sref<R>(A, v, rin);
-                Y[v * A.nnS + (int64_t)e * SRUN + tnode] = (R)(sref<R>(A, v, ri) + (al * xa + sv * xbv) / det);
-                Y[v * A.nnS + (int64_t)en * SRUN + tn] = (R)(sref<R>(A, v, rin) + (sv * xa + al * xbv) / det);
+                const double xa = (double)cur[k] - sref<R>(A, v, ri);
+                const double xbv = (double)cur[NQ] - sref<R>(A, v, rin);
+                Yv[eo + tnode] = (R)(sref<R>(A, v, ri) + (al * xa + sv * xbv) / det);
+                Yv[(int64_t)en * SRUN + tn] = (R)(sref<R>(A, v, rin) + (sv * xa + al * xbv) / det);
             } else if (!(k == 0 && ez > 0)) {
-                Y[v * A.nnS + (int64_t)e * SRUN + tnode] = B[v * A.nnS + (int64_t)e * SRUN + tnode];
+                Yv[eo + tnode] = cur[k];
             }
         }
+#pragma unroll
+        for (int q = 0; q <= NQ; ++q) cur[q] = nxt[q];
     }
 }
 
