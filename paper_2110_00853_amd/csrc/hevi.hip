@@ -680,6 +680,140 @@ __global__ __launch_bounds__(64) void k_vapply(const HeviArgs A, const double* _
     }
 }
 
+// a double from lane s of this lane's DPP quad
+template <int S>
+__device__ __forceinline__ double quad_bcast(double x)
+{
+    constexpr int CTRL = S | (S << 2) | (S << 4) | (S << 6);
+    const unsigned long long bits = __builtin_bit_cast(unsigned long long, x);
+    const int lo = __builtin_amdgcn_update_dpp((int)(unsigned)bits, (int)(unsigned)bits, CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp((int)(unsigned)(bits >> 32), (int)(unsigned)(bits >> 32), CTRL, 0xF,
+                                               0xF, false);
+    return __builtin_bit_cast(double, ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
+}
+
+// the same application with four lanes per line (a DPP quad, 16 lines per
+// wave, 64 per 256-thread block), the factor of every layer in LDS: lane q
+// holds rows q, q + 4, q + 8 (and q + 12 for q < 3) of the line's 15; the
+// right-hand sides of the other lanes and the coupling values come by DPP
+// quad broadcasts
+template <typename R>
+__global__ __launch_bounds__(256) void k_vapply4(const HeviArgs A, const double* __restrict__ F, const R* B, R* Y,
+                                                 int64_t n_lines)
+{
+    extern __shared__ double sFw[];  // [nz][HEVI_FAC]
+    const int nz = A.ne2;
+    for (int q = threadIdx.x; q < nz * HEVI_FAC; q += 256) sFw[q] = F[q];
+    __syncthreads();
+    const int q = threadIdx.x & 3;
+    const int64_t line_id = ((int64_t)blockIdx.x * 256 + threadIdx.x) >> 2;
+    // every lane of a quad takes part in the broadcasts; lanes past the last
+    // line compute on the last line and write nothing
+    const bool live = line_id < n_lines;
+    const int64_t line = live ? line_id : n_lines - 1;
+    const int node = (int)(line % (NQ * NQ));
+    const int64_t col = line / (NQ * NQ);
+    const int i = node % NQ, j = node / NQ;
+    const int ex = (int)(col % A.ne0), ey = (int)(col / A.ne0);
+    double* ys = A.scratch;
+    // this lane's rows r = q + 4 m (m = 3 only for q < 3)
+    int var[4], tnode[4], kr[4];
+    bool has[4];
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+        const int r = q + 4 * m;
+        has[m] = r < VS_N;
+        const int rr = has[m] ? r : 0, v3 = rr / NQ;
+        kr[m] = rr % NQ;
+        var[m] = v3 == 0 ? 0 : (v3 == 1 ? 3 : 4);
+        tnode[m] = i + NQ * (j + NQ * kr[m]);
+    }
+    auto load = [&](int ez, double* b) {
+        const int e = ex + A.ne0 * (ey + A.ne1 * ez);
+#pragma unroll
+        for (int m = 0; m < 4; ++m)
+            b[m] = has[m] ? (double)B[var[m] * A.nnS + (int64_t)e * SRUN + tnode[m]] -
+                                sref<R>(A, var[m], href(A, e, ez, kr[m], tnode[m]))
+                          : 0.0;
+    };
+    double yprev[3] = {0.0, 0.0, 0.0};
+    double bn[4];
+    load(0, bn);
+    for (int ez = 0; ez < nz; ++ez) {
+        const double* Fe = sFw + ez * HEVI_FAC;
+        double bm[4];
+#pragma unroll
+        for (int m = 0; m < 4; ++m) bm[m] = bn[m];
+        if (ez + 1 < nz) load(ez + 1, bn);
+        // Schur update of the bottom rows (0, 5, 10: lanes 0, 1, 2 at m = 0,
+        // 1, 2 respectively)
+#pragma unroll
+        for (int m = 0; m < 3; ++m)
+            if (q == m) {
+                double s = 0.0;
+#pragma unroll
+                for (int c = 0; c < 3; ++c) s += Fe[VS_N * VS_N + 3 * VS_N + 3 * m + c] * yprev[c];
+                // row 5 m sits at slot m' with q + 4 m' = 5 m
+                if (m == 0) bm[0] -= s;
+                if (m == 1) bm[1] -= s;
+                if (m == 2) bm[2] -= s;
+            }
+        // all 15 right-hand sides: row q' + 4 m' from lane q'
+        double b[VS_N];
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+            const double v0 = quad_bcast<0>(bm[m]), v1 = quad_bcast<1>(bm[m]), v2 = quad_bcast<2>(bm[m]),
+                         v3 = quad_bcast<3>(bm[m]);
+            if (4 * m + 0 < VS_N) b[4 * m + 0] = v0;
+            if (4 * m + 1 < VS_N) b[4 * m + 1] = v1;
+            if (4 * m + 2 < VS_N) b[4 * m + 2] = v2;
+            if (4 * m + 3 < VS_N) b[4 * m + 3] = v3;
+        }
+        double y[4];
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+            const int r = has[m] ? q + 4 * m : 0;
+            double acc = 0.0;
+#pragma unroll
+            for (int c = 0; c < VS_N; ++c) acc += Fe[r * VS_N + c] * b[c];
+            y[m] = acc;
+            if (live && has[m]) ys[((int64_t)ez * VS_N + q + 4 * m) * n_lines + line] = acc;
+        }
+        // y at the top rows 4, 9, 14: lane 0 m = 1, lane 1 m = 2, lane 2 m = 3
+        yprev[0] = quad_bcast<0>(y[1]);
+        yprev[1] = quad_bcast<1>(y[2]);
+        yprev[2] = quad_bcast<2>(y[3]);
+    }
+    double xb[3] = {0.0, 0.0, 0.0};
+    double yn[4];
+#pragma unroll
+    for (int m = 0; m < 4; ++m) yn[m] = has[m] ? ys[((int64_t)(nz - 1) * VS_N + q + 4 * m) * n_lines + line] : 0.0;
+    for (int ez = nz - 1; ez >= 0; --ez) {
+        const int e = ex + A.ne0 * (ey + A.ne1 * ez);
+        const double* Fe = sFw + ez * HEVI_FAC;
+        double x[4];
+#pragma unroll
+        for (int m = 0; m < 4; ++m) x[m] = yn[m];
+        if (ez > 0)
+#pragma unroll
+            for (int m = 0; m < 4; ++m)
+                yn[m] = has[m] ? ys[((int64_t)(ez - 1) * VS_N + q + 4 * m) * n_lines + line] : 0.0;
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+            const int r = has[m] ? q + 4 * m : 0;
+#pragma unroll
+            for (int w = 0; w < 3; ++w) x[m] -= Fe[VS_N * VS_N + 3 * r + w] * xb[w];
+            if (live && has[m])
+                Y[var[m] * A.nnS + (int64_t)e * SRUN + tnode[m]] =
+                    (R)(sref<R>(A, var[m], href(A, e, ez, kr[m], tnode[m])) + x[m]);
+        }
+        // x at the bottom rows 0, 5, 10: lane 0 m = 0, lane 1 m = 1, lane 2 m = 2
+        xb[0] = quad_bcast<0>(x[0]);
+        xb[1] = quad_bcast<1>(x[1]);
+        xb[2] = quad_bcast<2>(x[2]);
+    }
+}
+
 // the horizontal momenta of the lines with a common matrix: identity
 // except the 2 x 2 systems of the interior vertical faces, [1 + s, -s; -s,
 // 1 + s] with s = tau lift lam / 2; one thread per (line, variable).  Each
@@ -803,12 +937,13 @@ hipError_t launch_hevi_solve(cm_model* m, double tau, const void* B, void* Yout,
         const size_t whole = sizeof(double) * (size_t)A.ne2 * HEVI_FAC;
         const bool w = whole + 64 <= (size_t)lds_max;
         const double* Fd = m->d_hevi_fac;
+        const dim3 g4((unsigned)((4 * nl + 255) / 256)), b4(256);
         if (m->desc.precision == CM_FP64) {
-            if (w) hipLaunchKernelGGL((k_vapply<double, true>), ga, ba, whole, s, A, Fd, (const double*)B, (double*)Yout, nl);
+            if (w) hipLaunchKernelGGL(k_vapply4<double>, g4, b4, whole, s, A, Fd, (const double*)B, (double*)Yout, nl);
             else hipLaunchKernelGGL((k_vapply<double, false>), ga, ba, 0, s, A, Fd, (const double*)B, (double*)Yout, nl);
             hipLaunchKernelGGL(k_vmom<double>, gm, bm, 0, s, A, (const double*)B, (double*)Yout, nl);
         } else {
-            if (w) hipLaunchKernelGGL((k_vapply<float, true>), ga, ba, whole, s, A, Fd, (const float*)B, (float*)Yout, nl);
+            if (w) hipLaunchKernelGGL(k_vapply4<float>, g4, b4, whole, s, A, Fd, (const float*)B, (float*)Yout, nl);
             else hipLaunchKernelGGL((k_vapply<float, false>), ga, ba, 0, s, A, Fd, (const float*)B, (float*)Yout, nl);
             hipLaunchKernelGGL(k_vmom<float>, gm, bm, 0, s, A, (const float*)B, (float*)Yout, nl);
         }
