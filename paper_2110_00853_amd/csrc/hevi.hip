@@ -11,9 +11,14 @@
 //   k_vsolve : (I - tau L) x = B - Y_ref on every vertical node line, 16
 //              lanes per line: block-tridiagonal elimination over the
 //              element layers with 15 x 15 blocks for (rho, rho w, rho e_tot)
-//              (rows across lanes, partial pivoting through LDS), 2 x 2 face
-//              systems for the horizontal momenta (only the face penalty
-//              couples them)
+//              (rows across lanes, partial pivoting by a DPP maximum and lane
+//              permutes), 2 x 2 face systems for the horizontal momenta
+//              (only the face penalty couples them); for backgrounds given
+//              per node
+//   k_vfactor, k_vapply4 / k_vapply, k_vmom: the same solve when every line
+//              shares one matrix (background per level): the elimination
+//              once per tau, then its application per line, and the momenta
+//   k_href_table: the background's h_r and c_r per entry, for the solves
 //   k_combine: out = base + sum_i c_i X_i over the node slots
 #include <cmath>
 
